@@ -69,6 +69,8 @@ def lib():
         L.orc_canon.argtypes = [ctypes.c_int, ctypes.c_int, _u64p, _u64p, _u64p, _u64p]
         L.orc_multiply.restype = ctypes.c_int
         L.orc_multiply.argtypes = [ctypes.c_int] + [_u64p] * 6
+        L.orc_exact_sum.restype = ctypes.c_double
+        L.orc_exact_sum.argtypes = [_f64p, ctypes.c_size_t]
         L.orc_int_less.restype = ctypes.c_int
         L.orc_int_less.argtypes = [ctypes.c_int] + [_u64p] * 4
         _lib = L
@@ -97,6 +99,11 @@ def multiply(n: int, a, b):
     k = lib().orc_multiply(n, _words(a[0], W), _words(a[1], W), _words(b[0], W),
                            _words(b[1], W), rx, rz)
     return k, _join(rx), _join(rz)
+
+
+def exact_sum(values) -> float:
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    return lib().orc_exact_sum(v.ctypes.data_as(_f64p), len(v))
 
 
 def int_less(n: int, a, b) -> bool:

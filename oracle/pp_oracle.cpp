@@ -161,6 +161,43 @@ Pauli canon(const Pauli& s, int n, int group) {
   return s;
 }
 
+// Correctly rounded sum of doubles (Shewchuk, "Adaptive Precision
+// Floating-Point Arithmetic and Fast Robust Geometric Predicates", 1997):
+// keep the running sum as non-overlapping partials, each new addend folded
+// in with exact two-sums; finally add the partials from the largest down,
+// correcting a result that lands halfway between two doubles.
+double exact_sum(const std::vector<double>& xs) {
+  std::vector<double> partials;
+  for (double x : xs) {
+    size_t k = 0;
+    for (double y : partials) {
+      if (std::fabs(x) < std::fabs(y)) std::swap(x, y);
+      const double hi = x + y;
+      const double lo = y - (hi - x);
+      if (lo != 0.0) partials[k++] = lo;
+      x = hi;
+    }
+    partials.resize(k);
+    partials.push_back(x);
+  }
+  if (partials.empty()) return 0.0;
+  size_t n = partials.size();
+  double hi = partials[--n], lo = 0.0;
+  while (n > 0) {
+    const double x = hi, y = partials[--n];
+    hi = x + y;
+    const double yr = hi - x;
+    lo = y - yr;
+    if (lo != 0.0) break;
+  }
+  if (n > 0 && ((lo < 0.0 && partials[n - 1] < 0.0) || (lo > 0.0 && partials[n - 1] > 0.0))) {
+    const double y = lo * 2.0;
+    const double x = hi + y;
+    if (y == x - hi) hi = x;
+  }
+  return hi;
+}
+
 struct Oracle {
   int n = 0;
   int group = kNone;
@@ -211,12 +248,16 @@ void orc_add_term(void* h, const uint64_t* x, const uint64_t* z, double c) {
 }
 
 // Algorithm 1 step 1 and step 2b (Algorithms 2 and 3): replace every string
-// by its orbit representative and add the coefficients of each orbit.
+// by its orbit representative and add the coefficients of each orbit.  The
+// algorithms leave the order of the additions open; the orbit sum is taken
+// exactly and rounded once (exact_sum), so it does not depend on that order.
 void orc_merge(void* h) {
   auto* o = static_cast<Oracle*>(h);
   o->merged += o->terms.size();
+  std::map<Pauli, std::vector<double>> addends;
+  for (const auto& [s, c] : o->terms) addends[canon(s, o->n, o->group)].push_back(c);
   std::map<Pauli, double> merged;
-  for (const auto& [s, c] : o->terms) merged[canon(s, o->n, o->group)] += c;
+  for (const auto& [r, v] : addends) merged[r] = exact_sum(v);
   o->terms.swap(merged);
 }
 
@@ -327,6 +368,10 @@ int orc_multiply(int n, const uint64_t* ax, const uint64_t* az,
     rz[w] = r.z[w];
   }
   return k;
+}
+
+double orc_exact_sum(const double* v, size_t n) {
+  return exact_sum(std::vector<double>(v, v + n));
 }
 
 int orc_int_less(int n, const uint64_t* ax, const uint64_t* az,

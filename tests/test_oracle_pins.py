@@ -417,3 +417,23 @@ def test_work_counters():
     assert o.size() == 4
     o.apply_gate(*W.from_letters("IIZZ"), 0.3, 0.0, -1)   # all commute
     assert o.counters() == (6, 8)
+
+
+def test_orbit_sum_is_exactly_rounded():
+    """The merge adds an orbit's coefficients exactly and rounds once, so the
+    result is math.fsum's (the correctly rounded sum), in any order."""
+    rng = random.Random(17)
+    for _ in range(300):
+        k = rng.randint(0, 40)
+        g = [rng.gauss(0, 1) * 10.0 ** rng.uniform(-12, 12) for _ in range(k)]
+        g += [-v for v in g[: k // 3]]
+        rng.shuffle(g)
+        assert O.exact_sum(g) == math.fsum(g)
+    assert O.exact_sum([1e16, 1.0, -1e16]) == 1.0
+    # through the merge itself: three translates of one string, cancelling
+    n = 4
+    o = O.Oracle(n, "Zn")
+    for s, c in (("XIII", 1e16), ("IXII", 1.0), ("IIXI", -1e16)):
+        o.add(*W.from_letters(s), c)
+    o.merge()
+    assert o.as_dict() == {W.from_letters("XIII"): 1.0}

@@ -1,0 +1,228 @@
+/*
+ * pp.h -- C ABI of the MI355X (gfx950) symmetry-merging Pauli propagation
+ * library.
+ *
+ * The library evolves an observable O, stored as a set of Pauli strings
+ * with real coefficients, through a circuit of Pauli rotations in the
+ * Heisenberg picture and merges strings that are related by a symmetry of
+ * the circuit, following "Leveraging Symmetry Merging in Pauli Propagation"
+ * (Teng, Chang, Rudolph, Holmes, arXiv:2512.12094): Algorithm 1, the gate
+ * rule of Proposition 1, and the lowest-integer representatives of
+ * Algorithms 2 (translations Z_n) and 3 (permutations S_n).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A Pauli string on n qubits is a pair of bit masks (x, z) of W = ceil(n/64)
+ *   little-endian uint64 words each; qubit q is bit q%64 of word q/64
+ *   (symplectic form, Appendix E.2).  I=(0,0), X=(1,0), Y=(1,1), Z=(0,1).
+ *   Row r of an array of strings occupies words [r*W, r*W+W).  Bits at
+ *   positions >= n must be zero.
+ * - Coefficients are those of unnormalised Pauli operators, O = sum c_s s.
+ * - A gate (x, z, theta) is the rotation exp(-i theta/2 P).  In the
+ *   Heisenberg picture an anticommuting string Q becomes
+ *   cos(theta) Q + sin(theta) (iPQ) and a commuting one is unchanged
+ *   (Proposition 1, proof part (2), with the half-angle convention).
+ * - Representatives are the lowest-integer members of each orbit
+ *   (Definition "lowest integer representation", Appendix E.2): I->0, X->1,
+ *   Y->2, Z->3 as the base-4 digit of weight 4^q for qubit q.  For Z_n this
+ *   is the minimum over the n cyclic translations (Algorithm 2); for S_n it
+ *   is Z^{nZ} Y^{nY} X^{nX} I^{rest} from qubit 0 upward (Algorithm 3).
+ *   Merging adds the coefficients of the distinct strings of one orbit.
+ * - Supported sizes: PP_GROUP_NONE and PP_GROUP_PERMUTATION for 1 <= n <= 128,
+ *   PP_GROUP_TRANSLATION for 2 <= n <= 64.
+ *
+ * Memory, streams, ownership
+ * --------------------------
+ * - A handle owns all of its device memory.  It obtains that memory from the
+ *   caller's allocator (e.g. PyTorch's caching allocator) or, when the
+ *   allocator argument is NULL, from hipMalloc/hipFree.
+ * - Every call enqueues its kernels on the handle's HIP stream.  Host arrays
+ *   passed in are copied before the call returns; the caller keeps them.
+ *   Output arrays are owned by the caller.
+ * - Calls that synchronise the stream: pp_create, pp_apply_layer (once, to
+ *   learn whether the term store had to grow), pp_merge_canonicalize,
+ *   pp_expectation, pp_num_terms, pp_export_terms, pp_counters,
+ *   pp_batch_run.  pp_truncate does not synchronise.
+ * - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Errors
+ * ------
+ * Every int-returning function returns PP_OK (0) or a negative code; nothing
+ * throws across the ABI.  pp_last_error() returns a thread-local message for
+ * the most recent failure.  After PP_EINVAL / PP_ENOTSYM the handle is
+ * unchanged.  After PP_ECAPACITY / PP_ENOMEM inside pp_apply_layer the handle
+ * stays valid and holds the result of the gates that were applied before
+ * the one that did not fit (pp_last_error names how many).
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_state pp_state;
+typedef struct pp_program pp_program;
+
+enum {
+  PP_GROUP_NONE = 0,         /* plain Pauli propagation (no symmetry merge) */
+  PP_GROUP_TRANSLATION = 1,  /* cyclic translations Z_n                     */
+  PP_GROUP_PERMUTATION = 2   /* qubit permutations S_n                      */
+};
+
+enum { PP_F64 = 0 };
+
+enum {
+  PP_OK = 0,
+  PP_EINVAL = -1,     /* bad argument                                        */
+  PP_ENOTSYM = -2,    /* gate multiset not closed under the handle's group   */
+  PP_ENOMEM = -3,     /* the allocator returned NULL                         */
+  PP_ECAPACITY = -4,  /* the term store would exceed pp_set_max_terms        */
+  PP_EDEVICE = -5     /* a HIP runtime call failed                           */
+};
+
+typedef struct {
+  /* Returns device memory of at least `bytes` bytes usable on `stream`, or NULL. */
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  /* Releases memory obtained from alloc. */
+  void (*free)(void* p, void* stream, void* ctx);
+  void* ctx;
+} pp_allocator;
+
+/*
+ * pp_create -- Algorithm 1, step 1.
+ * Builds a handle for n_qubits qubits and merge group `group`, loads the
+ * observable rows (obs_x/obs_z: n_obs rows of W words, host memory;
+ * obs_coef: n_obs doubles, host), adds duplicate rows, and merges the rows
+ * by orbit representative.  dtype must be PP_F64.  hip_stream may be NULL
+ * (the null stream).  alloc may be NULL (hipMalloc).  On success *out holds
+ * the handle; release it with pp_destroy.
+ */
+int pp_create(pp_state** out, int n_qubits, int group, int dtype,
+              const uint64_t* obs_x, const uint64_t* obs_z,
+              const double* obs_coef, size_t n_obs, void* hip_stream,
+              const pp_allocator* alloc);
+
+/*
+ * pp_apply_layer -- Algorithm 1, step 2a, for one symmetric (sub-)layer.
+ * Applies n_gates rotations in the given order: gate k is
+ * exp(-i theta[k]/2 P_k) with P_k = rows k of gate_x/gate_z (host, W words
+ * each).  Each gate conjugates the current observable, O <- V_k^dag O V_k,
+ * so a caller that holds a time-ordered layer passes it reversed.  After
+ * every gate, identical strings are merged (standard PP, Sec. I) and terms
+ * with |c| < inner_eps or weight > inner_max_weight are dropped
+ * (inner_eps = 0 and inner_max_weight < 0 switch these off).
+ * merge_every must be 1.  For a handle whose group is not
+ * PP_GROUP_NONE the gate multiset must be closed under the group (every
+ * translate / permutation of each gate present with the same angle),
+ * otherwise PP_ENOTSYM.
+ */
+int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
+                   const double* theta, size_t n_gates, int merge_every,
+                   double inner_eps, int inner_max_weight);
+
+/*
+ * pp_merge_canonicalize -- Algorithm 1, step 2b (Algorithms 2 and 3).
+ * Replaces every string by its orbit representative and adds the
+ * coefficients per representative.  For PP_GROUP_NONE the set is already
+ * free of duplicates and the call only compacts the store.
+ */
+int pp_merge_canonicalize(pp_state* s);
+
+/*
+ * pp_truncate -- damping and truncation.
+ * First multiplies every coefficient by (1 - depol_p)^{weight} (depolarising
+ * noise on every qubit, Heisenberg picture; depol_p = 0: no damping), then
+ * drops terms with |c| < eps or weight > max_weight (eps = 0 and
+ * max_weight < 0: off).  Does not synchronise.
+ */
+int pp_truncate(pp_state* s, double eps, int max_weight, double depol_p);
+
+/*
+ * pp_expectation -- Algorithm 1, step 3.
+ * *out = Tr[rho O] for the symmetric product state rho = (|psi><psi|)^{(x)n}
+ * whose single-qubit Bloch vector is bloch_xyz = (<X>, <Y>, <Z>):
+ * sum_r c_r bx^{nX(r)} by^{nY(r)} bz^{nZ(r)}, reduced in FP64.
+ */
+int pp_expectation(pp_state* s, const double bloch_xyz[3], double* out);
+
+/* Number of live terms. */
+int pp_num_terms(pp_state* s, size_t* out);
+
+/*
+ * Copies the live terms to caller-owned host arrays (x, z: cap rows of W
+ * words; coef: cap doubles) in unspecified order; *n_out = number written.
+ * PP_EINVAL if cap is smaller than the number of live terms.
+ */
+int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef,
+                    size_t cap, size_t* n_out);
+
+/*
+ * Work counters since creation: out[0] = propagated = sum over gates of the
+ * live terms tested against the gate (Prop. 1's propagation unit);
+ * out[1] = merged = sum over merge points of the records entering the merge
+ * (after every gate: live terms + anticommuting terms; after a layer: the
+ * live terms fed to the symmetry merge).
+ */
+int pp_counters(pp_state* s, uint64_t out[2]);
+
+/* Upper bound on stored terms (live + not yet compacted); 0 = no limit. */
+int pp_set_max_terms(pp_state* s, size_t max_terms);
+
+void pp_destroy(pp_state* s);
+
+/* Thread-local message for the most recent error ("" if none). */
+const char* pp_last_error(void);
+
+/*
+ * Batched form.  A program is a whole propagation described on the host:
+ * sub-layers in Heisenberg order (n_sub of them; sub-layer j owns gates
+ * [sub_start[j], sub_start[j+1]) of gate_x/gate_z/theta, already in the
+ * order they are applied), each with its inner/outer truncation eps[j],
+ * max_weight[j] and damping depol_p[j] (applied before its gates), and the
+ * final Bloch vector.  The library uploads it once.  Every sub-layer runs
+ * damp -> gates (exact merge + truncation after each) -> symmetry merge ->
+ * truncation, and the program ends with the expectation value.
+ */
+int pp_program_create(pp_program** out, int n_qubits, size_t n_sub,
+                      const size_t* sub_start, const uint64_t* gate_x,
+                      const uint64_t* gate_z, const double* theta,
+                      const double* eps, const int* max_weight,
+                      const double* depol_p, const double bloch_xyz[3]);
+void pp_program_destroy(pp_program* p);
+
+/*
+ * Runs programs[i] on states[i] for i < n (n <= 1024), all instances
+ * advancing together: every step is one pass of a fixed sequence of
+ * persistent kernels that serve all instances at once, and steps are
+ * replayed from a captured HIP graph.  Each state must have been created on
+ * `hip_stream` with the program's n_qubits.  On return
+ * expectations[i] (host array, may be NULL) holds Tr[rho O] of instance i.
+ */
+int pp_batch_run(pp_state* const* states, const pp_program* const* programs,
+                 size_t n, void* hip_stream, double* expectations);
+
+/*
+ * Incremental form for serving: advances every listed instance by up to
+ * max_steps batched steps (graph replays) and sets done[i] = 1 for
+ * instances whose program has finished (expectations[i] then valid).
+ * Instances may join or leave between calls.  A state starts its program at
+ * the first pp_batch_step/pp_batch_run call that lists it with that program.
+ */
+int pp_batch_step(pp_state* const* states, const pp_program* const* programs,
+                  size_t n, void* hip_stream, int max_steps, int* done,
+                  double* expectations);
+
+/* Tuning knobs picked by the autotuner: threads per block (64..1024, a
+ * multiple of 64), maximum persistent blocks per launch, and steps per
+ * captured graph in the batched form. */
+int pp_set_tuning(int block_threads, int max_blocks, int graph_steps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PP_H */

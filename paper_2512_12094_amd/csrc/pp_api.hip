@@ -1,0 +1,951 @@
+// Host side of the C ABI declared in include/pp.h.
+//
+// A handle holds one instance: its term store (two halves plus tables, see
+// pp_types.h), a device copy of its buffer descriptor and dynamic state,
+// and a scratch program.  Every call turns into a short program of device
+// operations (pp_types.h: OpType) that the kernels of pp_kernels.hpp
+// execute; the host only re-launches after growing the store.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "pp.h"
+#include "pp_kernels.hpp"
+#include "pp_types.h"
+
+using namespace pp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct Tuning {
+  int max_blocks = 2048;
+  int graph_steps = 32;
+};
+Tuning g_tune;
+
+#define HIP_TRY(expr)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(PP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+uint32_t ceil_log2(uint64_t v) {
+  uint32_t b = 0;
+  while ((1ull << b) < v) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct pp_program {
+  int n = 0;
+  std::vector<Op> ops;        // host copy (table pointers already device)
+  Op* d_ops = nullptr;
+  double* d_tab = nullptr;
+  size_t n_gates = 0;
+};
+
+struct pp_state {
+  int n = 0, W = 1, group = 0;
+  hipStream_t stream = nullptr;
+  pp_allocator alloc{};
+  bool use_alloc = false;
+  size_t max_terms = 0;
+  InstBuf buf{};                       // host mirror of the descriptor
+  std::vector<void*> store;            // allocations of the current store
+  InstBuf* d_buf = nullptr;
+  InstDyn* d_dyn = nullptr;
+  const InstBuf** d_bufp = nullptr;    // 1-entry pointer arrays for Ctx
+  InstDyn** d_dynp = nullptr;
+  int* d_ninst = nullptr;
+  uint32_t* d_sync = nullptr;
+  Op* d_ops = nullptr;
+  size_t ops_cap = 0;
+  double* d_tab = nullptr;
+  size_t tab_cap = 0;
+  InstDyn* h_dyn = nullptr;            // pinned
+  const pp_program* batch_prog = nullptr;
+  // pinned staging ring for program uploads of calls that do not sync
+  struct Stage {
+    char* h = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+  } ring[4];
+  unsigned ring_pos = 0;
+};
+
+namespace {
+
+void* dev_alloc(pp_state* s, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (s->use_alloc) return s->alloc.alloc(bytes, s->stream, s->alloc.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(pp_state* s, void* p) {
+  if (!p) return;
+  if (s->use_alloc)
+    s->alloc.free(p, s->stream, s->alloc.ctx);
+  else
+    (void)hipFree(p);
+}
+
+Ctx single_ctx(pp_state* s) {
+  Ctx c;
+  c.bufs = s->d_bufp;
+  c.dyns = s->d_dynp;
+  c.ninst = s->d_ninst;
+  c.sync = s->d_sync;
+  return c;
+}
+
+int upload_buf(pp_state* s) {
+  HIP_TRY(hipMemcpyAsync(s->d_buf, &s->buf, sizeof(InstBuf), hipMemcpyHostToDevice, s->stream));
+  return PP_OK;
+}
+
+int read_dyn(pp_state* s) {
+  HIP_TRY(hipMemcpyAsync(s->h_dyn, s->d_dyn, sizeof(InstDyn), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return PP_OK;
+}
+
+// Allocates a store of capacity `cap` (both halves and all tables).
+int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* allocs) {
+  const int W = s->W;
+  InstBuf nb = s->buf;
+  nb.cap = cap;
+  nb.hg_bits = std::max<uint32_t>(10, ceil_log2(2ull * cap));
+  nb.hm_bits = nb.hg_bits;
+  const size_t ng = size_t(1) << nb.hg_bits, nm = size_t(1) << nb.hm_bits;
+  std::vector<void*> got;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = dev_alloc(s, bytes);
+    if (p) got.push_back(p);
+    return p;
+  };
+  bool ok = true;
+  for (int h = 0; h < 2; ++h) {
+    ok = ok && (nb.x[h] = (uint64_t*)take(sizeof(uint64_t) * W * cap));
+    ok = ok && (nb.z[h] = (uint64_t*)take(sizeof(uint64_t) * W * cap));
+    ok = ok && (nb.c[h] = (double*)take(sizeof(double) * cap));
+    for (int p = 0; p < 2; ++p) ok = ok && (nb.alive[h][p] = (uint8_t*)take(cap));
+  }
+  ok = ok && (nb.gtab = (uint64_t*)take(sizeof(uint64_t) * ng));
+  ok = ok && (nb.mkey = (uint64_t*)take(sizeof(uint64_t) * nm));
+  ok = ok && (nb.mfx = (uint64_t*)take(3 * sizeof(uint64_t) * nm));
+  const bool wide = !nb.narrow;
+  nb.mown = nullptr;
+  nb.wrep = nullptr;
+  nb.wslot = nullptr;
+  if (wide) {
+    ok = ok && (nb.mown = (uint32_t*)take(sizeof(uint32_t) * nm));
+    ok = ok && (nb.wrep = (uint64_t*)take(sizeof(uint64_t) * 2 * W * cap));
+    ok = ok && (nb.wslot = (uint32_t*)take(sizeof(uint32_t) * cap));
+  }
+  ok = ok && (nb.partial = (double*)take(sizeof(double) * ((cap + kTile - 1) / kTile + 1)));
+  if (!ok) {
+    for (void* p : got) dev_free(s, p);
+    return fail(PP_ENOMEM, "allocation of a term store of capacity " + std::to_string(cap) +
+                               " failed");
+  }
+  HIP_TRY(hipMemsetAsync(nb.gtab, 0, sizeof(uint64_t) * ng, s->stream));
+  HIP_TRY(hipMemsetAsync(nb.mkey, 0xFF, sizeof(uint64_t) * nm, s->stream));
+  HIP_TRY(hipMemsetAsync(nb.mfx, 0, 3 * sizeof(uint64_t) * nm, s->stream));
+  if (wide) HIP_TRY(hipMemsetAsync(nb.mown, 0xFF, sizeof(uint32_t) * nm, s->stream));
+  for (int h = 0; h < 2; ++h)
+    for (int p = 0; p < 2; ++p) HIP_TRY(hipMemsetAsync(nb.alive[h][p], 0, cap, s->stream));
+  *b = nb;
+  *allocs = std::move(got);
+  return PP_OK;
+}
+
+void free_store(pp_state* s, std::vector<void*>& allocs) {
+  for (void* p : allocs) dev_free(s, p);
+  allocs.clear();
+}
+
+int launch_blocks(uint64_t elements) {
+  const uint64_t tiles = (elements + kTile - 1) / kTile;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)g_tune.max_blocks));
+}
+
+// Grows (or just compacts) the store so that live + count + slack fits.
+int grow(pp_state* s) {
+  const InstDyn& d = *s->h_dyn;
+  const uint64_t need = (uint64_t)d.live + d.count;
+  // same capacity (a compaction) when the live terms leave enough room
+  uint64_t cap = std::max<uint64_t>({(uint64_t)s->buf.cap, 4 * need, 4096});
+  if (cap > 0xFFFFFFF0ull) cap = 0xFFFFFFF0ull;
+  if (s->max_terms && cap > s->max_terms) cap = s->max_terms;
+  if (cap < need + 1)
+    return fail(PP_ECAPACITY, "term store would need " + std::to_string(need + 1) +
+                                  " entries, limit " + std::to_string(s->max_terms));
+  InstBuf nb;
+  std::vector<void*> allocs;
+  int rc = alloc_store(s, (uint32_t)cap, &nb, &allocs);
+  if (rc) return rc;
+  nb.prog = s->buf.prog;
+  nb.prog_len = s->buf.prog_len;
+  hipLaunchKernelGGL(k_grow, dim3(launch_blocks(d.M)), dim3(kBlock), 0, s->stream, s->buf, nb,
+                     s->d_dyn, s->d_sync);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  free_store(s, s->store);
+  s->store = std::move(allocs);
+  s->buf = nb;
+  int r = upload_buf(s);
+  if (r) return r;
+  return read_dyn(s);
+}
+
+int ensure_ops(pp_state* s, size_t nops, size_t ntab) {
+  if (nops > s->ops_cap) {
+    dev_free(s, s->d_ops);
+    s->ops_cap = std::max<size_t>(nops, 2 * s->ops_cap);
+    s->d_ops = (Op*)dev_alloc(s, sizeof(Op) * s->ops_cap);
+    if (!s->d_ops) return fail(PP_ENOMEM, "program buffer");
+  }
+  if (ntab > s->tab_cap) {
+    dev_free(s, s->d_tab);
+    s->tab_cap = std::max<size_t>(ntab, 2 * s->tab_cap);
+    s->d_tab = (double*)dev_alloc(s, sizeof(double) * s->tab_cap);
+    if (!s->d_tab) return fail(PP_ENOMEM, "table buffer");
+  }
+  return PP_OK;
+}
+
+// Launches the kernels that execute ops[from..] assuming none overflows.
+int launch_ops(pp_state* s, const std::vector<Op>& ops, size_t from) {
+  const Ctx C = single_ctx(s);
+  const int gb = launch_blocks(s->buf.cap);
+  const int mb = launch_blocks(1ull << s->buf.hm_bits);
+  for (size_t k = from; k < ops.size(); ++k) {
+    switch (ops[k].type) {
+      case OP_GATE:
+        hipLaunchKernelGGL(k_gate, dim3(gb), dim3(kBlock), 0, s->stream, C);
+        break;
+      case OP_MERGE:
+        if (s->group == PP_GROUP_NONE && !ops[k].force_full) {
+          hipLaunchKernelGGL(k_compact, dim3(gb), dim3(kBlock), 0, s->stream, C);
+        } else if (s->buf.narrow) {
+          hipLaunchKernelGGL(k_merge_narrow, dim3(gb), dim3(kBlock), 0, s->stream, C);
+          hipLaunchKernelGGL(k_merge_collect, dim3(mb), dim3(kBlock), 0, s->stream, C);
+        } else {
+          hipLaunchKernelGGL(k_merge_wide1, dim3(gb), dim3(kBlock), 0, s->stream, C);
+          hipLaunchKernelGGL(k_merge_wide2, dim3(gb), dim3(kBlock), 0, s->stream, C);
+          hipLaunchKernelGGL(k_merge_collect, dim3(mb), dim3(kBlock), 0, s->stream, C);
+        }
+        break;
+      default:
+        hipLaunchKernelGGL(k_scan_op, dim3(gb), dim3(kBlock), 0, s->stream, C);
+        break;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return PP_OK;
+}
+
+// Uploads `ops` (and `tab`), runs them to completion, growing the store
+// when a gate does not fit.  Synchronises unless `nosync` and no op can
+// overflow.
+using TabRefs = std::vector<std::pair<size_t, size_t>>;   // (op index, table offset)
+
+int run_ops(pp_state* s, std::vector<Op> ops, const std::vector<double>& tab,
+            const TabRefs& refs, bool nosync) {
+  if (ops.empty()) return PP_OK;
+  int rc = ensure_ops(s, ops.size(), tab.size());
+  if (rc) return rc;
+  for (const auto& r : refs) ops[r.first].table = s->d_tab + r.second;
+  s->buf.prog = s->d_ops;
+  s->buf.prog_len = (uint32_t)ops.size();
+  s->batch_prog = nullptr;
+  {
+    // ops, tables and the buffer descriptor go through pinned staging
+    auto& st = s->ring[s->ring_pos++ % 4];
+    const size_t ob = sizeof(Op) * ops.size(), tb = sizeof(double) * tab.size();
+    const size_t bb = sizeof(InstBuf);
+    if (st.used) HIP_TRY(hipEventSynchronize(st.ev));
+    if (!st.ev) HIP_TRY(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
+    if (st.cap < ob + tb + bb) {
+      if (st.h) HIP_TRY(hipHostFree(st.h));
+      st.h = nullptr;
+      st.cap = std::max<size_t>(ob + tb + bb, 4096);
+      HIP_TRY(hipHostMalloc((void**)&st.h, st.cap, hipHostMallocDefault));
+    }
+    std::memcpy(st.h, &s->buf, bb);
+    std::memcpy(st.h + bb, ops.data(), ob);
+    if (tb) std::memcpy(st.h + bb + ob, tab.data(), tb);
+    HIP_TRY(hipMemcpyAsync(s->d_buf, st.h, bb, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->d_ops, st.h + bb, ob, hipMemcpyHostToDevice, s->stream));
+    if (tb)
+      HIP_TRY(hipMemcpyAsync(s->d_tab, st.h + bb + ob, tb, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipEventRecord(st.ev, s->stream));
+    st.used = true;
+  }
+  // pc = 0
+  hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, s->stream, s->d_dyn, 0u);
+  if ((rc = launch_ops(s, ops, 0))) return rc;
+  bool can_overflow = false;
+  for (const auto& op : ops) can_overflow |= op.type == OP_GATE || op.type == OP_MERGE;
+  if (nosync && !can_overflow) return PP_OK;
+  for (int guard = 0; guard < 1000; ++guard) {
+    if ((rc = read_dyn(s))) return rc;
+    const InstDyn& d = *s->h_dyn;
+    if (d.status & ST_RANGE)
+      return fail(PP_EINVAL, "a coefficient is not finite or exceeds 2^54 in magnitude");
+    if (d.pc >= ops.size()) return PP_OK;
+    if (d.status & ST_OVERFLOW) {
+      const uint32_t at = d.pc;
+      if ((rc = grow(s))) {
+        // the store holds the result of ops [0, at); let later calls run
+        const std::string msg = g_err;
+        s->h_dyn->status &= ~ST_OVERFLOW;
+        (void)hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s->stream);
+        (void)hipStreamSynchronize(s->stream);
+        g_err = msg + " (" + std::to_string(at) + " of " + std::to_string(ops.size()) +
+                " operations applied)";
+        return rc;
+      }
+      s->h_dyn->status &= ~ST_OVERFLOW;
+      HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s->stream));
+    }
+    if ((rc = launch_ops(s, ops, s->h_dyn->pc))) return rc;
+  }
+  return fail(PP_EDEVICE, "program did not complete");
+}
+
+Op make_op(uint32_t type) {
+  Op op;
+  std::memset(&op, 0, sizeof(op));
+  op.type = type;
+  op.next_gate = kNone32;
+  op.wmax = -1;
+  return op;
+}
+
+void set_next_gates(std::vector<Op>& ops) {
+  uint32_t next = kNone32;
+  for (size_t k = ops.size(); k-- > 0;) {
+    ops[k].next_gate = next;
+    if (ops[k].type == OP_GATE) next = (uint32_t)k;
+  }
+}
+
+bool valid_group_n(int group, int n) {
+  if (group == PP_GROUP_TRANSLATION) return n >= 2 && n <= 64;
+  if (group == PP_GROUP_NONE || group == PP_GROUP_PERMUTATION) return n >= 1 && n <= 128;
+  return false;
+}
+
+bool row_in_range(const uint64_t* x, const uint64_t* z, int n, int W) {
+  for (int w = 0; w < W; ++w) {
+    const int bits = std::min(64, n - 64 * w);
+    const uint64_t m = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
+    if ((x[w] & ~m) || (z[w] & ~m)) return false;
+  }
+  return true;
+}
+
+// Gate multiset closed under the group (Eq. (action): every group element
+// maps the layer onto itself).
+int check_symmetric(const pp_state* s, const uint64_t* gx, const uint64_t* gz,
+                    const double* theta, size_t K) {
+  const int n = s->n, W = s->W;
+  using Key = std::tuple<uint64_t, uint64_t, uint64_t, uint64_t, double>;
+  auto key = [&](const uint64_t* x, const uint64_t* z, double t) {
+    return Key(x[0], W > 1 ? x[1] : 0, z[0], W > 1 ? z[1] : 0, t);
+  };
+  if (s->group == PP_GROUP_TRANSLATION) {
+    std::map<Key, long> mult;
+    for (size_t k = 0; k < K; ++k) mult[key(gx + k * W, gz + k * W, theta[k])] += 1;
+    const uint64_t mask = n == 64 ? ~0ull : ((1ull << n) - 1);
+    for (const auto& [k, m] : mult) {
+      const uint64_t x = std::get<0>(k), z = std::get<2>(k);
+      const uint64_t tx = ((x >> 1) | (x << (n - 1))) & mask;   // T shifts left
+      const uint64_t tz = ((z >> 1) | (z << (n - 1))) & mask;
+      const uint64_t t1[1] = {tx}, t2[1] = {tz};
+      auto it = mult.find(key(t1, t2, std::get<4>(k)));
+      if (it == mult.end() || it->second != m)
+        return fail(PP_ENOTSYM, "gate layer is not closed under translations");
+    }
+  } else if (s->group == PP_GROUP_PERMUTATION) {
+    std::map<std::tuple<int, int, int, double>, long> cls;
+    std::map<Key, long> mult;
+    for (size_t k = 0; k < K; ++k) {
+      const uint64_t* x = gx + k * W;
+      const uint64_t* z = gz + k * W;
+      int a = 0, b = 0, c = 0;
+      for (int w = 0; w < W; ++w) {
+        a += __builtin_popcountll(x[w] & ~z[w]);
+        b += __builtin_popcountll(x[w] & z[w]);
+        c += __builtin_popcountll(z[w] & ~x[w]);
+      }
+      cls[{a, b, c, theta[k]}] += 1;
+      if (++mult[key(x, z, theta[k])] > 1)
+        return fail(PP_ENOTSYM, "repeated gate in a permutation-symmetric layer");
+    }
+    for (const auto& [c, m] : cls) {
+      // number of distinct strings with (nX, nY, nZ) letters: multinomial
+      const int a = std::get<0>(c), b = std::get<1>(c), cc = std::get<2>(c);
+      double lg = std::lgamma(n + 1.0) - std::lgamma(a + 1.0) - std::lgamma(b + 1.0) -
+                  std::lgamma(cc + 1.0) - std::lgamma(n - a - b - cc + 1.0);
+      const double cnt = std::exp(lg);
+      if (std::fabs(cnt - (double)m) > 0.5)
+        return fail(PP_ENOTSYM, "gate layer is not closed under permutations");
+    }
+  }
+  return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pp_last_error(void) { return g_err.c_str(); }
+
+int pp_set_tuning(int block_threads, int max_blocks, int graph_steps) {
+  if (block_threads != 0 && block_threads != kBlock)
+    return fail(PP_EINVAL, "block_threads must be 0 or " + std::to_string(kBlock));
+  if (max_blocks < 0 || graph_steps < 0) return fail(PP_EINVAL, "negative tuning value");
+  if (max_blocks) g_tune.max_blocks = max_blocks;
+  if (graph_steps) g_tune.graph_steps = graph_steps;
+  return PP_OK;
+}
+
+void pp_destroy(pp_state* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  free_store(s, s->store);
+  dev_free(s, s->d_ops);
+  dev_free(s, s->d_tab);
+  dev_free(s, s->d_buf);
+  dev_free(s, s->d_dyn);
+  dev_free(s, s->d_bufp);
+  dev_free(s, s->d_dynp);
+  dev_free(s, s->d_ninst);
+  dev_free(s, s->d_sync);
+  if (s->h_dyn) (void)hipHostFree(s->h_dyn);
+  for (auto& st : s->ring) {
+    if (st.h) (void)hipHostFree(st.h);
+    if (st.ev) (void)hipEventDestroy(st.ev);
+  }
+  delete s;
+}
+
+int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t* obs_x,
+              const uint64_t* obs_z, const double* obs_coef, size_t n_obs, void* hip_stream,
+              const pp_allocator* alloc) {
+  if (!out) return fail(PP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!valid_group_n(group, n_qubits))
+    return fail(PP_EINVAL, "unsupported (group, n_qubits) = (" + std::to_string(group) + ", " +
+                               std::to_string(n_qubits) + ")");
+  if (dtype != PP_F64) return fail(PP_EINVAL, "dtype must be PP_F64");
+  if (n_obs && (!obs_x || !obs_z || !obs_coef)) return fail(PP_EINVAL, "observable is NULL");
+  if (n_obs > 0x3FFFFFFFull) return fail(PP_EINVAL, "too many observable rows");
+  const int W = (n_qubits + 63) / 64;
+  for (size_t r = 0; r < n_obs; ++r)
+    if (!row_in_range(obs_x + r * W, obs_z + r * W, n_qubits, W))
+      return fail(PP_EINVAL, "observable row " + std::to_string(r) + " has bits >= n_qubits");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(PP_EINVAL, "incomplete allocator");
+
+  std::unique_ptr<pp_state> s(new pp_state);
+  s->n = n_qubits;
+  s->W = W;
+  s->group = group;
+  s->stream = (hipStream_t)hip_stream;
+  if (alloc) {
+    s->alloc = *alloc;
+    s->use_alloc = true;
+  }
+  std::memset(&s->buf, 0, sizeof(InstBuf));
+  s->buf.n = n_qubits;
+  s->buf.W = W;
+  s->buf.group = group;
+  s->buf.narrow = (group == PP_GROUP_PERMUTATION || n_qubits <= 32) ? 1u : 0u;
+
+  HIP_TRY(hipHostMalloc((void**)&s->h_dyn, sizeof(InstDyn), hipHostMallocDefault));
+  s->d_buf = (InstBuf*)dev_alloc(s.get(), sizeof(InstBuf));
+  s->d_dyn = (InstDyn*)dev_alloc(s.get(), sizeof(InstDyn));
+  s->d_bufp = (const InstBuf**)dev_alloc(s.get(), sizeof(void*));
+  s->d_dynp = (InstDyn**)dev_alloc(s.get(), sizeof(void*));
+  s->d_ninst = (int*)dev_alloc(s.get(), sizeof(int));
+  s->d_sync = (uint32_t*)dev_alloc(s.get(), 64);
+  if (!s->d_buf || !s->d_dyn || !s->d_bufp || !s->d_dynp || !s->d_ninst || !s->d_sync) {
+    pp_destroy(s.release());
+    return fail(PP_ENOMEM, "handle allocation failed");
+  }
+  const int one = 1;
+  int rc;
+  auto bail = [&](int code) {
+    pp_destroy(s.release());
+    return code;
+  };
+  if (hipMemcpyAsync(s->d_bufp, &s->d_buf, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
+      hipMemcpyAsync(s->d_dynp, &s->d_dyn, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
+      hipMemcpyAsync(s->d_ninst, &one, sizeof(int), hipMemcpyHostToDevice, s->stream) ||
+      hipMemsetAsync(s->d_sync, 0, 64, s->stream))
+    return bail(fail(PP_EDEVICE, "handle initialisation failed"));
+
+  const uint32_t cap = (uint32_t)std::max<uint64_t>(4096, 2 * n_obs);
+  if ((rc = alloc_store(s.get(), cap, &s->buf, &s->store))) return bail(rc);
+
+  // rows -> word-major planes of half 0, all alive
+  std::vector<uint64_t> xs((size_t)W * cap, 0), zs((size_t)W * cap, 0);
+  for (size_t r = 0; r < n_obs; ++r)
+    for (int w = 0; w < W; ++w) {
+      xs[(size_t)w * cap + r] = obs_x[r * W + w];
+      zs[(size_t)w * cap + r] = obs_z[r * W + w];
+    }
+  std::vector<uint8_t> ones(std::max<size_t>(n_obs, 1), 1);
+  if (hipMemcpyAsync(s->buf.x[0], xs.data(), sizeof(uint64_t) * xs.size(), hipMemcpyHostToDevice,
+                     s->stream) ||
+      hipMemcpyAsync(s->buf.z[0], zs.data(), sizeof(uint64_t) * zs.size(), hipMemcpyHostToDevice,
+                     s->stream) ||
+      (n_obs && hipMemcpyAsync(s->buf.c[0], obs_coef, sizeof(double) * n_obs,
+                               hipMemcpyHostToDevice, s->stream)) ||
+      (n_obs && hipMemcpyAsync(s->buf.alive[0][0], ones.data(), n_obs, hipMemcpyHostToDevice,
+                               s->stream)))
+    return bail(fail(PP_EDEVICE, "observable upload failed"));
+  InstDyn& d = *s->h_dyn;
+  std::memset(&d, 0, sizeof(InstDyn));
+  d.M = d.Mnext = (uint32_t)n_obs;
+  d.gen = 1;
+  d.count_for = kNone32;
+  d.live = (uint32_t)n_obs;
+  d.seed = 1;
+  d.failed_pc = kNone32;
+  if (hipMemcpyAsync(s->d_dyn, &d, sizeof(InstDyn), hipMemcpyHostToDevice, s->stream))
+    return bail(fail(PP_EDEVICE, "state upload failed"));
+  // Algorithm 1, step 1: merge the rows by representative (duplicates too)
+  std::vector<Op> ops(1, make_op(OP_MERGE));
+  ops[0].force_full = 1;
+  if ((rc = run_ops(s.get(), ops, {}, {}, false))) return bail(rc);
+  *out = s.release();
+  return PP_OK;
+}
+
+int pp_set_max_terms(pp_state* s, size_t max_terms) {
+  if (!s) return fail(PP_EINVAL, "state is NULL");
+  s->max_terms = max_terms;
+  return PP_OK;
+}
+
+int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
+                   const double* theta, size_t n_gates, int merge_every, double inner_eps,
+                   int inner_max_weight) {
+  if (!s) return fail(PP_EINVAL, "state is NULL");
+  if (merge_every != 1) return fail(PP_EINVAL, "merge_every must be 1");
+  if (!(inner_eps >= 0.0)) return fail(PP_EINVAL, "inner_eps must be >= 0");
+  if (n_gates == 0) return PP_OK;
+  if (!gate_x || !gate_z || !theta) return fail(PP_EINVAL, "gate arrays are NULL");
+  const int W = s->W;
+  for (size_t k = 0; k < n_gates; ++k) {
+    if (!row_in_range(gate_x + k * W, gate_z + k * W, s->n, W))
+      return fail(PP_EINVAL, "gate " + std::to_string(k) + " has bits >= n_qubits");
+    if (!std::isfinite(theta[k])) return fail(PP_EINVAL, "non-finite angle");
+  }
+  int rc = check_symmetric(s, gate_x, gate_z, theta, n_gates);
+  if (rc) return rc;
+  std::vector<Op> ops;
+  ops.reserve(n_gates + 1);
+  ops.push_back(make_op(OP_COUNT));
+  for (size_t k = 0; k < n_gates; ++k) {
+    Op op = make_op(OP_GATE);
+    for (int w = 0; w < W; ++w) {
+      op.px[w] = gate_x[k * W + w];
+      op.pz[w] = gate_z[k * W + w];
+    }
+    op.cs = std::cos(theta[k]);
+    op.sn = std::sin(theta[k]);
+    op.eps = inner_eps;
+    op.wmax = inner_max_weight < 0 ? -1 : inner_max_weight;
+    op.full_check = k == 0;
+    ops.push_back(op);
+  }
+  set_next_gates(ops);
+  return run_ops(s, ops, {}, {}, false);
+}
+
+int pp_merge_canonicalize(pp_state* s) {
+  if (!s) return fail(PP_EINVAL, "state is NULL");
+  std::vector<Op> ops(1, make_op(OP_MERGE));
+  return run_ops(s, ops, {}, {}, false);
+}
+
+int pp_truncate(pp_state* s, double eps, int max_weight, double depol_p) {
+  if (!s) return fail(PP_EINVAL, "state is NULL");
+  if (!(eps >= 0.0)) return fail(PP_EINVAL, "eps must be >= 0");
+  if (!(depol_p >= 0.0 && depol_p <= 1.0)) return fail(PP_EINVAL, "depol_p must be in [0, 1]");
+  std::vector<Op> ops;
+  std::vector<double> tab;
+  TabRefs refs;
+  if (depol_p > 0.0) {
+    refs.push_back({ops.size(), tab.size()});
+    for (int w = 0; w <= s->n; ++w) tab.push_back(std::pow(1.0 - depol_p, (double)w));
+    ops.push_back(make_op(OP_DAMP));
+  }
+  if (eps > 0.0 || max_weight >= 0) {
+    Op op = make_op(OP_TRUNC);
+    op.eps = eps;
+    op.wmax = max_weight < 0 ? -1 : max_weight;
+    ops.push_back(op);
+  }
+  return run_ops(s, ops, tab, refs, true);
+}
+
+int pp_expectation(pp_state* s, const double bloch_xyz[3], double* out) {
+  if (!s || !bloch_xyz || !out) return fail(PP_EINVAL, "NULL argument");
+  std::vector<double> tab;
+  for (int a = 0; a < 3; ++a) {
+    double p = 1.0;
+    for (int k = 0; k <= s->n; ++k) {
+      tab.push_back(p);
+      p *= bloch_xyz[a];
+    }
+  }
+  std::vector<Op> ops(1, make_op(OP_EXPECT));
+  int rc = run_ops(s, ops, tab, {{0, 0}}, false);
+  if (rc) return rc;
+  *out = s->h_dyn->expect;
+  return PP_OK;
+}
+
+int pp_num_terms(pp_state* s, size_t* out) {
+  if (!s || !out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  *out = s->h_dyn->live;
+  return PP_OK;
+}
+
+int pp_counters(pp_state* s, uint64_t out[2]) {
+  if (!s || !out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  out[0] = s->h_dyn->propagated;
+  out[1] = s->h_dyn->merged;
+  return PP_OK;
+}
+
+int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef, size_t cap,
+                    size_t* n_out) {
+  if (!s || !n_out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  const InstDyn d = *s->h_dyn;
+  if (cap < d.live) return fail(PP_EINVAL, "export capacity " + std::to_string(cap) + " < " +
+                                               std::to_string(d.live) + " live terms");
+  if (d.live && (!x || !z || !coef)) return fail(PP_EINVAL, "export arrays are NULL");
+  const int W = s->W;
+  const uint32_t M = d.M, C = s->buf.cap;
+  std::vector<uint64_t> xs((size_t)W * M), zs((size_t)W * M);
+  std::vector<double> cs(M);
+  std::vector<uint8_t> al(M);
+  for (int w = 0; w < W && M; ++w) {
+    HIP_TRY(hipMemcpyAsync(xs.data() + (size_t)w * M, s->buf.x[d.half] + (size_t)w * C,
+                           sizeof(uint64_t) * M, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(zs.data() + (size_t)w * M, s->buf.z[d.half] + (size_t)w * C,
+                           sizeof(uint64_t) * M, hipMemcpyDeviceToHost, s->stream));
+  }
+  if (M) {
+    HIP_TRY(hipMemcpyAsync(cs.data(), s->buf.c[d.half], sizeof(double) * M,
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(al.data(), s->buf.alive[d.half][d.parity], M, hipMemcpyDeviceToHost,
+                           s->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  size_t r = 0;
+  for (uint32_t i = 0; i < M; ++i) {
+    if (!al[i]) continue;
+    if (r >= cap) return fail(PP_EDEVICE, "live count mismatch");
+    for (int w = 0; w < W; ++w) {
+      x[r * W + w] = xs[(size_t)w * M + i];
+      z[r * W + w] = zs[(size_t)w * M + i];
+    }
+    coef[r] = cs[i];
+    ++r;
+  }
+  *n_out = r;
+  return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// programs and the batched form
+// ---------------------------------------------------------------------------
+int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t* sub_start,
+                      const uint64_t* gate_x, const uint64_t* gate_z, const double* theta,
+                      const double* eps, const int* max_weight, const double* depol_p,
+                      const double bloch_xyz[3]) {
+  if (!out) return fail(PP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_qubits < 1 || n_qubits > 128) return fail(PP_EINVAL, "n_qubits out of range");
+  if (!sub_start || !eps || !max_weight || !depol_p || !bloch_xyz)
+    return fail(PP_EINVAL, "NULL argument");
+  const int W = (n_qubits + 63) / 64;
+  const size_t K = sub_start[n_sub];
+  if (sub_start[0] != 0) return fail(PP_EINVAL, "sub_start[0] must be 0");
+  for (size_t j = 0; j < n_sub; ++j)
+    if (sub_start[j + 1] < sub_start[j]) return fail(PP_EINVAL, "sub_start not monotone");
+  if (K && (!gate_x || !gate_z || !theta)) return fail(PP_EINVAL, "gate arrays are NULL");
+  for (size_t k = 0; k < K; ++k)
+    if (!row_in_range(gate_x + k * W, gate_z + k * W, n_qubits, W))
+      return fail(PP_EINVAL, "gate " + std::to_string(k) + " has bits >= n_qubits");
+  std::unique_ptr<pp_program> p(new pp_program);
+  p->n = n_qubits;
+  p->n_gates = K;
+  std::vector<double> tab;
+  TabRefs refs;
+  std::vector<Op>& ops = p->ops;
+  ops.push_back(make_op(OP_COUNT));
+  for (size_t j = 0; j < n_sub; ++j) {
+    if (!(eps[j] >= 0.0) || !(depol_p[j] >= 0.0 && depol_p[j] <= 1.0))
+      return fail(PP_EINVAL, "bad sub-layer parameters");
+    if (depol_p[j] > 0.0) {
+      refs.push_back({ops.size(), tab.size()});
+      for (int w = 0; w <= n_qubits; ++w) tab.push_back(std::pow(1.0 - depol_p[j], (double)w));
+      ops.push_back(make_op(OP_DAMP));
+    }
+    for (size_t k = sub_start[j]; k < sub_start[j + 1]; ++k) {
+      Op op = make_op(OP_GATE);
+      for (int w = 0; w < W; ++w) {
+        op.px[w] = gate_x[k * W + w];
+        op.pz[w] = gate_z[k * W + w];
+      }
+      op.cs = std::cos(theta[k]);
+      op.sn = std::sin(theta[k]);
+      op.eps = eps[j];
+      op.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
+      op.full_check = k == sub_start[j];
+      ops.push_back(op);
+    }
+    ops.push_back(make_op(OP_MERGE));
+    if (eps[j] > 0.0 || max_weight[j] >= 0) {
+      Op op = make_op(OP_TRUNC);
+      op.eps = eps[j];
+      op.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
+      ops.push_back(op);
+    }
+  }
+  {
+    refs.push_back({ops.size(), tab.size()});
+    ops.push_back(make_op(OP_EXPECT));
+    for (int a = 0; a < 3; ++a) {
+      double v = 1.0;
+      for (int k = 0; k <= n_qubits; ++k) {
+        tab.push_back(v);
+        v *= bloch_xyz[a];
+      }
+    }
+  }
+  set_next_gates(ops);
+  if (hipMalloc((void**)&p->d_ops, sizeof(Op) * ops.size()) != hipSuccess ||
+      hipMalloc((void**)&p->d_tab, sizeof(double) * std::max<size_t>(tab.size(), 1)) !=
+          hipSuccess) {
+    pp_program_destroy(p.release());
+    return fail(PP_ENOMEM, "program allocation failed");
+  }
+  for (const auto& r : refs) ops[r.first].table = p->d_tab + r.second;
+  if (hipMemcpy(p->d_tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
+      hipMemcpy(p->d_ops, ops.data(), sizeof(Op) * ops.size(), hipMemcpyHostToDevice)) {
+    pp_program_destroy(p.release());
+    return fail(PP_EDEVICE, "program upload failed");
+  }
+  *out = p.release();
+  return PP_OK;
+}
+
+void pp_program_destroy(pp_program* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->d_ops) (void)hipFree(p->d_ops);
+  if (p->d_tab) (void)hipFree(p->d_tab);
+  delete p;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One batched context per stream: device pointer arrays, a done counter and
+// the captured graph of `graph_steps` steps.
+struct BatchCtx {
+  hipStream_t stream = nullptr;
+  const InstBuf** d_bufp = nullptr;
+  InstDyn** d_dynp = nullptr;
+  int* d_ninst = nullptr;
+  uint32_t* d_sync = nullptr;
+  InstDyn* d_gather = nullptr;
+  InstDyn* h_gather = nullptr;
+  int* h_ninst = nullptr;
+  const InstBuf** h_bufp = nullptr;
+  InstDyn** h_dynp = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int exec_steps = 0, exec_blocks = 0;
+};
+
+std::mutex g_batch_mu;
+std::map<hipStream_t, BatchCtx*> g_batches;
+
+int batch_ctx(hipStream_t stream, BatchCtx** out) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = g_batches.find(stream);
+  if (it != g_batches.end()) {
+    *out = it->second;
+    return PP_OK;
+  }
+  auto* b = new BatchCtx;
+  b->stream = stream;
+  if (hipMalloc((void**)&b->d_bufp, sizeof(void*) * kMaxInst) ||
+      hipMalloc((void**)&b->d_dynp, sizeof(void*) * kMaxInst) ||
+      hipMalloc((void**)&b->d_ninst, sizeof(int)) || hipMalloc((void**)&b->d_sync, 64) ||
+      hipMalloc((void**)&b->d_gather, sizeof(InstDyn) * kMaxInst) ||
+      hipHostMalloc((void**)&b->h_gather, sizeof(InstDyn) * kMaxInst, hipHostMallocDefault) ||
+      hipHostMalloc((void**)&b->h_ninst, sizeof(int), hipHostMallocDefault) ||
+      hipHostMalloc((void**)&b->h_bufp, sizeof(void*) * kMaxInst, hipHostMallocDefault) ||
+      hipHostMalloc((void**)&b->h_dynp, sizeof(void*) * kMaxInst, hipHostMallocDefault) ||
+      hipMemset(b->d_sync, 0, 64)) {
+    return fail(PP_ENOMEM, "batch context allocation failed");
+  }
+  g_batches[stream] = b;
+  *out = b;
+  return PP_OK;
+}
+
+void launch_step(BatchCtx* b, int blocks) {
+  Ctx C;
+  C.bufs = b->d_bufp;
+  C.dyns = b->d_dynp;
+  C.ninst = b->d_ninst;
+  C.sync = b->d_sync;
+  const dim3 g(blocks), t(kBlock);
+  hipLaunchKernelGGL(k_gate, g, t, 0, b->stream, C);
+  hipLaunchKernelGGL(k_merge_narrow, g, t, 0, b->stream, C);
+  hipLaunchKernelGGL(k_merge_wide1, g, t, 0, b->stream, C);
+  hipLaunchKernelGGL(k_merge_wide2, g, t, 0, b->stream, C);
+  hipLaunchKernelGGL(k_merge_collect, g, t, 0, b->stream, C);
+  hipLaunchKernelGGL(k_compact, g, t, 0, b->stream, C);
+  hipLaunchKernelGGL(k_scan_op, g, t, 0, b->stream, C);
+}
+
+int ensure_graph(BatchCtx* b) {
+  const int steps = std::max(1, g_tune.graph_steps), blocks = g_tune.max_blocks;
+  if (b->exec && b->exec_steps == steps && b->exec_blocks == blocks) return PP_OK;
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  hipGraph_t graph;
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < steps; ++k) launch_step(b, blocks);
+  HIP_TRY(hipStreamEndCapture(b->stream, &graph));
+  const hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(PP_EDEVICE, std::string("graph: ") + hipGetErrorString(e));
+  b->exec_steps = steps;
+  b->exec_blocks = blocks;
+  return PP_OK;
+}
+
+int batch_common(pp_state* const* states, const pp_program* const* programs, size_t n,
+                 void* hip_stream, int max_replays, int* done, double* expectations) {
+  if (!states || !programs) return fail(PP_EINVAL, "NULL argument");
+  if (n == 0) return PP_OK;
+  if (n > (size_t)kMaxInst) return fail(PP_EINVAL, "at most 1024 instances per batch");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  if (!stream) return fail(PP_EINVAL, "the batched form needs a non-null stream");
+  for (size_t i = 0; i < n; ++i) {
+    if (!states[i] || !programs[i]) return fail(PP_EINVAL, "NULL state or program");
+    if (states[i]->stream != stream) return fail(PP_EINVAL, "state created on another stream");
+    if (states[i]->n != programs[i]->n) return fail(PP_EINVAL, "program n differs from state n");
+  }
+  BatchCtx* b;
+  int rc = batch_ctx(stream, &b);
+  if (rc) return rc;
+  // (re)start instances whose program changed
+  for (size_t i = 0; i < n; ++i) {
+    pp_state* s = states[i];
+    if (s->batch_prog != programs[i]) {
+      s->buf.prog = programs[i]->d_ops;
+      s->buf.prog_len = (uint32_t)programs[i]->ops.size();
+      s->batch_prog = programs[i];
+      if ((rc = upload_buf(s))) return rc;
+      hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, stream, s->d_dyn, 0u);
+    }
+    b->h_bufp[i] = s->d_buf;
+    b->h_dynp[i] = s->d_dyn;
+  }
+  *b->h_ninst = (int)n;
+  HIP_TRY(hipMemcpyAsync(b->d_bufp, b->h_bufp, sizeof(void*) * n, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(b->d_dynp, b->h_dynp, sizeof(void*) * n, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(b->d_ninst, b->h_ninst, sizeof(int), hipMemcpyHostToDevice, stream));
+  if ((rc = ensure_graph(b))) return rc;
+  for (int rep = 0; max_replays < 0 || rep < max_replays; ++rep) {
+    HIP_TRY(hipGraphLaunch(b->exec, stream));
+    hipLaunchKernelGGL(k_gather_dyn, dim3((n + 255) / 256), dim3(256), 0, stream, b->d_dynp,
+                       b->d_ninst, b->d_gather);
+    HIP_TRY(hipMemcpyAsync(b->h_gather, b->d_gather, sizeof(InstDyn) * n, hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    bool all_done = true;
+    for (size_t i = 0; i < n; ++i) {
+      pp_state* s = states[i];
+      *s->h_dyn = b->h_gather[i];
+      if (s->h_dyn->status & ST_OVERFLOW) {
+        if ((rc = grow(s))) return rc;
+        s->h_dyn->status &= ~ST_OVERFLOW;
+        HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                               hipMemcpyHostToDevice, stream));
+      }
+      all_done = all_done && s->h_dyn->pc >= s->buf.prog_len;
+    }
+    if (all_done) break;
+  }
+  for (size_t i = 0; i < n; ++i) {
+    const bool fin = states[i]->h_dyn->pc >= states[i]->buf.prog_len;
+    if (done) done[i] = fin ? 1 : 0;
+    if (expectations && fin) expectations[i] = states[i]->h_dyn->expect;
+  }
+  return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pp_batch_run(pp_state* const* states, const pp_program* const* programs, size_t n,
+                 void* hip_stream, double* expectations) {
+  return batch_common(states, programs, n, hip_stream, -1, nullptr, expectations);
+}
+
+int pp_batch_step(pp_state* const* states, const pp_program* const* programs, size_t n,
+                  void* hip_stream, int max_steps, int* done, double* expectations) {
+  if (max_steps <= 0) return fail(PP_EINVAL, "max_steps must be > 0");
+  const int per = std::max(1, g_tune.graph_steps);
+  return batch_common(states, programs, n, hip_stream, (max_steps + per - 1) / per, done,
+                      expectations);
+}
+
+}  // extern "C"

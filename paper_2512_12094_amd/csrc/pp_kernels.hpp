@@ -1,0 +1,1201 @@
+// gfx950 kernels of the symmetry-merging Pauli propagation library.
+//
+// Every kernel serves a list of instances (one for the single-handle calls,
+// up to kMaxInst for the batched form).  A kernel is launched with a fixed
+// grid; each block first plans the work of the instances whose current
+// operation (program[pc]) belongs to this kernel, as a prefix sum of tiles
+// in LDS, then walks the tiles grid-stride.  The last block to finish
+// (threadfence + done counter) advances the program counters.  Term counts
+// therefore stay on the device and launches never depend on them, so the
+// per-step sequence of launches can be captured into a HIP graph.
+//
+// Paper: Teng, Chang, Rudolph, Holmes, arXiv:2512.12094.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pp_fixed.h"
+#include "pp_types.h"
+
+namespace pp {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 4;
+constexpr int kTile = kBlock * kItems;
+constexpr int kWaves = kBlock / 64;
+
+struct Ctx {
+  const InstBuf* const* bufs;
+  InstDyn* const* dyns;
+  const int* ninst;     // device-resident instance count (graph-stable)
+  uint32_t* sync;       // done counter, reset by the last block
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+// splitmix64 finalizer (Steele, Lea, Flood, "Fast splittable pseudorandom
+// number generators", OOPSLA 2014): a bijective 64-bit mixer.
+__host__ __device__ inline uint64_t mix64(uint64_t v) {
+  v ^= v >> 30;
+  v *= 0xbf58476d1ce4e5b9ull;
+  v ^= v >> 27;
+  v *= 0x94d049bb133111ebull;
+  v ^= v >> 31;
+  return v;
+}
+
+__device__ inline uint64_t hash_key(const uint64_t* x, const uint64_t* z, int W,
+                                    uint64_t seed) {
+  uint64_t h = mix64(seed ^ 0x9e3779b97f4a7c15ull);
+  for (int w = 0; w < W; ++w) {
+    h = mix64(h ^ x[w]);
+    h = mix64(h ^ z[w] ^ 0x632be59bd9b4e019ull);
+  }
+  return h;
+}
+
+// Symplectic product: P and Q anticommute iff the number of qubits where
+// x_Q z_P + z_Q x_P = 1 is odd.
+__device__ inline bool anticommutes(const uint64_t* qx, const uint64_t* qz,
+                                    const uint64_t* px, const uint64_t* pz, int W) {
+  uint32_t par = 0;
+  for (int w = 0; w < W; ++w) par += __popcll((qx[w] & pz[w]) ^ (qz[w] & px[w]));
+  return par & 1u;
+}
+
+__device__ inline int weight(const uint64_t* x, const uint64_t* z, int W) {
+  int s = 0;
+  for (int w = 0; w < W; ++w) s += __popcll(x[w] | z[w]);
+  return s;
+}
+
+// With P = i^{|px&pz|} X^px Z^pz (Y = iXZ per qubit), P Q = i^phi R with
+// phi = |px&pz| + |qx&qz| + 2|pz&qx| - |rx&rz| (mod 4) and R = P xor Q.
+// For anticommuting P, Q the phi is odd and iPQ = i^{1+phi} R = sigma R with
+// sigma = +1 for phi = 3 and -1 for phi = 1.
+__device__ inline int product_sign(const uint64_t* px, const uint64_t* pz,
+                                   const uint64_t* qx, const uint64_t* qz,
+                                   const uint64_t* rx, const uint64_t* rz, int W) {
+  int phi = 0;
+  for (int w = 0; w < W; ++w)
+    phi += __popcll(px[w] & pz[w]) + __popcll(qx[w] & qz[w]) +
+           2 * __popcll(pz[w] & qx[w]) - __popcll(rx[w] & rz[w]);
+  return ((phi & 3) == 3) ? 1 : -1;
+}
+
+// int(a) < int(b) in the paper's base-4 order (qubit q = digit of weight
+// 4^q, digit = (x xor z) + 2 z: I0 X1 Y2 Z3), one word.
+__device__ inline bool int_less1(uint64_t xa, uint64_t za, uint64_t xb, uint64_t zb) {
+  const uint64_t d = (xa ^ xb) | (za ^ zb);
+  if (d == 0) return false;
+  const int t = 63 - __clzll(d);
+  const uint32_t ca = (uint32_t)(((xa ^ za) >> t) & 1) | (uint32_t)(((za >> t) & 1) << 1);
+  const uint32_t cb = (uint32_t)(((xb ^ zb) >> t) & 1) | (uint32_t)(((zb >> t) & 1) << 1);
+  return ca < cb;
+}
+
+// rotate right by j within n bits (0 <= j < n): bit (q + j) mod n -> bit q,
+// i.e. T^j (qubit q of T^j s is qubit q + j of s).
+__device__ inline uint64_t rotr_n(uint64_t v, int j, int n, uint64_t mask) {
+  if (j == 0) return v;
+  return ((v >> j) | (v << (n - j))) & mask;
+}
+
+// Algorithm 2 representative for n <= 64: the translation with the smallest
+// base-4 integer.  That translation puts a longest cyclic run of identities
+// on the most significant qubits (any other one has a non-identity digit
+// among those top digits), so only the translations that align a longest
+// run with the top are compared; a string without identities compares all.
+__device__ inline void canon_translation(uint64_t x, uint64_t z, int n,
+                                         uint64_t* rx, uint64_t* rz) {
+  const uint64_t mask = (n == 64) ? ~0ull : ((1ull << n) - 1);
+  const uint64_t idm = ~(x | z) & mask;
+  if (idm == mask) { *rx = 0; *rz = 0; return; }
+  uint64_t bx = x, bz = z;
+  if (idm == 0) {
+    for (int j = 1; j < n; ++j) {
+      const uint64_t tx = rotr_n(x, j, n, mask), tz = rotr_n(z, j, n, mask);
+      if (int_less1(tx, tz, bx, bz)) { bx = tx; bz = tz; }
+    }
+  } else {
+    // S_len bit a <=> qubits a .. a+len-1 (cyclic) are all identities.
+    uint64_t pw[7];
+    pw[0] = idm;
+    int nb = 1;
+    while (nb < 7 && (1 << nb) <= n) {
+      pw[nb] = pw[nb - 1] & rotr_n(pw[nb - 1], (1 << (nb - 1)) % n, n, mask);
+      ++nb;
+    }
+    uint64_t cur = mask;
+    int len = 0;
+    for (int b = nb - 1; b >= 0; --b) {
+      if (len + (1 << b) > n - 1) continue;
+      const uint64_t cand = cur & rotr_n(pw[b], len, n, mask);
+      if (cand) { cur = cand; len += 1 << b; }
+    }
+    // cur: starts of the longest runs; translation j = (a + len) mod n puts
+    // the run starting at qubit a onto qubits n-len .. n-1.
+    bool first = true;
+    while (cur) {
+      const int a = __ffsll((unsigned long long)cur) - 1;
+      cur &= cur - 1;
+      int j = a + len;
+      if (j >= n) j -= n;
+      const uint64_t tx = rotr_n(x, j, n, mask), tz = rotr_n(z, j, n, mask);
+      if (first || int_less1(tx, tz, bx, bz)) { bx = tx; bz = tz; first = false; }
+    }
+  }
+  *rx = bx;
+  *rz = bz;
+}
+
+// Algorithm 3: counts of X, Y, Z letters.
+__device__ inline void perm_counts(const uint64_t* x, const uint64_t* z, int W,
+                                   uint32_t* nx, uint32_t* ny, uint32_t* nz) {
+  uint32_t a = 0, b = 0, c = 0;
+  for (int w = 0; w < W; ++w) {
+    a += __popcll(x[w] & ~z[w]);
+    b += __popcll(x[w] & z[w]);
+    c += __popcll(z[w] & ~x[w]);
+  }
+  *nx = a; *ny = b; *nz = c;
+}
+
+// Z^{nZ} Y^{nY} X^{nX} from qubit 0: z bits [0, nZ+nY), x bits [nZ, nZ+nY+nX).
+__device__ inline void perm_rep(uint32_t nx, uint32_t ny, uint32_t nz, int W,
+                                uint64_t* rx, uint64_t* rz) {
+  const uint32_t zlo = 0, zhi = nz + ny, xlo = nz, xhi = nz + ny + nx;
+  for (int w = 0; w < W; ++w) {
+    const uint32_t lo = 64u * w, hi = lo + 64u;
+    auto range = [&](uint32_t a, uint32_t b) -> uint64_t {  // bits [a,b) of this word
+      const uint32_t s = a > lo ? a : lo, e = b < hi ? b : hi;
+      if (s >= e) return 0ull;
+      const uint32_t len = e - s;
+      const uint64_t m = (len == 64) ? ~0ull : ((1ull << len) - 1);
+      return m << (s - lo);
+    };
+    rx[w] = range(xlo, xhi);
+    rz[w] = range(zlo, zhi);
+  }
+}
+
+// Narrow merge key: the representative itself, packed into 64 bits.
+__device__ inline uint64_t narrow_key(const InstBuf& b, const uint64_t* x,
+                                      const uint64_t* z) {
+  if (b.group == 2) {
+    uint32_t nx, ny, nz;
+    perm_counts(x, z, b.W, &nx, &ny, &nz);
+    return (uint64_t)nx | ((uint64_t)ny << 8) | ((uint64_t)nz << 16);
+  }
+  uint64_t rx = x[0], rz = z[0];
+  if (b.group == 1) canon_translation(x[0], z[0], b.n, &rx, &rz);
+  return rx | (rz << 32);   // n <= 32
+}
+
+__device__ inline void narrow_decode(const InstBuf& b, uint64_t key, uint64_t* rx,
+                                     uint64_t* rz) {
+  if (b.group == 2) {
+    perm_rep((uint32_t)(key & 0xff), (uint32_t)((key >> 8) & 0xff),
+             (uint32_t)((key >> 16) & 0xff), b.W, rx, rz);
+    return;
+  }
+  rx[0] = key & 0xffffffffull;
+  rz[0] = key >> 32;
+  for (int w = 1; w < b.W; ++w) { rx[w] = 0; rz[w] = 0; }
+}
+
+// Representative as a string (wide path: Z_n with n <= 64, or identity).
+__device__ inline void rep_string(const InstBuf& b, const uint64_t* x, const uint64_t* z,
+                                  uint64_t* rx, uint64_t* rz) {
+  if (b.group == 1) {
+    canon_translation(x[0], z[0], b.n, rx, rz);
+    for (int w = 1; w < b.W; ++w) { rx[w] = 0; rz[w] = 0; }
+  } else if (b.group == 2) {
+    uint32_t nx, ny, nz;
+    perm_counts(x, z, b.W, &nx, &ny, &nz);
+    perm_rep(nx, ny, nz, b.W, rx, rz);
+  } else {
+    for (int w = 0; w < b.W; ++w) { rx[w] = x[w]; rz[w] = z[w]; }
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Exclusive block scan of one value per thread; *total = block sum.
+// s_tmp needs kWaves + 1 entries.  Contains __syncthreads.
+__device__ inline uint32_t block_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tmp[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int w = 0; w < kWaves; ++w) { const uint32_t t = s_tmp[w]; s_tmp[w] = acc; acc += t; }
+    s_tmp[kWaves] = acc;
+  }
+  __syncthreads();
+  const uint32_t r = x - v + s_tmp[wid];
+  *total = s_tmp[kWaves];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
+  uint32_t t;
+  block_scan(v, s_tmp, &t);
+  return t;
+}
+
+// Fixed-order block sum of doubles (deterministic for a given assignment).
+__device__ inline double block_sum_f64(double v, double* s_d) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) s_d[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kWaves; ++w) r += s_d[w];
+  __syncthreads();
+  return r;   // valid in thread 0
+}
+
+__device__ inline uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide "am I the last block of this launch" (threadfence reduction).
+__device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t = atomicAdd(sync, 1u);
+    *s_flag = (t == gridDim.x - 1) ? 1u : 0u;
+    if (*s_flag) atomicExch(sync, 0u);
+  }
+  __syncthreads();
+  const bool r = *s_flag != 0;
+  if (r) __threadfence();
+  return r;
+}
+
+// Prefix of tiles over instances: s_pref[i] = first tile of instance i.
+// tiles(i) returns the tile count of instance i (0 when not served).
+template <class F>
+__device__ inline uint32_t plan_tiles(int ninst, F tiles, uint32_t* s_pref, uint32_t* s_tmp) {
+  constexpr int kPer = kMaxInst / kBlock;
+  uint32_t loc[kPer];
+  uint32_t sum = 0;
+  const int base = threadIdx.x * kPer;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = base + k;
+    loc[k] = (i < ninst) ? tiles(i) : 0u;
+    sum += loc[k];
+  }
+  uint32_t total;
+  uint32_t off = block_scan(sum, s_tmp, &total);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = base + k;
+    if (i < ninst) s_pref[i] = off;
+    off += loc[k];
+  }
+  __syncthreads();
+  return total;
+}
+
+__device__ inline int find_inst(const uint32_t* s_pref, int ninst, uint32_t t) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_pref[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline uint32_t ceil_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
+
+__device__ inline const Op* cur_op(const InstBuf& b, const InstDyn& d) {
+  return d.pc < b.prog_len ? &b.prog[d.pc] : nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// gate table
+// ---------------------------------------------------------------------------
+// Finds the live entry with key (rx, rz) among entries [0, Mstart), else -1.
+// Entries appended by the running gate (index >= Mstart) are skipped: no
+// gate ever looks up a string that the same gate appends, except the
+// appending thread itself, which knows it is absent.
+__device__ inline int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mstart,
+                                    const uint8_t* alive, const uint64_t* X,
+                                    const uint64_t* Z, const uint64_t* rx,
+                                    const uint64_t* rz) {
+  const int W = b.W;
+  const uint32_t cap = b.cap;
+  const uint64_t mask = (1ull << b.hg_bits) - 1;
+  uint64_t s = hash_key(rx, rz, W, 0) >> (64 - b.hg_bits);
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    const uint64_t v = b.gtab[s];
+    if ((uint32_t)(v >> 32) != gen) return -1;
+    const uint32_t idx = (uint32_t)v;
+    if (idx < Mstart && alive[idx]) {
+      bool eq = true;
+      for (int w = 0; w < W; ++w)
+        eq = eq && X[(size_t)w * cap + idx] == rx[w] && Z[(size_t)w * cap + idx] == rz[w];
+      if (eq) return idx;
+    }
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// Inserts index `idx` (insert-only: the caller guarantees that no live entry
+// with this key exists and that no thread compares keys of this generation
+// in the same launch, so no key is read here).
+__device__ inline void gt_insert(uint64_t* gtab, uint32_t bits, uint32_t gen, uint32_t idx,
+                                 uint64_t h) {
+  const uint64_t mask = (1ull << bits) - 1;
+  uint64_t s = h >> (64 - bits);
+  const uint64_t nv = ((uint64_t)gen << 32) | idx;
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    unsigned long long v = gtab[s];
+    while ((uint32_t)(v >> 32) != gen) {
+      const unsigned long long old =
+          atomicCAS((unsigned long long*)&gtab[s], v, (unsigned long long)nv);
+      if (old == v) return;
+      v = old;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exact sums: 192-bit two's-complement fixed point, kFxFrac fraction bits
+// ---------------------------------------------------------------------------
+// acc += v with one integer atomic per non-zero limb; the carries returned
+// by the lower limbs are added into the next limb, so the final value is the
+// exact sum of all contributions whatever their order.
+__device__ inline void fx_atomic_add(uint64_t* acc, Fx v) {
+  unsigned long long* a = (unsigned long long*)acc;
+  uint64_t c0 = 0;
+  if (v.l0) {
+    const uint64_t o0 = atomicAdd(&a[0], (unsigned long long)v.l0);
+    c0 = (o0 + v.l0 < o0) ? 1u : 0u;
+  }
+  const uint64_t t1 = v.l1 + c0;
+  uint64_t c1 = (t1 < c0) ? 1u : 0u;
+  if (t1) {
+    const uint64_t o1 = atomicAdd(&a[1], (unsigned long long)t1);
+    c1 += (o1 + t1 < o1) ? 1u : 0u;
+  }
+  const uint64_t t2 = v.l2 + c1;
+  if (t2) atomicAdd(&a[2], (unsigned long long)t2);
+}
+
+__device__ inline Fx wave_sum_fx(Fx v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    Fx w;
+    w.l0 = __shfl_xor(v.l0, o, 64);
+    w.l1 = __shfl_xor(v.l1, o, 64);
+    w.l2 = __shfl_xor(v.l2, o, 64);
+    v = fx_add(v, w);
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// merge table
+// ---------------------------------------------------------------------------
+// Find-or-insert of a 64-bit key; returns the slot.
+__device__ inline uint64_t mt_slot(uint64_t* mkey, uint32_t bits, uint64_t key) {
+  const uint64_t mask = (1ull << bits) - 1;
+  uint64_t s = mix64(key) >> (64 - bits);
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    unsigned long long k = mkey[s];
+    if (k == kEmpty64) {
+      k = atomicCAS((unsigned long long*)&mkey[s], (unsigned long long)kEmpty64,
+                    (unsigned long long)key);
+      if (k == kEmpty64) return s;
+    }
+    if (k == key) return s;
+    s = (s + 1) & mask;
+  }
+  return kEmpty64;   // unreachable: the table is at most half full
+}
+
+__device__ inline void mt_add(const InstBuf& b, InstDyn& d, uint64_t key, Fx v) {
+  if (key == kEmpty64) {        // the one key equal to the empty marker
+    fx_atomic_add(d.special_fx, v);
+    atomicOr(&d.special, 1u);
+    return;
+  }
+  const uint64_t s = mt_slot(b.mkey, b.hm_bits, key);
+  if (s != kEmpty64) fx_atomic_add(&b.mfx[3 * s], v);
+}
+
+// Adds (key, v) of every active lane, first combining lanes of one wave
+// that share a key (large orbits, e.g. S_n, collapse many records onto few
+// representatives).  Must be called by all lanes of the wave.
+__device__ inline void wave_merge_add(const InstBuf& b, InstDyn& d, bool act,
+                                      uint64_t key, Fx v) {
+  const int lane = threadIdx.x & 63;
+  for (int it = 0; it < 4; ++it) {
+    const unsigned long long am = __ballot(act);
+    if (am == 0) return;
+    const int leader = __ffsll((unsigned long long)am) - 1;
+    const uint64_t lk = __shfl(key, leader, 64);
+    const bool m = act && key == lk;
+    const unsigned long long mm = __ballot(m);
+    if (__popcll(mm) == 1) break;
+    const Fx zero{0, 0, 0};
+    const Fx s = wave_sum_fx(m ? v : zero);
+    if (lane == leader) mt_add(b, d, lk, s);
+    if (m) act = false;
+  }
+  if (act) mt_add(b, d, key, v);
+}
+
+// ---------------------------------------------------------------------------
+// views
+// ---------------------------------------------------------------------------
+struct View {
+  uint64_t* X;
+  uint64_t* Z;
+  double* C;
+  uint8_t* al;      // alive, current parity
+  uint8_t* aln;     // alive, other parity
+  uint32_t cap;
+  int W;
+};
+
+__device__ inline View view_of(const InstBuf& b, const InstDyn& d) {
+  View v;
+  const uint32_t h = d.half, p = d.parity;
+  v.X = b.x[h];
+  v.Z = b.z[h];
+  v.C = b.c[h];
+  v.al = b.alive[h][p];
+  v.aln = b.alive[h][p ^ 1];
+  v.cap = b.cap;
+  v.W = b.W;
+  return v;
+}
+
+__device__ inline void load_key(const View& v, uint32_t i, uint64_t* x, uint64_t* z) {
+  for (int w = 0; w < v.W; ++w) {
+    x[w] = v.X[(size_t)w * v.cap + i];
+    z[w] = v.Z[(size_t)w * v.cap + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GATE: one Pauli rotation (Prop. 1) + exact merge + truncation
+// ---------------------------------------------------------------------------
+// 0 = not served, 1 = run, 2 = would overflow (appends <= count)
+__device__ inline int gate_state(const InstBuf& b, const InstDyn& d) {
+  if (d.status & ST_OVERFLOW) return 0;
+  const Op* op = cur_op(b, d);
+  if (!op || op->type != OP_GATE) return 0;
+  if (d.count_for != d.pc) return 2;
+  if ((uint64_t)d.M + d.count > b.cap) return 2;
+  return 1;
+}
+
+__device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
+                                 uint32_t* s_tmp, uint32_t* s_base) {
+  const View v = view_of(b, d);
+  const Op& op = b.prog[d.pc];
+  const int W = v.W;
+  const uint32_t M = d.M, gen = d.gen;
+  const double cs = op.cs, sn = op.sn, eps = op.eps;
+  const int wmax = op.wmax;
+  const bool full = op.full_check != 0;
+  uint64_t px[kMaxW], pz[kMaxW], nxm[kMaxW], nzm[kMaxW];
+  for (int w = 0; w < W; ++w) { px[w] = op.px[w]; pz[w] = op.pz[w]; }
+  const bool has_next = op.next_gate != kNone32;
+  if (has_next) {
+    const Op& nx = b.prog[op.next_gate];
+    for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
+  }
+  uint32_t my_live = 0, my_cnt = 0;
+  uint64_t chx[kItems][kMaxW], chz[kItems][kMaxW];
+  double chc[kItems];
+  bool chv[kItems];
+
+  auto tally = [&](const uint64_t* x, const uint64_t* z) {
+    ++my_live;
+    if (has_next && anticommutes(x, z, nxm, nzm, W)) ++my_cnt;
+  };
+  auto heavy = [&](const uint64_t* x, const uint64_t* z) {
+    return wmax >= 0 && weight(x, z, W) > wmax;
+  };
+
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    chv[k] = false;
+    const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    if (i >= M) continue;
+    if (!v.al[i]) { v.aln[i] = 0; continue; }
+    uint64_t qx[kMaxW], qz[kMaxW];
+    load_key(v, i, qx, qz);
+    if (!anticommutes(qx, qz, px, pz, W)) {        // [P, Q] = 0: unchanged
+      bool keep = true;
+      if (full) {
+        const double c = v.C[i];
+        keep = fabs(c) >= eps && !heavy(qx, qz);
+      }
+      v.aln[i] = keep ? 1 : 0;
+      if (keep) tally(qx, qz);
+      continue;
+    }
+    uint64_t rx[kMaxW], rz[kMaxW];
+    for (int w = 0; w < W; ++w) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
+    const int sig = product_sign(px, pz, qx, qz, rx, rz, W);   // i P Q = sig R
+    const int64_t j = gt_lookup(b, gen, M, v.al, v.X, v.Z, rx, rz);
+    if (j >= 0) {
+      if ((uint32_t)j < i) continue;                 // the partner's thread leads
+      // Both Q and R = PQ live: the gate acts on span{Q, R} as a rotation.
+      // i P R = -sig Q.
+      const double cq = v.C[i], cr = v.C[j];
+      const double aq = cs * cq, bq = sn * cr;
+      const double nq = (sig > 0) ? aq - bq : aq + bq;
+      const double ar = cs * cr, br = sn * cq;
+      const double nr = (sig > 0) ? ar + br : ar - br;
+      v.C[i] = nq;
+      v.C[j] = nr;
+      const bool kq = fabs(nq) >= eps && !(full && heavy(qx, qz));
+      const bool kr = fabs(nr) >= eps && !(full && heavy(rx, rz));
+      v.aln[i] = kq ? 1 : 0;
+      v.aln[j] = kr ? 1 : 0;
+      if (kq) tally(qx, qz);
+      if (kr) tally(rx, rz);
+    } else {
+      const double cq = v.C[i];
+      const double nq = cs * cq;
+      const double t = sn * cq;
+      const double child = (sig > 0) ? t : -t;
+      v.C[i] = nq;
+      const bool kq = fabs(nq) >= eps && !(full && heavy(qx, qz));
+      v.aln[i] = kq ? 1 : 0;
+      if (kq) tally(qx, qz);
+      if (fabs(child) >= eps && !heavy(rx, rz)) {
+        chv[k] = true;
+        for (int w = 0; w < W; ++w) { chx[k][w] = rx[w]; chz[k][w] = rz[w]; }
+        chc[k] = child;
+        tally(rx, rz);
+      }
+    }
+  }
+  // append the new strings: one atomic per tile
+  uint32_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) mine += chv[k] ? 1u : 0u;
+  uint32_t total;
+  uint32_t off = block_scan(mine, s_tmp, &total);
+  if (threadIdx.x == 0) *s_base = total ? atomicAdd(&d.Mnext, total) : 0u;
+  __syncthreads();
+  const uint32_t base = *s_base;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (!chv[k]) continue;
+    const uint32_t pos = base + off++;
+    if (pos >= v.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }   // guard
+    for (int w = 0; w < W; ++w) {
+      v.X[(size_t)w * v.cap + pos] = chx[k][w];
+      v.Z[(size_t)w * v.cap + pos] = chz[k][w];
+    }
+    v.C[pos] = chc[k];
+    v.aln[pos] = 1;
+    gt_insert(b.gtab, b.hg_bits, gen, pos, hash_key(chx[k], chz[k], W, 0));
+  }
+  const uint32_t bl = block_sum_u32(my_live, s_tmp);
+  const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
+  if (threadIdx.x == 0) {
+    if (bl) atomicAdd(&d.acc_live, bl);
+    if (bc) atomicAdd(&d.acc_count, bc);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag, s_base;
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    const InstBuf& b = *C.bufs[i];
+    const InstDyn& d = *C.dyns[i];
+    return gate_state(b, d) == 1 ? ceil_tiles(d.M) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_inst(s_pref, ninst, t);
+    gate_tile(*C.bufs[i], *C.dyns[i], t - s_pref[i], s_tmp, &s_base);
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    const int st = gate_state(b, d);
+    if (st == 2) { d.status |= ST_OVERFLOW; d.failed_pc = d.pc; continue; }
+    if (st != 1) continue;
+    const Op& op = b.prog[d.pc];
+    d.propagated += d.live;
+    d.merged += (uint64_t)d.live + d.count;
+    d.M = ld_agent(&d.Mnext);
+    d.Mnext = d.M;
+    d.parity ^= 1u;
+    d.live = ld_agent(&d.acc_live);
+    d.count = ld_agent(&d.acc_count);
+    d.count_for = op.next_gate;
+    d.acc_live = 0;
+    d.acc_count = 0;
+    d.pc += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MERGE, narrow keys: one pass, representative -> hash table -> FP64 sums
+// ---------------------------------------------------------------------------
+__device__ inline bool merge_served(const InstBuf& b, const InstDyn& d, bool narrow,
+                                    uint32_t phase) {
+  if (d.status & ST_OVERFLOW) return false;
+  const Op* op = cur_op(b, d);
+  if (!op || op->type != OP_MERGE) return false;
+  if (b.group == 0 && !op->force_full) return false;   // plain PP: compaction
+  return (b.narrow != 0) == narrow && d.mphase == phase;
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag;
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    return merge_served(*C.bufs[i], *C.dyns[i], true, 0) ? ceil_tiles(C.dyns[i]->M) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int inst = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[inst];
+    InstDyn& d = *C.dyns[inst];
+    const View v = view_of(b, d);
+    const uint32_t tile = t - s_pref[inst];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      const bool act = i < d.M && v.al[i];
+      uint64_t key = 0;
+      Fx c{0, 0, 0};
+      bool range = false;
+      if (act) {
+        uint64_t qx[kMaxW], qz[kMaxW];
+        load_key(v, i, qx, qz);
+        key = narrow_key(b, qx, qz);
+        c = fx_from_double(v.C[i], &range);
+      }
+      if (range) atomicOr(&d.status, ST_RANGE);
+      wave_merge_add(b, d, act, key, c);
+    }
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
+    InstDyn& d = *C.dyns[i];
+    if (!merge_served(*C.bufs[i], d, true, 0)) continue;
+    d.merged += d.live;
+    d.mphase = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MERGE, wide keys: (1) representative + 64-bit hash slot, (2) first record
+// of each slot owns it; every record compares its representative with the
+// owner's (a mismatch is a hash collision: the merge restarts with another
+// seed) and adds its coefficient.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag;
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    return merge_served(*C.bufs[i], *C.dyns[i], false, 0) ? ceil_tiles(C.dyns[i]->M) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int inst = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[inst];
+    InstDyn& d = *C.dyns[inst];
+    const View v = view_of(b, d);
+    const uint32_t tile = t - s_pref[inst];
+    const int W = b.W;
+    const uint64_t seed = d.seed;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      if (i >= d.M) continue;
+      if (!v.al[i]) { b.wslot[i] = kNone32; continue; }
+      uint64_t qx[kMaxW], qz[kMaxW], rx[kMaxW], rz[kMaxW];
+      load_key(v, i, qx, qz);
+      rep_string(b, qx, qz, rx, rz);
+      for (int w = 0; w < W; ++w) {
+        b.wrep[(size_t)w * b.cap + i] = rx[w];
+        b.wrep[(size_t)(W + w) * b.cap + i] = rz[w];
+      }
+      uint64_t h = hash_key(rx, rz, W, seed);
+      if (h == kEmpty64) h -= 1;
+      b.wslot[i] = (uint32_t)mt_slot(b.mkey, b.hm_bits, h);
+    }
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
+    InstDyn& d = *C.dyns[i];
+    if (!merge_served(*C.bufs[i], d, false, 0)) continue;
+    d.merged += d.live;
+    d.mphase = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_wide2(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag;
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    return merge_served(*C.bufs[i], *C.dyns[i], false, 1) ? ceil_tiles(C.dyns[i]->M) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int inst = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[inst];
+    InstDyn& d = *C.dyns[inst];
+    const View v = view_of(b, d);
+    const uint32_t tile = t - s_pref[inst];
+    const int W = b.W;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      if (i >= d.M) continue;
+      const uint32_t s = b.wslot[i];
+      if (s == kNone32) continue;
+      const uint32_t o = atomicCAS(&b.mown[s], kNone32, i);
+      const uint32_t owner = (o == kNone32) ? i : o;
+      bool same = true;
+      if (owner != i)
+        for (int w = 0; w < 2 * W; ++w)
+          same = same && b.wrep[(size_t)w * b.cap + i] == b.wrep[(size_t)w * b.cap + owner];
+      if (same) {
+        bool range = false;
+        fx_atomic_add(&b.mfx[3 * (size_t)s], fx_from_double(v.C[i], &range));
+        if (range) atomicOr(&d.status, ST_RANGE);
+      } else {
+        atomicOr(&d.status, ST_COLLISION);
+      }
+    }
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
+    InstDyn& d = *C.dyns[i];
+    if (!merge_served(*C.bufs[i], d, false, 1)) continue;
+    d.mphase = 2;
+  }
+}
+
+// Writes one output term at the cursor position `pos` of the other half.
+__device__ inline void emit_term(const InstBuf& b, const InstDyn& d, uint32_t pos,
+                                 const uint64_t* x, const uint64_t* z, double c) {
+  const uint32_t h = d.half ^ 1u;
+  const int W = b.W;
+  for (int w = 0; w < W; ++w) {
+    b.x[h][(size_t)w * b.cap + pos] = x[w];
+    b.z[h][(size_t)w * b.cap + pos] = z[w];
+  }
+  b.c[h][pos] = c;
+  b.alive[h][0][pos] = 1;
+  b.alive[h][1][pos] = 1;
+  gt_insert(b.gtab, b.hg_bits, d.gen + 1, pos, hash_key(x, z, W, 0));
+}
+
+// After a merge or compaction: the other half becomes current.
+__device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
+  const Op& op = b.prog[d.pc];
+  d.M = d.nuniq;
+  d.Mnext = d.M;
+  d.half ^= 1u;
+  d.parity = 0;
+  d.gen += 1;
+  d.live = ld_agent(&d.acc_live);
+  d.count = ld_agent(&d.acc_count);
+  d.count_for = op.next_gate;
+  d.acc_live = 0;
+  d.acc_count = 0;
+  d.nuniq = 0;
+  d.mphase = 0;
+  d.pc += 1;
+}
+
+// Collect: every occupied merge slot becomes one representative of the new
+// half; slots are cleared for the next merge.
+__global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag, s_base_v;
+  uint32_t* s_base = &s_base_v;
+  const int ninst = *C.ninst;
+  auto served = [&](int i) {
+    const InstBuf& b = *C.bufs[i];
+    const InstDyn& d = *C.dyns[i];
+    return merge_served(b, d, true, 1) || merge_served(b, d, false, 2);
+  };
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    return served(i) ? ceil_tiles(1u << C.bufs[i]->hm_bits) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int inst = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[inst];
+    InstDyn& d = *C.dyns[inst];
+    const uint32_t tile = t - s_pref[inst];
+    const bool collided = (d.status & ST_COLLISION) != 0;
+    const uint32_t nslots = 1u << b.hm_bits;
+    const int W = b.W;
+    const Op& op = b.prog[d.pc];
+    const bool has_next = op.next_gate != kNone32;
+    uint64_t nxm[kMaxW], nzm[kMaxW];
+    if (has_next) {
+      const Op& nx = b.prog[op.next_gate];
+      for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
+    }
+    uint64_t ox[kItems][kMaxW], oz[kItems][kMaxW];
+    double oc[kItems];
+    bool ov[kItems];
+    uint32_t mine = 0, my_cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      ov[k] = false;
+      const uint32_t s = tile * kTile + k * kBlock + threadIdx.x;
+      if (s >= nslots) continue;
+      const uint64_t key = b.mkey[s];
+      if (key == kEmpty64) continue;
+      if (!collided) {
+        if (b.narrow) {
+          narrow_decode(b, key, ox[k], oz[k]);
+        } else {
+          const uint32_t o = b.mown[s];
+          for (int w = 0; w < W; ++w) {
+            ox[k][w] = b.wrep[(size_t)w * b.cap + o];
+            oz[k][w] = b.wrep[(size_t)(W + w) * b.cap + o];
+          }
+        }
+        const Fx f{b.mfx[3 * (size_t)s], b.mfx[3 * (size_t)s + 1], b.mfx[3 * (size_t)s + 2]};
+        oc[k] = fx_to_double(f);
+        ov[k] = true;
+        ++mine;
+        if (has_next && anticommutes(ox[k], oz[k], nxm, nzm, W)) ++my_cnt;
+      }
+      b.mkey[s] = kEmpty64;
+      b.mfx[3 * (size_t)s] = 0;
+      b.mfx[3 * (size_t)s + 1] = 0;
+      b.mfx[3 * (size_t)s + 2] = 0;
+      if (!b.narrow) b.mown[s] = kNone32;
+    }
+    uint32_t tot;
+    uint32_t off = block_scan(mine, s_tmp, &tot);
+    if (threadIdx.x == 0) *s_base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    __syncthreads();
+    const uint32_t base = *s_base;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (!ov[k]) continue;
+      const uint32_t pos = base + off++;
+      if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
+      emit_term(b, d, pos, ox[k], oz[k], oc[k]);
+    }
+    const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
+    if (threadIdx.x == 0) {
+      if (tot) atomicAdd(&d.acc_live, tot);
+      if (bc) atomicAdd(&d.acc_count, bc);
+    }
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
+    if (!served(i)) continue;
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    if (d.status & ST_COLLISION) {     // retry this merge with another seed
+      d.status &= ~ST_COLLISION;
+      d.special = 0;
+      d.special_fx[0] = d.special_fx[1] = d.special_fx[2] = 0;
+      d.seed += 1;
+      d.mphase = 0;
+      d.nuniq = 0;
+      d.acc_live = 0;
+      d.acc_count = 0;
+      continue;
+    }
+    d.nuniq = ld_agent(&d.nuniq);
+    if (d.special) {                   // narrow key equal to the empty marker
+      uint64_t x[kMaxW], z[kMaxW];
+      narrow_decode(b, kEmpty64, x, z);
+      const uint32_t pos = d.nuniq;
+      if (pos < b.cap) {
+        const Fx f{d.special_fx[0], d.special_fx[1], d.special_fx[2]};
+        emit_term(b, d, pos, x, z, fx_to_double(f));
+        d.nuniq = pos + 1;
+        d.acc_live += 1;
+        const Op& op = b.prog[d.pc];
+        if (op.next_gate != kNone32) {
+          const Op& nx = b.prog[op.next_gate];
+          if (anticommutes(x, z, nx.px, nx.pz, b.W)) d.acc_count += 1;
+        }
+      } else {
+        d.status |= ST_OVERFLOW;
+      }
+      d.special = 0;
+      d.special_fx[0] = d.special_fx[1] = d.special_fx[2] = 0;
+    }
+    finish_rebuild(b, d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MERGE for plain PP: the set is already free of duplicates, so the merge
+// only drops dead entries (compaction into the other half).
+// ---------------------------------------------------------------------------
+__device__ inline bool compact_served(const InstBuf& b, const InstDyn& d) {
+  if (d.status & ST_OVERFLOW) return false;
+  const Op* op = cur_op(b, d);
+  return op && op->type == OP_MERGE && b.group == 0 && !op->force_full;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag, s_base_v;
+  uint32_t* s_base = &s_base_v;
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    return compact_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles(C.dyns[i]->M) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int inst = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[inst];
+    InstDyn& d = *C.dyns[inst];
+    const View v = view_of(b, d);
+    const uint32_t tile = t - s_pref[inst];
+    const int W = b.W;
+    const Op& op = b.prog[d.pc];
+    const bool has_next = op.next_gate != kNone32;
+    uint64_t nxm[kMaxW], nzm[kMaxW];
+    if (has_next) {
+      const Op& nx = b.prog[op.next_gate];
+      for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
+    }
+    bool ov[kItems];
+    uint32_t mine = 0, my_cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      ov[k] = i < d.M && v.al[i];
+      mine += ov[k] ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t off = block_scan(mine, s_tmp, &tot);
+    if (threadIdx.x == 0) *s_base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    __syncthreads();
+    const uint32_t base = *s_base;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (!ov[k]) continue;
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      const uint32_t pos = base + off++;
+      if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
+      uint64_t x[kMaxW], z[kMaxW];
+      load_key(v, i, x, z);
+      emit_term(b, d, pos, x, z, v.C[i]);
+      if (has_next && anticommutes(x, z, nxm, nzm, W)) ++my_cnt;
+    }
+    const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
+    if (threadIdx.x == 0) {
+      if (tot) atomicAdd(&d.acc_live, tot);
+      if (bc) atomicAdd(&d.acc_count, bc);
+    }
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    if (!compact_served(b, d)) continue;
+    d.merged += d.live;
+    d.nuniq = ld_agent(&d.nuniq);
+    finish_rebuild(b, d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DAMP / TRUNC / COUNT / EXPECT: one streaming pass over the live terms
+// ---------------------------------------------------------------------------
+__device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
+  if (d.status & ST_OVERFLOW) return false;
+  const Op* op = cur_op(b, d);
+  if (!op) return false;
+  return op->type == OP_DAMP || op->type == OP_TRUNC || op->type == OP_COUNT ||
+         op->type == OP_EXPECT;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ double s_d[kWaves];
+  __shared__ uint32_t s_flag;
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    return scan_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles(C.dyns[i]->M) : 0u;
+  }, s_pref, s_tmp);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int inst = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[inst];
+    InstDyn& d = *C.dyns[inst];
+    const View v = view_of(b, d);
+    const uint32_t tile = t - s_pref[inst];
+    const int W = b.W, n = b.n;
+    const Op& op = b.prog[d.pc];
+    const uint32_t type = op.type;
+    const bool has_next = op.next_gate != kNone32;
+    uint64_t nxm[kMaxW], nzm[kMaxW];
+    if (has_next) {
+      const Op& nx = b.prog[op.next_gate];
+      for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
+    }
+    uint32_t my_live = 0, my_cnt = 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      if (i >= d.M || !v.al[i]) continue;
+      uint64_t x[kMaxW], z[kMaxW];
+      load_key(v, i, x, z);
+      double c = v.C[i];
+      if (type == OP_DAMP) {
+        c = c * op.table[weight(x, z, W)];
+        v.C[i] = c;
+      } else if (type == OP_TRUNC) {
+        const bool keep = fabs(c) >= op.eps && !(op.wmax >= 0 && weight(x, z, W) > op.wmax);
+        if (!keep) { v.al[i] = 0; continue; }
+      } else if (type == OP_EXPECT) {
+        uint32_t nx, ny, nz;
+        perm_counts(x, z, W, &nx, &ny, &nz);
+        acc += c * op.table[nx] * op.table[(n + 1) + ny] * op.table[2 * (n + 1) + nz];
+      }
+      ++my_live;
+      if (has_next && anticommutes(x, z, nxm, nzm, W)) ++my_cnt;
+    }
+    if (type == OP_EXPECT) {
+      const double s = block_sum_f64(acc, s_d);
+      if (threadIdx.x == 0) b.partial[tile] = s;
+    }
+    const uint32_t bl = block_sum_u32(my_live, s_tmp);
+    const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
+    if (threadIdx.x == 0) {
+      if (bl) atomicAdd(&d.acc_live, bl);
+      if (bc) atomicAdd(&d.acc_count, bc);
+    }
+  }
+  if (!last_block(C.sync, &s_flag)) return;
+  for (int i = 0; i < ninst; ++i) {            // whole block per instance
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    if (!scan_served(b, d)) continue;          // uniform across the block
+    const Op& op = b.prog[d.pc];
+    if (op.type == OP_EXPECT) {
+      const uint32_t nt = ceil_tiles(d.M);
+      double s = 0.0;
+      for (uint32_t t = threadIdx.x; t < nt; t += kBlock) s += b.partial[t];
+      s = block_sum_f64(s, s_d);
+      if (threadIdx.x == 0) d.expect = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      d.live = ld_agent(&d.acc_live);
+      d.count = ld_agent(&d.acc_count);
+      d.count_for = op.next_gate;
+      d.acc_live = 0;
+      d.acc_count = 0;
+      d.pc += 1;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-driven growth / compaction of one instance into a new store.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_grow(InstBuf src, InstBuf dst, InstDyn* dp,
+                                                 uint32_t* sync) {
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ uint32_t s_flag, s_base_v;
+  uint32_t* s_base = &s_base_v;
+  InstDyn& d = *dp;
+  const View v = view_of(src, d);
+  const uint32_t M = d.M;
+  const int W = src.W;
+  const uint32_t tiles = (M + kTile - 1) / kTile;
+  for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    bool ov[kItems];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      ov[k] = i < M && v.al[i];
+      mine += ov[k] ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t off = block_scan(mine, s_tmp, &tot);
+    if (threadIdx.x == 0) *s_base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    __syncthreads();
+    const uint32_t base = *s_base;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (!ov[k]) continue;
+      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      const uint32_t pos = base + off++;
+      if (pos >= dst.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
+      uint64_t x[kMaxW], z[kMaxW];
+      load_key(v, i, x, z);
+      for (int w = 0; w < W; ++w) {
+        dst.x[0][(size_t)w * dst.cap + pos] = x[w];
+        dst.z[0][(size_t)w * dst.cap + pos] = z[w];
+      }
+      dst.c[0][pos] = v.C[i];
+      dst.alive[0][0][pos] = 1;
+      dst.alive[0][1][pos] = 1;
+      gt_insert(dst.gtab, dst.hg_bits, 1u, pos, hash_key(x, z, W, 0));
+    }
+  }
+  if (!last_block(sync, &s_flag)) return;
+  if (threadIdx.x == 0) {
+    d.M = ld_agent(&d.nuniq);
+    d.Mnext = d.M;
+    d.nuniq = 0;
+    d.half = 0;
+    d.parity = 0;
+    d.gen = 1;
+  }
+}
+
+__global__ void k_set_pc(InstDyn* d, uint32_t pc) { d->pc = pc; }
+
+// Copies the per-instance dynamic state into one contiguous buffer (host
+// polling of a batch with one transfer).
+__global__ void k_gather_dyn(InstDyn* const* dyns, const int* ninst, InstDyn* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < *ninst) out[i] = *dyns[i];
+}
+
+}  // namespace pp

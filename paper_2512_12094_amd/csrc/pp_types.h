@@ -1,0 +1,115 @@
+// Internal data layout of the gfx950 Pauli propagation library (shared by
+// host and device code).
+//
+// Term store (per instance, one per handle)
+// -----------------------------------------
+// Two halves of structure-of-arrays buffers, each of capacity `cap`:
+//   x[h][w*cap + i], z[h][w*cap + i]   uint64 words of term i's masks
+//   c[h][i]                            FP64 coefficient
+//   alive[h][p][i]                     uint8 liveness, double-buffered (p)
+// Gates update coefficients in place and append new strings at the end of
+// the current half; a term that is truncated is only marked dead.  A
+// symmetry merge (or a compaction) writes the surviving unique terms into
+// the other half and flips `half`.
+//
+// Gate table: open addressing, linear probing, 2^hg_bits uint64 slots, slot
+// value (generation << 32) | index.  A slot whose generation differs from
+// the instance's current one is empty, so a rebuild only bumps `gen`.
+//
+// Merge table: 2^hm_bits slots of (key, sum[, owner]).  Keys are the
+// representative itself when it fits 64 bits exactly ("narrow"), else a
+// 64-bit hash of it with the owning record's full representative kept in
+// `wrep` and compared for every record ("wide").  Sums are exact: every
+// coefficient becomes a 192-bit two's-complement fixed-point integer with
+// kFxFrac fraction bits and the three 64-bit limbs are added with integer
+// atomics and carries, so the orbit sum is exact, independent of the order
+// of the additions, and rounded to FP64 once.
+#pragma once
+#include <cstdint>
+
+namespace pp {
+
+constexpr int kMaxW = 2;                   // up to 128 qubits
+constexpr uint32_t kNone32 = 0xFFFFFFFFu;
+constexpr uint64_t kEmpty64 = ~0ull;
+constexpr int kMaxInst = 1024;             // instances per batched launch
+
+enum OpType : uint32_t {
+  OP_END = 0,
+  OP_GATE = 1,     // one Pauli rotation + exact merge + truncation
+  OP_MERGE = 2,    // symmetry merge by orbit representative
+  OP_DAMP = 3,     // c *= (1-p)^weight
+  OP_TRUNC = 4,    // drop |c| < eps or weight > wmax
+  OP_COUNT = 5,    // only recount (live, anticommuting with next gate)
+  OP_EXPECT = 6,   // expectation in a symmetric product state
+};
+
+enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u };
+
+constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
+constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
+
+struct Op {
+  uint32_t type;
+  uint32_t full_check;   // GATE: re-check |c| and weight of every live term
+  uint32_t next_gate;    // index of the next GATE op after this one, or kNone32
+  int32_t wmax;          // GATE/TRUNC: weight limit (< 0: off)
+  uint32_t force_full;   // MERGE with group NONE: merge duplicates (creation)
+  uint32_t pad;
+  uint64_t px[kMaxW];    // GATE: the rotation's Pauli string
+  uint64_t pz[kMaxW];
+  double cs, sn;         // GATE: cos(theta), sin(theta)
+  double eps;            // GATE/TRUNC: coefficient threshold (0: off)
+  const double* table;   // DAMP: (1-p)^w for w = 0..n;
+                         // EXPECT: bx^k, by^k, bz^k for k = 0..n (3 blocks)
+};
+
+struct InstBuf {
+  uint64_t* x[2];
+  uint64_t* z[2];
+  double* c[2];
+  uint8_t* alive[2][2];  // [half][parity]
+  uint64_t* gtab;
+  uint64_t* mkey;
+  uint64_t* mfx;         // 3 limbs per slot: [3*slot + k]
+  uint32_t* mown;
+  uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
+  uint32_t* wslot;
+  double* partial;       // EXPECT partial sums, one per tile
+  const Op* prog;
+  uint32_t prog_len;
+  uint32_t cap;
+  uint32_t hg_bits;
+  uint32_t hm_bits;
+  int32_t n;
+  int32_t W;
+  int32_t group;
+  uint32_t narrow;       // merge keys fit 64 bits exactly
+};
+
+struct InstDyn {
+  uint64_t propagated;   // work counters (see pp_counters)
+  uint64_t merged;
+  uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
+  double expect;
+  uint32_t M;            // entries in the current half (live and dead)
+  uint32_t Mnext;        // append cursor while a gate runs
+  uint32_t half;
+  uint32_t parity;
+  uint32_t gen;          // gate-table generation
+  uint32_t pc;           // program counter
+  uint32_t status;       // ST_* bits
+  uint32_t count;        // live terms anticommuting with gate op `count_for`
+  uint32_t count_for;
+  uint32_t live;         // live terms
+  uint32_t nuniq;        // output cursor of a merge / compaction
+  uint32_t mphase;       // merge progress: 0 none, 1 inserted, 2 owned (wide)
+  uint32_t seed;         // wide-merge hash seed (bumped on a collision)
+  uint32_t acc_count;    // accumulators of the running kernel
+  uint32_t acc_live;
+  uint32_t special;
+  uint32_t failed_pc;
+  uint32_t pad;
+};
+
+}  // namespace pp

@@ -1,0 +1,54 @@
+"""The C ABI library loads and exports every entry point of include/pp.h
+(no compute calls, so this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pp.h")
+LIB = os.path.join(ROOT, "paper_2512_12094_amd", "libpp.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pp_create", "pp_apply_layer", "pp_merge_canonicalize", "pp_truncate",
+                     "pp_expectation", "pp_num_terms", "pp_export_terms", "pp_destroy",
+                     "pp_last_error", "pp_batch_run"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpp.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpp.so not built")
+def test_binding_names_match_the_header():
+    from paper_2512_12094_amd import _lib
+    for n in declared_functions():
+        if n in ("pp_last_error",):
+            continue
+        assert hasattr(_lib, n), n
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpp.so not built")
+def test_argument_errors_need_no_gpu():
+    """Validation happens on the host before any device call."""
+    from paper_2512_12094_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.pp_create(ctypes.byref(h), 0, 0, 0, None, None, None, 0, None, None) == -1
+    assert b"unsupported" in L.pp_last_error()
+    assert L.pp_create(ctypes.byref(h), 65, 1, 0, None, None, None, 0, None, None) == -1
+    assert L.pp_create(ctypes.byref(h), 8, 1, 7, None, None, None, 0, None, None) == -1
+    assert L.pp_set_tuning(100, 0, 0) == -1

@@ -1,0 +1,233 @@
+"""HIP path vs CPU oracle on the same seeded circuits (calls go through the
+C ABI).  Sizes are chosen so that the oracle finishes in seconds while the
+sets span many 1024-term tiles and a ragged last tile."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2512_12094_amd import workloads as W
+from tests.parity import compare_expectation, compare_terms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_12094_amd import _lib
+    _lib.lib()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    return dict(torch=torch, stream=stream, handle=int(stream.cuda_stream),
+                alloc=_lib.TorchAllocator(0))
+
+
+def run_both(gpu, prog, group=None, max_sub=None, allocator="torch"):
+    from paper_2512_12094_amd import driver
+    print(f"[case] {prog.name} group={group or prog.group} n={prog.n} "
+          f"sublayers={max_sub or len(prog.sublayers)}", flush=True)
+    alloc = gpu["alloc"] if allocator == "torch" else None
+    res = driver.propagate(prog, group=group, stream=gpu["handle"], allocator=alloc,
+                           max_sublayers=max_sub)
+    if max_sub is not None:
+        ref = O.run_program(prog, group=group, max_sublayers=max_sub)
+    else:
+        ref = O.run_program(prog, group=group)
+    return res, ref
+
+
+def check(res, ref, prog, eps=None, what=""):
+    eps = prog.meta.get("eps", 0.0) if eps is None else eps
+    n, skipped = compare_terms(res.terms, ref.terms, eps, what=what)
+    compare_expectation(res.expectation, ref.expectation, ref.terms, what=what)
+    if skipped == 0:
+        assert (res.propagated, res.merged) == (ref.propagated, ref.merged), what
+    return n
+
+
+def test_config1_translation(gpu):
+    prog = W.config1()
+    res, ref = run_both(gpu, prog)
+    assert check(res, ref, prog, what="c1") == 2048
+
+
+def test_config1_plain(gpu):
+    prog = W.config1()
+    res, ref = run_both(gpu, prog, group="none")
+    assert check(res, ref, prog, what="c1 plain") == 16384
+
+
+def test_config1_hipmalloc_allocator(gpu):
+    prog = W.config1()
+    res, ref = run_both(gpu, prog, allocator=None)
+    check(res, ref, prog, what="c1 hipMalloc")
+
+
+@pytest.mark.parametrize("group", ["Zn", "none"])
+def test_config2_prefix(gpu, group):
+    """Z_32 XXZ ring with eps = 1e-4, weight <= 8, random Bloch state."""
+    prog = W.config2()
+    res, ref = run_both(gpu, prog, group=group, max_sub=12)
+    check(res, ref, prog, what=f"c2 {group}")
+
+
+def test_translation_wide_keys(gpu):
+    """n = 48 > 32: merge keys do not fit 64 bits (hash + owner compare)."""
+    prog = W.xxz_ring(48, 2, 0.3, 1.4, eps=1e-6, obs=W.sum_ring_pairs(48, "X"),
+                      bloch=W.random_bloch(48), name="z48")
+    res, ref = run_both(gpu, prog)
+    check(res, ref, prog, what="z48")
+
+
+def test_translation_n64_wide(gpu):
+    prog = W.xxz_ring(64, 1, 0.2, 0.7, eps=1e-5, wmax=6, name="z64")
+    res, ref = run_both(gpu, prog)
+    check(res, ref, prog, what="z64")
+
+
+def test_permutation_config3_prefix(gpu):
+    """S_64 all-to-all Heisenberg, noise p = 1e-3, eps = 1e-5: the first two
+    sub-layers in Heisenberg order (the second grows to ~6e5 terms)."""
+    prog = W.config3()
+    res, ref = run_both(gpu, prog, max_sub=2)
+    check(res, ref, prog, what="c3")
+
+
+def test_permutation_two_words(gpu):
+    """n = 100: strings span two 64-bit words."""
+    prog = W.heisenberg_all_to_all(100, 1, 0.01, eps=1e-4, p=2e-3,
+                                   obs=W.sum_single(100, "X", 0.01), bloch=W.random_bloch(5),
+                                   name="s100")
+    res, ref = run_both(gpu, prog, max_sub=2)
+    check(res, ref, prog, what="s100")
+
+
+def test_plain_two_words(gpu):
+    prog = W.xxz_ring(70, 1, 0.3, 1.1, eps=1e-3, obs=W.sum_ring_pairs(70, "Z"),
+                      group="none", name="plain70")
+    res, ref = run_both(gpu, prog)
+    check(res, ref, prog, what="plain70")
+
+
+@pytest.mark.parametrize("group", ["Zn", "none"])
+def test_noise_damping(gpu, group):
+    prog = W.xxz_ring(12, 3, 0.4, 0.8, p=0.03, eps=1e-7, obs=W.sum_ring_pairs(12, "Y"),
+                      bloch=W.random_bloch(12), name="noisy12")
+    res, ref = run_both(gpu, prog, group=group)
+    check(res, ref, prog, what=f"noise {group}")
+
+
+def test_single_qubit_gates_ising(gpu):
+    """Tilted-field Ising ring (RZZ bonds, RZ and RX fields)."""
+    prog = W.tilted_ising_ring(9, 4, 0.25)
+    res, ref = run_both(gpu, prog)
+    check(res, ref, prog, what="ising9")
+    neck = sum(4 ** math.gcd(j, 9) for j in range(1, 10)) // 9
+    assert len(res.terms) <= neck - 1
+
+
+def test_s2_invariant(gpu):
+    n = 10
+    prog = W.heisenberg_all_to_all(n, 2, 0.3, obs=W.total_spin_squared(n), bloch=W.PLUS_STATE,
+                                   name="s2_10")
+    res, ref = run_both(gpu, prog)
+    check(res, ref, prog, what="s2")
+    assert abs(res.expectation - n * (n + 2) / 4) < 1e-10
+
+
+def test_edge_observables(gpu):
+    from paper_2512_12094_amd import driver
+    print("[case] edge observables", flush=True)
+    for obs, want in (([], 0.0), ([(0, 0, 2.5)], 2.5), ([(1, 0, 1.0), (1, 0, -1.0)], 0.0)):
+        prog = W.xxz_ring(8, 1, 0.3, 1.0, obs=obs, name="edge")
+        res = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"])
+        ref = O.run_program(prog)
+        compare_terms(res.terms, ref.terms, what="edge")
+        assert abs(res.expectation - want) < 1e-12
+
+
+def test_angles_zero_and_pi(gpu):
+    """theta = 0 keeps exact-zero children; theta = pi flips anticommuting terms."""
+    for th in (0.0, math.pi):
+        prog = W.xxz_ring(6, 1, th, 1.0, obs=W.sum_single(6, "X") + W.sum_ring_pairs(6, "Z"),
+                          bloch=W.random_bloch(3), name=f"theta{th}")
+        res, ref = run_both(gpu, prog, group="none")
+        check(res, ref, prog, what=f"theta={th}")
+
+
+def test_repeat_runs_agree(gpu):
+    from paper_2512_12094_amd import driver
+    print("[case] repeat", flush=True)
+    prog = W.config2()
+    a = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"], max_sublayers=9)
+    b = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"], max_sublayers=9)
+    compare_terms(a.terms, b.terms, prog.meta["eps"], rel=1e-14, what="repeat")
+
+
+def test_errors(gpu):
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    print("[case] errors", flush=True)
+    prog = W.config1()
+    ps = driver.PauliSet.from_program(prog, stream=gpu["handle"], allocator=gpu["alloc"])
+    before = ps.as_dict()
+    # not closed under translations: one bond only
+    with pytest.raises(L.PPError) as e:
+        L.pp_apply_layer(ps.h, [3], [0], [0.1], 1)
+    assert e.value.code == -2
+    with pytest.raises(L.PPError) as e:
+        L.pp_apply_layer(ps.h, [1 << 9], [0], [0.1], 1)      # bit >= n
+    assert e.value.code == -1
+    with pytest.raises(L.PPError) as e:
+        L.pp_apply_layer(ps.h, [3], [0], [0.1], 1, merge_every=2)
+    assert e.value.code == -1
+    assert ps.as_dict() == before                             # unchanged
+    ps.close()
+
+
+def test_capacity_limit(gpu):
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    print("[case] capacity", flush=True)
+    prog = W.config1().with_group("none")
+    ps = driver.PauliSet.from_program(prog, stream=gpu["handle"], allocator=gpu["alloc"])
+    L.pp_set_max_terms(ps.h, 5000)
+    layers = driver.heisenberg_layers(prog)
+    with pytest.raises(L.PPError) as e:
+        for la in layers:
+            ps.apply_layer(la)
+    assert e.value.code == -4
+    # the handle stays usable and consistent
+    n = ps.num_terms()
+    assert 0 < n <= 5000
+    x, z, c = ps.export()
+    assert len(c) == n
+    ps.close()
+
+
+def test_batch_matches_solo(gpu):
+    """Batched form: every instance equals its own oracle run."""
+    from paper_2512_12094_amd import driver
+    print("[case] batch", flush=True)
+    rng = np.random.default_rng(11)
+    progs = []
+    for k in range(6):
+        n = int(rng.choice([8, 12, 16, 24, 40]))
+        progs.append(W.xxz_ring(n, int(rng.integers(1, 4)), float(rng.uniform(0.05, 0.3)),
+                                float(rng.uniform(0.5, 2)), eps=1e-6, name=f"b{k}_n{n}"))
+    progs.append(W.heisenberg_all_to_all(20, 1, 0.1, eps=1e-5, p=1e-3, name="b_s20"))
+    progs.append(W.xxz_ring(10, 2, 0.2, 1.0, eps=0.0, group="none", name="b_plain10"))
+    e, sets, dprogs, wall = driver.batch_propagate(progs, gpu["handle"], gpu["alloc"])
+    for p, ei, s in zip(progs, e, sets):
+        ref = O.run_program(p)
+        compare_terms(s.as_dict(), ref.terms, p.meta.get("eps", 0.0), what=p.name)
+        compare_expectation(ei, ref.expectation, ref.terms, what=p.name)
+        assert s.counters() == (ref.propagated, ref.merged), p.name
+    for s in sets:
+        s.close()
+    for d in dprogs:
+        d.close()

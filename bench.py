@@ -1,0 +1,232 @@
+"""Throughput of symmetry-merging Pauli propagation on one MI355X.
+
+One step = Algorithm 1 over the Z_32 XXZ ring workload (20 Trotter steps of
+RXX(0.05), RYY(0.05), RZZ(0.075) sub-layers on all 32 bonds, O = sum X_i
+X_{i+1}, eps = 1e-4, weight <= 8, symmetric product state): create + merge
+the observable, 60 x (32 gates with exact merge and truncation, symmetry
+merge, truncation), expectation.  Every step runs in the HIP kernels of
+libpp.so through its C ABI on one stream; the inputs (gate tables) are
+uploaded once per call, the term sets never leave the device.
+
+value = (propagated + merged) terms / second, the paper's two work units
+(Prop. 1: terms tested against a gate; records entering a merge), counted on
+the device and equal to the oracle's counts (tests/test_gpu_parity.py).
+
+The JSON line also carries: the same circuit without symmetry merging
+(plain PP), the roofline of the dominant kernel (per-kernel durations from
+HIP events recorded on the library's stream over the timed steps), the
+exact-merge pass on a large record stream, and the CPU oracle timed on a
+bounded prefix of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, bytes/s * 1e-9
+
+METRIC = "Pauli terms propagated+merged/sec (sym PP vs plain PP); p50/p99 job latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-merge-pass", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--merge-log2n", type=int, default=24)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for PMC scaling)")
+    return ap.parse_args()
+
+
+def gate_bytes(wc, W=1):
+    """Algorithmic bytes of the gate kernel: every live term's key is read
+    (16W B); every anticommuting term's coefficient is read and written
+    (16 B); every appended child is written (16W + 8 B)."""
+    return 16 * W * wc["propagated"] + 16 * wc["anticommuting"] + (16 * W + 8) * wc["appended"]
+
+
+def merge_bytes(wc, W=1):
+    """Algorithmic bytes of a symmetry merge: every record read (16W + 8 B),
+    every representative written (16W + 8 B)."""
+    return (16 * W + 8) * (wc["merge_in"] + wc["merge_out"])
+
+
+def run_steps(prog, group, steps, stream, alloc, profile):
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    import torch
+    layers = driver.heisenberg_layers(prog)
+    totals = dict(propagated=0, merged=0, anticommuting=0, appended=0, merge_in=0,
+                  merge_out=0)
+    kern = {k: [0, 0.0] for k in L.KERNELS}
+    L.pp_profile(None, profile)
+    e = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ps = driver.PauliSet.from_program(prog, group, stream, alloc)
+        driver.run_layers(ps, layers)
+        e = ps.expectation(prog.bloch)
+        wc = L.pp_work_counters(ps.h)
+        for k in totals:
+            totals[k] += wc[k]
+        if profile:
+            for k, (n, ms) in L.pp_profile_read(ps.h).items():
+                kern[k][0] += n
+                kern[k][1] += ms
+        ps.close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    L.pp_profile(None, False)
+    return wall, totals, kern, e
+
+
+def merge_pass(stream, alloc, log2n):
+    """Exact merge of 2^log2n records: random weight <= 8 Z_32 strings, each
+    emitted in 32 random rotations (Algorithm 1 step 1 on that stream)."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import workloads as W
+    import numpy as np
+    import torch
+    x, z, c = W.merge_stress_records(log2n, 32, seed=7)
+    L.pp_profile(None, True)
+    torch.cuda.synchronize()
+    h = L.pp_create(32, "Zn", x.reshape(-1, 1), z.reshape(-1, 1), c, stream, alloc)
+    prof = L.pp_profile_read(h)
+    wc = L.pp_work_counters(h)
+    L.pp_destroy(h)
+    L.pp_profile(None, False)
+    ms = prof["merge_narrow"][1] + prof["merge_collect"][1]
+    nbytes = merge_bytes(wc)
+    return dict(records=int(wc["merge_in"]), representatives=int(wc["merge_out"]),
+                ms=round(ms, 4), insert_ms=round(prof["merge_narrow"][1], 4),
+                collect_ms=round(prof["merge_collect"][1], 4),
+                records_per_s=wc["merge_in"] / (ms * 1e-3),
+                algorithmic_GBs=round(nbytes / (ms * 1e-3) / 1e9, 1),
+                frac_of_hbm=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+
+
+def cpu_baseline(prog, seconds):
+    from oracle import oracle as O
+    r = O.run_program(prog, keep_terms=False, time_budget=seconds)
+    units = r.propagated + r.merged
+    return dict(value=units / r.wall, unit="terms/s", cores=1, kind="oracle",
+                sample=f"first {r.sublayers_done} of {len(prog.sublayers)} sub-layers of the "
+                       f"same workload ({units} terms in {r.wall:.1f} s, one thread)")
+
+
+def host_info():
+    info = dict(nproc=os.cpu_count())
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                info["cpu"] = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return info
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the term set "
+              "would shard by representative hash with an all-to-all per layer, which this "
+              "build does not implement.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import workloads as W
+    L.lib()
+    torch.cuda.set_device(0)
+    stream_obj = torch.cuda.Stream()
+    stream = int(stream_obj.cuda_stream)
+    alloc = L.TorchAllocator(0)
+    prog = W.config2()
+
+    with torch.cuda.stream(stream_obj):
+        if args.copy_calibration:
+            a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            print(json.dumps({"copy_calibration_bytes_each_way": a.numel() * 4}),
+                  file=sys.stderr, flush=True)
+        run_steps(prog, "Zn", args.warmup, stream, alloc, False)
+        print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+        wall, tot, kern, e = run_steps(prog, "Zn", args.steps, stream, alloc, True)
+        print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+        units = tot["propagated"] + tot["merged"]
+        value = units / wall
+        gate_n, gate_ms = kern["gate"]
+        gb = gate_bytes(tot)
+        roof = dict(bound="hbm", kernel="k_gate",
+                    achieved=round(gb / (gate_ms * 1e-3) / 1e9, 2), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(gb / (gate_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                    traffic=None, launches=gate_n,
+                    avg_launch_us=round(gate_ms * 1e3 / max(gate_n, 1), 3),
+                    bytes_per_launch=round(gb / max(gate_n, 1), 1))
+        kernels = {k: dict(launches=n, ms=round(ms, 3)) for k, (n, ms) in kern.items() if n}
+        plain = None
+        if not args.no_plain:
+            run_steps(prog, "none", 1, stream, alloc, False)
+            pw, ptot, pkern, pe = run_steps(prog, "none", max(1, args.steps // 2), stream,
+                                            alloc, False)
+            psteps = max(1, args.steps // 2)
+            plain = dict(value=(ptot["propagated"] + ptot["merged"]) / pw, unit="terms/s",
+                         ms_per_step=round(pw / psteps * 1e3, 3),
+                         terms_per_step=(ptot["propagated"] + ptot["merged"]) // psteps,
+                         expectation=pe)
+            print(f"[bench] plain PP done", file=sys.stderr, flush=True)
+        mp = None
+        if not args.no_merge_pass:
+            merge_pass(stream, alloc, args.merge_log2n)            # warm
+            mp = merge_pass(stream, alloc, args.merge_log2n)
+            print(f"[bench] merge pass done", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2_z32_xxz: Z_32 ring, 20 XXZ Trotter steps (theta 0.05, "
+                               "Delta 1.5), O = sum X_i X_{i+1}, eps 1e-4, weight <= 8, "
+                               "symmetry PP under translations",
+                   "n": 32, "sublayers": 60, "gates": 1920,
+                   "terms_per_step": units // args.steps, "expectation": e},
+        "plain_pp": plain,
+        "roofline": roof,
+        "kernels": kernels,
+        "merge_pass": mp,
+        "host": host_info(),
+        "platform": platform.node(),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prog, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

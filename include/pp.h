@@ -169,6 +169,42 @@ int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef,
  */
 int pp_counters(pp_state* s, uint64_t out[2]);
 
+/*
+ * Finer work counters: out[0] propagated, out[1] merged (as pp_counters),
+ * out[2] = sum over gates of the live terms that anticommute with the gate,
+ * out[3] = strings appended by gates (children whose partner was absent),
+ * out[4] = records entering symmetry merges / compactions,
+ * out[5] = representatives leaving them.  These are the unit counts of the
+ * algorithmic-bytes model of each kernel.
+ */
+int pp_work_counters(pp_state* s, uint64_t out[6]);
+
+/* Kernel kinds for per-kernel timing. */
+enum {
+  PP_K_GATE = 0,          /* one rotation + exact merge + truncation     */
+  PP_K_MERGE_NARROW = 1,  /* representative + exact sum, 64-bit keys     */
+  PP_K_MERGE_WIDE1 = 2,   /* representative + hash slot, wider keys      */
+  PP_K_MERGE_WIDE2 = 3,   /* owner compare + exact sum, wider keys       */
+  PP_K_MERGE_COLLECT = 4, /* merge table -> new term store               */
+  PP_K_COMPACT = 5,       /* plain-PP layer end: drop dead entries       */
+  PP_K_SCAN = 6,          /* damping / truncation / recount / expectation */
+  PP_K_GROW = 7,          /* store growth                                */
+  PP_KERNEL_KINDS = 8
+};
+
+/*
+ * pp_profile(s, 1) resets and starts per-kernel timing: every kernel this
+ * handle launches from then on is bracketed by HIP events recorded on the
+ * handle's stream; pp_profile(s, 0) stops.  pp_profile_read returns, per
+ * kernel kind, the number of timed launches and their summed duration in
+ * milliseconds (both synchronise).  pp_profile(NULL, on) sets whether
+ * handles created afterwards start timed (their pp_create included).  The
+ * batched form is not timed.
+ */
+int pp_profile(pp_state* s, int enable);
+int pp_profile_read(pp_state* s, uint64_t launches[PP_KERNEL_KINDS],
+                    double milliseconds[PP_KERNEL_KINDS]);
+
 /* Upper bound on stored terms (live + not yet compacted); 0 = no limit. */
 int pp_set_max_terms(pp_state* s, size_t max_terms);
 
@@ -216,10 +252,15 @@ int pp_batch_step(pp_state* const* states, const pp_program* const* programs,
                   size_t n, void* hip_stream, int max_steps, int* done,
                   double* expectations);
 
-/* Tuning knobs picked by the autotuner: threads per block (64..1024, a
- * multiple of 64), maximum persistent blocks per launch, and steps per
- * captured graph in the batched form. */
-int pp_set_tuning(int block_threads, int max_blocks, int graph_steps);
+/*
+ * Launch tuning (process-wide; the autotuner picks it per workload class):
+ * terms per thread of the gate kernel and of the streaming kernels (merge,
+ * compaction, damping/truncation/expectation) in {1, 2, 4, 8}, the cap on
+ * blocks per launch, and the batched steps per captured graph.  A 0 keeps
+ * the current value.  pp_get_tuning returns the four current values.
+ */
+int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_steps);
+int pp_get_tuning(int out[4]);
 
 #ifdef __cplusplus
 }

@@ -64,6 +64,9 @@ def lib():
                                   ctypes.POINTER(ctypes.c_size_t)]
     L.pp_counters.argtypes = [_vp, _u64p]
     L.pp_set_max_terms.argtypes = [_vp, ctypes.c_size_t]
+    L.pp_work_counters.argtypes = [_vp, _u64p]
+    L.pp_profile.argtypes = [_vp, ctypes.c_int]
+    L.pp_profile_read.argtypes = [_vp, _u64p, _f64p]
     L.pp_destroy.argtypes = [_vp]
     L.pp_destroy.restype = None
     L.pp_program_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_size_t,
@@ -75,7 +78,8 @@ def lib():
                                _f64p]
     L.pp_batch_step.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_size_t, _vp,
                                 ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p]
-    L.pp_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.pp_set_tuning.argtypes = [ctypes.c_int] * 4
+    L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     _lib = L
     return L
 
@@ -190,6 +194,28 @@ def pp_counters(h):
     return int(out[0]), int(out[1])
 
 
+KERNELS = ["gate", "merge_narrow", "merge_wide1", "merge_wide2", "merge_collect", "compact",
+           "scan", "grow"]
+
+
+def pp_work_counters(h):
+    out = (ctypes.c_uint64 * 6)()
+    _check(lib().pp_work_counters(h, out))
+    keys = ["propagated", "merged", "anticommuting", "appended", "merge_in", "merge_out"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def pp_profile(h, enable=True):
+    _check(lib().pp_profile(h, 1 if enable else 0))
+
+
+def pp_profile_read(h):
+    n = (ctypes.c_uint64 * len(KERNELS))()
+    ms = (ctypes.c_double * len(KERNELS))()
+    _check(lib().pp_profile_read(h, n, ms))
+    return {k: (int(n[i]), float(ms[i])) for i, k in enumerate(KERNELS)}
+
+
 def pp_set_max_terms(h, max_terms):
     _check(lib().pp_set_max_terms(h, max_terms))
 
@@ -241,5 +267,12 @@ def pp_batch_step(states, programs, stream, max_steps):
     return np.array(list(done), dtype=bool), out
 
 
-def pp_set_tuning(block_threads=0, max_blocks=0, graph_steps=0):
-    _check(lib().pp_set_tuning(block_threads, max_blocks, graph_steps))
+def pp_set_tuning(gate_items=0, stream_items=0, max_blocks=0, graph_steps=0):
+    _check(lib().pp_set_tuning(gate_items, stream_items, max_blocks, graph_steps))
+
+
+def pp_get_tuning():
+    out = (ctypes.c_int * 4)()
+    _check(lib().pp_get_tuning(out))
+    return dict(gate_items=out[0], stream_items=out[1], max_blocks=out[2],
+                graph_steps=out[3])

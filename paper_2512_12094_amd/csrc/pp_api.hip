@@ -33,10 +33,13 @@ int fail(int code, const std::string& msg) {
 }
 
 struct Tuning {
-  int max_blocks = 2048;
-  int graph_steps = 32;
+  int gate_items = 1;     // terms per thread in the gate kernel
+  int stream_items = 1;   // terms per thread in merge / compaction / scan kernels
+  int max_blocks = 2048;  // persistent grid cap
+  int graph_steps = 32;   // batched steps per captured graph
 };
 Tuning g_tune;
+bool g_prof_default = false;   // pp_profile(NULL, on): new handles start timed
 
 #define HIP_TRY(expr)                                                            \
   do {                                                                           \
@@ -89,6 +92,16 @@ struct pp_state {
     bool used = false;
   } ring[4];
   unsigned ring_pos = 0;
+  // per-kernel timing with events on this stream (pp_profile)
+  bool prof = false;
+  struct Pend {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Pend> pend;
+  std::vector<hipEvent_t> pool;
+  uint64_t prof_n[PP_KERNEL_KINDS] = {};
+  double prof_ms[PP_KERNEL_KINDS] = {};
 };
 
 namespace {
@@ -109,6 +122,47 @@ void dev_free(pp_state* s, void* p) {
     (void)hipFree(p);
 }
 
+hipEvent_t prof_event(pp_state* s) {
+  hipEvent_t e = nullptr;
+  if (!s->pool.empty()) {
+    e = s->pool.back();
+    s->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  return e;
+}
+
+// Records an event before a launch (or nullptr when not profiling).
+hipEvent_t prof_begin(pp_state* s) {
+  if (!s->prof) return nullptr;
+  hipEvent_t a = prof_event(s);
+  if (a) (void)hipEventRecord(a, s->stream);
+  return a;
+}
+
+void prof_end(pp_state* s, int kind, hipEvent_t a) {
+  if (!a) return;
+  hipEvent_t b = prof_event(s);
+  if (!b) return;
+  (void)hipEventRecord(b, s->stream);
+  s->pend.push_back({kind, a, b});
+}
+
+// After a stream synchronisation: fold the finished intervals in.
+void prof_resolve(pp_state* s) {
+  for (const auto& p : s->pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      s->prof_n[p.k] += 1;
+      s->prof_ms[p.k] += ms;
+    }
+    s->pool.push_back(p.a);
+    s->pool.push_back(p.b);
+  }
+  s->pend.clear();
+}
+
 Ctx single_ctx(pp_state* s) {
   Ctx c;
   c.bufs = s->d_bufp;
@@ -123,9 +177,12 @@ int upload_buf(pp_state* s) {
   return PP_OK;
 }
 
+void prof_resolve(pp_state* s);
+
 int read_dyn(pp_state* s) {
   HIP_TRY(hipMemcpyAsync(s->h_dyn, s->d_dyn, sizeof(InstDyn), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  prof_resolve(s);
   return PP_OK;
 }
 
@@ -162,7 +219,7 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
     ok = ok && (nb.wrep = (uint64_t*)take(sizeof(uint64_t) * 2 * W * cap));
     ok = ok && (nb.wslot = (uint32_t*)take(sizeof(uint32_t) * cap));
   }
-  ok = ok && (nb.partial = (double*)take(sizeof(double) * ((cap + kTile - 1) / kTile + 1)));
+  ok = ok && (nb.partial = (double*)take(sizeof(double) * ((cap + kBlock - 1) / kBlock + 1)));
   if (!ok) {
     for (void* p : got) dev_free(s, p);
     return fail(PP_ENOMEM, "allocation of a term store of capacity " + std::to_string(cap) +
@@ -184,10 +241,32 @@ void free_store(pp_state* s, std::vector<void*>& allocs) {
   allocs.clear();
 }
 
-int launch_blocks(uint64_t elements) {
-  const uint64_t tiles = (elements + kTile - 1) / kTile;
+int launch_blocks(uint64_t elements, int items = 4) {
+  const uint64_t tile = (uint64_t)kBlock * items;
+  const uint64_t tiles = (elements + tile - 1) / tile;
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)g_tune.max_blocks));
 }
+
+using KernelFn = void (*)(Ctx);
+
+#define PP_PICK(kern, it) \
+  ((it) == 1 ? &kern<1> : (it) == 2 ? &kern<2> : (it) == 8 ? &kern<8> : &kern<4>)
+
+// Kernel of a kind with the tuned items per thread.
+KernelFn kernel_of(int kind) {
+  const int gi = g_tune.gate_items, si = g_tune.stream_items;
+  switch (kind) {
+    case PP_K_GATE: return PP_PICK(k_gate, gi);
+    case PP_K_MERGE_NARROW: return PP_PICK(k_merge_narrow, si);
+    case PP_K_MERGE_WIDE1: return PP_PICK(k_merge_wide1, si);
+    case PP_K_MERGE_WIDE2: return PP_PICK(k_merge_wide2, si);
+    case PP_K_MERGE_COLLECT: return PP_PICK(k_merge_collect, si);
+    case PP_K_COMPACT: return PP_PICK(k_compact, si);
+    default: return PP_PICK(k_scan_op, si);
+  }
+}
+
+int items_of(int kind) { return kind == PP_K_GATE ? g_tune.gate_items : g_tune.stream_items; }
 
 // Grows (or just compacts) the store so that live + count + slack fits.
 int grow(pp_state* s) {
@@ -206,8 +285,10 @@ int grow(pp_state* s) {
   if (rc) return rc;
   nb.prog = s->buf.prog;
   nb.prog_len = s->buf.prog_len;
+  hipEvent_t ev = prof_begin(s);
   hipLaunchKernelGGL(k_grow, dim3(launch_blocks(d.M)), dim3(kBlock), 0, s->stream, s->buf, nb,
                      s->d_dyn, s->d_sync);
+  prof_end(s, PP_K_GROW, ev);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s->stream));
   free_store(s, s->store);
@@ -237,27 +318,32 @@ int ensure_ops(pp_state* s, size_t nops, size_t ntab) {
 // Launches the kernels that execute ops[from..] assuming none overflows.
 int launch_ops(pp_state* s, const std::vector<Op>& ops, size_t from) {
   const Ctx C = single_ctx(s);
-  const int gb = launch_blocks(s->buf.cap);
-  const int mb = launch_blocks(1ull << s->buf.hm_bits);
+  auto launch = [&](int kind) {
+    const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
+    const int grid = launch_blocks(elems, items_of(kind));
+    hipEvent_t ev = prof_begin(s);
+    hipLaunchKernelGGL(kernel_of(kind), dim3(grid), dim3(kBlock), 0, s->stream, C);
+    prof_end(s, kind, ev);
+  };
   for (size_t k = from; k < ops.size(); ++k) {
     switch (ops[k].type) {
       case OP_GATE:
-        hipLaunchKernelGGL(k_gate, dim3(gb), dim3(kBlock), 0, s->stream, C);
+        launch(PP_K_GATE);
         break;
       case OP_MERGE:
         if (s->group == PP_GROUP_NONE && !ops[k].force_full) {
-          hipLaunchKernelGGL(k_compact, dim3(gb), dim3(kBlock), 0, s->stream, C);
+          launch(PP_K_COMPACT);
         } else if (s->buf.narrow) {
-          hipLaunchKernelGGL(k_merge_narrow, dim3(gb), dim3(kBlock), 0, s->stream, C);
-          hipLaunchKernelGGL(k_merge_collect, dim3(mb), dim3(kBlock), 0, s->stream, C);
+          launch(PP_K_MERGE_NARROW);
+          launch(PP_K_MERGE_COLLECT);
         } else {
-          hipLaunchKernelGGL(k_merge_wide1, dim3(gb), dim3(kBlock), 0, s->stream, C);
-          hipLaunchKernelGGL(k_merge_wide2, dim3(gb), dim3(kBlock), 0, s->stream, C);
-          hipLaunchKernelGGL(k_merge_collect, dim3(mb), dim3(kBlock), 0, s->stream, C);
+          launch(PP_K_MERGE_WIDE1);
+          launch(PP_K_MERGE_WIDE2);
+          launch(PP_K_MERGE_COLLECT);
         }
         break;
       default:
-        hipLaunchKernelGGL(k_scan_op, dim3(gb), dim3(kBlock), 0, s->stream, C);
+        launch(PP_K_SCAN);
         break;
     }
   }
@@ -425,12 +511,24 @@ extern "C" {
 
 const char* pp_last_error(void) { return g_err.c_str(); }
 
-int pp_set_tuning(int block_threads, int max_blocks, int graph_steps) {
-  if (block_threads != 0 && block_threads != kBlock)
-    return fail(PP_EINVAL, "block_threads must be 0 or " + std::to_string(kBlock));
+int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_steps) {
+  auto ok_items = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
+  if (!ok_items(gate_items) || !ok_items(stream_items))
+    return fail(PP_EINVAL, "items per thread must be 0 (keep), 1, 2, 4 or 8");
   if (max_blocks < 0 || graph_steps < 0) return fail(PP_EINVAL, "negative tuning value");
+  if (gate_items) g_tune.gate_items = gate_items;
+  if (stream_items) g_tune.stream_items = stream_items;
   if (max_blocks) g_tune.max_blocks = max_blocks;
   if (graph_steps) g_tune.graph_steps = graph_steps;
+  return PP_OK;
+}
+
+int pp_get_tuning(int out[4]) {
+  if (!out) return fail(PP_EINVAL, "NULL argument");
+  out[0] = g_tune.gate_items;
+  out[1] = g_tune.stream_items;
+  out[2] = g_tune.max_blocks;
+  out[3] = g_tune.graph_steps;
   return PP_OK;
 }
 
@@ -451,6 +549,8 @@ void pp_destroy(pp_state* s) {
     if (st.h) (void)hipHostFree(st.h);
     if (st.ev) (void)hipEventDestroy(st.ev);
   }
+  prof_resolve(s);
+  for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -476,6 +576,7 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   s->W = W;
   s->group = group;
   s->stream = (hipStream_t)hip_stream;
+  s->prof = g_prof_default;
   if (alloc) {
     s->alloc = *alloc;
     s->use_alloc = true;
@@ -544,6 +645,47 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   ops[0].force_full = 1;
   if ((rc = run_ops(s.get(), ops, {}, {}, false))) return bail(rc);
   *out = s.release();
+  return PP_OK;
+}
+
+int pp_work_counters(pp_state* s, uint64_t out[6]) {
+  if (!s || !out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  const InstDyn& d = *s->h_dyn;
+  out[0] = d.propagated;
+  out[1] = d.merged;
+  out[2] = d.anti_total;
+  out[3] = d.appended;
+  out[4] = d.merge_in;
+  out[5] = d.merge_out;
+  return PP_OK;
+}
+
+int pp_profile(pp_state* s, int enable) {
+  if (!s) {
+    g_prof_default = enable != 0;
+    return PP_OK;
+  }
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  s->prof = enable != 0;
+  for (int k = 0; k < PP_KERNEL_KINDS; ++k) {
+    s->prof_n[k] = 0;
+    s->prof_ms[k] = 0.0;
+  }
+  return PP_OK;
+}
+
+int pp_profile_read(pp_state* s, uint64_t launches[PP_KERNEL_KINDS],
+                    double milliseconds[PP_KERNEL_KINDS]) {
+  if (!s || !launches || !milliseconds) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  for (int k = 0; k < PP_KERNEL_KINDS; ++k) {
+    launches[k] = s->prof_n[k];
+    milliseconds[k] = s->prof_ms[k];
+  }
   return PP_OK;
 }
 
@@ -841,13 +983,9 @@ void launch_step(BatchCtx* b, int blocks) {
   C.ninst = b->d_ninst;
   C.sync = b->d_sync;
   const dim3 g(blocks), t(kBlock);
-  hipLaunchKernelGGL(k_gate, g, t, 0, b->stream, C);
-  hipLaunchKernelGGL(k_merge_narrow, g, t, 0, b->stream, C);
-  hipLaunchKernelGGL(k_merge_wide1, g, t, 0, b->stream, C);
-  hipLaunchKernelGGL(k_merge_wide2, g, t, 0, b->stream, C);
-  hipLaunchKernelGGL(k_merge_collect, g, t, 0, b->stream, C);
-  hipLaunchKernelGGL(k_compact, g, t, 0, b->stream, C);
-  hipLaunchKernelGGL(k_scan_op, g, t, 0, b->stream, C);
+  for (int kind : {PP_K_GATE, PP_K_MERGE_NARROW, PP_K_MERGE_WIDE1, PP_K_MERGE_WIDE2,
+                   PP_K_MERGE_COLLECT, PP_K_COMPACT, PP_K_SCAN})
+    hipLaunchKernelGGL(kernel_of(kind), g, t, 0, b->stream, C);
 }
 
 int ensure_graph(BatchCtx* b) {

@@ -275,19 +275,27 @@ __device__ inline uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Block-wide "am I the last block of this launch" (threadfence reduction).
-__device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag) {
+// Block-wide "am I the last working block of this launch" (threadfence
+// reduction over the `workers` blocks that had tiles).
+__device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers) {
+  if (workers <= 1) return true;       // block 0 did all the work itself
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
     const uint32_t t = atomicAdd(sync, 1u);
-    *s_flag = (t == gridDim.x - 1) ? 1u : 0u;
+    *s_flag = (t == workers - 1) ? 1u : 0u;
     if (*s_flag) atomicExch(sync, 0u);
   }
   __syncthreads();
   const bool r = *s_flag != 0;
   if (r) __threadfence();
   return r;
+}
+
+// Blocks beyond the tile count leave at once; block 0 always stays so that
+// the program counters advance even when no instance has work.
+__device__ inline uint32_t worker_count(uint32_t total) {
+  return total < gridDim.x ? (total ? total : 1u) : gridDim.x;
 }
 
 // Prefix of tiles over instances: s_pref[i] = first tile of instance i.
@@ -325,7 +333,8 @@ __device__ inline int find_inst(const uint32_t* s_pref, int ninst, uint32_t t) {
   return lo;
 }
 
-__device__ inline uint32_t ceil_tiles(uint32_t n) { return (n + kTile - 1) / kTile; }
+template <int IT>
+__device__ inline uint32_t ceil_tiles(uint32_t n) { return (n + kBlock * IT - 1) / (kBlock * IT); }
 
 __device__ inline const Op* cur_op(const InstBuf& b, const InstDyn& d) {
   return d.pc < b.prog_len ? &b.prog[d.pc] : nullptr;
@@ -513,6 +522,7 @@ __device__ inline int gate_state(const InstBuf& b, const InstDyn& d) {
   return 1;
 }
 
+template <int IT>
 __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
                                  uint32_t* s_tmp, uint32_t* s_base) {
   const View v = view_of(b, d);
@@ -530,9 +540,9 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
     for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
   }
   uint32_t my_live = 0, my_cnt = 0;
-  uint64_t chx[kItems][kMaxW], chz[kItems][kMaxW];
-  double chc[kItems];
-  bool chv[kItems];
+  uint64_t chx[IT][kMaxW], chz[IT][kMaxW];
+  double chc[IT];
+  bool chv[IT];
 
   auto tally = [&](const uint64_t* x, const uint64_t* z) {
     ++my_live;
@@ -543,9 +553,9 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
   };
 
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
+  for (int k = 0; k < IT; ++k) {
     chv[k] = false;
-    const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
     if (i >= M) continue;
     if (!v.al[i]) { v.aln[i] = 0; continue; }
     uint64_t qx[kMaxW], qz[kMaxW];
@@ -601,14 +611,14 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
   // append the new strings: one atomic per tile
   uint32_t mine = 0;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) mine += chv[k] ? 1u : 0u;
+  for (int k = 0; k < IT; ++k) mine += chv[k] ? 1u : 0u;
   uint32_t total;
   uint32_t off = block_scan(mine, s_tmp, &total);
   if (threadIdx.x == 0) *s_base = total ? atomicAdd(&d.Mnext, total) : 0u;
   __syncthreads();
   const uint32_t base = *s_base;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
+  for (int k = 0; k < IT; ++k) {
     if (!chv[k]) continue;
     const uint32_t pos = base + off++;
     if (pos >= v.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }   // guard
@@ -628,6 +638,7 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
   }
 }
 
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
@@ -636,13 +647,15 @@ __global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
     const InstBuf& b = *C.bufs[i];
     const InstDyn& d = *C.dyns[i];
-    return gate_state(b, d) == 1 ? ceil_tiles(d.M) : 0u;
+    return gate_state(b, d) == 1 ? ceil_tiles<IT>(d.M) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int i = find_inst(s_pref, ninst, t);
-    gate_tile(*C.bufs[i], *C.dyns[i], t - s_pref[i], s_tmp, &s_base);
+    gate_tile<IT>(*C.bufs[i], *C.dyns[i], t - s_pref[i], s_tmp, &s_base);
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = threadIdx.x; i < ninst; i += kBlock) {
     const InstBuf& b = *C.bufs[i];
     InstDyn& d = *C.dyns[i];
@@ -652,6 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
     const Op& op = b.prog[d.pc];
     d.propagated += d.live;
     d.merged += (uint64_t)d.live + d.count;
+    d.anti_total += d.count;
+    d.appended += ld_agent(&d.Mnext) - d.M;
     d.M = ld_agent(&d.Mnext);
     d.Mnext = d.M;
     d.parity ^= 1u;
@@ -676,14 +691,17 @@ __device__ inline bool merge_served(const InstBuf& b, const InstDyn& d, bool nar
   return (b.narrow != 0) == narrow && d.mphase == phase;
 }
 
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
   __shared__ uint32_t s_flag;
   const int ninst = *C.ninst;
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return merge_served(*C.bufs[i], *C.dyns[i], true, 0) ? ceil_tiles(C.dyns[i]->M) : 0u;
+    return merge_served(*C.bufs[i], *C.dyns[i], true, 0) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int inst = find_inst(s_pref, ninst, t);
     const InstBuf& b = *C.bufs[inst];
@@ -691,8 +709,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
     const View v = view_of(b, d);
     const uint32_t tile = t - s_pref[inst];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       const bool act = i < d.M && v.al[i];
       uint64_t key = 0;
       Fx c{0, 0, 0};
@@ -707,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
       wave_merge_add(b, d, act, key, c);
     }
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = threadIdx.x; i < ninst; i += kBlock) {
     InstDyn& d = *C.dyns[i];
     if (!merge_served(*C.bufs[i], d, true, 0)) continue;
@@ -722,14 +740,17 @@ __global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
 // owner's (a mismatch is a hash collision: the merge restarts with another
 // seed) and adds its coefficient.
 // ---------------------------------------------------------------------------
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
   __shared__ uint32_t s_flag;
   const int ninst = *C.ninst;
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return merge_served(*C.bufs[i], *C.dyns[i], false, 0) ? ceil_tiles(C.dyns[i]->M) : 0u;
+    return merge_served(*C.bufs[i], *C.dyns[i], false, 0) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int inst = find_inst(s_pref, ninst, t);
     const InstBuf& b = *C.bufs[inst];
@@ -739,8 +760,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
     const int W = b.W;
     const uint64_t seed = d.seed;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (i >= d.M) continue;
       if (!v.al[i]) { b.wslot[i] = kNone32; continue; }
       uint64_t qx[kMaxW], qz[kMaxW], rx[kMaxW], rz[kMaxW];
@@ -755,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
       b.wslot[i] = (uint32_t)mt_slot(b.mkey, b.hm_bits, h);
     }
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = threadIdx.x; i < ninst; i += kBlock) {
     InstDyn& d = *C.dyns[i];
     if (!merge_served(*C.bufs[i], d, false, 0)) continue;
@@ -764,14 +785,17 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
   }
 }
 
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_merge_wide2(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
   __shared__ uint32_t s_flag;
   const int ninst = *C.ninst;
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return merge_served(*C.bufs[i], *C.dyns[i], false, 1) ? ceil_tiles(C.dyns[i]->M) : 0u;
+    return merge_served(*C.bufs[i], *C.dyns[i], false, 1) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int inst = find_inst(s_pref, ninst, t);
     const InstBuf& b = *C.bufs[inst];
@@ -780,8 +804,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide2(Ctx C) {
     const uint32_t tile = t - s_pref[inst];
     const int W = b.W;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (i >= d.M) continue;
       const uint32_t s = b.wslot[i];
       if (s == kNone32) continue;
@@ -800,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide2(Ctx C) {
       }
     }
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = threadIdx.x; i < ninst; i += kBlock) {
     InstDyn& d = *C.dyns[i];
     if (!merge_served(*C.bufs[i], d, false, 1)) continue;
@@ -826,6 +850,8 @@ __device__ inline void emit_term(const InstBuf& b, const InstDyn& d, uint32_t po
 // After a merge or compaction: the other half becomes current.
 __device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
   const Op& op = b.prog[d.pc];
+  d.merge_in += d.live;
+  d.merge_out += d.nuniq;
   d.M = d.nuniq;
   d.Mnext = d.M;
   d.half ^= 1u;
@@ -843,6 +869,7 @@ __device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
 
 // Collect: every occupied merge slot becomes one representative of the new
 // half; slots are cleared for the next merge.
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
@@ -855,8 +882,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
     return merge_served(b, d, true, 1) || merge_served(b, d, false, 2);
   };
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return served(i) ? ceil_tiles(1u << C.bufs[i]->hm_bits) : 0u;
+    return served(i) ? ceil_tiles<IT>(1u << C.bufs[i]->hm_bits) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int inst = find_inst(s_pref, ninst, t);
     const InstBuf& b = *C.bufs[inst];
@@ -872,14 +901,14 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
       const Op& nx = b.prog[op.next_gate];
       for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
     }
-    uint64_t ox[kItems][kMaxW], oz[kItems][kMaxW];
-    double oc[kItems];
-    bool ov[kItems];
+    uint64_t ox[IT][kMaxW], oz[IT][kMaxW];
+    double oc[IT];
+    bool ov[IT];
     uint32_t mine = 0, my_cnt = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < IT; ++k) {
       ov[k] = false;
-      const uint32_t s = tile * kTile + k * kBlock + threadIdx.x;
+      const uint32_t s = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (s >= nslots) continue;
       const uint64_t key = b.mkey[s];
       if (key == kEmpty64) continue;
@@ -911,7 +940,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
     __syncthreads();
     const uint32_t base = *s_base;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < IT; ++k) {
       if (!ov[k]) continue;
       const uint32_t pos = base + off++;
       if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
@@ -923,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
       if (bc) atomicAdd(&d.acc_count, bc);
     }
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = threadIdx.x; i < ninst; i += kBlock) {
     if (!served(i)) continue;
     const InstBuf& b = *C.bufs[i];
@@ -974,6 +1003,7 @@ __device__ inline bool compact_served(const InstBuf& b, const InstDyn& d) {
   return op && op->type == OP_MERGE && b.group == 0 && !op->force_full;
 }
 
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
@@ -981,8 +1011,10 @@ __global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
   uint32_t* s_base = &s_base_v;
   const int ninst = *C.ninst;
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return compact_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles(C.dyns[i]->M) : 0u;
+    return compact_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int inst = find_inst(s_pref, ninst, t);
     const InstBuf& b = *C.bufs[inst];
@@ -997,11 +1029,11 @@ __global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
       const Op& nx = b.prog[op.next_gate];
       for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
     }
-    bool ov[kItems];
+    bool ov[IT];
     uint32_t mine = 0, my_cnt = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       ov[k] = i < d.M && v.al[i];
       mine += ov[k] ? 1u : 0u;
     }
@@ -1011,9 +1043,9 @@ __global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
     __syncthreads();
     const uint32_t base = *s_base;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < IT; ++k) {
       if (!ov[k]) continue;
-      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       const uint32_t pos = base + off++;
       if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
       uint64_t x[kMaxW], z[kMaxW];
@@ -1027,7 +1059,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
       if (bc) atomicAdd(&d.acc_count, bc);
     }
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = threadIdx.x; i < ninst; i += kBlock) {
     const InstBuf& b = *C.bufs[i];
     InstDyn& d = *C.dyns[i];
@@ -1049,6 +1081,7 @@ __device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
          op->type == OP_EXPECT;
 }
 
+template <int IT>
 __global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
   __shared__ uint32_t s_pref[kMaxInst];
   __shared__ uint32_t s_tmp[kWaves + 1];
@@ -1056,8 +1089,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
   __shared__ uint32_t s_flag;
   const int ninst = *C.ninst;
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return scan_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles(C.dyns[i]->M) : 0u;
+    return scan_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
   }, s_pref, s_tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int inst = find_inst(s_pref, ninst, t);
     const InstBuf& b = *C.bufs[inst];
@@ -1076,8 +1111,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
     uint32_t my_live = 0, my_cnt = 0;
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t i = tile * kTile + k * kBlock + threadIdx.x;
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (i >= d.M || !v.al[i]) continue;
       uint64_t x[kMaxW], z[kMaxW];
       load_key(v, i, x, z);
@@ -1107,14 +1142,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
       if (bc) atomicAdd(&d.acc_count, bc);
     }
   }
-  if (!last_block(C.sync, &s_flag)) return;
+  if (!last_block(C.sync, &s_flag, workers)) return;
   for (int i = 0; i < ninst; ++i) {            // whole block per instance
     const InstBuf& b = *C.bufs[i];
     InstDyn& d = *C.dyns[i];
     if (!scan_served(b, d)) continue;          // uniform across the block
     const Op& op = b.prog[d.pc];
     if (op.type == OP_EXPECT) {
-      const uint32_t nt = ceil_tiles(d.M);
+      const uint32_t nt = ceil_tiles<IT>(d.M);
       double s = 0.0;
       for (uint32_t t = threadIdx.x; t < nt; t += kBlock) s += b.partial[t];
       s = block_sum_f64(s, s_d);
@@ -1146,6 +1181,8 @@ __global__ __launch_bounds__(kBlock) void k_grow(InstBuf src, InstBuf dst, InstD
   const uint32_t M = d.M;
   const int W = src.W;
   const uint32_t tiles = (M + kTile - 1) / kTile;
+  const uint32_t workers = worker_count(tiles);
+  if (blockIdx.x >= workers) return;
   for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     bool ov[kItems];
     uint32_t mine = 0;
@@ -1178,7 +1215,7 @@ __global__ __launch_bounds__(kBlock) void k_grow(InstBuf src, InstBuf dst, InstD
       gt_insert(dst.gtab, dst.hg_bits, 1u, pos, hash_key(x, z, W, 0));
     }
   }
-  if (!last_block(sync, &s_flag)) return;
+  if (!last_block(sync, &s_flag, workers)) return;
   if (threadIdx.x == 0) {
     d.M = ld_agent(&d.nuniq);
     d.Mnext = d.M;

@@ -88,8 +88,12 @@ struct InstBuf {
 };
 
 struct InstDyn {
-  uint64_t propagated;   // work counters (see pp_counters)
+  uint64_t propagated;   // work counters (see pp_counters, pp_work_counters)
   uint64_t merged;
+  uint64_t anti_total;   // sum over gates of the anticommuting live terms
+  uint64_t appended;     // strings appended by gates
+  uint64_t merge_in;     // records entering symmetry merges / compactions
+  uint64_t merge_out;    // representatives leaving them
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
   double expect;
   uint32_t M;            // entries in the current half (live and dead)

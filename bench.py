@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-merge-pass", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--event-every", type=int, default=16,
+                    help="time every N-th launch of each kernel kind with HIP events")
     ap.add_argument("--merge-log2n", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
@@ -64,22 +66,28 @@ def merge_bytes(wc, W=1):
     return (16 * W + 8) * (wc["merge_in"] + wc["merge_out"])
 
 
-def run_steps(prog, group, steps, stream, alloc, profile):
+def run_steps(prog, group, steps, stream, alloc, profile, mode="program"):
+    """`steps` propagations; mode "program" = one device program per step
+    (pp_batch_run with one instance), "calls" = one C call per operation."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
     import torch
     layers = driver.heisenberg_layers(prog)
+    dp = driver.device_program(prog) if mode == "program" else None
     totals = dict(propagated=0, merged=0, anticommuting=0, appended=0, merge_in=0,
                   merge_out=0)
     kern = {k: [0, 0.0] for k in L.KERNELS}
-    L.pp_profile(None, profile)
+    L.pp_profile(None, int(profile))
     e = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         ps = driver.PauliSet.from_program(prog, group, stream, alloc)
-        driver.run_layers(ps, layers)
-        e = ps.expectation(prog.bloch)
+        if mode == "program":
+            e = float(L.pp_batch_run([ps.h], [dp.h], stream)[0])
+        else:
+            driver.run_layers(ps, layers)
+            e = ps.expectation(prog.bloch)
         wc = L.pp_work_counters(ps.h)
         for k in totals:
             totals[k] += wc[k]
@@ -90,7 +98,7 @@ def run_steps(prog, group, steps, stream, alloc, profile):
         ps.close()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    L.pp_profile(None, False)
+    L.pp_profile(None, 0)
     return wall, totals, kern, e
 
 
@@ -168,19 +176,30 @@ def main():
                   file=sys.stderr, flush=True)
         run_steps(prog, "Zn", args.warmup, stream, alloc, False)
         print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-        wall, tot, kern, e = run_steps(prog, "Zn", args.steps, stream, alloc, True)
+        # timed region: HIP events on the library's stream around every
+        # args.event_every-th launch of each kernel kind
+        wall, tot, kern, e = run_steps(prog, "Zn", args.steps, stream, alloc, args.event_every)
         print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+        # the same steps without events, and through one C call per operation
+        wall_np, _, _, _ = run_steps(prog, "Zn", args.steps, stream, alloc, 0)
+        wall_calls, _, _, _ = run_steps(prog, "Zn", args.steps, stream, alloc, False,
+                                        mode="calls")
         units = tot["propagated"] + tot["merged"]
         value = units / wall
-        gate_n, gate_ms = kern["gate"]
+        gate_n, gate_ms = kern["gate"]             # sampled launches and their time
+        gates_run = prog.n_gates * args.steps       # every gate op runs once per step
         gb = gate_bytes(tot)
-        roof = dict(bound="hbm", kernel="k_gate",
-                    achieved=round(gb / (gate_ms * 1e-3) / 1e9, 2), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(gb / (gate_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                    traffic=None, launches=gate_n,
-                    avg_launch_us=round(gate_ms * 1e3 / max(gate_n, 1), 3),
-                    bytes_per_launch=round(gb / max(gate_n, 1), 1))
+        avg_s = gate_ms * 1e-3 / max(gate_n, 1)
+        bpl = gb / gates_run
+        roof = dict(bound="hbm", kernel="k_gate", achieved=round(bpl / avg_s / 1e9, 2),
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 5), traffic=None,
+                    avg_launch_us=round(avg_s * 1e6, 3), timed_launches=gate_n,
+                    launches=gates_run, bytes_per_launch=round(bpl, 1),
+                    est_kernel_ms_per_step=round(avg_s * 1e3 * prog.n_gates, 3))
         kernels = {k: dict(launches=n, ms=round(ms, 3)) for k, (n, ms) in kern.items() if n}
+        variants = dict(ms_per_step_without_events=round(wall_np / args.steps * 1e3, 3),
+                        ms_per_step_one_call_per_op=round(wall_calls / args.steps * 1e3, 3))
         plain = None
         if not args.no_plain:
             run_steps(prog, "none", 1, stream, alloc, False)
@@ -219,6 +238,7 @@ def main():
         "plain_pp": plain,
         "roofline": roof,
         "kernels": kernels,
+        "variants": variants,
         "merge_pass": mp,
         "host": host_info(),
         "platform": platform.node(),

@@ -193,15 +193,16 @@ enum {
 };
 
 /*
- * pp_profile(s, 1) resets and starts per-kernel timing: every kernel this
- * handle launches from then on is bracketed by HIP events recorded on the
- * handle's stream; pp_profile(s, 0) stops.  pp_profile_read returns, per
- * kernel kind, the number of timed launches and their summed duration in
- * milliseconds (both synchronise).  pp_profile(NULL, on) sets whether
- * handles created afterwards start timed (their pp_create included).  The
- * batched form is not timed.
+ * pp_profile(s, every) resets the per-kernel timing of handle s and, for
+ * every > 0, brackets every `every`-th launch of each kernel kind with HIP
+ * events recorded on the handle's stream (1 = every launch; 0 = off).
+ * pp_profile_read returns, per kernel kind, the number of timed launches
+ * and their summed duration in milliseconds (both synchronise).
+ * pp_profile(NULL, every) sets the value that handles created afterwards
+ * start with (their pp_create included).  The batched form of more than one
+ * instance is not timed.
  */
-int pp_profile(pp_state* s, int enable);
+int pp_profile(pp_state* s, int every);
 int pp_profile_read(pp_state* s, uint64_t launches[PP_KERNEL_KINDS],
                     double milliseconds[PP_KERNEL_KINDS]);
 

@@ -205,8 +205,9 @@ def pp_work_counters(h):
     return {k: int(v) for k, v in zip(keys, out)}
 
 
-def pp_profile(h, enable=True):
-    _check(lib().pp_profile(h, 1 if enable else 0))
+def pp_profile(h, every=1):
+    """every: bracket every `every`-th launch per kernel kind (0 = off)."""
+    _check(lib().pp_profile(h, int(every)))
 
 
 def pp_profile_read(h):

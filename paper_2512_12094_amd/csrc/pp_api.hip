@@ -39,7 +39,7 @@ struct Tuning {
   int graph_steps = 32;   // batched steps per captured graph
 };
 Tuning g_tune;
-bool g_prof_default = false;   // pp_profile(NULL, on): new handles start timed
+int g_prof_default = 0;   // pp_profile(NULL, every): new handles start timed
 
 #define HIP_TRY(expr)                                                            \
   do {                                                                           \
@@ -84,6 +84,8 @@ struct pp_state {
   size_t tab_cap = 0;
   InstDyn* h_dyn = nullptr;            // pinned
   const pp_program* batch_prog = nullptr;
+  InstDyn* solo_slots = nullptr;       // pinned status slots of solo_program
+  hipEvent_t solo_ev[2] = {nullptr, nullptr};
   // pinned staging ring for program uploads of calls that do not sync
   struct Stage {
     char* h = nullptr;
@@ -92,8 +94,10 @@ struct pp_state {
     bool used = false;
   } ring[4];
   unsigned ring_pos = 0;
-  // per-kernel timing with events on this stream (pp_profile)
-  bool prof = false;
+  // per-kernel timing with events on this stream (pp_profile): every
+  // prof_every-th launch of each kind is bracketed (0 = off)
+  int prof_every = 0;
+  uint64_t prof_seen[PP_KERNEL_KINDS] = {};
   struct Pend {
     int k;
     hipEvent_t a, b;
@@ -133,9 +137,10 @@ hipEvent_t prof_event(pp_state* s) {
   return e;
 }
 
-// Records an event before a launch (or nullptr when not profiling).
-hipEvent_t prof_begin(pp_state* s) {
-  if (!s->prof) return nullptr;
+// Records an event before a sampled launch (or returns nullptr).
+hipEvent_t prof_begin(pp_state* s, int kind) {
+  if (s->prof_every <= 0) return nullptr;
+  if (s->prof_seen[kind]++ % (uint64_t)s->prof_every != 0) return nullptr;
   hipEvent_t a = prof_event(s);
   if (a) (void)hipEventRecord(a, s->stream);
   return a;
@@ -149,9 +154,15 @@ void prof_end(pp_state* s, int kind, hipEvent_t a) {
   s->pend.push_back({kind, a, b});
 }
 
-// After a stream synchronisation: fold the finished intervals in.
+// Folds the finished intervals in (unfinished ones stay pending).
 void prof_resolve(pp_state* s) {
-  for (const auto& p : s->pend) {
+  size_t keep = 0;
+  for (size_t i = 0; i < s->pend.size(); ++i) {
+    const auto p = s->pend[i];
+    if (hipEventQuery(p.b) != hipSuccess) {
+      s->pend[keep++] = p;
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       s->prof_n[p.k] += 1;
@@ -160,7 +171,7 @@ void prof_resolve(pp_state* s) {
     s->pool.push_back(p.a);
     s->pool.push_back(p.b);
   }
-  s->pend.clear();
+  s->pend.resize(keep);
 }
 
 Ctx single_ctx(pp_state* s) {
@@ -266,6 +277,21 @@ KernelFn kernel_of(int kind) {
   }
 }
 
+using SoloFn = void (*)(Solo);
+
+SoloFn solo_of(int kind) {
+  const int gi = g_tune.gate_items, si = g_tune.stream_items;
+  switch (kind) {
+    case PP_K_GATE: return PP_PICK(k_gate_solo, gi);
+    case PP_K_MERGE_NARROW: return PP_PICK(k_merge_narrow_solo, si);
+    case PP_K_MERGE_WIDE1: return PP_PICK(k_merge_wide1_solo, si);
+    case PP_K_MERGE_WIDE2: return PP_PICK(k_merge_wide2_solo, si);
+    case PP_K_MERGE_COLLECT: return PP_PICK(k_merge_collect_solo, si);
+    case PP_K_COMPACT: return PP_PICK(k_compact_solo, si);
+    default: return PP_PICK(k_scan_op_solo, si);
+  }
+}
+
 int items_of(int kind) { return kind == PP_K_GATE ? g_tune.gate_items : g_tune.stream_items; }
 
 // Grows (or just compacts) the store so that live + count + slack fits.
@@ -285,7 +311,7 @@ int grow(pp_state* s) {
   if (rc) return rc;
   nb.prog = s->buf.prog;
   nb.prog_len = s->buf.prog_len;
-  hipEvent_t ev = prof_begin(s);
+  hipEvent_t ev = prof_begin(s, PP_K_GROW);
   hipLaunchKernelGGL(k_grow, dim3(launch_blocks(d.M)), dim3(kBlock), 0, s->stream, s->buf, nb,
                      s->d_dyn, s->d_sync);
   prof_end(s, PP_K_GROW, ev);
@@ -316,39 +342,57 @@ int ensure_ops(pp_state* s, size_t nops, size_t ntab) {
 }
 
 // Launches the kernels that execute ops[from..] assuming none overflows.
-int launch_ops(pp_state* s, const std::vector<Op>& ops, size_t from) {
-  const Ctx C = single_ctx(s);
-  auto launch = [&](int kind) {
-    const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
-    const int grid = launch_blocks(elems, items_of(kind));
-    hipEvent_t ev = prof_begin(s);
-    hipLaunchKernelGGL(kernel_of(kind), dim3(grid), dim3(kBlock), 0, s->stream, C);
-    prof_end(s, kind, ev);
-  };
-  for (size_t k = from; k < ops.size(); ++k) {
-    switch (ops[k].type) {
-      case OP_GATE:
-        launch(PP_K_GATE);
-        break;
-      case OP_MERGE:
-        if (s->group == PP_GROUP_NONE && !ops[k].force_full) {
-          launch(PP_K_COMPACT);
-        } else if (s->buf.narrow) {
-          launch(PP_K_MERGE_NARROW);
-          launch(PP_K_MERGE_COLLECT);
-        } else {
-          launch(PP_K_MERGE_WIDE1);
-          launch(PP_K_MERGE_WIDE2);
-          launch(PP_K_MERGE_COLLECT);
-        }
-        break;
-      default:
-        launch(PP_K_SCAN);
-        break;
+// Kernel kinds that execute one op of this handle.
+void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
+  switch (op.type) {
+    case OP_GATE:
+      out->push_back(PP_K_GATE);
+      break;
+    case OP_MERGE:
+      if (s->group == PP_GROUP_NONE && !op.force_full) {
+        out->push_back(PP_K_COMPACT);
+      } else if (s->buf.narrow) {
+        out->push_back(PP_K_MERGE_NARROW);
+        out->push_back(PP_K_MERGE_COLLECT);
+      } else {
+        out->push_back(PP_K_MERGE_WIDE1);
+        out->push_back(PP_K_MERGE_WIDE2);
+        out->push_back(PP_K_MERGE_COLLECT);
+      }
+      break;
+    default:
+      out->push_back(PP_K_SCAN);
+      break;
+  }
+}
+
+// Launches the single-instance kernels of ops [from, to) (op index k is a
+// launch argument: a launch whose op is not the current one does nothing,
+// so everything after an overflow is skipped on the device).
+int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
+  std::vector<int> kinds;
+  for (size_t k = from; k < to; ++k) {
+    kinds.clear();
+    kinds_of(s, ops[k], &kinds);
+    for (int kind : kinds) {
+      const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
+      const int grid = launch_blocks(elems, items_of(kind));
+      Solo S;
+      S.b = s->d_buf;
+      S.d = s->d_dyn;
+      S.sync = s->d_sync;
+      S.k = (uint32_t)k;
+      hipEvent_t ev = prof_begin(s, kind);
+      hipLaunchKernelGGL(solo_of(kind), dim3(grid), dim3(kBlock), 0, s->stream, S);
+      prof_end(s, kind, ev);
     }
   }
   HIP_TRY(hipGetLastError());
   return PP_OK;
+}
+
+int launch_ops(pp_state* s, const std::vector<Op>& ops, size_t from) {
+  return launch_range(s, ops.data(), from, ops.size());
 }
 
 // Uploads `ops` (and `tab`), runs them to completion, growing the store
@@ -551,6 +595,9 @@ void pp_destroy(pp_state* s) {
   }
   prof_resolve(s);
   for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
+  if (s->solo_slots) (void)hipHostFree(s->solo_slots);
+  for (auto e : s->solo_ev)
+    if (e) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -576,7 +623,7 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   s->W = W;
   s->group = group;
   s->stream = (hipStream_t)hip_stream;
-  s->prof = g_prof_default;
+  s->prof_every = g_prof_default;
   if (alloc) {
     s->alloc = *alloc;
     s->use_alloc = true;
@@ -662,17 +709,19 @@ int pp_work_counters(pp_state* s, uint64_t out[6]) {
   return PP_OK;
 }
 
-int pp_profile(pp_state* s, int enable) {
+int pp_profile(pp_state* s, int every) {
+  if (every < 0) return fail(PP_EINVAL, "every must be >= 0");
   if (!s) {
-    g_prof_default = enable != 0;
+    g_prof_default = every;
     return PP_OK;
   }
   int rc = read_dyn(s);
   if (rc) return rc;
-  s->prof = enable != 0;
+  s->prof_every = every;
   for (int k = 0; k < PP_KERNEL_KINDS; ++k) {
     s->prof_n[k] = 0;
     s->prof_ms[k] = 0.0;
+    s->prof_seen[k] = 0;
   }
   return PP_OK;
 }
@@ -1007,6 +1056,101 @@ int ensure_graph(BatchCtx* b) {
   return PP_OK;
 }
 
+// One instance through a whole program: the kernels of each sub-layer chunk
+// are launched ahead (at most two chunks in flight); after each chunk the
+// dynamic state is copied to pinned memory behind an event, so the host
+// learns of an overflow (or a merge retry) without draining the stream, and
+// only then synchronises, grows and relaunches from the op that stopped.
+int solo_program(pp_state* s, const pp_program* p, double* expectation) {
+  int rc;
+  const hipStream_t st = s->stream;
+  const Op* ops = p->ops.data();
+  const size_t len = p->ops.size();
+  s->buf.prog = p->d_ops;
+  s->buf.prog_len = (uint32_t)len;
+  s->batch_prog = p;
+  if ((rc = upload_buf(s))) return rc;
+  hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, st, s->d_dyn, 0u);
+  // chunk ends: after a MERGE (and the TRUNC that follows it), or the last op
+  std::vector<size_t> ends;
+  for (size_t k = 0; k < len; ++k) {
+    const bool merge_end = ops[k].type == OP_MERGE && !(k + 1 < len && ops[k + 1].type == OP_TRUNC);
+    if (merge_end || ops[k].type == OP_TRUNC || k + 1 == len) ends.push_back(k + 1);
+  }
+  if (!s->solo_slots) {
+    HIP_TRY(hipHostMalloc((void**)&s->solo_slots, sizeof(InstDyn) * 2, hipHostMallocDefault));
+    for (auto& e : s->solo_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  size_t next_chunk = 0, launched_to = 0;
+  std::vector<size_t> inflight;            // chunk indices, oldest first
+  for (int guard = 0; guard < 1 << 30; ++guard) {
+    while (inflight.size() < 2 && next_chunk < ends.size()) {
+      const size_t end = ends[next_chunk];
+      if ((rc = launch_range(s, ops, launched_to, end))) return rc;
+      const int slot = (int)(next_chunk & 1);
+      HIP_TRY(hipMemcpyAsync(&s->solo_slots[slot], s->d_dyn, sizeof(InstDyn),
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipEventRecord(s->solo_ev[slot], st));
+      inflight.push_back(next_chunk);
+      launched_to = end;
+      ++next_chunk;
+    }
+    if (inflight.empty()) break;
+    const size_t c = inflight.front();
+    inflight.erase(inflight.begin());
+    HIP_TRY(hipEventSynchronize(s->solo_ev[c & 1]));
+    const InstDyn dy = s->solo_slots[c & 1];
+    if (dy.status & ST_RANGE)
+      return fail(PP_EINVAL, "a coefficient is not finite or exceeds 2^54 in magnitude");
+    if (dy.pc >= ends[c]) {
+      if (dy.pc >= len && inflight.empty() && next_chunk >= ends.size()) {
+        *s->h_dyn = dy;
+        if (expectation) *expectation = dy.expect;
+        prof_resolve(s);
+        return PP_OK;
+      }
+      // grow ahead of time when the store is a third full, so that a gate
+      // rarely has to stop (and the launches queued behind it idle)
+      if ((uint64_t)dy.M * 3 > s->buf.cap && next_chunk < ends.size()) {
+        if ((rc = read_dyn(s))) return rc;
+        if (s->h_dyn->pc < len && !(s->h_dyn->status & ST_OVERFLOW) &&
+            (uint64_t)s->h_dyn->M * 3 > s->buf.cap) {
+          if ((rc = grow(s))) return rc;
+        }
+        inflight.clear();
+        if (s->h_dyn->status & ST_OVERFLOW) {
+          if ((rc = grow(s))) return rc;
+          s->h_dyn->status &= ~ST_OVERFLOW;
+          HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, st));
+        }
+        launched_to = s->h_dyn->pc;
+        next_chunk = 0;
+        while (next_chunk < ends.size() && ends[next_chunk] <= launched_to) ++next_chunk;
+        if (s->h_dyn->pc >= len) {
+          if (expectation) *expectation = s->h_dyn->expect;
+          prof_resolve(s);
+          return PP_OK;
+        }
+      }
+      continue;
+    }
+    // stopped inside chunk c: drain, grow if needed, resume at its pc
+    if ((rc = read_dyn(s))) return rc;
+    if (s->h_dyn->status & ST_OVERFLOW) {
+      if ((rc = grow(s))) return rc;
+      s->h_dyn->status &= ~ST_OVERFLOW;
+      HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                             hipMemcpyHostToDevice, st));
+    }
+    inflight.clear();
+    launched_to = s->h_dyn->pc;
+    next_chunk = 0;
+    while (next_chunk < ends.size() && ends[next_chunk] <= launched_to) ++next_chunk;
+  }
+  return fail(PP_EDEVICE, "program did not complete");
+}
+
 int batch_common(pp_state* const* states, const pp_program* const* programs, size_t n,
                  void* hip_stream, int max_replays, int* done, double* expectations) {
   if (!states || !programs) return fail(PP_EINVAL, "NULL argument");
@@ -1075,6 +1219,12 @@ extern "C" {
 
 int pp_batch_run(pp_state* const* states, const pp_program* const* programs, size_t n,
                  void* hip_stream, double* expectations) {
+  if (n == 1 && states && programs && states[0] && programs[0]) {
+    if (states[0]->stream != (hipStream_t)hip_stream)
+      return fail(PP_EINVAL, "state created on another stream");
+    if (states[0]->n != programs[0]->n) return fail(PP_EINVAL, "program n differs from state n");
+    return solo_program(states[0], programs[0], expectations);
+  }
   return batch_common(states, programs, n, hip_stream, -1, nullptr, expectations);
 }
 

@@ -275,20 +275,50 @@ __device__ inline uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Block-wide "am I the last working block of this launch" (threadfence
-// reduction over the `workers` blocks that had tiles).
-__device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers) {
+__device__ inline uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One atomic per block for both counts of the running kernel (called by
+// thread 0; the returned value is consumed so that the add has completed
+// before the block reports itself done).
+__device__ inline void add_acc(InstDyn& d, uint32_t live, uint32_t cnt) {
+  const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
+  if (v) {
+    const uint64_t old = atomicAdd((unsigned long long*)&d.acc, (unsigned long long)v);
+    __shared__ volatile uint64_t s_token;
+    s_token = old;
+  }
+}
+
+// live = low half, anticommuting count = high half; clears the accumulator.
+__device__ inline void take_acc(InstDyn& d) {
+  const uint64_t v = ld_agent(&d.acc);
+  d.live = (uint32_t)v;
+  d.count = (uint32_t)(v >> 32);
+  d.acc = 0;
+}
+
+// Block-wide "am I the last working block of this launch" over the
+// `workers` blocks that had tiles.  Within a launch, blocks hand results to
+// the last block only through device-scope atomics that thread 0 issued and
+// waited on (their returned values are consumed) before it increments the
+// done counter, and the last block reads them with agent-scope atomic loads,
+// so no fence is needed.  `fence` adds one for a last block that reads
+// plain stores of other blocks (the expectation's partial sums).
+__device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers,
+                                  bool fence = false) {
   if (workers <= 1) return true;       // block 0 did all the work itself
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    if (fence) __threadfence();
     const uint32_t t = atomicAdd(sync, 1u);
     *s_flag = (t == workers - 1) ? 1u : 0u;
     if (*s_flag) atomicExch(sync, 0u);
   }
   __syncthreads();
   const bool r = *s_flag != 0;
-  if (r) __threadfence();
+  if (r && fence) __threadfence();
   return r;
 }
 
@@ -633,35 +663,71 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
   const uint32_t bl = block_sum_u32(my_live, s_tmp);
   const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
   if (threadIdx.x == 0) {
-    if (bl) atomicAdd(&d.acc_live, bl);
-    if (bc) atomicAdd(&d.acc_count, bc);
+    add_acc(d, bl, bc);
   }
 }
 
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ uint32_t s_flag, s_base;
-  const int ninst = *C.ninst;
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    const InstBuf& b = *C.bufs[i];
-    const InstDyn& d = *C.dyns[i];
-    return gate_state(b, d) == 1 ? ceil_tiles<IT>(d.M) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int i = find_inst(s_pref, ninst, t);
-    gate_tile<IT>(*C.bufs[i], *C.dyns[i], t - s_pref[i], s_tmp, &s_base);
+// ---------------------------------------------------------------------------
+// Kernel kinds.  Each kind provides
+//   state(b, d)   0: instance not served by this kernel now, 1: run,
+//                 2: would overflow (gate only: mark and skip);
+//   elems(b, d)   number of elements the tiles cover;
+//   tile<IT>()    the work of one tile of kBlock * IT elements;
+//   finish()      run by every thread of the last block, per served
+//                 instance: fold the accumulators, advance pc.
+// run_multi serves a list of instances (batched form); run_solo serves one
+// instance whose current op index is a launch argument, so a captured
+// sequence of solo launches replays a fixed list of operations.
+// ---------------------------------------------------------------------------
+struct Smem {
+  uint32_t tmp[kWaves + 1];
+  uint32_t base;
+  uint32_t flag;
+  double dsum[kWaves];
+};
+
+struct Solo {
+  const InstBuf* b;
+  InstDyn* d;
+  uint32_t* sync;
+  uint32_t k;          // index of the op this launch executes
+};
+
+// next gate's Pauli string, for the anticommutation count that bounds the
+// next gate's appends
+struct NextGate {
+  bool has;
+  uint64_t x[kMaxW], z[kMaxW];
+  __device__ NextGate(const InstBuf& b, const Op& op) {
+    has = op.next_gate != kNone32;
+    if (has) {
+      const Op& nx = b.prog[op.next_gate];
+      for (int w = 0; w < b.W; ++w) { x[w] = nx.px[w]; z[w] = nx.pz[w]; }
+    }
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = threadIdx.x; i < ninst; i += kBlock) {
-    const InstBuf& b = *C.bufs[i];
-    InstDyn& d = *C.dyns[i];
-    const int st = gate_state(b, d);
-    if (st == 2) { d.status |= ST_OVERFLOW; d.failed_pc = d.pc; continue; }
-    if (st != 1) continue;
+  __device__ bool anti(const uint64_t* qx, const uint64_t* qz, int W) const {
+    return has && anticommutes(qx, qz, x, z, W);
+  }
+};
+
+__device__ inline void add_counts(InstDyn& d, uint32_t live, uint32_t cnt, Smem& sm) {
+  const uint32_t bl = block_sum_u32(live, sm.tmp);
+  const uint32_t bc = block_sum_u32(cnt, sm.tmp);
+  if (threadIdx.x == 0) {
+    add_acc(d, bl, bc);
+  }
+}
+
+struct GateKind {
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) { return gate_state(b, d); }
+  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
+    gate_tile<IT>(b, d, t, sm.tmp, &sm.base);
+  }
+  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x != 0) return;
     const Op& op = b.prog[d.pc];
     d.propagated += d.live;
     d.merged += (uint64_t)d.live + d.count;
@@ -670,18 +736,13 @@ __global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
     d.M = ld_agent(&d.Mnext);
     d.Mnext = d.M;
     d.parity ^= 1u;
-    d.live = ld_agent(&d.acc_live);
-    d.count = ld_agent(&d.acc_count);
+    take_acc(d);
     d.count_for = op.next_gate;
-    d.acc_live = 0;
-    d.acc_count = 0;
     d.pc += 1;
   }
-}
+};
 
-// ---------------------------------------------------------------------------
-// MERGE, narrow keys: one pass, representative -> hash table -> FP64 sums
-// ---------------------------------------------------------------------------
+// MERGE, narrow keys: one pass, representative -> hash table -> exact sums
 __device__ inline bool merge_served(const InstBuf& b, const InstDyn& d, bool narrow,
                                     uint32_t phase) {
   if (d.status & ST_OVERFLOW) return false;
@@ -691,26 +752,18 @@ __device__ inline bool merge_served(const InstBuf& b, const InstDyn& d, bool nar
   return (b.narrow != 0) == narrow && d.mphase == phase;
 }
 
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ uint32_t s_flag;
-  const int ninst = *C.ninst;
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return merge_served(*C.bufs[i], *C.dyns[i], true, 0) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int inst = find_inst(s_pref, ninst, t);
-    const InstBuf& b = *C.bufs[inst];
-    InstDyn& d = *C.dyns[inst];
+struct MergeNarrowKind {
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+    return merge_served(b, d, true, 0) ? 1 : 0;
+  }
+  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
     const View v = view_of(b, d);
-    const uint32_t tile = t - s_pref[inst];
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       const bool act = i < d.M && v.al[i];
       uint64_t key = 0;
       Fx c{0, 0, 0};
@@ -725,43 +778,31 @@ __global__ __launch_bounds__(kBlock) void k_merge_narrow(Ctx C) {
       wave_merge_add(b, d, act, key, c);
     }
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = threadIdx.x; i < ninst; i += kBlock) {
-    InstDyn& d = *C.dyns[i];
-    if (!merge_served(*C.bufs[i], d, true, 0)) continue;
+  __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x != 0) return;
     d.merged += d.live;
     d.mphase = 1;
   }
-}
+};
 
-// ---------------------------------------------------------------------------
-// MERGE, wide keys: (1) representative + 64-bit hash slot, (2) first record
-// of each slot owns it; every record compares its representative with the
-// owner's (a mismatch is a hash collision: the merge restarts with another
-// seed) and adds its coefficient.
-// ---------------------------------------------------------------------------
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ uint32_t s_flag;
-  const int ninst = *C.ninst;
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return merge_served(*C.bufs[i], *C.dyns[i], false, 0) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int inst = find_inst(s_pref, ninst, t);
-    const InstBuf& b = *C.bufs[inst];
-    InstDyn& d = *C.dyns[inst];
+// MERGE, wide keys: (1) representative + 64-bit hash slot, (2) the first
+// record of each slot owns it; every record compares its representative with
+// the owner's (a mismatch is a hash collision: the merge restarts with
+// another seed) and adds its coefficient.
+struct MergeWide1Kind {
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+    return merge_served(b, d, false, 0) ? 1 : 0;
+  }
+  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
     const View v = view_of(b, d);
-    const uint32_t tile = t - s_pref[inst];
     const int W = b.W;
     const uint64_t seed = d.seed;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (i >= d.M) continue;
       if (!v.al[i]) { b.wslot[i] = kNone32; continue; }
       uint64_t qx[kMaxW], qz[kMaxW], rx[kMaxW], rz[kMaxW];
@@ -776,36 +817,26 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide1(Ctx C) {
       b.wslot[i] = (uint32_t)mt_slot(b.mkey, b.hm_bits, h);
     }
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = threadIdx.x; i < ninst; i += kBlock) {
-    InstDyn& d = *C.dyns[i];
-    if (!merge_served(*C.bufs[i], d, false, 0)) continue;
+  __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x != 0) return;
     d.merged += d.live;
     d.mphase = 1;
   }
-}
+};
 
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_merge_wide2(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ uint32_t s_flag;
-  const int ninst = *C.ninst;
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return merge_served(*C.bufs[i], *C.dyns[i], false, 1) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int inst = find_inst(s_pref, ninst, t);
-    const InstBuf& b = *C.bufs[inst];
-    InstDyn& d = *C.dyns[inst];
+struct MergeWide2Kind {
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+    return merge_served(b, d, false, 1) ? 1 : 0;
+  }
+  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
     const View v = view_of(b, d);
-    const uint32_t tile = t - s_pref[inst];
     const int W = b.W;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (i >= d.M) continue;
       const uint32_t s = b.wslot[i];
       if (s == kNone32) continue;
@@ -824,13 +855,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_wide2(Ctx C) {
       }
     }
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = threadIdx.x; i < ninst; i += kBlock) {
-    InstDyn& d = *C.dyns[i];
-    if (!merge_served(*C.bufs[i], d, false, 1)) continue;
-    d.mphase = 2;
+  __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x == 0) d.mphase = 2;
   }
-}
+};
 
 // Writes one output term at the cursor position `pos` of the other half.
 __device__ inline void emit_term(const InstBuf& b, const InstDyn& d, uint32_t pos,
@@ -857,11 +885,8 @@ __device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
   d.half ^= 1u;
   d.parity = 0;
   d.gen += 1;
-  d.live = ld_agent(&d.acc_live);
-  d.count = ld_agent(&d.acc_count);
+  take_acc(d);
   d.count_for = op.next_gate;
-  d.acc_live = 0;
-  d.acc_count = 0;
   d.nuniq = 0;
   d.mphase = 0;
   d.pc += 1;
@@ -869,38 +894,18 @@ __device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
 
 // Collect: every occupied merge slot becomes one representative of the new
 // half; slots are cleared for the next merge.
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ uint32_t s_flag, s_base_v;
-  uint32_t* s_base = &s_base_v;
-  const int ninst = *C.ninst;
-  auto served = [&](int i) {
-    const InstBuf& b = *C.bufs[i];
-    const InstDyn& d = *C.dyns[i];
-    return merge_served(b, d, true, 1) || merge_served(b, d, false, 2);
-  };
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return served(i) ? ceil_tiles<IT>(1u << C.bufs[i]->hm_bits) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int inst = find_inst(s_pref, ninst, t);
-    const InstBuf& b = *C.bufs[inst];
-    InstDyn& d = *C.dyns[inst];
-    const uint32_t tile = t - s_pref[inst];
+struct CollectKind {
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+    return (merge_served(b, d, true, 1) || merge_served(b, d, false, 2)) ? 1 : 0;
+  }
+  __device__ static uint32_t elems(const InstBuf& b, const InstDyn&) { return 1u << b.hm_bits; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const bool collided = (d.status & ST_COLLISION) != 0;
     const uint32_t nslots = 1u << b.hm_bits;
     const int W = b.W;
-    const Op& op = b.prog[d.pc];
-    const bool has_next = op.next_gate != kNone32;
-    uint64_t nxm[kMaxW], nzm[kMaxW];
-    if (has_next) {
-      const Op& nx = b.prog[op.next_gate];
-      for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
-    }
+    const NextGate ng(b, b.prog[d.pc]);
     uint64_t ox[IT][kMaxW], oz[IT][kMaxW];
     double oc[IT];
     bool ov[IT];
@@ -908,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       ov[k] = false;
-      const uint32_t s = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t s = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (s >= nslots) continue;
       const uint64_t key = b.mkey[s];
       if (key == kEmpty64) continue;
@@ -926,7 +931,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
         oc[k] = fx_to_double(f);
         ov[k] = true;
         ++mine;
-        if (has_next && anticommutes(ox[k], oz[k], nxm, nzm, W)) ++my_cnt;
+        if (ng.anti(ox[k], oz[k], W)) ++my_cnt;
       }
       b.mkey[s] = kEmpty64;
       b.mfx[3 * (size_t)s] = 0;
@@ -935,10 +940,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
       if (!b.narrow) b.mown[s] = kNone32;
     }
     uint32_t tot;
-    uint32_t off = block_scan(mine, s_tmp, &tot);
-    if (threadIdx.x == 0) *s_base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    uint32_t off = block_scan(mine, sm.tmp, &tot);
+    if (threadIdx.x == 0) sm.base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
     __syncthreads();
-    const uint32_t base = *s_base;
+    const uint32_t base = sm.base;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       if (!ov[k]) continue;
@@ -946,17 +951,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
       if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
       emit_term(b, d, pos, ox[k], oz[k], oc[k]);
     }
-    const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
-    if (threadIdx.x == 0) {
-      if (tot) atomicAdd(&d.acc_live, tot);
-      if (bc) atomicAdd(&d.acc_count, bc);
-    }
+    add_counts(d, mine, my_cnt, sm);
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = threadIdx.x; i < ninst; i += kBlock) {
-    if (!served(i)) continue;
-    const InstBuf& b = *C.bufs[i];
-    InstDyn& d = *C.dyns[i];
+  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x != 0) return;
     if (d.status & ST_COLLISION) {     // retry this merge with another seed
       d.status &= ~ST_COLLISION;
       d.special = 0;
@@ -964,9 +962,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
       d.seed += 1;
       d.mphase = 0;
       d.nuniq = 0;
-      d.acc_live = 0;
-      d.acc_count = 0;
-      continue;
+      d.acc = 0;
+      return;
     }
     d.nuniq = ld_agent(&d.nuniq);
     if (d.special) {                   // narrow key equal to the empty marker
@@ -977,12 +974,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
         const Fx f{d.special_fx[0], d.special_fx[1], d.special_fx[2]};
         emit_term(b, d, pos, x, z, fx_to_double(f));
         d.nuniq = pos + 1;
-        d.acc_live += 1;
-        const Op& op = b.prog[d.pc];
-        if (op.next_gate != kNone32) {
-          const Op& nx = b.prog[op.next_gate];
-          if (anticommutes(x, z, nx.px, nx.pz, b.W)) d.acc_count += 1;
-        }
+        const NextGate ng(b, b.prog[d.pc]);
+        d.acc += 1ull + (ng.anti(x, z, b.W) ? (1ull << 32) : 0ull);
       } else {
         d.status |= ST_OVERFLOW;
       }
@@ -991,88 +984,62 @@ __global__ __launch_bounds__(kBlock) void k_merge_collect(Ctx C) {
     }
     finish_rebuild(b, d);
   }
-}
+};
 
-// ---------------------------------------------------------------------------
 // MERGE for plain PP: the set is already free of duplicates, so the merge
 // only drops dead entries (compaction into the other half).
-// ---------------------------------------------------------------------------
 __device__ inline bool compact_served(const InstBuf& b, const InstDyn& d) {
   if (d.status & ST_OVERFLOW) return false;
   const Op* op = cur_op(b, d);
   return op && op->type == OP_MERGE && b.group == 0 && !op->force_full;
 }
 
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_compact(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ uint32_t s_flag, s_base_v;
-  uint32_t* s_base = &s_base_v;
-  const int ninst = *C.ninst;
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return compact_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int inst = find_inst(s_pref, ninst, t);
-    const InstBuf& b = *C.bufs[inst];
-    InstDyn& d = *C.dyns[inst];
+struct CompactKind {
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+    return compact_served(b, d) ? 1 : 0;
+  }
+  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const View v = view_of(b, d);
-    const uint32_t tile = t - s_pref[inst];
     const int W = b.W;
-    const Op& op = b.prog[d.pc];
-    const bool has_next = op.next_gate != kNone32;
-    uint64_t nxm[kMaxW], nzm[kMaxW];
-    if (has_next) {
-      const Op& nx = b.prog[op.next_gate];
-      for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
-    }
+    const NextGate ng(b, b.prog[d.pc]);
     bool ov[IT];
     uint32_t mine = 0, my_cnt = 0;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       ov[k] = i < d.M && v.al[i];
       mine += ov[k] ? 1u : 0u;
     }
     uint32_t tot;
-    uint32_t off = block_scan(mine, s_tmp, &tot);
-    if (threadIdx.x == 0) *s_base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    uint32_t off = block_scan(mine, sm.tmp, &tot);
+    if (threadIdx.x == 0) sm.base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
     __syncthreads();
-    const uint32_t base = *s_base;
+    const uint32_t base = sm.base;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       if (!ov[k]) continue;
-      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       const uint32_t pos = base + off++;
       if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
       uint64_t x[kMaxW], z[kMaxW];
       load_key(v, i, x, z);
       emit_term(b, d, pos, x, z, v.C[i]);
-      if (has_next && anticommutes(x, z, nxm, nzm, W)) ++my_cnt;
+      if (ng.anti(x, z, W)) ++my_cnt;
     }
-    const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
-    if (threadIdx.x == 0) {
-      if (tot) atomicAdd(&d.acc_live, tot);
-      if (bc) atomicAdd(&d.acc_count, bc);
-    }
+    add_counts(d, mine, my_cnt, sm);
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = threadIdx.x; i < ninst; i += kBlock) {
-    const InstBuf& b = *C.bufs[i];
-    InstDyn& d = *C.dyns[i];
-    if (!compact_served(b, d)) continue;
+  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x != 0) return;
     d.merged += d.live;
     d.nuniq = ld_agent(&d.nuniq);
     finish_rebuild(b, d);
   }
-}
+};
 
-// ---------------------------------------------------------------------------
 // DAMP / TRUNC / COUNT / EXPECT: one streaming pass over the live terms
-// ---------------------------------------------------------------------------
 __device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
   if (d.status & ST_OVERFLOW) return false;
   const Op* op = cur_op(b, d);
@@ -1081,38 +1048,27 @@ __device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
          op->type == OP_EXPECT;
 }
 
-template <int IT>
-__global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
-  __shared__ uint32_t s_pref[kMaxInst];
-  __shared__ uint32_t s_tmp[kWaves + 1];
-  __shared__ double s_d[kWaves];
-  __shared__ uint32_t s_flag;
-  const int ninst = *C.ninst;
-  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
-    return scan_served(*C.bufs[i], *C.dyns[i]) ? ceil_tiles<IT>(C.dyns[i]->M) : 0u;
-  }, s_pref, s_tmp);
-  const uint32_t workers = worker_count(total);
-  if (blockIdx.x >= workers) return;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int inst = find_inst(s_pref, ninst, t);
-    const InstBuf& b = *C.bufs[inst];
-    InstDyn& d = *C.dyns[inst];
+struct ScanKind {
+  // the expectation's last block sums the other blocks' plain stores
+  __device__ static bool needs_fence(const InstBuf& b, const InstDyn& d) {
+    return b.prog[d.pc].type == OP_EXPECT;
+  }
+  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+    return scan_served(b, d) ? 1 : 0;
+  }
+  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const View v = view_of(b, d);
-    const uint32_t tile = t - s_pref[inst];
     const int W = b.W, n = b.n;
     const Op& op = b.prog[d.pc];
     const uint32_t type = op.type;
-    const bool has_next = op.next_gate != kNone32;
-    uint64_t nxm[kMaxW], nzm[kMaxW];
-    if (has_next) {
-      const Op& nx = b.prog[op.next_gate];
-      for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
-    }
+    const NextGate ng(b, op);
     uint32_t my_live = 0, my_cnt = 0;
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-      const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+      const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       if (i >= d.M || !v.al[i]) continue;
       uint64_t x[kMaxW], z[kMaxW];
       load_key(v, i, x, z);
@@ -1129,44 +1085,106 @@ __global__ __launch_bounds__(kBlock) void k_scan_op(Ctx C) {
         acc += c * op.table[nx] * op.table[(n + 1) + ny] * op.table[2 * (n + 1) + nz];
       }
       ++my_live;
-      if (has_next && anticommutes(x, z, nxm, nzm, W)) ++my_cnt;
+      if (ng.anti(x, z, W)) ++my_cnt;
     }
     if (type == OP_EXPECT) {
-      const double s = block_sum_f64(acc, s_d);
-      if (threadIdx.x == 0) b.partial[tile] = s;
+      const double s = block_sum_f64(acc, sm.dsum);
+      if (threadIdx.x == 0) b.partial[t] = s;
     }
-    const uint32_t bl = block_sum_u32(my_live, s_tmp);
-    const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
-    if (threadIdx.x == 0) {
-      if (bl) atomicAdd(&d.acc_live, bl);
-      if (bc) atomicAdd(&d.acc_count, bc);
-    }
+    add_counts(d, my_live, my_cnt, sm);
   }
-  if (!last_block(C.sync, &s_flag, workers)) return;
-  for (int i = 0; i < ninst; ++i) {            // whole block per instance
-    const InstBuf& b = *C.bufs[i];
-    InstDyn& d = *C.dyns[i];
-    if (!scan_served(b, d)) continue;          // uniform across the block
+  // whole block (the expectation's partials are summed in tile order)
+  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t tiles, Smem& sm) {
     const Op& op = b.prog[d.pc];
     if (op.type == OP_EXPECT) {
-      const uint32_t nt = ceil_tiles<IT>(d.M);
       double s = 0.0;
-      for (uint32_t t = threadIdx.x; t < nt; t += kBlock) s += b.partial[t];
-      s = block_sum_f64(s, s_d);
+      for (uint32_t t = threadIdx.x; t < tiles; t += kBlock) s += b.partial[t];
+      s = block_sum_f64(s, sm.dsum);
       if (threadIdx.x == 0) d.expect = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      d.live = ld_agent(&d.acc_live);
-      d.count = ld_agent(&d.acc_count);
+      take_acc(d);
       d.count_for = op.next_gate;
-      d.acc_live = 0;
-      d.acc_count = 0;
       d.pc += 1;
     }
     __syncthreads();
   }
+};
+
+// ---------------------------------------------------------------------------
+// runners
+// ---------------------------------------------------------------------------
+template <class K, int IT>
+__device__ inline void run_multi(const Ctx& C, Smem& sm, uint32_t* s_pref) {
+  const int ninst = *C.ninst;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    const InstBuf& b = *C.bufs[i];
+    const InstDyn& d = *C.dyns[i];
+    return K::state(b, d) == 1 ? ceil_tiles<IT>(K::elems(b, d)) : 0u;
+  }, s_pref, sm.tmp);
+  const uint32_t workers = worker_count(total);
+  if (blockIdx.x >= workers) return;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_inst(s_pref, ninst, t);
+    K::template tile<IT>(*C.bufs[i], *C.dyns[i], t - s_pref[i], sm);
+  }
+  if (!last_block(C.sync, &sm.flag, workers, true)) return;
+  for (int i = 0; i < ninst; ++i) {        // block-uniform loop
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    const int st = K::state(b, d);
+    const uint32_t tiles = ceil_tiles<IT>(K::elems(b, d));
+    __syncthreads();                       // all read the state before it changes
+    if (st == 2) {
+      if (threadIdx.x == 0) { d.status |= ST_OVERFLOW; d.failed_pc = d.pc; }
+      continue;
+    }
+    if (st != 1) continue;
+    K::finish(b, d, tiles, sm);
+    __syncthreads();
+  }
 }
+
+template <class K, int IT>
+__device__ inline void run_solo(const Solo& S, Smem& sm) {
+  const InstBuf& b = *S.b;
+  InstDyn& d = *S.d;
+  if (d.pc != S.k) return;                 // an earlier op did not complete
+  const int st = K::state(b, d);
+  if (st == 2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { d.status |= ST_OVERFLOW; d.failed_pc = d.pc; }
+    return;
+  }
+  if (st != 1) return;
+  const uint32_t tiles = ceil_tiles<IT>(K::elems(b, d));
+  const uint32_t workers = worker_count(tiles);
+  if (blockIdx.x >= workers) return;
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) K::template tile<IT>(b, d, t, sm);
+  if (!last_block(S.sync, &sm.flag, workers, K::needs_fence(b, d))) return;
+  K::finish(b, d, tiles, sm);
+}
+
+#define PP_KERNEL_PAIR(name, Kind)                                                    \
+  template <int IT>                                                                  \
+  __global__ __launch_bounds__(kBlock) void name(Ctx C) {                             \
+    __shared__ uint32_t s_pref[kMaxInst];                                            \
+    __shared__ Smem sm;                                                              \
+    run_multi<Kind, IT>(C, sm, s_pref);                                              \
+  }                                                                                  \
+  template <int IT>                                                                  \
+  __global__ __launch_bounds__(kBlock) void name##_solo(Solo S) {                     \
+    __shared__ Smem sm;                                                              \
+    run_solo<Kind, IT>(S, sm);                                                       \
+  }
+
+PP_KERNEL_PAIR(k_gate, GateKind)
+PP_KERNEL_PAIR(k_merge_narrow, MergeNarrowKind)
+PP_KERNEL_PAIR(k_merge_wide1, MergeWide1Kind)
+PP_KERNEL_PAIR(k_merge_wide2, MergeWide2Kind)
+PP_KERNEL_PAIR(k_merge_collect, CollectKind)
+PP_KERNEL_PAIR(k_compact, CompactKind)
+PP_KERNEL_PAIR(k_scan_op, ScanKind)
 
 // ---------------------------------------------------------------------------
 // Host-driven growth / compaction of one instance into a new store.

@@ -94,6 +94,7 @@ struct InstDyn {
   uint64_t appended;     // strings appended by gates
   uint64_t merge_in;     // records entering symmetry merges / compactions
   uint64_t merge_out;    // representatives leaving them
+  uint64_t acc;          // running kernel's counts: live | anticommuting << 32
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
   double expect;
   uint32_t M;            // entries in the current half (live and dead)
@@ -109,8 +110,6 @@ struct InstDyn {
   uint32_t nuniq;        // output cursor of a merge / compaction
   uint32_t mphase;       // merge progress: 0 none, 1 inserted, 2 owned (wide)
   uint32_t seed;         // wide-merge hash seed (bumped on a collision)
-  uint32_t acc_count;    // accumulators of the running kernel
-  uint32_t acc_live;
   uint32_t special;
   uint32_t failed_pc;
   uint32_t pad;

@@ -204,6 +204,31 @@ class DeviceProgram:
             pass
 
 
+def device_program(prog: Program) -> "DeviceProgram":
+    """The program uploaded once and cached on the Program object."""
+    dp = prog.meta.get("_dprog")
+    if dp is None or dp.h is None:
+        dp = DeviceProgram(prog)
+        prog.meta["_dprog"] = dp
+    return dp
+
+
+def propagate_program(prog: Program, group: str | None = None, stream: int = 0,
+                      allocator=None, keep_terms: bool = False) -> GpuResult:
+    """Algorithm 1 as one device program (pp_program + pp_batch_run with one
+    instance): all sub-layers are queued ahead and the host only checks the
+    device status between sub-layers."""
+    dp = device_program(prog)
+    t0 = time.perf_counter()
+    ps = PauliSet.from_program(prog, group, stream, allocator)
+    e = float(L.pp_batch_run([ps.h], [dp.h], stream)[0])
+    wall = time.perf_counter() - t0
+    prop, merged = ps.counters()
+    terms = ps.as_dict() if keep_terms else {}
+    ps.close()
+    return GpuResult(e, terms, prop, merged, [], wall)
+
+
 def batch_propagate(progs, stream: int, allocator=None, group=None):
     """All programs in one batched run; returns (expectations, handles)."""
     sets = [PauliSet.from_program(p, group, stream, allocator) for p in progs]

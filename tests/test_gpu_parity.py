@@ -231,3 +231,30 @@ def test_batch_matches_solo(gpu):
         s.close()
     for d in dprogs:
         d.close()
+
+
+def heisenberg_prefix(prog, k):
+    """The first k sub-layers in Heisenberg order = the last k in time."""
+    return W.Program(prog.name + f"[:{k}]", prog.n, prog.group, prog.obs,
+                     prog.sublayers[len(prog.sublayers) - k:], prog.bloch, dict(prog.meta))
+
+
+@pytest.mark.parametrize("which", ["c2", "c2plain", "c3", "z48"])
+def test_program_path_matches_oracle(gpu, which):
+    """One device program per propagation (pp_batch_run with one instance):
+    all sub-layers queued ahead, growth handled mid-program."""
+    from paper_2512_12094_amd import driver
+    if which == "c2":
+        prog, group = heisenberg_prefix(W.config2(), 12), None
+    elif which == "c2plain":
+        prog, group = heisenberg_prefix(W.config2(), 9), "none"
+    elif which == "c3":
+        prog, group = heisenberg_prefix(W.config3(), 2), None
+    else:
+        prog, group = W.xxz_ring(48, 2, 0.3, 1.4, eps=1e-6, obs=W.sum_ring_pairs(48, "X"),
+                                 bloch=W.random_bloch(48), name="z48"), None
+    print(f"[case] program {prog.name} group={group or prog.group}", flush=True)
+    res = driver.propagate_program(prog, group=group, stream=gpu["handle"],
+                                   allocator=gpu["alloc"], keep_terms=True)
+    ref = O.run_program(prog, group=group)
+    check(res, ref, prog, what=f"program {which}")

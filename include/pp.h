@@ -245,9 +245,13 @@ int pp_batch_run(pp_state* const* states, const pp_program* const* programs,
 /*
  * Incremental form for serving: advances every listed instance by up to
  * max_steps batched steps (graph replays) and sets done[i] = 1 for
- * instances whose program has finished (expectations[i] then valid).
- * Instances may join or leave between calls.  A state starts its program at
- * the first pp_batch_step/pp_batch_run call that lists it with that program.
+ * instances whose program has finished (expectations[i] then valid),
+ * 0 for running ones and -1 for one whose term store could not grow
+ * (allocator failure or pp_set_max_terms); a failed instance stops, the
+ * others continue, and the call still returns PP_OK.  Instances may join or
+ * leave between calls.  A state starts its program at the first
+ * pp_batch_step/pp_batch_run call that lists it with that program.
+ * pp_batch_run returns the first failure's code instead.
  */
 int pp_batch_step(pp_state* const* states, const pp_program* const* programs,
                   size_t n, void* hip_stream, int max_steps, int* done,
@@ -257,11 +261,13 @@ int pp_batch_step(pp_state* const* states, const pp_program* const* programs,
  * Launch tuning (process-wide; the autotuner picks it per workload class):
  * terms per thread of the gate kernel and of the streaming kernels (merge,
  * compaction, damping/truncation/expectation) in {1, 2, 4, 8}, the cap on
- * blocks per launch, and the batched steps per captured graph.  A 0 keeps
- * the current value.  pp_get_tuning returns the four current values.
+ * blocks per launch, the batched steps per captured graph, and the gate
+ * launches per batched step (1..64).  A 0 keeps the current value.
+ * pp_get_tuning returns the five current values in that order.
  */
-int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_steps);
-int pp_get_tuning(int out[4]);
+int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_steps,
+                  int gates_per_step);
+int pp_get_tuning(int out[5]);
 
 #ifdef __cplusplus
 }

@@ -78,7 +78,7 @@ def lib():
                                _f64p]
     L.pp_batch_step.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_size_t, _vp,
                                 ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p]
-    L.pp_set_tuning.argtypes = [ctypes.c_int] * 4
+    L.pp_set_tuning.argtypes = [ctypes.c_int] * 5
     L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     _lib = L
     return L
@@ -265,15 +265,18 @@ def pp_batch_step(states, programs, stream, max_steps):
     out = np.zeros(n, dtype=np.float64)
     _check(lib().pp_batch_step(S, P, n, _vp(stream), max_steps, done,
                                out.ctypes.data_as(_f64p)))
-    return np.array(list(done), dtype=bool), out
+    return np.array(list(done), dtype=np.int32), out
 
 
-def pp_set_tuning(gate_items=0, stream_items=0, max_blocks=0, graph_steps=0):
-    _check(lib().pp_set_tuning(gate_items, stream_items, max_blocks, graph_steps))
+TUNING_KEYS = ["gate_items", "stream_items", "max_blocks", "graph_steps", "gates_per_step"]
+
+
+def pp_set_tuning(gate_items=0, stream_items=0, max_blocks=0, graph_steps=0, gates_per_step=0):
+    _check(lib().pp_set_tuning(gate_items, stream_items, max_blocks, graph_steps,
+                               gates_per_step))
 
 
 def pp_get_tuning():
-    out = (ctypes.c_int * 4)()
+    out = (ctypes.c_int * 5)()
     _check(lib().pp_get_tuning(out))
-    return dict(gate_items=out[0], stream_items=out[1], max_blocks=out[2],
-                graph_steps=out[3])
+    return dict(zip(TUNING_KEYS, list(out)))

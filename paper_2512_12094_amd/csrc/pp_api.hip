@@ -37,6 +37,7 @@ struct Tuning {
   int stream_items = 1;   // terms per thread in merge / compaction / scan kernels
   int max_blocks = 2048;  // persistent grid cap
   int graph_steps = 32;   // batched steps per captured graph
+  int gates_per_step = 4; // gate launches per batched step
 };
 Tuning g_tune;
 int g_prof_default = 0;   // pp_profile(NULL, every): new handles start timed
@@ -84,6 +85,7 @@ struct pp_state {
   size_t tab_cap = 0;
   InstDyn* h_dyn = nullptr;            // pinned
   const pp_program* batch_prog = nullptr;
+  int fail_code = PP_OK;               // why a batched instance stopped
   InstDyn* solo_slots = nullptr;       // pinned status slots of solo_program
   hipEvent_t solo_ev[2] = {nullptr, nullptr};
   // pinned staging ring for program uploads of calls that do not sync
@@ -204,6 +206,11 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   nb.cap = cap;
   nb.hg_bits = std::max<uint32_t>(10, ceil_log2(2ull * cap));
   nb.hm_bits = nb.hg_bits;
+  if (s->group == PP_GROUP_PERMUTATION) {
+    // a permutation merge has at most binom(n+3, 3) representatives
+    const uint64_t reps = (uint64_t)(s->n + 3) * (s->n + 2) * (s->n + 1) / 6;
+    nb.hm_bits = std::min(nb.hm_bits, std::max<uint32_t>(10, ceil_log2(2 * reps)));
+  }
   const size_t ng = size_t(1) << nb.hg_bits, nm = size_t(1) << nb.hm_bits;
   std::vector<void*> got;
   auto take = [&](size_t bytes) -> void* {
@@ -230,7 +237,6 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
     ok = ok && (nb.wrep = (uint64_t*)take(sizeof(uint64_t) * 2 * W * cap));
     ok = ok && (nb.wslot = (uint32_t*)take(sizeof(uint32_t) * cap));
   }
-  ok = ok && (nb.partial = (double*)take(sizeof(double) * ((cap + kBlock - 1) / kBlock + 1)));
   if (!ok) {
     for (void* p : got) dev_free(s, p);
     return fail(PP_ENOMEM, "allocation of a term store of capacity " + std::to_string(cap) +
@@ -298,8 +304,11 @@ int items_of(int kind) { return kind == PP_K_GATE ? g_tune.gate_items : g_tune.s
 int grow(pp_state* s) {
   const InstDyn& d = *s->h_dyn;
   const uint64_t need = (uint64_t)d.live + d.count;
-  // same capacity (a compaction) when the live terms leave enough room
-  uint64_t cap = std::max<uint64_t>({(uint64_t)s->buf.cap, 4 * need, 4096});
+  // same capacity (a compaction) when the live terms leave enough room;
+  // the headroom shrinks from 4x to 1.5x for very large sets
+  const uint64_t head = need < (1ull << 24) ? 4 * need : need < (1ull << 27) ? 2 * need
+                                                                            : need * 3 / 2;
+  uint64_t cap = std::max<uint64_t>({(uint64_t)s->buf.cap, head, 4096});
   if (cap > 0xFFFFFFF0ull) cap = 0xFFFFFFF0ull;
   if (s->max_terms && cap > s->max_terms) cap = s->max_terms;
   if (cap < need + 1)
@@ -555,24 +564,28 @@ extern "C" {
 
 const char* pp_last_error(void) { return g_err.c_str(); }
 
-int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_steps) {
+int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_steps,
+                  int gates_per_step) {
   auto ok_items = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
   if (!ok_items(gate_items) || !ok_items(stream_items))
     return fail(PP_EINVAL, "items per thread must be 0 (keep), 1, 2, 4 or 8");
-  if (max_blocks < 0 || graph_steps < 0) return fail(PP_EINVAL, "negative tuning value");
+  if (max_blocks < 0 || graph_steps < 0 || gates_per_step < 0 || gates_per_step > 64)
+    return fail(PP_EINVAL, "tuning value out of range");
   if (gate_items) g_tune.gate_items = gate_items;
   if (stream_items) g_tune.stream_items = stream_items;
   if (max_blocks) g_tune.max_blocks = max_blocks;
   if (graph_steps) g_tune.graph_steps = graph_steps;
+  if (gates_per_step) g_tune.gates_per_step = gates_per_step;
   return PP_OK;
 }
 
-int pp_get_tuning(int out[4]) {
+int pp_get_tuning(int out[5]) {
   if (!out) return fail(PP_EINVAL, "NULL argument");
   out[0] = g_tune.gate_items;
   out[1] = g_tune.stream_items;
   out[2] = g_tune.max_blocks;
   out[3] = g_tune.graph_steps;
+  out[4] = g_tune.gates_per_step;
   return PP_OK;
 }
 
@@ -994,7 +1007,7 @@ struct BatchCtx {
   const InstBuf** h_bufp = nullptr;
   InstDyn** h_dynp = nullptr;
   hipGraphExec_t exec = nullptr;
-  int exec_steps = 0, exec_blocks = 0;
+  int exec_steps = 0, exec_blocks = 0, exec_sig = 0;
 };
 
 std::mutex g_batch_mu;
@@ -1025,6 +1038,10 @@ int batch_ctx(hipStream_t stream, BatchCtx** out) {
   return PP_OK;
 }
 
+// One batched step: every instance inside a layer advances up to
+// gates_per_step gates, then merges, compactions and the streaming ops run
+// for the instances that reached them (two scans: truncation, then the
+// next layer's damping).
 void launch_step(BatchCtx* b, int blocks) {
   Ctx C;
   C.bufs = b->d_bufp;
@@ -1032,14 +1049,18 @@ void launch_step(BatchCtx* b, int blocks) {
   C.ninst = b->d_ninst;
   C.sync = b->d_sync;
   const dim3 g(blocks), t(kBlock);
-  for (int kind : {PP_K_GATE, PP_K_MERGE_NARROW, PP_K_MERGE_WIDE1, PP_K_MERGE_WIDE2,
-                   PP_K_MERGE_COLLECT, PP_K_COMPACT, PP_K_SCAN})
+  for (int k = 0; k < std::max(1, g_tune.gates_per_step); ++k)
+    hipLaunchKernelGGL(kernel_of(PP_K_GATE), g, t, 0, b->stream, C);
+  for (int kind : {PP_K_MERGE_NARROW, PP_K_MERGE_WIDE1, PP_K_MERGE_WIDE2, PP_K_MERGE_COLLECT,
+                   PP_K_COMPACT, PP_K_SCAN, PP_K_SCAN})
     hipLaunchKernelGGL(kernel_of(kind), g, t, 0, b->stream, C);
 }
 
 int ensure_graph(BatchCtx* b) {
   const int steps = std::max(1, g_tune.graph_steps), blocks = g_tune.max_blocks;
-  if (b->exec && b->exec_steps == steps && b->exec_blocks == blocks) return PP_OK;
+  const int sig = g_tune.gates_per_step * 1000003 + g_tune.gate_items * 101 + g_tune.stream_items;
+  if (b->exec && b->exec_steps == steps && b->exec_blocks == blocks && b->exec_sig == sig)
+    return PP_OK;
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -1053,6 +1074,7 @@ int ensure_graph(BatchCtx* b) {
   if (e != hipSuccess) return fail(PP_EDEVICE, std::string("graph: ") + hipGetErrorString(e));
   b->exec_steps = steps;
   b->exec_blocks = blocks;
+  b->exec_sig = sig;
   return PP_OK;
 }
 
@@ -1170,6 +1192,7 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
   for (size_t i = 0; i < n; ++i) {
     pp_state* s = states[i];
     if (s->batch_prog != programs[i]) {
+      if (s->h_dyn->status & ST_FAILED) return fail(PP_EINVAL, "state failed in an earlier batch");
       s->buf.prog = programs[i]->d_ops;
       s->buf.prog_len = (uint32_t)programs[i]->ops.size();
       s->batch_prog = programs[i];
@@ -1195,21 +1218,41 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
     for (size_t i = 0; i < n; ++i) {
       pp_state* s = states[i];
       *s->h_dyn = b->h_gather[i];
-      if (s->h_dyn->status & ST_OVERFLOW) {
-        if ((rc = grow(s))) return rc;
-        s->h_dyn->status &= ~ST_OVERFLOW;
+      if (s->h_dyn->status & ST_FAILED) continue;
+      if ((s->h_dyn->status & ST_OVERFLOW)) {
+        // an instance that cannot grow stops (kernels keep skipping it);
+        // the others go on
+        const int g = grow(s);
+        s->h_dyn->status = g ? (s->h_dyn->status | ST_FAILED) : (s->h_dyn->status & ~ST_OVERFLOW);
         HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
                                hipMemcpyHostToDevice, stream));
+        if (g) {
+          s->fail_code = g;
+          continue;
+        }
+      }
+      if (s->h_dyn->status & ST_RANGE) {
+        s->h_dyn->status |= ST_FAILED | ST_OVERFLOW;
+        s->fail_code = PP_EINVAL;
+        HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                               hipMemcpyHostToDevice, stream));
+        continue;
       }
       all_done = all_done && s->h_dyn->pc >= s->buf.prog_len;
     }
     if (all_done) break;
   }
+  int first_fail = PP_OK;
   for (size_t i = 0; i < n; ++i) {
-    const bool fin = states[i]->h_dyn->pc >= states[i]->buf.prog_len;
-    if (done) done[i] = fin ? 1 : 0;
-    if (expectations && fin) expectations[i] = states[i]->h_dyn->expect;
+    const InstDyn& d = *states[i]->h_dyn;
+    const bool failed = (d.status & ST_FAILED) != 0;
+    const bool fin = !failed && d.pc >= states[i]->buf.prog_len;
+    if (done) done[i] = failed ? -1 : (fin ? 1 : 0);
+    if (expectations && fin) expectations[i] = d.expect;
+    if (failed && first_fail == PP_OK) first_fail = states[i]->fail_code;
   }
+  if (first_fail != PP_OK && !done)
+    return fail(first_fail, "an instance of the batch could not grow its term store");
   return PP_OK;
 }
 

@@ -258,18 +258,9 @@ __device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
   return t;
 }
 
-// Fixed-order block sum of doubles (deterministic for a given assignment).
-__device__ inline double block_sum_f64(double v, double* s_d) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) s_d[wid] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kWaves; ++w) r += s_d[w];
-  __syncthreads();
-  return r;   // valid in thread 0
-}
+// Makes the wave wait for a returned value (an atomic's result) before it
+// issues anything after this point; emits no instruction of its own.
+__device__ inline void consume(uint64_t v) { asm volatile("" : : "v"(v)); }
 
 __device__ inline uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -285,9 +276,7 @@ __device__ inline uint64_t ld_agent(const uint64_t* p) {
 __device__ inline void add_acc(InstDyn& d, uint32_t live, uint32_t cnt) {
   const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
   if (v) {
-    const uint64_t old = atomicAdd((unsigned long long*)&d.acc, (unsigned long long)v);
-    __shared__ volatile uint64_t s_token;
-    s_token = old;
+    consume(atomicAdd((unsigned long long*)&d.acc, (unsigned long long)v));
   }
 }
 
@@ -305,7 +294,7 @@ __device__ inline void take_acc(InstDyn& d) {
 // waited on (their returned values are consumed) before it increments the
 // done counter, and the last block reads them with agent-scope atomic loads,
 // so no fence is needed.  `fence` adds one for a last block that reads
-// plain stores of other blocks (the expectation's partial sums).
+// plain stores of other blocks (the multi-instance runner keeps it).
 __device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers,
                                   bool fence = false) {
   if (workers <= 1) return true;       // block 0 did all the work itself
@@ -441,6 +430,19 @@ __device__ inline void fx_atomic_add(uint64_t* acc, Fx v) {
   }
   const uint64_t t2 = v.l2 + c1;
   if (t2) atomicAdd(&a[2], (unsigned long long)t2);
+}
+
+// As fx_atomic_add, but every limb's atomic returns and the last value is
+// consumed, so the whole addition has completed when this returns.
+__device__ inline void fx_atomic_add_wait(uint64_t* acc, Fx v) {
+  unsigned long long* a = (unsigned long long*)acc;
+  const uint64_t o0 = atomicAdd(&a[0], (unsigned long long)v.l0);
+  const uint64_t c0 = (o0 + v.l0 < o0) ? 1u : 0u;
+  const uint64_t t1 = v.l1 + c0;
+  uint64_t c1 = (t1 < c0) ? 1u : 0u;
+  const uint64_t o1 = atomicAdd(&a[1], (unsigned long long)t1);
+  c1 += (o1 + t1 < o1) ? 1u : 0u;
+  consume(atomicAdd(&a[2], (unsigned long long)(v.l2 + c1)));
 }
 
 __device__ inline Fx wave_sum_fx(Fx v) {
@@ -683,7 +685,7 @@ struct Smem {
   uint32_t tmp[kWaves + 1];
   uint32_t base;
   uint32_t flag;
-  double dsum[kWaves];
+  uint64_t wfx[kWaves][3];
 };
 
 struct Solo {
@@ -1049,10 +1051,7 @@ __device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
 }
 
 struct ScanKind {
-  // the expectation's last block sums the other blocks' plain stores
-  __device__ static bool needs_fence(const InstBuf& b, const InstDyn& d) {
-    return b.prog[d.pc].type == OP_EXPECT;
-  }
+  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
   __device__ static int state(const InstBuf& b, const InstDyn& d) {
     return scan_served(b, d) ? 1 : 0;
   }
@@ -1065,7 +1064,8 @@ struct ScanKind {
     const uint32_t type = op.type;
     const NextGate ng(b, op);
     uint32_t my_live = 0, my_cnt = 0;
-    double acc = 0.0;
+    Fx acc{0, 0, 0};
+    bool range = false;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
@@ -1082,33 +1082,40 @@ struct ScanKind {
       } else if (type == OP_EXPECT) {
         uint32_t nx, ny, nz;
         perm_counts(x, z, W, &nx, &ny, &nz);
-        acc += c * op.table[nx] * op.table[(n + 1) + ny] * op.table[2 * (n + 1) + nz];
+        const double term =
+            c * op.table[nx] * op.table[(n + 1) + ny] * op.table[2 * (n + 1) + nz];
+        acc = fx_add(acc, fx_from_double(term, &range));
       }
       ++my_live;
       if (ng.anti(x, z, W)) ++my_cnt;
     }
-    if (type == OP_EXPECT) {
-      const double s = block_sum_f64(acc, sm.dsum);
-      if (threadIdx.x == 0) b.partial[t] = s;
+    if (type == OP_EXPECT) {          // exact sum: integer limbs, any order
+      if (range) atomicOr(&d.status, ST_RANGE);
+      const Fx w = wave_sum_fx(acc);
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+      if (lane == 0) { sm.wfx[wid][0] = w.l0; sm.wfx[wid][1] = w.l1; sm.wfx[wid][2] = w.l2; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        Fx s{0, 0, 0};
+        for (int q = 0; q < kWaves; ++q) s = fx_add(s, Fx{sm.wfx[q][0], sm.wfx[q][1], sm.wfx[q][2]});
+        if (s.l0 | s.l1 | s.l2) fx_atomic_add_wait(d.expect_fx, s);
+      }
+      __syncthreads();
     }
     add_counts(d, my_live, my_cnt, sm);
   }
-  // whole block (the expectation's partials are summed in tile order)
-  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t tiles, Smem& sm) {
+  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+    if (threadIdx.x != 0) return;
     const Op& op = b.prog[d.pc];
     if (op.type == OP_EXPECT) {
-      double s = 0.0;
-      for (uint32_t t = threadIdx.x; t < tiles; t += kBlock) s += b.partial[t];
-      s = block_sum_f64(s, sm.dsum);
-      if (threadIdx.x == 0) d.expect = s;
+      const Fx f{ld_agent(&d.expect_fx[0]), ld_agent(&d.expect_fx[1]),
+                 ld_agent(&d.expect_fx[2])};
+      d.expect = fx_to_double(f);
+      d.expect_fx[0] = d.expect_fx[1] = d.expect_fx[2] = 0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      take_acc(d);
-      d.count_for = op.next_gate;
-      d.pc += 1;
-    }
-    __syncthreads();
+    take_acc(d);
+    d.count_for = op.next_gate;
+    d.pc += 1;
   }
 };
 

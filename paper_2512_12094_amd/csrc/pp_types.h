@@ -44,7 +44,7 @@ enum OpType : uint32_t {
   OP_EXPECT = 6,   // expectation in a symmetric product state
 };
 
-enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u };
+enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u, ST_FAILED = 8u };
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
@@ -75,7 +75,6 @@ struct InstBuf {
   uint32_t* mown;
   uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
   uint32_t* wslot;
-  double* partial;       // EXPECT partial sums, one per tile
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;
@@ -96,7 +95,8 @@ struct InstDyn {
   uint64_t merge_out;    // representatives leaving them
   uint64_t acc;          // running kernel's counts: live | anticommuting << 32
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
-  double expect;
+  uint64_t expect_fx[3];    // exact expectation accumulator
+ double expect;
   uint32_t M;            // entries in the current half (live and dead)
   uint32_t Mnext;        // append cursor while a gate runs
   uint32_t half;

@@ -1,0 +1,197 @@
+"""Served form: continuous batching of propagation jobs on one GPU.
+
+Jobs (a `workloads.Program` each, with an arrival time) enter a FIFO queue.
+Every iteration of the event loop
+
+1. moves the jobs that have arrived into the waiting queue;
+2. admits waiting jobs in order while their estimated memory (estimated
+   peak terms x bytes per stored term) fits the HBM budget and a batch slot
+   is free: the job's handle is created (Algorithm 1 step 1 on the device)
+   and its program uploaded; its Pauli set then stays on the device;
+3. advances every admitted job together by a few batched steps
+   (pp_batch_step: one persistent launch per kernel kind serves all jobs);
+4. retires finished jobs (expectation, latency = finish - arrival) and frees
+   their memory; a job whose store outgrew its estimate is re-queued with a
+   doubled estimate (it restarts from its observable, nothing is reused).
+
+Jobs that arrive while others run join at the next iteration.  The GPU work
+goes through an engine object so the policy can be exercised on the CPU with
+a fake engine (tests/test_serve.py).
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .workloads import Program, n_words
+
+# bytes of device memory per unit of store capacity (both halves of x, z, c,
+# four alive arrays, gate table, merge table with 3-limb sums, partials)
+_BYTES_PER_SLOT = {1: 2 * (8 + 8 + 8) + 4 + 2 * 8 + 2 * (8 + 24) + 1,
+                   2: 2 * (16 + 16 + 8) + 4 + 2 * 8 + 2 * (8 + 24 + 4) + 4 * 8 + 4 + 1}
+
+
+def bytes_per_term(n: int) -> int:
+    """Device bytes per stored term, with the store's 4x growth headroom."""
+    return 4 * _BYTES_PER_SLOT[min(2, n_words(n))]
+
+
+@dataclass
+class JobResult:
+    name: str
+    arrival: float
+    admitted: float = math.nan
+    finished: float = math.nan
+    expectation: float = math.nan
+    units: int = 0                # propagated + merged terms
+    retries: int = 0
+    est_terms: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Estimator:
+    """Peak stored terms of a job, by class (group, n, eps decade), learned
+    from finished jobs (largest seen x 2), with a prior for unseen classes;
+    never above the store limit `cap_terms`."""
+
+    def __init__(self, prior: int = 1 << 16, cap_terms: int = 1 << 28):
+        self.prior, self.cap_terms = prior, cap_terms
+        self.seen: dict = {}
+
+    @staticmethod
+    def key(prog: Program):
+        eps = prog.meta.get("eps", 0.0) or 1e-16
+        return (prog.group, prog.n, int(math.floor(math.log10(eps))))
+
+    def estimate(self, prog: Program) -> int:
+        v = self.seen.get(self.key(prog))
+        return min(self.cap_terms, 2 * v if v else self.prior)
+
+    def observe(self, prog: Program, peak_terms: int):
+        k = self.key(prog)
+        self.seen[k] = max(self.seen.get(k, 0), int(peak_terms))
+
+
+class GpuEngine:
+    """The device side: one handle and one uploaded program per job."""
+
+    def __init__(self, stream: int, allocator=None, steps_per_iter: int = 32):
+        from . import _lib as L
+        from . import driver
+        self.L, self.driver = L, driver
+        self.stream, self.allocator = stream, allocator
+        self.steps_per_iter = steps_per_iter
+
+    def start(self, job_prog: Program, max_terms: int):
+        ps = self.driver.PauliSet.from_program(job_prog, None, self.stream, self.allocator)
+        self.L.pp_set_max_terms(ps.h, max_terms)
+        dp = self.driver.device_program(job_prog)
+        return (ps, dp)
+
+    def step(self, handles):
+        done, e = self.L.pp_batch_step([h[0].h for h in handles], [h[1].h for h in handles],
+                                       self.stream, self.steps_per_iter)
+        return done, e
+
+    def finish(self, handle):
+        ps, _ = handle
+        wc = self.L.pp_work_counters(ps.h)
+        units = wc["propagated"] + wc["merged"]
+        peak = max(wc["merge_in"], 1)
+        ps.close()
+        return units, peak
+
+    def abort(self, handle):
+        handle[0].close()
+
+
+@dataclass
+class Server:
+    engine: object
+    hbm_budget: float                      # bytes available to job stores
+    max_active: int = 256
+    estimator: Estimator = field(default_factory=Estimator)
+    clock: object = time.perf_counter
+    sleep: object = time.sleep
+    max_retries: int = 6
+
+    def run(self, jobs, on_event=None):
+        """Serves `jobs` (objects with .arrival and .program); returns
+        JobResult per job in input order."""
+        order = sorted(range(len(jobs)), key=lambda i: jobs[i].arrival)
+        pending = deque(order)
+        waiting = deque()
+        active = []                       # (index, handle, bytes, est)
+        results = [JobResult(getattr(j.program, "name", str(i)), j.arrival)
+                   for i, j in enumerate(jobs)]
+        used = 0.0
+        self.peak_used = 0.0
+        t0 = self.clock()
+        while pending or waiting or active:
+            now = self.clock() - t0
+            while pending and jobs[pending[0]].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission, in arrival order
+            while waiting and len(active) < self.max_active:
+                i = waiting[0]
+                prog = jobs[i].program
+                est = max(results[i].est_terms, self.estimator.estimate(prog))
+                need = est * bytes_per_term(prog.n)
+                if active and used + need > self.hbm_budget:
+                    break
+                waiting.popleft()
+                results[i].est_terms = est
+                results[i].admitted = self.clock() - t0
+                handle = self.engine.start(prog, 4 * est)
+                active.append((i, handle, need, est))
+                used += need
+                self.peak_used = max(self.peak_used, used)
+                if on_event:
+                    on_event("admit", i, used)
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, jobs[pending[0]].arrival - (self.clock() - t0)))
+                continue
+            done, e = self.engine.step([a[1] for a in active])
+            now = self.clock() - t0
+            keep = []
+            for (i, handle, need, est), dn, ei in zip(active, done, e):
+                if dn == 1:
+                    units, peak = self.engine.finish(handle)
+                    r = results[i]
+                    r.finished, r.expectation, r.units = now, float(ei), units
+                    self.estimator.observe(jobs[i].program, peak)
+                    used -= need
+                    if on_event:
+                        on_event("finish", i, used)
+                elif dn < 0:              # outgrew its estimate: restart, larger
+                    self.engine.abort(handle)
+                    used -= need
+                    r = results[i]
+                    r.retries += 1
+                    if r.retries > self.max_retries:
+                        raise RuntimeError(f"job {r.name} does not fit after {r.retries} tries")
+                    r.est_terms = 2 * est
+                    waiting.appendleft(i)
+                    if on_event:
+                        on_event("requeue", i, used)
+                else:
+                    keep.append((i, handle, need, est))
+            active = keep
+        return results
+
+
+def summarize(results, wall: float) -> dict:
+    lat = np.array([r.latency for r in results])
+    units = sum(r.units for r in results)
+    return dict(jobs=len(results), p50_s=float(np.percentile(lat, 50)),
+                p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
+                terms_per_s=units / wall if wall > 0 else float("nan"), wall_s=wall,
+                retries=int(sum(r.retries for r in results)))

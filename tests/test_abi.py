@@ -51,5 +51,6 @@ def test_argument_errors_need_no_gpu():
     assert b"unsupported" in L.pp_last_error()
     assert L.pp_create(ctypes.byref(h), 65, 1, 0, None, None, None, 0, None, None) == -1
     assert L.pp_create(ctypes.byref(h), 8, 1, 7, None, None, None, 0, None, None) == -1
-    assert L.pp_set_tuning(3, 0, 0, 0) == -1
-    assert L.pp_set_tuning(0, 16, 0, 0) == -1
+    assert L.pp_set_tuning(3, 0, 0, 0, 0) == -1
+    assert L.pp_set_tuning(0, 16, 0, 0, 0) == -1
+    assert L.pp_set_tuning(0, 0, 0, 0, 65) == -1

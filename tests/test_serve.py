@@ -1,0 +1,120 @@
+"""Serving policy on the CPU with a fake engine and a fake clock: admission
+never exceeds the memory budget, jobs that arrive later join while others
+run, a job that outgrows its estimate is re-queued with a doubled estimate,
+latency is finish - arrival."""
+from dataclasses import dataclass
+
+from paper_2512_12094_amd import serve, workloads as W
+
+
+@dataclass
+class FakeJob:
+    arrival: float
+    program: object
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-3)
+
+
+class FakeEngine:
+    """A job needs `work` steps; it fails (outgrows its store) when its true
+    peak exceeds the store limit it was started with."""
+
+    def __init__(self, clock, work, peak, step_time=0.01):
+        self.clock, self.work, self.peak, self.step_time = clock, work, peak, step_time
+        self.started = []
+
+    def start(self, prog, max_terms):
+        h = dict(name=prog.name, left=self.work[prog.name], max_terms=max_terms)
+        self.started.append((prog.name, max_terms))
+        return h
+
+    def step(self, handles):
+        self.clock.t += self.step_time
+        done, e = [], []
+        for h in handles:
+            if self.peak[h["name"]] > h["max_terms"]:
+                done.append(-1)
+            else:
+                h["left"] -= 1
+                done.append(1 if h["left"] <= 0 else 0)
+            e.append(float(len(h["name"])))
+        return done, e
+
+    def finish(self, h):
+        return 100, self.peak[h["name"]]
+
+    def abort(self, h):
+        pass
+
+
+def make_jobs(k, gap=0.005):
+    jobs = []
+    for i in range(k):
+        p = W.xxz_ring(16, 1, 0.1, 1.0, eps=1e-4, name=f"j{i}")
+        jobs.append(FakeJob(i * gap, p))
+    return jobs
+
+
+def test_budget_is_never_exceeded_and_jobs_overlap():
+    clock = FakeClock()
+    jobs = make_jobs(20)
+    eng = FakeEngine(clock, {j.program.name: 5 for j in jobs},
+                     {j.program.name: 1000 for j in jobs})
+    budget = 3.5 * (1 << 16) * serve.bytes_per_term(16)   # room for 3 jobs
+    events = []
+    srv = serve.Server(eng, budget, clock=clock, sleep=clock.sleep)
+    res = srv.run(jobs, on_event=lambda kind, i, used: events.append((kind, i, used)))
+    assert all(r.finished >= r.arrival for r in res)
+    assert srv.peak_used <= budget
+    # continuous batching: a job admitted while another was active
+    active, overlapped = set(), False
+    for kind, i, used in events:
+        if kind == "admit":
+            overlapped |= bool(active)
+            active.add(i)
+        elif kind == "finish":
+            active.discard(i)
+    assert overlapped
+    # FIFO admission
+    admits = [i for kind, i, _ in events if kind == "admit"]
+    assert admits == sorted(admits)
+
+
+def test_underestimate_is_requeued_with_doubled_estimate():
+    clock = FakeClock()
+    jobs = make_jobs(3)
+    big = jobs[1].program.name
+    peak = {j.program.name: 10 for j in jobs}
+    peak[big] = 3 * 4 * (1 << 16)          # beyond the prior's store limit
+    eng = FakeEngine(clock, {j.program.name: 3 for j in jobs}, peak)
+    srv = serve.Server(eng, 1e15, clock=clock, sleep=clock.sleep)
+    res = srv.run(jobs)
+    assert res[1].retries == 2
+    starts = [m for name, m in eng.started if name == big]
+    assert starts == [4 * (1 << 16), 8 * (1 << 16), 16 * (1 << 16)]
+    assert all(r.finished > 0 for r in res)
+
+
+def test_estimator_learns_from_finished_jobs():
+    est = serve.Estimator(prior=100)
+    p = W.xxz_ring(16, 1, 0.1, 1.0, eps=1e-4)
+    assert est.estimate(p) == 100
+    est.observe(p, 700)
+    assert est.estimate(p) == 1400
+
+
+def test_summary():
+    rs = [serve.JobResult("a", 0.0, finished=1.0, units=10),
+          serve.JobResult("b", 0.5, finished=3.5, units=30)]
+    s = serve.summarize(rs, 4.0)
+    assert s["terms_per_s"] == 10.0 and s["jobs"] == 2
+    assert 1.0 <= s["p50_s"] <= 3.0

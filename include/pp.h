@@ -194,8 +194,11 @@ enum {
 
 /*
  * pp_profile(s, every) resets the per-kernel timing of handle s and, for
- * every > 0, brackets every `every`-th launch of each kernel kind with HIP
- * events recorded on the handle's stream (1 = every launch; 0 = off).
+ * every > 0, brackets every `every`-th run of back-to-back launches of one
+ * kernel kind (for instance the gate launches of one sub-layer) with two HIP
+ * events recorded on the handle's stream (1 = every run; 0 = off); the
+ * interval counts for each launch of the run, so the average includes the
+ * gaps between launches of the run but no event sits between them.
  * pp_profile_read returns, per kernel kind, the number of timed launches
  * and their summed duration in milliseconds (both synchronise).
  * pp_profile(NULL, every) sets the value that handles created afterwards

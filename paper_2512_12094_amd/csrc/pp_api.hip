@@ -97,11 +97,13 @@ struct pp_state {
   } ring[4];
   unsigned ring_pos = 0;
   // per-kernel timing with events on this stream (pp_profile): every
-  // prof_every-th launch of each kind is bracketed (0 = off)
+  // prof_every-th run of back-to-back launches of one kind is bracketed by
+  // two events, and the interval is shared by the run's launches (0 = off)
   int prof_every = 0;
   uint64_t prof_seen[PP_KERNEL_KINDS] = {};
   struct Pend {
     int k;
+    uint32_t len;
     hipEvent_t a, b;
   };
   std::vector<Pend> pend;
@@ -139,7 +141,7 @@ hipEvent_t prof_event(pp_state* s) {
   return e;
 }
 
-// Records an event before a sampled launch (or returns nullptr).
+// Records an event before a sampled run of launches (or returns nullptr).
 hipEvent_t prof_begin(pp_state* s, int kind) {
   if (s->prof_every <= 0) return nullptr;
   if (s->prof_seen[kind]++ % (uint64_t)s->prof_every != 0) return nullptr;
@@ -148,12 +150,12 @@ hipEvent_t prof_begin(pp_state* s, int kind) {
   return a;
 }
 
-void prof_end(pp_state* s, int kind, hipEvent_t a) {
+void prof_end(pp_state* s, int kind, hipEvent_t a, uint32_t len = 1) {
   if (!a) return;
   hipEvent_t b = prof_event(s);
   if (!b) return;
   (void)hipEventRecord(b, s->stream);
-  s->pend.push_back({kind, a, b});
+  s->pend.push_back({kind, len, a, b});
 }
 
 // Folds the finished intervals in (unfinished ones stay pending).
@@ -167,7 +169,7 @@ void prof_resolve(pp_state* s) {
     }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      s->prof_n[p.k] += 1;
+      s->prof_n[p.k] += p.len;
       s->prof_ms[p.k] += ms;
     }
     s->pool.push_back(p.a);
@@ -228,6 +230,7 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   ok = ok && (nb.gtab = (uint64_t*)take(sizeof(uint64_t) * ng));
   ok = ok && (nb.mkey = (uint64_t*)take(sizeof(uint64_t) * nm));
   ok = ok && (nb.mfx = (uint64_t*)take(3 * sizeof(uint64_t) * nm));
+  ok = ok && (nb.accs = (uint64_t*)take(kAccBytes));
   const bool wide = !nb.narrow;
   nb.mown = nullptr;
   nb.wrep = nullptr;
@@ -245,6 +248,7 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   HIP_TRY(hipMemsetAsync(nb.gtab, 0, sizeof(uint64_t) * ng, s->stream));
   HIP_TRY(hipMemsetAsync(nb.mkey, 0xFF, sizeof(uint64_t) * nm, s->stream));
   HIP_TRY(hipMemsetAsync(nb.mfx, 0, 3 * sizeof(uint64_t) * nm, s->stream));
+  HIP_TRY(hipMemsetAsync(nb.accs, 0, kAccBytes, s->stream));
   if (wide) HIP_TRY(hipMemsetAsync(nb.mown, 0xFF, sizeof(uint32_t) * nm, s->stream));
   for (int h = 0; h < 2; ++h)
     for (int p = 0; p < 2; ++p) HIP_TRY(hipMemsetAsync(nb.alive[h][p], 0, cap, s->stream));
@@ -377,13 +381,24 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
 
 // Launches the single-instance kernels of ops [from, to) (op index k is a
 // launch argument: a launch whose op is not the current one does nothing,
-// so everything after an overflow is skipped on the device).
+// so everything after an overflow is skipped on the device).  With
+// profiling on, each run of back-to-back launches of one kind is timed as a
+// whole, so the events do not sit between the launches they time.
 int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
   std::vector<int> kinds;
+  int run_kind = -1;
+  uint32_t run_len = 0;
+  hipEvent_t run_ev = nullptr;
   for (size_t k = from; k < to; ++k) {
     kinds.clear();
     kinds_of(s, ops[k], &kinds);
     for (int kind : kinds) {
+      if (kind != run_kind) {
+        if (run_kind >= 0) prof_end(s, run_kind, run_ev, run_len);
+        run_kind = kind;
+        run_len = 0;
+        run_ev = prof_begin(s, kind);
+      }
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
       const int grid = launch_blocks(elems, items_of(kind));
       Solo S;
@@ -391,11 +406,11 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      hipEvent_t ev = prof_begin(s, kind);
       hipLaunchKernelGGL(solo_of(kind), dim3(grid), dim3(kBlock), 0, s->stream, S);
-      prof_end(s, kind, ev);
+      ++run_len;
     }
   }
+  if (run_kind >= 0) prof_end(s, run_kind, run_ev, run_len);
   HIP_TRY(hipGetLastError());
   return PP_OK;
 }
@@ -653,7 +668,7 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   s->d_bufp = (const InstBuf**)dev_alloc(s.get(), sizeof(void*));
   s->d_dynp = (InstDyn**)dev_alloc(s.get(), sizeof(void*));
   s->d_ninst = (int*)dev_alloc(s.get(), sizeof(int));
-  s->d_sync = (uint32_t*)dev_alloc(s.get(), 64);
+  s->d_sync = (uint32_t*)dev_alloc(s.get(), kSyncBytes);
   if (!s->d_buf || !s->d_dyn || !s->d_bufp || !s->d_dynp || !s->d_ninst || !s->d_sync) {
     pp_destroy(s.release());
     return fail(PP_ENOMEM, "handle allocation failed");
@@ -667,7 +682,7 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   if (hipMemcpyAsync(s->d_bufp, &s->d_buf, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
       hipMemcpyAsync(s->d_dynp, &s->d_dyn, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
       hipMemcpyAsync(s->d_ninst, &one, sizeof(int), hipMemcpyHostToDevice, s->stream) ||
-      hipMemsetAsync(s->d_sync, 0, 64, s->stream))
+      hipMemsetAsync(s->d_sync, 0, kSyncBytes, s->stream))
     return bail(fail(PP_EDEVICE, "handle initialisation failed"));
 
   const uint32_t cap = (uint32_t)std::max<uint64_t>(4096, 2 * n_obs);
@@ -1024,13 +1039,13 @@ int batch_ctx(hipStream_t stream, BatchCtx** out) {
   b->stream = stream;
   if (hipMalloc((void**)&b->d_bufp, sizeof(void*) * kMaxInst) ||
       hipMalloc((void**)&b->d_dynp, sizeof(void*) * kMaxInst) ||
-      hipMalloc((void**)&b->d_ninst, sizeof(int)) || hipMalloc((void**)&b->d_sync, 64) ||
+      hipMalloc((void**)&b->d_ninst, sizeof(int)) || hipMalloc((void**)&b->d_sync, kSyncBytes) ||
       hipMalloc((void**)&b->d_gather, sizeof(InstDyn) * kMaxInst) ||
       hipHostMalloc((void**)&b->h_gather, sizeof(InstDyn) * kMaxInst, hipHostMallocDefault) ||
       hipHostMalloc((void**)&b->h_ninst, sizeof(int), hipHostMallocDefault) ||
       hipHostMalloc((void**)&b->h_bufp, sizeof(void*) * kMaxInst, hipHostMallocDefault) ||
       hipHostMalloc((void**)&b->h_dynp, sizeof(void*) * kMaxInst, hipHostMallocDefault) ||
-      hipMemset(b->d_sync, 0, 64)) {
+      hipMemset(b->d_sync, 0, kSyncBytes)) {
     return fail(PP_ENOMEM, "batch context allocation failed");
   }
   g_batches[stream] = b;

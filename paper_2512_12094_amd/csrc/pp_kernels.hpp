@@ -270,40 +270,84 @@ __device__ inline uint64_t ld_agent(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One atomic per block for both counts of the running kernel (called by
-// thread 0; the returned value is consumed so that the add has completed
-// before the block reports itself done).
-__device__ inline void add_acc(InstDyn& d, uint32_t live, uint32_t cnt) {
+// Launches of up to kTreeMin working blocks count on one line (one atomic
+// round trip less on the critical path); larger ones use the shards.
+constexpr uint32_t kTreeMin = 256;
+__device__ inline uint32_t acc_shards(uint32_t workers) {
+  return workers > kTreeMin ? (uint32_t)kAccShards : 1u;
+}
+
+// Adds a block's counts (live | anticommuting << 32) to accumulator shard
+// blockIdx % nsh (called by thread 0 once per block and instance; the
+// returned value is consumed so that the add has completed before the block
+// reports itself done).
+// With one shard the counts go to d.acc itself.
+__device__ inline void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint32_t live,
+                               uint32_t cnt) {
   const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
   if (v) {
-    consume(atomicAdd((unsigned long long*)&d.acc, (unsigned long long)v));
+    unsigned long long* a = nsh == 1
+        ? (unsigned long long*)&d.acc
+        : (unsigned long long*)&b.accs[(blockIdx.x % nsh) * kLineU64];
+    consume(atomicAdd(a, (unsigned long long)v));
   }
+}
+
+// Last block, one thread: moves the shard totals into d.acc and clears them.
+__device__ inline void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
+  if (nsh == 1) {
+    d.acc = ld_agent(&d.acc);
+    return;
+  }
+  uint64_t v = 0;
+  for (uint32_t s = 0; s < nsh; ++s)
+    v += atomicExch((unsigned long long*)&b.accs[s * kLineU64], 0ull);
+  d.acc += v;
 }
 
 // live = low half, anticommuting count = high half; clears the accumulator.
 __device__ inline void take_acc(InstDyn& d) {
-  const uint64_t v = ld_agent(&d.acc);
+  const uint64_t v = d.acc;
   d.live = (uint32_t)v;
   d.count = (uint32_t)(v >> 32);
   d.acc = 0;
 }
 
 // Block-wide "am I the last working block of this launch" over the
-// `workers` blocks that had tiles.  Within a launch, blocks hand results to
-// the last block only through device-scope atomics that thread 0 issued and
-// waited on (their returned values are consumed) before it increments the
-// done counter, and the last block reads them with agent-scope atomic loads,
-// so no fence is needed.  `fence` adds one for a last block that reads
-// plain stores of other blocks (the multi-instance runner keeps it).
+// `workers` blocks that had tiles.  Beyond kTreeMin workers the done
+// counter is a two-level tree:
+// block b counts in shard b % kSyncShards, the block completing a shard
+// counts in the root, and the block completing the root is the last one.
+// Within a launch, blocks hand results to the last block only through
+// device-scope atomics that thread 0 issued and waited on (their returned
+// values are consumed) before it counts itself, and every level's count is
+// issued only after the level below returned, so no fence is needed.
+// `fence` adds one for a last block that reads plain stores of other blocks
+// (the multi-instance runner keeps it).
 __device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers,
                                   bool fence = false) {
   if (workers <= 1) return true;       // block 0 did all the work itself
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && workers <= kTreeMin) {   // one level
     if (fence) __threadfence();
     const uint32_t t = atomicAdd(sync, 1u);
     *s_flag = (t == workers - 1) ? 1u : 0u;
     if (*s_flag) atomicExch(sync, 0u);
+  } else if (threadIdx.x == 0) {
+    if (fence) __threadfence();
+    const uint32_t sh = blockIdx.x % kSyncShards;
+    const uint32_t members = (workers - sh + kSyncShards - 1) / kSyncShards;
+    const uint32_t roots = workers < (uint32_t)kSyncShards ? workers : kSyncShards;
+    uint32_t* cs = sync + (1 + sh) * kLineU32;
+    uint32_t last = 0;
+    if (atomicAdd(cs, 1u) == members - 1) {
+      atomicExch(cs, 0u);
+      if (atomicAdd(sync, 1u) == roots - 1) {
+        atomicExch(sync, 0u);
+        last = 1;
+      }
+    }
+    *s_flag = last;
   }
   __syncthreads();
   const bool r = *s_flag != 0;
@@ -459,6 +503,14 @@ __device__ inline Fx wave_sum_fx(Fx v) {
 // ---------------------------------------------------------------------------
 // merge table
 // ---------------------------------------------------------------------------
+// Slots of the merge table used by a merge of the current d.M records:
+// at least twice the records (load factor <= 1/2).
+__device__ inline uint32_t merge_bits(const InstBuf& b, const InstDyn& d) {
+  const uint64_t need = 2ull * d.M;
+  const uint32_t bits = need > 1 ? 64u - (uint32_t)__clzll((long long)(need - 1)) : 0u;
+  return bits < 10u ? (10u < b.hm_bits ? 10u : b.hm_bits) : (bits < b.hm_bits ? bits : b.hm_bits);
+}
+
 // Find-or-insert of a 64-bit key; returns the slot.
 __device__ inline uint64_t mt_slot(uint64_t* mkey, uint32_t bits, uint64_t key) {
   const uint64_t mask = (1ull << bits) - 1;
@@ -482,7 +534,7 @@ __device__ inline void mt_add(const InstBuf& b, InstDyn& d, uint64_t key, Fx v) 
     atomicOr(&d.special, 1u);
     return;
   }
-  const uint64_t s = mt_slot(b.mkey, b.hm_bits, key);
+  const uint64_t s = mt_slot(b.mkey, merge_bits(b, d), key);
   if (s != kEmpty64) fx_atomic_add(&b.mfx[3 * s], v);
 }
 
@@ -554,9 +606,33 @@ __device__ inline int gate_state(const InstBuf& b, const InstDyn& d) {
   return 1;
 }
 
+struct Smem {
+  uint32_t tmp[kWaves + 1];
+  uint32_t base;
+  uint32_t flag;
+  uint64_t wfx[kWaves][3];
+  // counts and expectation partial sum of this block's tiles of one
+  // instance, kept by thread 0 and added to the instance once (flush)
+  uint32_t plive, pcnt;
+  uint64_t pfx[3];
+};
+
+__device__ inline void pend_reset(Smem& sm) {
+  sm.plive = sm.pcnt = 0;
+  sm.pfx[0] = sm.pfx[1] = sm.pfx[2] = 0;
+}
+
+// Thread 0: adds the pending counts / sum to the instance and resets them.
+__device__ inline void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh) {
+  add_acc(b, d, nsh, sm.plive, sm.pcnt);
+  if (sm.pfx[0] | sm.pfx[1] | sm.pfx[2]) fx_atomic_add_wait(d.expect_fx, Fx{sm.pfx[0], sm.pfx[1], sm.pfx[2]});
+  pend_reset(sm);
+}
+
 template <int IT>
-__device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
-                                 uint32_t* s_tmp, uint32_t* s_base) {
+__device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Smem& sm) {
+  uint32_t* s_tmp = sm.tmp;
+  uint32_t* s_base = &sm.base;
   const View v = view_of(b, d);
   const Op& op = b.prog[d.pc];
   const int W = v.W;
@@ -665,7 +741,8 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
   const uint32_t bl = block_sum_u32(my_live, s_tmp);
   const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
   if (threadIdx.x == 0) {
-    add_acc(d, bl, bc);
+    sm.plive += bl;
+    sm.pcnt += bc;
   }
 }
 
@@ -681,13 +758,6 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile,
 // instance whose current op index is a launch argument, so a captured
 // sequence of solo launches replays a fixed list of operations.
 // ---------------------------------------------------------------------------
-struct Smem {
-  uint32_t tmp[kWaves + 1];
-  uint32_t base;
-  uint32_t flag;
-  uint64_t wfx[kWaves][3];
-};
-
 struct Solo {
   const InstBuf* b;
   InstDyn* d;
@@ -712,11 +782,12 @@ struct NextGate {
   }
 };
 
-__device__ inline void add_counts(InstDyn& d, uint32_t live, uint32_t cnt, Smem& sm) {
+__device__ inline void add_counts(InstDyn&, uint32_t live, uint32_t cnt, Smem& sm) {
   const uint32_t bl = block_sum_u32(live, sm.tmp);
   const uint32_t bc = block_sum_u32(cnt, sm.tmp);
   if (threadIdx.x == 0) {
-    add_acc(d, bl, bc);
+    sm.plive += bl;
+    sm.pcnt += bc;
   }
 }
 
@@ -726,10 +797,9 @@ struct GateKind {
   __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
   __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
-    gate_tile<IT>(b, d, t, sm.tmp, &sm.base);
+    gate_tile<IT>(b, d, t, sm);
   }
   __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x != 0) return;
     const Op& op = b.prog[d.pc];
     d.propagated += d.live;
     d.merged += (uint64_t)d.live + d.count;
@@ -781,7 +851,6 @@ struct MergeNarrowKind {
     }
   }
   __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x != 0) return;
     d.merged += d.live;
     d.mphase = 1;
   }
@@ -816,11 +885,10 @@ struct MergeWide1Kind {
       }
       uint64_t h = hash_key(rx, rz, W, seed);
       if (h == kEmpty64) h -= 1;
-      b.wslot[i] = (uint32_t)mt_slot(b.mkey, b.hm_bits, h);
+      b.wslot[i] = (uint32_t)mt_slot(b.mkey, merge_bits(b, d), h);
     }
   }
   __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x != 0) return;
     d.merged += d.live;
     d.mphase = 1;
   }
@@ -858,7 +926,7 @@ struct MergeWide2Kind {
     }
   }
   __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x == 0) d.mphase = 2;
+    d.mphase = 2;
   }
 };
 
@@ -901,11 +969,13 @@ struct CollectKind {
   __device__ static int state(const InstBuf& b, const InstDyn& d) {
     return (merge_served(b, d, true, 1) || merge_served(b, d, false, 2)) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf& b, const InstDyn&) { return 1u << b.hm_bits; }
+  __device__ static uint32_t elems(const InstBuf& b, const InstDyn& d) {
+    return 1u << merge_bits(b, d);
+  }
   template <int IT>
   __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const bool collided = (d.status & ST_COLLISION) != 0;
-    const uint32_t nslots = 1u << b.hm_bits;
+    const uint32_t nslots = 1u << merge_bits(b, d);
     const int W = b.W;
     const NextGate ng(b, b.prog[d.pc]);
     uint64_t ox[IT][kMaxW], oz[IT][kMaxW];
@@ -956,7 +1026,6 @@ struct CollectKind {
     add_counts(d, mine, my_cnt, sm);
   }
   __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x != 0) return;
     if (d.status & ST_COLLISION) {     // retry this merge with another seed
       d.status &= ~ST_COLLISION;
       d.special = 0;
@@ -1034,7 +1103,6 @@ struct CompactKind {
     add_counts(d, mine, my_cnt, sm);
   }
   __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x != 0) return;
     d.merged += d.live;
     d.nuniq = ld_agent(&d.nuniq);
     finish_rebuild(b, d);
@@ -1096,16 +1164,17 @@ struct ScanKind {
       if (lane == 0) { sm.wfx[wid][0] = w.l0; sm.wfx[wid][1] = w.l1; sm.wfx[wid][2] = w.l2; }
       __syncthreads();
       if (threadIdx.x == 0) {
-        Fx s{0, 0, 0};
+        Fx s{sm.pfx[0], sm.pfx[1], sm.pfx[2]};
         for (int q = 0; q < kWaves; ++q) s = fx_add(s, Fx{sm.wfx[q][0], sm.wfx[q][1], sm.wfx[q][2]});
-        if (s.l0 | s.l1 | s.l2) fx_atomic_add_wait(d.expect_fx, s);
+        sm.pfx[0] = s.l0;
+        sm.pfx[1] = s.l1;
+        sm.pfx[2] = s.l2;
       }
       __syncthreads();
     }
     add_counts(d, my_live, my_cnt, sm);
   }
   __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
-    if (threadIdx.x != 0) return;
     const Op& op = b.prog[d.pc];
     if (op.type == OP_EXPECT) {
       const Fx f{ld_agent(&d.expect_fx[0]), ld_agent(&d.expect_fx[1]),
@@ -1132,24 +1201,32 @@ __device__ inline void run_multi(const Ctx& C, Smem& sm, uint32_t* s_pref) {
   }, s_pref, sm.tmp);
   const uint32_t workers = worker_count(total);
   if (blockIdx.x >= workers) return;
+  const uint32_t nsh = acc_shards(workers);
+  if (threadIdx.x == 0) pend_reset(sm);
+  int cur = -1;                            // instance of the pending counts
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int i = find_inst(s_pref, ninst, t);
+    if (i != cur) {
+      if (cur >= 0 && threadIdx.x == 0) flush(*C.bufs[cur], *C.dyns[cur], sm, nsh);
+      cur = i;
+    }
     K::template tile<IT>(*C.bufs[i], *C.dyns[i], t - s_pref[i], sm);
   }
+  if (cur >= 0 && threadIdx.x == 0) flush(*C.bufs[cur], *C.dyns[cur], sm, nsh);
   if (!last_block(C.sync, &sm.flag, workers, true)) return;
-  for (int i = 0; i < ninst; ++i) {        // block-uniform loop
+  // one thread per instance: each finish touches only its own instance
+  for (int i = threadIdx.x; i < ninst; i += kBlock) {
     const InstBuf& b = *C.bufs[i];
     InstDyn& d = *C.dyns[i];
     const int st = K::state(b, d);
-    const uint32_t tiles = ceil_tiles<IT>(K::elems(b, d));
-    __syncthreads();                       // all read the state before it changes
     if (st == 2) {
-      if (threadIdx.x == 0) { d.status |= ST_OVERFLOW; d.failed_pc = d.pc; }
+      d.status |= ST_OVERFLOW;
+      d.failed_pc = d.pc;
       continue;
     }
     if (st != 1) continue;
-    K::finish(b, d, tiles, sm);
-    __syncthreads();
+    fold_acc(b, d, nsh);
+    K::finish(b, d, ceil_tiles<IT>(K::elems(b, d)), sm);
   }
 }
 
@@ -1167,9 +1244,15 @@ __device__ inline void run_solo(const Solo& S, Smem& sm) {
   const uint32_t tiles = ceil_tiles<IT>(K::elems(b, d));
   const uint32_t workers = worker_count(tiles);
   if (blockIdx.x >= workers) return;
+  const uint32_t nsh = acc_shards(workers);
+  if (threadIdx.x == 0) pend_reset(sm);
   for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) K::template tile<IT>(b, d, t, sm);
+  if (threadIdx.x == 0) flush(b, d, sm, nsh);
   if (!last_block(S.sync, &sm.flag, workers, K::needs_fence(b, d))) return;
-  K::finish(b, d, tiles, sm);
+  if (threadIdx.x == 0) {
+    fold_acc(b, d, nsh);
+    K::finish(b, d, tiles, sm);
+  }
 }
 
 #define PP_KERNEL_PAIR(name, Kind)                                                    \

@@ -16,7 +16,9 @@
 // value (generation << 32) | index.  A slot whose generation differs from
 // the instance's current one is empty, so a rebuild only bumps `gen`.
 //
-// Merge table: 2^hm_bits slots of (key, sum[, owner]).  Keys are the
+// Merge table: 2^hm_bits slots of (key, sum[, owner]); a merge of M records
+// uses only the first 2^b slots, b = ceil(log2(2M)) (at least 10, at most
+// hm_bits), so the collect pass scans what the merge can fill.  Keys are the
 // representative itself when it fits 64 bits exactly ("narrow"), else a
 // 64-bit hash of it with the owning record's full representative kept in
 // `wrep` and compared for every record ("wide").  Sums are exact: every
@@ -25,6 +27,7 @@
 // atomics and carries, so the orbit sum is exact, independent of the order
 // of the additions, and rounded to FP64 once.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 namespace pp {
@@ -45,6 +48,17 @@ enum OpType : uint32_t {
 };
 
 enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u, ST_FAILED = 8u };
+
+// Contended device-scope atomics on one address serialise (about 12 ns each
+// on gfx950), so per-launch counts go to kAccShards accumulators and the
+// done counter is a two-level tree of kSyncShards; each shard sits on its
+// own 128-byte line (kLineU64 / kLineU32 entries apart).
+constexpr int kAccShards = 16;
+constexpr int kSyncShards = 16;
+constexpr int kLineU64 = 16;
+constexpr int kLineU32 = 32;
+constexpr size_t kSyncBytes = (1 + kSyncShards) * kLineU32 * sizeof(uint32_t);
+constexpr size_t kAccBytes = kAccShards * kLineU64 * sizeof(uint64_t);
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
@@ -75,6 +89,7 @@ struct InstBuf {
   uint32_t* mown;
   uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
   uint32_t* wslot;
+  uint64_t* accs;        // kAccShards count accumulators (live | count << 32)
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;
@@ -93,7 +108,7 @@ struct InstDyn {
   uint64_t appended;     // strings appended by gates
   uint64_t merge_in;     // records entering symmetry merges / compactions
   uint64_t merge_out;    // representatives leaving them
-  uint64_t acc;          // running kernel's counts: live | anticommuting << 32
+  uint64_t acc;          // counts folded from the shards by the last block
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
   uint64_t expect_fx[3];    // exact expectation accumulator
  double expect;

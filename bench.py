@@ -14,9 +14,13 @@ the device and equal to the oracle's counts (tests/test_gpu_parity.py).
 
 The JSON line also carries: the same circuit without symmetry merging
 (plain PP), the roofline of the dominant kernel (per-kernel durations from
-HIP events recorded on the library's stream over the timed steps), the
-exact-merge pass on a large record stream, and the CPU oracle timed on a
-bounded prefix of the same workload.
+HIP events recorded on the library's stream over the timed steps; HBM
+traffic from the committed rocprofv3 counter summary when it matches the
+current kernel sources), the exact-merge pass on a large record stream, the
+batched form against a per-instance loop on a sample of the batched ring
+workload, the served form (continuous batching, p50/p99 latency) on a
+sample of the mixed job stream, and the CPU oracle timed on a bounded
+prefix of the same workload.
 """
 from __future__ import annotations
 
@@ -45,11 +49,20 @@ def parse():
     ap.add_argument("--no-merge-pass", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--event-every", type=int, default=16,
-                    help="time every N-th launch of each kernel kind with HIP events")
+    ap.add_argument("--event-every", type=int, default=4,
+                    help="time every N-th run of back-to-back launches of one kernel "
+                         "kind with HIP events")
     ap.add_argument("--merge-log2n", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-sublayers", type=int, default=12)
+    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--serve-sublayers", type=int, default=3)
+    ap.add_argument("--serve-cap-terms", type=int, default=1 << 24,
+                    help="largest estimate a served job may reach (store = 4x)")
     return ap.parse_args()
 
 
@@ -127,6 +140,163 @@ def merge_pass(stream, alloc, log2n):
                 frac_of_hbm=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
 
 
+def prefix(prog, k):
+    """The first k sub-layers of a program in Heisenberg order (the last k
+    of its time order): a bounded sample of the same circuit."""
+    from paper_2512_12094_amd import workloads as W
+    k = min(k, len(prog.sublayers))
+    return W.Program(f"{prog.name}[:{k}]", prog.n, prog.group, prog.obs,
+                     prog.sublayers[len(prog.sublayers) - k:], prog.bloch, dict(prog.meta))
+
+
+def batched_leg(stream, alloc, count, sublayers):
+    """Batched ring instances (uneven n, depth, angles, thresholds; each cut
+    to its first `sublayers` sub-layers): one batched run against a loop of
+    single-instance runs over the same instances.  Both include creating
+    each instance's set from its observable."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from paper_2512_12094_amd import workloads as W
+    import torch
+    progs = [prefix(p, sublayers) for p in W.config4()[:count]]
+    dps = [driver.device_program(p) for p in progs]
+
+    def solo_loop():
+        es, units = [], 0
+        for p, dp in zip(progs, dps):
+            ps = driver.PauliSet.from_program(p, None, stream, alloc)
+            es.append(float(L.pp_batch_run([ps.h], [dp.h], stream)[0]))
+            wc = L.pp_work_counters(ps.h)
+            units += wc["propagated"] + wc["merged"]
+            ps.close()
+        return es, units
+
+    def batch():
+        sets = [driver.PauliSet.from_program(p, None, stream, alloc) for p in progs]
+        e = L.pp_batch_run([s.h for s in sets], [d.h for d in dps], stream)
+        units = 0
+        for s in sets:
+            wc = L.pp_work_counters(s.h)
+            units += wc["propagated"] + wc["merged"]
+            s.close()
+        return [float(v) for v in e], units
+
+    out = {}
+    for name, fn in (("per_instance", solo_loop), ("batched", batch)):
+        fn()                                   # warm (graph capture, allocator)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        es, units = fn()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = dict(value=units / wall, unit="terms/s", wall_s=round(wall, 4), units=units)
+        out[name + "_e"] = es
+    same = sum(a == b for a, b in zip(out.pop("per_instance_e"), out.pop("batched_e")))
+    out.update(instances=len(progs), sublayers_each=sublayers,
+               gates=sum(p.n_gates for p in progs),
+               speedup=round(out["batched"]["value"] / out["per_instance"]["value"], 3),
+               bitwise_equal_expectations=f"{same}/{len(progs)}",
+               knobs=L.pp_get_tuning())
+    return out
+
+
+def served_leg(stream, alloc, count, sublayers, cap_terms, seed=5):
+    """Continuous batching of a mixed job stream (rings and all-to-all
+    Heisenberg jobs, each cut to its first `sublayers` sub-layers).  A first,
+    untimed pass serves every job once (the estimator learns peak sizes per
+    job class; a job whose store would exceed 4 x cap_terms entries is
+    rejected and listed).  On the jobs that completed, the leg then times:
+    a loop of single-instance runs; serving them all arriving at once (the
+    capacity); serving them with Poisson arrivals at 0.8 x that rate (p50 /
+    p99 latency)."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from paper_2512_12094_amd import serve
+    from paper_2512_12094_amd import workloads as W
+    import numpy as np
+    import torch
+    jobs = [W.Job(0.0, prefix(j.program, sublayers)) for j in W.config5(count=count)]
+    free, _ = torch.cuda.mem_get_info()
+    budget = 0.8 * free
+    est = serve.Estimator(cap_terms=cap_terms)
+    eng = serve.GpuEngine(stream, alloc, steps_per_iter=16)
+
+    def run(js, label):
+        srv = serve.Server(eng, budget, estimator=est)
+        ended = [0]
+
+        def progress(kind, i, used):
+            if kind in ("finish", "reject"):
+                ended[0] += 1
+                if ended[0] % 25 == 0:
+                    print(f"[bench] served ({label}): {ended[0]}/{len(js)} jobs ended",
+                          file=sys.stderr, flush=True)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = srv.run(js, on_event=progress)
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    first, _ = run(jobs, "learning")
+    done = [j for j, r in zip(jobs, first) if not r.rejected]
+    rejected = sorted({f"{j.program.group} n={j.program.n}"
+                       for j, r in zip(jobs, first) if r.rejected})
+
+    # single-instance loop over the same jobs
+    dps = [driver.device_program(j.program) for j in done]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    units_solo = 0
+    for j, dp in zip(done, dps):
+        ps = driver.PauliSet.from_program(j.program, None, stream, alloc)
+        L.pp_set_max_terms(ps.h, 4 * cap_terms)
+        L.pp_batch_run([ps.h], [dp.h], stream)
+        wc = L.pp_work_counters(ps.h)
+        units_solo += wc["propagated"] + wc["merged"]
+        ps.close()
+    torch.cuda.synchronize()
+    wall_solo = time.perf_counter() - t0
+
+    burst, wall_b = run(done, "burst")
+    rate = 0.8 * len(done) / wall_b
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=len(done)))
+    timed = [W.Job(float(a), j.program) for a, j in zip(t, done)]
+    res, wall = run(timed, "Poisson")
+    summ = serve.summarize(res, wall)
+    burst_s = serve.summarize(burst, wall_b)
+    summ.update(sampled_jobs=len(jobs), sublayers_each=sublayers,
+                store_limit_terms=4 * cap_terms, rejected_in_learning_pass=len(jobs) - len(done),
+                rejected_kinds=rejected, ring_jobs=sum(j.program.group == "Zn" for j in done),
+                arrival_rate_per_s=round(rate, 2),
+                burst=dict(terms_per_s=burst_s["terms_per_s"], wall_s=round(wall_b, 4),
+                           jobs_per_s=round(len(done) / wall_b, 2), p99_s=burst_s["p99_s"]),
+                per_instance=dict(terms_per_s=units_solo / wall_solo, wall_s=round(wall_solo, 4)),
+                burst_vs_per_instance=round(burst_s["terms_per_s"] / (units_solo / wall_solo), 3),
+                hbm_budget_GB=round(budget / 1e9, 1))
+    return summ
+
+
+def pmc_traffic(bytes_launches):
+    """HBM bytes per gate launch from the committed rocprofv3 counter
+    summary, when it was taken on the kernel sources as they are now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_gate_c2_z32_pmc.json")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as f:
+        pmc = json.load(f)
+    h = hashlib.sha256()
+    for name in pmc["sources"]:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != pmc["sources_sha256"]:
+        return None, "kernel sources changed since the counters were taken"
+    return (pmc["fetch_kib_per_launch"] * pmc["fetch_scale"] +
+            pmc["write_kib_per_launch"] * pmc["write_scale"]) * 1024.0, pmc["command"]
+
+
 def cpu_baseline(prog, seconds):
     from oracle import oracle as O
     r = O.run_program(prog, keep_terms=False, time_budget=seconds)
@@ -165,6 +335,8 @@ def main():
     alloc = L.TorchAllocator(0)
     prog = W.config2()
 
+    from paper_2512_12094_amd import autotune
+    tuned_single = autotune.apply(autotune.class_key("single", "Zn", 32))
     with torch.cuda.stream(stream_obj):
         if args.copy_calibration:
             a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB
@@ -211,11 +383,24 @@ def main():
                          terms_per_step=(ptot["propagated"] + ptot["merged"]) // psteps,
                          expectation=pe)
             print(f"[bench] plain PP done", file=sys.stderr, flush=True)
+        traffic, traffic_src = pmc_traffic(None)
+        roof["traffic"] = round(traffic, 1) if traffic is not None else None
+        roof["traffic_source"] = traffic_src
         mp = None
         if not args.no_merge_pass:
             merge_pass(stream, alloc, args.merge_log2n)            # warm
             mp = merge_pass(stream, alloc, args.merge_log2n)
             print(f"[bench] merge pass done", file=sys.stderr, flush=True)
+        batched = served = None
+        if not args.no_batched:
+            tuned_batch = autotune.apply(autotune.class_key("batch", "Zn"))
+            batched = batched_leg(stream, alloc, args.batch_count, args.batch_sublayers)
+            batched["tuned"] = tuned_batch is not None
+            print(f"[bench] batched leg done", file=sys.stderr, flush=True)
+        if not args.no_served:
+            served = served_leg(stream, alloc, args.serve_count, args.serve_sublayers,
+                                args.serve_cap_terms)
+            print(f"[bench] served leg done", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -239,7 +424,10 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "variants": variants,
+        "tuning": {"single": tuned_single, "source": autotune.cache_path()},
         "merge_pass": mp,
+        "batched": batched,
+        "served": served,
         "host": host_info(),
         "platform": platform.node(),
     }

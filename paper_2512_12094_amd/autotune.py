@@ -124,3 +124,49 @@ def tune(key: str, run, knobs=BATCH_KNOBS, reps: int = 3, rounds: int = 2,
         baseline_seconds=trials[0][1])
     save_cache(cache, path)
     return best
+
+
+def _tune_workloads(path: str | None, log=print) -> dict:
+    """Tunes the classes of the ring workloads: one-instance Z_32 programs
+    (the 20-step XXZ ring) and batched rings (256 instances of mixed n,
+    12 sub-layers each)."""
+    import torch
+    from . import driver
+    from . import workloads as W
+    L.lib()
+    torch.cuda.set_device(0)
+    so = torch.cuda.Stream()
+    stream = int(so.cuda_stream)
+    alloc = L.TorchAllocator(0)
+    out = {}
+    with torch.cuda.stream(so):
+        prog = W.config2()
+        dp = driver.device_program(prog)
+
+        def single():
+            ps = driver.PauliSet.from_program(prog, None, stream, alloc)
+            L.pp_batch_run([ps.h], [dp.h], stream)
+            ps.close()
+
+        out["single:Zn:n32"] = tune(class_key("single", "Zn", 32), single, SINGLE_KNOBS,
+                                    path=path, log=log)
+        progs = []
+        for p in W.config4():
+            k = min(12, len(p.sublayers))
+            progs.append(W.Program(p.name, p.n, p.group, p.obs, p.sublayers[len(p.sublayers) - k:],
+                                   p.bloch, dict(p.meta)))
+        dps = [driver.device_program(p) for p in progs]
+
+        def batch():
+            sets = [driver.PauliSet.from_program(p, None, stream, alloc) for p in progs]
+            L.pp_batch_run([s.h for s in sets], [d.h for d in dps], stream)
+            for s in sets:
+                s.close()
+
+        out["batch:Zn"] = tune(class_key("batch", "Zn"), batch, BATCH_KNOBS, path=path, log=log)
+    return out
+
+
+if __name__ == "__main__":
+    import sys
+    print(json.dumps(_tune_workloads(sys.argv[1] if len(sys.argv) > 1 else None)), flush=True)

@@ -100,6 +100,7 @@ struct pp_state {
   // prof_every-th run of back-to-back launches of one kind is bracketed by
   // two events, and the interval is shared by the run's launches (0 = off)
   int prof_every = 0;
+  uint32_t m_hint = 0;     // term count last read back (picks tile sizes)
   uint64_t prof_seen[PP_KERNEL_KINDS] = {};
   struct Pend {
     int k;
@@ -197,6 +198,7 @@ void prof_resolve(pp_state* s);
 int read_dyn(pp_state* s) {
   HIP_TRY(hipMemcpyAsync(s->h_dyn, s->d_dyn, sizeof(InstDyn), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  s->m_hint = s->h_dyn->M;
   prof_resolve(s);
   return PP_OK;
 }
@@ -289,8 +291,19 @@ KernelFn kernel_of(int kind) {
 
 using SoloFn = void (*)(Solo);
 
-SoloFn solo_of(int kind) {
-  const int gi = g_tune.gate_items, si = g_tune.stream_items;
+// Launches over large sets take at least kBigItems items per thread: a tile
+// reserves its appended strings with one atomic on the instance's cursor,
+// and those atomics serialise, so fewer, larger tiles run faster there.
+constexpr uint32_t kBigSet = 1u << 19;
+constexpr int kBigItems = 4;
+
+int gate_items(bool big) { return big ? std::max(g_tune.gate_items, kBigItems) : g_tune.gate_items; }
+int stream_items(bool big) {
+  return big ? std::max(g_tune.stream_items, kBigItems) : g_tune.stream_items;
+}
+
+SoloFn solo_of(int kind, bool big) {
+  const int gi = gate_items(big), si = stream_items(big);
   switch (kind) {
     case PP_K_GATE: return PP_PICK(k_gate_solo, gi);
     case PP_K_MERGE_NARROW: return PP_PICK(k_merge_narrow_solo, si);
@@ -302,7 +315,9 @@ SoloFn solo_of(int kind) {
   }
 }
 
-int items_of(int kind) { return kind == PP_K_GATE ? g_tune.gate_items : g_tune.stream_items; }
+int items_of(int kind, bool big = false) {
+  return kind == PP_K_GATE ? gate_items(big) : stream_items(big);
+}
 
 // Grows (or just compacts) the store so that live + count + slack fits.
 int grow(pp_state* s) {
@@ -386,6 +401,7 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
 // whole, so the events do not sit between the launches they time.
 int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
   std::vector<int> kinds;
+  const bool big = s->m_hint >= kBigSet;   // last term count seen on the host
   int run_kind = -1;
   uint32_t run_len = 0;
   hipEvent_t run_ev = nullptr;
@@ -400,13 +416,13 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
         run_ev = prof_begin(s, kind);
       }
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
-      const int grid = launch_blocks(elems, items_of(kind));
+      const int grid = launch_blocks(elems, items_of(kind, big));
       Solo S;
       S.b = s->d_buf;
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      hipLaunchKernelGGL(solo_of(kind), dim3(grid), dim3(kBlock), 0, s->stream, S);
+      hipLaunchKernelGGL(solo_of(kind, big), dim3(grid), dim3(kBlock), 0, s->stream, S);
       ++run_len;
     }
   }
@@ -1137,6 +1153,7 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation) {
     inflight.erase(inflight.begin());
     HIP_TRY(hipEventSynchronize(s->solo_ev[c & 1]));
     const InstDyn dy = s->solo_slots[c & 1];
+    s->m_hint = dy.M;
     if (dy.status & ST_RANGE)
       return fail(PP_EINVAL, "a coefficient is not finite or exceeds 2^54 in magnitude");
     if (dy.pc >= ends[c]) {

@@ -11,8 +11,12 @@ Every iteration of the event loop
 3. advances every admitted job together by a few batched steps
    (pp_batch_step: one persistent launch per kernel kind serves all jobs);
 4. retires finished jobs (expectation, latency = finish - arrival) and frees
-   their memory; a job whose store outgrew its estimate is re-queued with a
-   doubled estimate (it restarts from its observable, nothing is reused).
+   their memory; a job whose store outgrew its estimate is re-queued with
+   four times the estimate (it restarts from its observable, nothing is
+   reused), and rejected once it has failed at the largest estimate the
+   store limit allows, or would not fit the whole budget (its result then
+   says so).  A failure also raises the starting estimate of later jobs of
+   the same class.
 
 Jobs that arrive while others run join at the next iteration.  The GPU work
 goes through an engine object so the policy can be exercised on the CPU with
@@ -50,6 +54,7 @@ class JobResult:
     units: int = 0                # propagated + merged terms
     retries: int = 0
     est_terms: int = 0
+    rejected: bool = False
 
     @property
     def latency(self) -> float:
@@ -77,6 +82,11 @@ class Estimator:
     def observe(self, prog: Program, peak_terms: int):
         k = self.key(prog)
         self.seen[k] = max(self.seen.get(k, 0), int(peak_terms))
+
+    def failed(self, prog: Program, store_terms: int):
+        """A job of this class outgrew a store of `store_terms` entries: jobs
+        of the class start from twice that (capped) from now on."""
+        self.observe(prog, store_terms)
 
 
 class GpuEngine:
@@ -120,7 +130,8 @@ class Server:
     estimator: Estimator = field(default_factory=Estimator)
     clock: object = time.perf_counter
     sleep: object = time.sleep
-    max_retries: int = 6
+    max_retries: int = 8
+    growth: int = 4                        # estimate factor after a failure
 
     def run(self, jobs, on_event=None):
         """Serves `jobs` (objects with .arrival and .program); returns
@@ -176,12 +187,20 @@ class Server:
                     used -= need
                     r = results[i]
                     r.retries += 1
-                    if r.retries > self.max_retries:
-                        raise RuntimeError(f"job {r.name} does not fit after {r.retries} tries")
-                    r.est_terms = 2 * est
-                    waiting.appendleft(i)
-                    if on_event:
-                        on_event("requeue", i, used)
+                    new_est = self.growth * est
+                    prog = jobs[i].program
+                    self.estimator.failed(prog, 4 * est)
+                    if (r.retries > self.max_retries or est >= self.estimator.cap_terms or
+                            min(new_est, self.estimator.cap_terms) * bytes_per_term(prog.n) >
+                            self.hbm_budget):
+                        r.rejected, r.finished = True, now
+                        if on_event:
+                            on_event("reject", i, used)
+                    else:                 # the last try is at the limit itself
+                        r.est_terms = min(new_est, self.estimator.cap_terms)
+                        waiting.appendleft(i)
+                        if on_event:
+                            on_event("requeue", i, used)
                 else:
                     keep.append((i, handle, need, est))
             active = keep
@@ -189,9 +208,13 @@ class Server:
 
 
 def summarize(results, wall: float) -> dict:
-    lat = np.array([r.latency for r in results])
-    units = sum(r.units for r in results)
-    return dict(jobs=len(results), p50_s=float(np.percentile(lat, 50)),
-                p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
+    """Latency percentiles over the completed jobs, throughput over all
+    completed work, counts of retries and rejections."""
+    done = [r for r in results if not r.rejected]
+    lat = np.array([r.latency for r in done]) if done else np.array([math.nan])
+    units = sum(r.units for r in done)
+    return dict(jobs=len(results), completed=len(done), rejected=len(results) - len(done),
+                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                mean_s=float(lat.mean()),
                 terms_per_s=units / wall if wall > 0 else float("nan"), wall_s=wall,
                 retries=int(sum(r.retries for r in results)))

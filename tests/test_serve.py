@@ -89,19 +89,43 @@ def test_budget_is_never_exceeded_and_jobs_overlap():
     assert admits == sorted(admits)
 
 
-def test_underestimate_is_requeued_with_doubled_estimate():
+def test_underestimate_is_requeued_with_larger_estimate():
     clock = FakeClock()
     jobs = make_jobs(3)
     big = jobs[1].program.name
     peak = {j.program.name: 10 for j in jobs}
-    peak[big] = 3 * 4 * (1 << 16)          # beyond the prior's store limit
+    peak[big] = 12 * (1 << 16)             # beyond the prior's store limit
     eng = FakeEngine(clock, {j.program.name: 3 for j in jobs}, peak)
     srv = serve.Server(eng, 1e15, clock=clock, sleep=clock.sleep)
     res = srv.run(jobs)
-    assert res[1].retries == 2
+    assert res[1].retries == 1 and not res[1].rejected
     starts = [m for name, m in eng.started if name == big]
-    assert starts == [4 * (1 << 16), 8 * (1 << 16), 16 * (1 << 16)]
+    # the failure at 4 x 2^16 raises the class estimate to twice that
+    assert starts == [4 * (1 << 16), 32 * (1 << 16)]
     assert all(r.finished > 0 for r in res)
+
+
+def test_job_beyond_the_store_limit_is_rejected_not_fatal():
+    clock = FakeClock()
+    jobs = make_jobs(3)
+    jobs[0] = FakeJob(0.0, W.xxz_ring(24, 1, 0.1, 1.0, eps=1e-4, name="huge"))
+    huge = "huge"
+    peak = {j.program.name: 10 for j in jobs}
+    peak[huge] = 1 << 40
+    eng = FakeEngine(clock, {j.program.name: 3 for j in jobs}, peak)
+    srv = serve.Server(eng, 1e15, estimator=serve.Estimator(cap_terms=1 << 22), clock=clock,
+                       sleep=clock.sleep)
+    res = srv.run(jobs)
+    assert res[0].rejected and not res[1].rejected and not res[2].rejected
+    s = serve.summarize(res, 1.0)
+    assert s["rejected"] == 1 and s["completed"] == 2
+    # the huge job's last try was at the limit (4 x cap_terms entries)
+    assert eng.started[-1][1] == 4 * (1 << 22) or ("huge", 4 * (1 << 22)) in eng.started
+    # a later job of the class that outgrew the limit starts at the limit
+    late = FakeJob(0.0, W.xxz_ring(24, 1, 0.1, 1.0, eps=1e-4, name="late"))
+    eng.work["late"], eng.peak["late"] = 3, 10
+    res2 = srv.run([late])
+    assert not res2[0].rejected and eng.started[-1] == ("late", 4 * (1 << 22))
 
 
 def test_estimator_learns_from_finished_jobs():

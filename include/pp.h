@@ -73,7 +73,17 @@ enum {
   PP_GROUP_PERMUTATION = 2   /* qubit permutations S_n                      */
 };
 
-enum { PP_F64 = 0 };
+/*
+ * Coefficient precision.  PP_F64: coefficients stored and rotated in FP64.
+ * PP_F32_COMPENSATED: coefficients stored in FP32 (4 bytes per term) and
+ * each rotation computed in FP32 with cos and sin rounded to FP32 once;
+ * damping factors are rounded to FP32 the same way.  In both modes every
+ * merge sum (inner exact merges and orbit sums, Algorithms 2 and 3) is
+ * exact (integer fixed point) and rounded once to FP64, then, in FP32 mode,
+ * to FP32; this is at least as accurate as compensated summation.  The
+ * expectation is an exact sum of FP64 products, rounded once to FP64.
+ */
+enum { PP_F64 = 0, PP_F32_COMPENSATED = 1 };
 
 enum {
   PP_OK = 0,
@@ -97,7 +107,8 @@ typedef struct {
  * Builds a handle for n_qubits qubits and merge group `group`, loads the
  * observable rows (obs_x/obs_z: n_obs rows of W words, host memory;
  * obs_coef: n_obs doubles, host), adds duplicate rows, and merges the rows
- * by orbit representative.  dtype must be PP_F64.  hip_stream may be NULL
+ * by orbit representative.  dtype is PP_F64 or PP_F32_COMPENSATED (FP32
+ * mode rounds each obs_coef to FP32 once).  hip_stream may be NULL
  * (the null stream).  alloc may be NULL (hipMalloc).  On success *out holds
  * the handle; release it with pp_destroy.
  */

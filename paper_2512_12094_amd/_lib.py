@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libpp.so")
 
 PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2}
 PP_F64 = 0
+PP_F32_COMPENSATED = 1
+DTYPES = {"f64": PP_F64, "f32": PP_F32_COMPENSATED}
 ERRORS = {-1: "PP_EINVAL", -2: "PP_ENOTSYM", -3: "PP_ENOMEM", -4: "PP_ECAPACITY",
           -5: "PP_EDEVICE"}
 
@@ -133,16 +135,17 @@ def current_stream_handle():
 # ---------------------------------------------------------------------------
 # entry points (same names as include/pp.h)
 # ---------------------------------------------------------------------------
-def pp_create(n, group, obs_x, obs_z, obs_coef, stream=0, allocator=None):
-    """obs_x/obs_z: (rows, W) uint64 arrays; obs_coef: (rows,) float64."""
+def pp_create(n, group, obs_x, obs_z, obs_coef, stream=0, allocator=None, dtype="f64"):
+    """obs_x/obs_z: (rows, W) uint64 arrays; obs_coef: (rows,) float64;
+    dtype "f64" (PP_F64) or "f32" (PP_F32_COMPENSATED)."""
     W = (n + 63) // 64
     x, xp = _u64(np.asarray(obs_x, dtype=np.uint64).reshape(-1, W))
     z, zp = _u64(np.asarray(obs_z, dtype=np.uint64).reshape(-1, W))
     c, cp = _f64(obs_coef)
     h = _vp()
     al = ctypes.byref(allocator.struct) if allocator is not None else None
-    _check(lib().pp_create(ctypes.byref(h), n, PP_GROUP.get(group, group), PP_F64, xp, zp, cp,
-                           len(c), _vp(stream or None), al))
+    _check(lib().pp_create(ctypes.byref(h), n, PP_GROUP.get(group, group),
+                           DTYPES.get(dtype, dtype), xp, zp, cp, len(c), _vp(stream or None), al))
     return h
 
 

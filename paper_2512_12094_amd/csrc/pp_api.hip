@@ -226,7 +226,7 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   for (int h = 0; h < 2; ++h) {
     ok = ok && (nb.x[h] = (uint64_t*)take(sizeof(uint64_t) * W * cap));
     ok = ok && (nb.z[h] = (uint64_t*)take(sizeof(uint64_t) * W * cap));
-    ok = ok && (nb.c[h] = (double*)take(sizeof(double) * cap));
+    ok = ok && (nb.c[h] = take((nb.f32 ? sizeof(float) : sizeof(double)) * cap));
     for (int p = 0; p < 2; ++p) ok = ok && (nb.alive[h][p] = (uint8_t*)take(cap));
   }
   ok = ok && (nb.gtab = (uint64_t*)take(sizeof(uint64_t) * ng));
@@ -653,7 +653,8 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   if (!valid_group_n(group, n_qubits))
     return fail(PP_EINVAL, "unsupported (group, n_qubits) = (" + std::to_string(group) + ", " +
                                std::to_string(n_qubits) + ")");
-  if (dtype != PP_F64) return fail(PP_EINVAL, "dtype must be PP_F64");
+  if (dtype != PP_F64 && dtype != PP_F32_COMPENSATED)
+    return fail(PP_EINVAL, "dtype must be PP_F64 or PP_F32_COMPENSATED");
   if (n_obs && (!obs_x || !obs_z || !obs_coef)) return fail(PP_EINVAL, "observable is NULL");
   if (n_obs > 0x3FFFFFFFull) return fail(PP_EINVAL, "too many observable rows");
   const int W = (n_qubits + 63) / 64;
@@ -677,6 +678,7 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   s->buf.W = W;
   s->buf.group = group;
   s->buf.narrow = (group == PP_GROUP_PERMUTATION || n_qubits <= 32) ? 1u : 0u;
+  s->buf.f32 = dtype == PP_F32_COMPENSATED ? 1u : 0u;
 
   HIP_TRY(hipHostMalloc((void**)&s->h_dyn, sizeof(InstDyn), hipHostMallocDefault));
   s->d_buf = (InstBuf*)dev_alloc(s.get(), sizeof(InstBuf));
@@ -712,12 +714,16 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
       zs[(size_t)w * cap + r] = obs_z[r * W + w];
     }
   std::vector<uint8_t> ones(std::max<size_t>(n_obs, 1), 1);
+  // FP32 storage: each observable coefficient is rounded once
+  std::vector<float> cf(s->buf.f32 ? n_obs : 0);
+  for (size_t r = 0; r < cf.size(); ++r) cf[r] = (float)obs_coef[r];
+  const void* csrc = s->buf.f32 ? (const void*)cf.data() : (const void*)obs_coef;
+  const size_t csize = (s->buf.f32 ? sizeof(float) : sizeof(double)) * n_obs;
   if (hipMemcpyAsync(s->buf.x[0], xs.data(), sizeof(uint64_t) * xs.size(), hipMemcpyHostToDevice,
                      s->stream) ||
       hipMemcpyAsync(s->buf.z[0], zs.data(), sizeof(uint64_t) * zs.size(), hipMemcpyHostToDevice,
                      s->stream) ||
-      (n_obs && hipMemcpyAsync(s->buf.c[0], obs_coef, sizeof(double) * n_obs,
-                               hipMemcpyHostToDevice, s->stream)) ||
+      (n_obs && hipMemcpyAsync(s->buf.c[0], csrc, csize, hipMemcpyHostToDevice, s->stream)) ||
       (n_obs && hipMemcpyAsync(s->buf.alive[0][0], ones.data(), n_obs, hipMemcpyHostToDevice,
                                s->stream)))
     return bail(fail(PP_EDEVICE, "observable upload failed"));
@@ -898,6 +904,7 @@ int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef, size_t 
   const uint32_t M = d.M, C = s->buf.cap;
   std::vector<uint64_t> xs((size_t)W * M), zs((size_t)W * M);
   std::vector<double> cs(M);
+  std::vector<float> cf(s->buf.f32 ? M : 0);
   std::vector<uint8_t> al(M);
   for (int w = 0; w < W && M; ++w) {
     HIP_TRY(hipMemcpyAsync(xs.data() + (size_t)w * M, s->buf.x[d.half] + (size_t)w * C,
@@ -906,12 +913,17 @@ int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef, size_t 
                            sizeof(uint64_t) * M, hipMemcpyDeviceToHost, s->stream));
   }
   if (M) {
-    HIP_TRY(hipMemcpyAsync(cs.data(), s->buf.c[d.half], sizeof(double) * M,
-                           hipMemcpyDeviceToHost, s->stream));
+    if (s->buf.f32)
+      HIP_TRY(hipMemcpyAsync(cf.data(), s->buf.c[d.half], sizeof(float) * M,
+                             hipMemcpyDeviceToHost, s->stream));
+    else
+      HIP_TRY(hipMemcpyAsync(cs.data(), s->buf.c[d.half], sizeof(double) * M,
+                             hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipMemcpyAsync(al.data(), s->buf.alive[d.half][d.parity], M, hipMemcpyDeviceToHost,
                            s->stream));
   }
   HIP_TRY(hipStreamSynchronize(s->stream));
+  for (size_t i = 0; i < cf.size(); ++i) cs[i] = (double)cf[i];
   size_t r = 0;
   for (uint32_t i = 0; i < M; ++i) {
     if (!al[i]) continue;

@@ -566,11 +566,23 @@ __device__ inline void wave_merge_add(const InstBuf& b, InstDyn& d, bool act,
 struct View {
   uint64_t* X;
   uint64_t* Z;
-  double* C;
+  void* C;          // double[] or, when f32, float[]
   uint8_t* al;      // alive, current parity
   uint8_t* aln;     // alive, other parity
   uint32_t cap;
   int W;
+  bool f32;
+  // coefficient i as FP64 (exact for either storage)
+  __device__ double getc(uint32_t i) const {
+    return f32 ? (double)static_cast<const float*>(C)[i] : static_cast<const double*>(C)[i];
+  }
+  // stores c, rounded to FP32 when the storage is FP32
+  __device__ void setc(uint32_t i, double c) const {
+    if (f32)
+      static_cast<float*>(C)[i] = (float)c;
+    else
+      static_cast<double*>(C)[i] = c;
+  }
 };
 
 __device__ inline View view_of(const InstBuf& b, const InstDyn& d) {
@@ -583,7 +595,41 @@ __device__ inline View view_of(const InstBuf& b, const InstDyn& d) {
   v.aln = b.alive[h][p ^ 1];
   v.cap = b.cap;
   v.W = b.W;
+  v.f32 = b.f32 != 0;
   return v;
+}
+
+// The rotation of a pair on span{Q, R} (R = PQ, i P Q = sig R, i P R = -sig Q):
+//   c_Q' = cos c_Q - sig sin c_R,   c_R' = cos c_R + sig sin c_Q.
+// In FP32 mode cos and sin are rounded to FP32 once and the products and
+// sums are FP32 operations; results are returned widened to FP64 (exact).
+__device__ inline void rotate_pair(bool f32, double cs, double sn, int sig, double cq, double cr,
+                                   double* nq, double* nr) {
+  if (f32) {
+    const float c = (float)cs, s = (float)sn, q = (float)cq, r = (float)cr;
+    const float aq = c * q, bq = s * r, ar = c * r, br = s * q;
+    *nq = (double)(sig > 0 ? aq - bq : aq + bq);
+    *nr = (double)(sig > 0 ? ar + br : ar - br);
+  } else {
+    const double aq = cs * cq, bq = sn * cr, ar = cs * cr, br = sn * cq;
+    *nq = sig > 0 ? aq - bq : aq + bq;
+    *nr = sig > 0 ? ar + br : ar - br;
+  }
+}
+
+// Partner absent: c_Q' = cos c_Q and the new string R gets sig sin c_Q.
+__device__ inline void rotate_single(bool f32, double cs, double sn, int sig, double cq,
+                                     double* nq, double* child) {
+  if (f32) {
+    const float c = (float)cs, s = (float)sn, q = (float)cq;
+    const float t = s * q;
+    *nq = (double)(c * q);
+    *child = (double)(sig > 0 ? t : -t);
+  } else {
+    const double t = sn * cq;
+    *nq = cs * cq;
+    *child = sig > 0 ? t : -t;
+  }
 }
 
 __device__ inline void load_key(const View& v, uint32_t i, uint64_t* x, uint64_t* z) {
@@ -671,7 +717,7 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
     if (!anticommutes(qx, qz, px, pz, W)) {        // [P, Q] = 0: unchanged
       bool keep = true;
       if (full) {
-        const double c = v.C[i];
+        const double c = v.getc(i);
         keep = fabs(c) >= eps && !heavy(qx, qz);
       }
       v.aln[i] = keep ? 1 : 0;
@@ -686,13 +732,10 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
       if ((uint32_t)j < i) continue;                 // the partner's thread leads
       // Both Q and R = PQ live: the gate acts on span{Q, R} as a rotation.
       // i P R = -sig Q.
-      const double cq = v.C[i], cr = v.C[j];
-      const double aq = cs * cq, bq = sn * cr;
-      const double nq = (sig > 0) ? aq - bq : aq + bq;
-      const double ar = cs * cr, br = sn * cq;
-      const double nr = (sig > 0) ? ar + br : ar - br;
-      v.C[i] = nq;
-      v.C[j] = nr;
+      double nq, nr;
+      rotate_pair(v.f32, cs, sn, sig, v.getc(i), v.getc((uint32_t)j), &nq, &nr);
+      v.setc(i, nq);
+      v.setc((uint32_t)j, nr);
       const bool kq = fabs(nq) >= eps && !(full && heavy(qx, qz));
       const bool kr = fabs(nr) >= eps && !(full && heavy(rx, rz));
       v.aln[i] = kq ? 1 : 0;
@@ -700,11 +743,9 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
       if (kq) tally(qx, qz);
       if (kr) tally(rx, rz);
     } else {
-      const double cq = v.C[i];
-      const double nq = cs * cq;
-      const double t = sn * cq;
-      const double child = (sig > 0) ? t : -t;
-      v.C[i] = nq;
+      double nq, child;
+      rotate_single(v.f32, cs, sn, sig, v.getc(i), &nq, &child);
+      v.setc(i, nq);
       const bool kq = fabs(nq) >= eps && !(full && heavy(qx, qz));
       v.aln[i] = kq ? 1 : 0;
       if (kq) tally(qx, qz);
@@ -734,7 +775,7 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
       v.X[(size_t)w * v.cap + pos] = chx[k][w];
       v.Z[(size_t)w * v.cap + pos] = chz[k][w];
     }
-    v.C[pos] = chc[k];
+    v.setc(pos, chc[k]);
     v.aln[pos] = 1;
     gt_insert(b.gtab, b.hg_bits, gen, pos, hash_key(chx[k], chz[k], W, 0));
   }
@@ -844,7 +885,7 @@ struct MergeNarrowKind {
         uint64_t qx[kMaxW], qz[kMaxW];
         load_key(v, i, qx, qz);
         key = narrow_key(b, qx, qz);
-        c = fx_from_double(v.C[i], &range);
+        c = fx_from_double(v.getc(i), &range);
       }
       if (range) atomicOr(&d.status, ST_RANGE);
       wave_merge_add(b, d, act, key, c);
@@ -918,7 +959,7 @@ struct MergeWide2Kind {
           same = same && b.wrep[(size_t)w * b.cap + i] == b.wrep[(size_t)w * b.cap + owner];
       if (same) {
         bool range = false;
-        fx_atomic_add(&b.mfx[3 * (size_t)s], fx_from_double(v.C[i], &range));
+        fx_atomic_add(&b.mfx[3 * (size_t)s], fx_from_double(v.getc(i), &range));
         if (range) atomicOr(&d.status, ST_RANGE);
       } else {
         atomicOr(&d.status, ST_COLLISION);
@@ -939,7 +980,10 @@ __device__ inline void emit_term(const InstBuf& b, const InstDyn& d, uint32_t po
     b.x[h][(size_t)w * b.cap + pos] = x[w];
     b.z[h][(size_t)w * b.cap + pos] = z[w];
   }
-  b.c[h][pos] = c;
+  if (b.f32)
+    static_cast<float*>(b.c[h])[pos] = (float)c;
+  else
+    static_cast<double*>(b.c[h])[pos] = c;
   b.alive[h][0][pos] = 1;
   b.alive[h][1][pos] = 1;
   gt_insert(b.gtab, b.hg_bits, d.gen + 1, pos, hash_key(x, z, W, 0));
@@ -1097,7 +1141,7 @@ struct CompactKind {
       if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
       uint64_t x[kMaxW], z[kMaxW];
       load_key(v, i, x, z);
-      emit_term(b, d, pos, x, z, v.C[i]);
+      emit_term(b, d, pos, x, z, v.getc(i));
       if (ng.anti(x, z, W)) ++my_cnt;
     }
     add_counts(d, mine, my_cnt, sm);
@@ -1140,10 +1184,11 @@ struct ScanKind {
       if (i >= d.M || !v.al[i]) continue;
       uint64_t x[kMaxW], z[kMaxW];
       load_key(v, i, x, z);
-      double c = v.C[i];
+      double c = v.getc(i);
       if (type == OP_DAMP) {
-        c = c * op.table[weight(x, z, W)];
-        v.C[i] = c;
+        const double f = op.table[weight(x, z, W)];
+        c = v.f32 ? (double)((float)c * (float)f) : c * f;
+        v.setc(i, c);
       } else if (type == OP_TRUNC) {
         const bool keep = fabs(c) >= op.eps && !(op.wmax >= 0 && weight(x, z, W) > op.wmax);
         if (!keep) { v.al[i] = 0; continue; }
@@ -1317,7 +1362,10 @@ __global__ __launch_bounds__(kBlock) void k_grow(InstBuf src, InstBuf dst, InstD
         dst.x[0][(size_t)w * dst.cap + pos] = x[w];
         dst.z[0][(size_t)w * dst.cap + pos] = z[w];
       }
-      dst.c[0][pos] = v.C[i];
+      if (v.f32)
+        static_cast<float*>(dst.c[0])[pos] = static_cast<const float*>(v.C)[i];
+      else
+        static_cast<double*>(dst.c[0])[pos] = static_cast<const double*>(v.C)[i];
       dst.alive[0][0][pos] = 1;
       dst.alive[0][1][pos] = 1;
       gt_insert(dst.gtab, dst.hg_bits, 1u, pos, hash_key(x, z, W, 0));

@@ -5,7 +5,9 @@
 // -----------------------------------------
 // Two halves of structure-of-arrays buffers, each of capacity `cap`:
 //   x[h][w*cap + i], z[h][w*cap + i]   uint64 words of term i's masks
-//   c[h][i]                            FP64 coefficient
+//   c[h][i]                            coefficient: FP64, or FP32 when
+//                                      the handle was created with
+//                                      PP_F32_COMPENSATED (f32 != 0)
 //   alive[h][p][i]                     uint8 liveness, double-buffered (p)
 // Gates update coefficients in place and append new strings at the end of
 // the current half; a term that is truncated is only marked dead.  A
@@ -81,7 +83,7 @@ struct Op {
 struct InstBuf {
   uint64_t* x[2];
   uint64_t* z[2];
-  double* c[2];
+  void* c[2];            // double[cap], or float[cap] when f32
   uint8_t* alive[2][2];  // [half][parity]
   uint64_t* gtab;
   uint64_t* mkey;
@@ -99,6 +101,7 @@ struct InstBuf {
   int32_t W;
   int32_t group;
   uint32_t narrow;       // merge keys fit 64 bits exactly
+  uint32_t f32;          // coefficients stored and rotated in FP32
 };
 
 struct InstDyn {

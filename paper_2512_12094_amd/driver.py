@@ -80,16 +80,17 @@ class PauliSet:
     """A handle (pp_state) with the observable loaded and merged."""
 
     def __init__(self, n: int, group: str, obs_x, obs_z, obs_c, stream: int = 0,
-                 allocator=None):
-        self.n, self.group, self.W = n, group, n_words(n)
-        self.h = L.pp_create(n, group, obs_x, obs_z, obs_c, stream, allocator)
+                 allocator=None, dtype: str = "f64"):
+        self.n, self.group, self.W, self.dtype = n, group, n_words(n), dtype
+        self.h = L.pp_create(n, group, obs_x, obs_z, obs_c, stream, allocator, dtype)
         self._allocator = allocator
 
     @classmethod
     def from_program(cls, prog: Program, group: str | None = None, stream: int = 0,
-                     allocator=None):
+                     allocator=None, dtype: str = "f64"):
         x, z, c = observable_arrays(prog)
-        return cls(prog.n, prog.group if group is None else group, x, z, c, stream, allocator)
+        return cls(prog.n, prog.group if group is None else group, x, z, c, stream, allocator,
+                   dtype)
 
     def apply_layer(self, la: LayerArrays):
         L.pp_apply_layer(self.h, la.gx, la.gz, la.theta, self.W, 1, la.eps, la.wmax)
@@ -149,14 +150,14 @@ def run_layers(ps: PauliSet, layers, record_sizes=False):
 
 def propagate(prog: Program, group: str | None = None, keep_terms: bool = True,
               stream: int = 0, allocator=None, record_sizes: bool = False,
-              max_sublayers: int | None = None) -> GpuResult:
+              max_sublayers: int | None = None, dtype: str = "f64") -> GpuResult:
     """Algorithm 1 through the C ABI; returns the expectation (and the final
     representative set when keep_terms)."""
     layers = heisenberg_layers(prog)
     if max_sublayers is not None:
         layers = layers[:max_sublayers]
     t0 = time.perf_counter()
-    ps = PauliSet.from_program(prog, group, stream, allocator)
+    ps = PauliSet.from_program(prog, group, stream, allocator, dtype)
     sizes = run_layers(ps, layers, record_sizes)
     e = ps.expectation(prog.bloch)
     wall = time.perf_counter() - t0
@@ -214,13 +215,13 @@ def device_program(prog: Program) -> "DeviceProgram":
 
 
 def propagate_program(prog: Program, group: str | None = None, stream: int = 0,
-                      allocator=None, keep_terms: bool = False) -> GpuResult:
+                      allocator=None, keep_terms: bool = False, dtype: str = "f64") -> GpuResult:
     """Algorithm 1 as one device program (pp_program + pp_batch_run with one
     instance): all sub-layers are queued ahead and the host only checks the
     device status between sub-layers."""
     dp = device_program(prog)
     t0 = time.perf_counter()
-    ps = PauliSet.from_program(prog, group, stream, allocator)
+    ps = PauliSet.from_program(prog, group, stream, allocator, dtype)
     e = float(L.pp_batch_run([ps.h], [dp.h], stream)[0])
     wall = time.perf_counter() - t0
     prop, merged = ps.counters()
@@ -229,9 +230,9 @@ def propagate_program(prog: Program, group: str | None = None, stream: int = 0,
     return GpuResult(e, terms, prop, merged, [], wall)
 
 
-def batch_propagate(progs, stream: int, allocator=None, group=None):
+def batch_propagate(progs, stream: int, allocator=None, group=None, dtype: str = "f64"):
     """All programs in one batched run; returns (expectations, handles)."""
-    sets = [PauliSet.from_program(p, group, stream, allocator) for p in progs]
+    sets = [PauliSet.from_program(p, group, stream, allocator, dtype) for p in progs]
     dprogs = [DeviceProgram(p) for p in progs]
     t0 = time.perf_counter()
     e = L.pp_batch_run([s.h for s in sets], [d.h for d in dprogs], stream)

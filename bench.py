@@ -385,6 +385,7 @@ def main():
             print(f"[bench] plain PP done", file=sys.stderr, flush=True)
         traffic, traffic_src = pmc_traffic(None)
         roof["traffic"] = round(traffic, 1) if traffic is not None else None
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
         roof["traffic_source"] = traffic_src
         mp = None
         if not args.no_merge_pass:

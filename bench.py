@@ -115,14 +115,18 @@ def run_steps(prog, group, steps, stream, alloc, profile, mode="program"):
     return wall, totals, kern, e
 
 
-def merge_pass(stream, alloc, log2n):
+MERGE_KINDS = ("merge_narrow", "merge_wide1", "merge_wide2", "part_sort", "part_agg",
+               "merge_collect")
+
+
+def merge_pass(stream, alloc, log2n, dup=32):
     """Exact merge of 2^log2n records: random weight <= 8 Z_32 strings, each
-    emitted in 32 random rotations (Algorithm 1 step 1 on that stream)."""
+    emitted in `dup` random rotations (Algorithm 1 step 1 on that stream).
+    The duration is the sum of the merge kernels' HIP-event intervals."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import workloads as W
-    import numpy as np
     import torch
-    x, z, c = W.merge_stress_records(log2n, 32, seed=7)
+    x, z, c = W.merge_stress_records(log2n, dup, seed=7)
     L.pp_profile(None, True)
     torch.cuda.synchronize()
     h = L.pp_create(32, "Zn", x.reshape(-1, 1), z.reshape(-1, 1), c, stream, alloc)
@@ -130,11 +134,11 @@ def merge_pass(stream, alloc, log2n):
     wc = L.pp_work_counters(h)
     L.pp_destroy(h)
     L.pp_profile(None, False)
-    ms = prof["merge_narrow"][1] + prof["merge_collect"][1]
+    ms = sum(prof[k][1] for k in MERGE_KINDS)
     nbytes = merge_bytes(wc)
     return dict(records=int(wc["merge_in"]), representatives=int(wc["merge_out"]),
-                ms=round(ms, 4), insert_ms=round(prof["merge_narrow"][1], 4),
-                collect_ms=round(prof["merge_collect"][1], 4),
+                rotations_per_string=dup, ms=round(ms, 4),
+                kernels_ms={k: round(prof[k][1], 4) for k in MERGE_KINDS if prof[k][0]},
                 records_per_s=wc["merge_in"] / (ms * 1e-3),
                 algorithmic_GBs=round(nbytes / (ms * 1e-3) / 1e9, 1),
                 frac_of_hbm=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
@@ -152,8 +156,10 @@ def prefix(prog, k):
 def batched_leg(stream, alloc, count, sublayers):
     """Batched ring instances (uneven n, depth, angles, thresholds; each cut
     to its first `sublayers` sub-layers): one batched run against a loop of
-    single-instance runs over the same instances.  Both include creating
-    each instance's set from its observable."""
+    single-instance runs over the same instances, and the batched run with
+    FP32 coefficients (largest relative deviation of its expectations from
+    the FP64 ones).  All include creating each instance's set from its
+    observable."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
     from paper_2512_12094_amd import workloads as W
@@ -171,8 +177,8 @@ def batched_leg(stream, alloc, count, sublayers):
             ps.close()
         return es, units
 
-    def batch():
-        sets = [driver.PauliSet.from_program(p, None, stream, alloc) for p in progs]
+    def batch(dtype="f64"):
+        sets = [driver.PauliSet.from_program(p, None, stream, alloc, dtype) for p in progs]
         e = L.pp_batch_run([s.h for s in sets], [d.h for d in dps], stream)
         units = 0
         for s in sets:
@@ -182,7 +188,8 @@ def batched_leg(stream, alloc, count, sublayers):
         return [float(v) for v in e], units
 
     out = {}
-    for name, fn in (("per_instance", solo_loop), ("batched", batch)):
+    for name, fn in (("per_instance", solo_loop), ("batched", batch),
+                     ("batched_f32", lambda: batch("f32"))):
         fn()                                   # warm (graph capture, allocator)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -191,7 +198,10 @@ def batched_leg(stream, alloc, count, sublayers):
         wall = time.perf_counter() - t0
         out[name] = dict(value=units / wall, unit="terms/s", wall_s=round(wall, 4), units=units)
         out[name + "_e"] = es
-    same = sum(a == b for a, b in zip(out.pop("per_instance_e"), out.pop("batched_e")))
+    e32 = out.pop("batched_f32_e")
+    same = sum(a == b for a, b in zip(out.pop("per_instance_e"), out["batched_e"]))
+    out["batched_f32"]["max_rel_dev_from_f64"] = max(
+        abs(a - b) / max(abs(b), 1e-300) for a, b in zip(e32, out.pop("batched_e")))
     out.update(instances=len(progs), sublayers_each=sublayers,
                gates=sum(p.n_gates for p in progs),
                speedup=round(out["batched"]["value"] / out["per_instance"]["value"], 3),
@@ -391,6 +401,10 @@ def main():
         if not args.no_merge_pass:
             merge_pass(stream, alloc, args.merge_log2n)            # warm
             mp = merge_pass(stream, alloc, args.merge_log2n)
+            mp["other_duplicate_factors"] = [
+                {k: v for k, v in merge_pass(stream, alloc, args.merge_log2n, d).items()
+                 if k in ("rotations_per_string", "representatives", "ms", "algorithmic_GBs",
+                          "frac_of_hbm")} for d in (1, 4)]
             print(f"[bench] merge pass done", file=sys.stderr, flush=True)
         batched = served = None
         if not args.no_batched:

@@ -200,7 +200,9 @@ enum {
   PP_K_COMPACT = 5,       /* plain-PP layer end: drop dead entries       */
   PP_K_SCAN = 6,          /* damping / truncation / recount / expectation */
   PP_K_GROW = 7,          /* store growth                                */
-  PP_KERNEL_KINDS = 8
+  PP_K_PART_SORT = 8,     /* partitioned merge, pass 1: sort tiles       */
+  PP_K_PART_AGG = 9,      /* partitioned merge, pass 2: LDS exact sums   */
+  PP_KERNEL_KINDS = 10
 };
 
 /*

@@ -198,7 +198,7 @@ def pp_counters(h):
 
 
 KERNELS = ["gate", "merge_narrow", "merge_wide1", "merge_wide2", "merge_collect", "compact",
-           "scan", "grow"]
+           "scan", "grow", "part_sort", "part_agg"]
 
 
 def pp_work_counters(h):

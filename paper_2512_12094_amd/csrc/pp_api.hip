@@ -233,6 +233,16 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   ok = ok && (nb.mkey = (uint64_t*)take(sizeof(uint64_t) * nm));
   ok = ok && (nb.mfx = (uint64_t*)take(3 * sizeof(uint64_t) * nm));
   ok = ok && (nb.accs = (uint64_t*)take(kAccBytes));
+  // staging of the partitioned merge (narrow keys, not S_n, large stores)
+  nb.pkey = nullptr;
+  nb.pcoef = nullptr;
+  nb.ppre = nullptr;
+  if (nb.narrow && s->group != PP_GROUP_PERMUTATION && cap >= kPartMin) {
+    const size_t tiles = (cap + kPartTile - 1) / kPartTile;
+    ok = ok && (nb.pkey = (uint64_t*)take(sizeof(uint64_t) * tiles * kPartTile));
+    ok = ok && (nb.pcoef = (double*)take(sizeof(double) * tiles * kPartTile));
+    ok = ok && (nb.ppre = (uint16_t*)take(sizeof(uint16_t) * tiles * (kParts + 1)));
+  }
   const bool wide = !nb.narrow;
   nb.mown = nullptr;
   nb.wrep = nullptr;
@@ -311,6 +321,8 @@ SoloFn solo_of(int kind, bool big) {
     case PP_K_MERGE_WIDE2: return PP_PICK(k_merge_wide2_solo, si);
     case PP_K_MERGE_COLLECT: return PP_PICK(k_merge_collect_solo, si);
     case PP_K_COMPACT: return PP_PICK(k_compact_solo, si);
+    case PP_K_PART_SORT: return &k_part_sort_solo;
+    case PP_K_PART_AGG: return &k_part_agg_solo;
     default: return PP_PICK(k_scan_op_solo, si);
   }
 }
@@ -381,6 +393,10 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
         out->push_back(PP_K_COMPACT);
       } else if (s->buf.narrow) {
         out->push_back(PP_K_MERGE_NARROW);
+        if (s->buf.pkey && !s->buf.nopart) {   // large merges: partitioned
+          out->push_back(PP_K_PART_SORT);
+          out->push_back(PP_K_PART_AGG);
+        }
         out->push_back(PP_K_MERGE_COLLECT);
       } else {
         out->push_back(PP_K_MERGE_WIDE1);
@@ -416,9 +432,11 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
         run_ev = prof_begin(s, kind);
       }
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
-      const int grid = launch_blocks(elems, items_of(kind, big));
+      const int grid = kind == PP_K_PART_AGG    ? kParts
+                       : kind == PP_K_PART_SORT ? launch_blocks(elems, kPartTile / kBlock)
+                                                : launch_blocks(elems, items_of(kind, big));
       Solo S;
-      S.b = s->d_buf;
+      S.b = s->buf;
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
@@ -448,6 +466,7 @@ int run_ops(pp_state* s, std::vector<Op> ops, const std::vector<double>& tab,
   for (const auto& r : refs) ops[r.first].table = s->d_tab + r.second;
   s->buf.prog = s->d_ops;
   s->buf.prog_len = (uint32_t)ops.size();
+  s->buf.nopart = 0;
   s->batch_prog = nullptr;
   {
     // ops, tables and the buffer descriptor go through pinned staging
@@ -1133,6 +1152,7 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation) {
   const size_t len = p->ops.size();
   s->buf.prog = p->d_ops;
   s->buf.prog_len = (uint32_t)len;
+  s->buf.nopart = 0;
   s->batch_prog = p;
   if ((rc = upload_buf(s))) return rc;
   hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, st, s->d_dyn, 0u);
@@ -1240,8 +1260,12 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
       s->buf.prog = programs[i]->d_ops;
       s->buf.prog_len = (uint32_t)programs[i]->ops.size();
       s->batch_prog = programs[i];
+      s->buf.nopart = 1;                   // the batched steps have no partitioned merge
       if ((rc = upload_buf(s))) return rc;
       hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, stream, s->d_dyn, 0u);
+    } else if (!s->buf.nopart) {
+      s->buf.nopart = 1;
+      if ((rc = upload_buf(s))) return rc;
     }
     b->h_bufp[i] = s->d_buf;
     b->h_dynp[i] = s->d_dyn;

@@ -16,7 +16,7 @@ struct Fx {
   uint64_t l0, l1, l2;
 };
 
-__host__ __device__ inline Fx fx_neg(Fx v) {
+__host__ __device__ __forceinline__ Fx fx_neg(Fx v) {
   Fx r;
   r.l0 = ~v.l0 + 1;
   const uint64_t c0 = (r.l0 == 0) ? 1u : 0u;
@@ -26,7 +26,7 @@ __host__ __device__ inline Fx fx_neg(Fx v) {
   return r;
 }
 
-__host__ __device__ inline Fx fx_add(Fx a, Fx b) {
+__host__ __device__ __forceinline__ Fx fx_add(Fx a, Fx b) {
   Fx r;
   r.l0 = a.l0 + b.l0;
   const uint64_t c0 = r.l0 < a.l0 ? 1u : 0u;
@@ -41,7 +41,7 @@ __host__ __device__ inline Fx fx_add(Fx a, Fx b) {
 // c * 2^kFxFrac as an integer: exact for |c| >= 2^(52 - kFxFrac), rounded
 // to the nearest multiple of 2^-kFxFrac below that; |c| >= 2^54 (or a NaN/Inf)
 // raises *range.
-__host__ __device__ inline Fx fx_from_double(double c, bool* range) {
+__host__ __device__ __forceinline__ Fx fx_from_double(double c, bool* range) {
   Fx r{0, 0, 0};
   const uint64_t bits = __builtin_bit_cast(uint64_t, c);
   const bool neg = (bits >> 63) != 0;
@@ -65,7 +65,7 @@ __host__ __device__ inline Fx fx_from_double(double c, bool* range) {
 }
 
 // Rounds the 192-bit value to the nearest double (ties to even).
-__host__ __device__ inline double fx_to_double(Fx v) {
+__host__ __device__ __forceinline__ double fx_to_double(Fx v) {
   const bool neg = (int64_t)v.l2 < 0;
   if (neg) v = fx_neg(v);
   int p;

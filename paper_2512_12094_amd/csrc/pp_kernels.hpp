@@ -23,6 +23,11 @@ constexpr int kItems = 4;
 constexpr int kTile = kBlock * kItems;
 constexpr int kWaves = kBlock / 64;
 
+// Loops over the W words of a string run to the compile-time kMaxW with a
+// guard, so per-string arrays of kMaxW words are indexed by constants and
+// stay in registers (a runtime trip count would put them in scratch).
+#define PP_FOR_W(w, lo, n, lim) _Pragma("unroll") for (int w = (lo); w < (lim); ++w) if (w < (n))
+
 struct Ctx {
   const InstBuf* const* bufs;
   InstDyn* const* dyns;
@@ -35,7 +40,7 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 // splitmix64 finalizer (Steele, Lea, Flood, "Fast splittable pseudorandom
 // number generators", OOPSLA 2014): a bijective 64-bit mixer.
-__host__ __device__ inline uint64_t mix64(uint64_t v) {
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t v) {
   v ^= v >> 30;
   v *= 0xbf58476d1ce4e5b9ull;
   v ^= v >> 27;
@@ -44,10 +49,10 @@ __host__ __device__ inline uint64_t mix64(uint64_t v) {
   return v;
 }
 
-__device__ inline uint64_t hash_key(const uint64_t* x, const uint64_t* z, int W,
+__device__ __forceinline__ uint64_t hash_key(const uint64_t* x, const uint64_t* z, int W,
                                     uint64_t seed) {
   uint64_t h = mix64(seed ^ 0x9e3779b97f4a7c15ull);
-  for (int w = 0; w < W; ++w) {
+  PP_FOR_W(w, 0, W, kMaxW) {
     h = mix64(h ^ x[w]);
     h = mix64(h ^ z[w] ^ 0x632be59bd9b4e019ull);
   }
@@ -56,16 +61,16 @@ __device__ inline uint64_t hash_key(const uint64_t* x, const uint64_t* z, int W,
 
 // Symplectic product: P and Q anticommute iff the number of qubits where
 // x_Q z_P + z_Q x_P = 1 is odd.
-__device__ inline bool anticommutes(const uint64_t* qx, const uint64_t* qz,
+__device__ __forceinline__ bool anticommutes(const uint64_t* qx, const uint64_t* qz,
                                     const uint64_t* px, const uint64_t* pz, int W) {
   uint32_t par = 0;
-  for (int w = 0; w < W; ++w) par += __popcll((qx[w] & pz[w]) ^ (qz[w] & px[w]));
+  PP_FOR_W(w, 0, W, kMaxW) par += __popcll((qx[w] & pz[w]) ^ (qz[w] & px[w]));
   return par & 1u;
 }
 
-__device__ inline int weight(const uint64_t* x, const uint64_t* z, int W) {
+__device__ __forceinline__ int weight(const uint64_t* x, const uint64_t* z, int W) {
   int s = 0;
-  for (int w = 0; w < W; ++w) s += __popcll(x[w] | z[w]);
+  PP_FOR_W(w, 0, W, kMaxW) s += __popcll(x[w] | z[w]);
   return s;
 }
 
@@ -73,11 +78,11 @@ __device__ inline int weight(const uint64_t* x, const uint64_t* z, int W) {
 // phi = |px&pz| + |qx&qz| + 2|pz&qx| - |rx&rz| (mod 4) and R = P xor Q.
 // For anticommuting P, Q the phi is odd and iPQ = i^{1+phi} R = sigma R with
 // sigma = +1 for phi = 3 and -1 for phi = 1.
-__device__ inline int product_sign(const uint64_t* px, const uint64_t* pz,
+__device__ __forceinline__ int product_sign(const uint64_t* px, const uint64_t* pz,
                                    const uint64_t* qx, const uint64_t* qz,
                                    const uint64_t* rx, const uint64_t* rz, int W) {
   int phi = 0;
-  for (int w = 0; w < W; ++w)
+  PP_FOR_W(w, 0, W, kMaxW)
     phi += __popcll(px[w] & pz[w]) + __popcll(qx[w] & qz[w]) +
            2 * __popcll(pz[w] & qx[w]) - __popcll(rx[w] & rz[w]);
   return ((phi & 3) == 3) ? 1 : -1;
@@ -85,7 +90,7 @@ __device__ inline int product_sign(const uint64_t* px, const uint64_t* pz,
 
 // int(a) < int(b) in the paper's base-4 order (qubit q = digit of weight
 // 4^q, digit = (x xor z) + 2 z: I0 X1 Y2 Z3), one word.
-__device__ inline bool int_less1(uint64_t xa, uint64_t za, uint64_t xb, uint64_t zb) {
+__device__ __forceinline__ bool int_less1(uint64_t xa, uint64_t za, uint64_t xb, uint64_t zb) {
   const uint64_t d = (xa ^ xb) | (za ^ zb);
   if (d == 0) return false;
   const int t = 63 - __clzll(d);
@@ -96,7 +101,7 @@ __device__ inline bool int_less1(uint64_t xa, uint64_t za, uint64_t xb, uint64_t
 
 // rotate right by j within n bits (0 <= j < n): bit (q + j) mod n -> bit q,
 // i.e. T^j (qubit q of T^j s is qubit q + j of s).
-__device__ inline uint64_t rotr_n(uint64_t v, int j, int n, uint64_t mask) {
+__device__ __forceinline__ uint64_t rotr_n(uint64_t v, int j, int n, uint64_t mask) {
   if (j == 0) return v;
   return ((v >> j) | (v << (n - j))) & mask;
 }
@@ -106,7 +111,7 @@ __device__ inline uint64_t rotr_n(uint64_t v, int j, int n, uint64_t mask) {
 // on the most significant qubits (any other one has a non-identity digit
 // among those top digits), so only the translations that align a longest
 // run with the top are compared; a string without identities compares all.
-__device__ inline void canon_translation(uint64_t x, uint64_t z, int n,
+__device__ __forceinline__ void canon_translation(uint64_t x, uint64_t z, int n,
                                          uint64_t* rx, uint64_t* rz) {
   const uint64_t mask = (n == 64) ? ~0ull : ((1ull << n) - 1);
   const uint64_t idm = ~(x | z) & mask;
@@ -119,17 +124,23 @@ __device__ inline void canon_translation(uint64_t x, uint64_t z, int n,
     }
   } else {
     // S_len bit a <=> qubits a .. a+len-1 (cyclic) are all identities.
+    // (loops unrolled over the 7 levels so that pw stays in registers)
     uint64_t pw[7];
     pw[0] = idm;
     int nb = 1;
-    while (nb < 7 && (1 << nb) <= n) {
-      pw[nb] = pw[nb - 1] & rotr_n(pw[nb - 1], (1 << (nb - 1)) % n, n, mask);
-      ++nb;
+#pragma unroll
+    for (int k = 1; k < 7; ++k) {
+      pw[k] = 0;
+      if ((1 << k) <= n) {
+        pw[k] = pw[k - 1] & rotr_n(pw[k - 1], (1 << (k - 1)) % n, n, mask);
+        nb = k + 1;
+      }
     }
     uint64_t cur = mask;
     int len = 0;
-    for (int b = nb - 1; b >= 0; --b) {
-      if (len + (1 << b) > n - 1) continue;
+#pragma unroll
+    for (int b = 6; b >= 0; --b) {
+      if (b >= nb || len + (1 << b) > n - 1) continue;
       const uint64_t cand = cur & rotr_n(pw[b], len, n, mask);
       if (cand) { cur = cand; len += 1 << b; }
     }
@@ -150,10 +161,10 @@ __device__ inline void canon_translation(uint64_t x, uint64_t z, int n,
 }
 
 // Algorithm 3: counts of X, Y, Z letters.
-__device__ inline void perm_counts(const uint64_t* x, const uint64_t* z, int W,
+__device__ __forceinline__ void perm_counts(const uint64_t* x, const uint64_t* z, int W,
                                    uint32_t* nx, uint32_t* ny, uint32_t* nz) {
   uint32_t a = 0, b = 0, c = 0;
-  for (int w = 0; w < W; ++w) {
+  PP_FOR_W(w, 0, W, kMaxW) {
     a += __popcll(x[w] & ~z[w]);
     b += __popcll(x[w] & z[w]);
     c += __popcll(z[w] & ~x[w]);
@@ -162,10 +173,10 @@ __device__ inline void perm_counts(const uint64_t* x, const uint64_t* z, int W,
 }
 
 // Z^{nZ} Y^{nY} X^{nX} from qubit 0: z bits [0, nZ+nY), x bits [nZ, nZ+nY+nX).
-__device__ inline void perm_rep(uint32_t nx, uint32_t ny, uint32_t nz, int W,
+__device__ __forceinline__ void perm_rep(uint32_t nx, uint32_t ny, uint32_t nz, int W,
                                 uint64_t* rx, uint64_t* rz) {
   const uint32_t zlo = 0, zhi = nz + ny, xlo = nz, xhi = nz + ny + nx;
-  for (int w = 0; w < W; ++w) {
+  PP_FOR_W(w, 0, W, kMaxW) {
     const uint32_t lo = 64u * w, hi = lo + 64u;
     auto range = [&](uint32_t a, uint32_t b) -> uint64_t {  // bits [a,b) of this word
       const uint32_t s = a > lo ? a : lo, e = b < hi ? b : hi;
@@ -180,7 +191,7 @@ __device__ inline void perm_rep(uint32_t nx, uint32_t ny, uint32_t nz, int W,
 }
 
 // Narrow merge key: the representative itself, packed into 64 bits.
-__device__ inline uint64_t narrow_key(const InstBuf& b, const uint64_t* x,
+__device__ __forceinline__ uint64_t narrow_key(const InstBuf& b, const uint64_t* x,
                                       const uint64_t* z) {
   if (b.group == 2) {
     uint32_t nx, ny, nz;
@@ -192,7 +203,7 @@ __device__ inline uint64_t narrow_key(const InstBuf& b, const uint64_t* x,
   return rx | (rz << 32);   // n <= 32
 }
 
-__device__ inline void narrow_decode(const InstBuf& b, uint64_t key, uint64_t* rx,
+__device__ __forceinline__ void narrow_decode(const InstBuf& b, uint64_t key, uint64_t* rx,
                                      uint64_t* rz) {
   if (b.group == 2) {
     perm_rep((uint32_t)(key & 0xff), (uint32_t)((key >> 8) & 0xff),
@@ -201,37 +212,37 @@ __device__ inline void narrow_decode(const InstBuf& b, uint64_t key, uint64_t* r
   }
   rx[0] = key & 0xffffffffull;
   rz[0] = key >> 32;
-  for (int w = 1; w < b.W; ++w) { rx[w] = 0; rz[w] = 0; }
+  PP_FOR_W(w, 1, b.W, kMaxW) { rx[w] = 0; rz[w] = 0; }
 }
 
 // Representative as a string (wide path: Z_n with n <= 64, or identity).
-__device__ inline void rep_string(const InstBuf& b, const uint64_t* x, const uint64_t* z,
+__device__ __forceinline__ void rep_string(const InstBuf& b, const uint64_t* x, const uint64_t* z,
                                   uint64_t* rx, uint64_t* rz) {
   if (b.group == 1) {
     canon_translation(x[0], z[0], b.n, rx, rz);
-    for (int w = 1; w < b.W; ++w) { rx[w] = 0; rz[w] = 0; }
+    PP_FOR_W(w, 1, b.W, kMaxW) { rx[w] = 0; rz[w] = 0; }
   } else if (b.group == 2) {
     uint32_t nx, ny, nz;
     perm_counts(x, z, b.W, &nx, &ny, &nz);
     perm_rep(nx, ny, nz, b.W, rx, rz);
   } else {
-    for (int w = 0; w < b.W; ++w) { rx[w] = x[w]; rz[w] = z[w]; }
+    PP_FOR_W(w, 0, b.W, kMaxW) { rx[w] = x[w]; rz[w] = z[w]; }
   }
 }
 
-__device__ inline double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
 // Exclusive block scan of one value per thread; *total = block sum.
 // s_tmp needs kWaves + 1 entries.  Contains __syncthreads.
-__device__ inline uint32_t block_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t x = v;
   for (int o = 1; o < 64; o <<= 1) {
@@ -252,7 +263,7 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* s_tmp, uint32_t* tot
   return r;
 }
 
-__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
   uint32_t t;
   block_scan(v, s_tmp, &t);
   return t;
@@ -260,20 +271,20 @@ __device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
 
 // Makes the wave wait for a returned value (an atomic's result) before it
 // issues anything after this point; emits no instruction of its own.
-__device__ inline void consume(uint64_t v) { asm volatile("" : : "v"(v)); }
+__device__ __forceinline__ void consume(uint64_t v) { asm volatile("" : : "v"(v)); }
 
-__device__ inline uint32_t ld_agent(const uint32_t* p) {
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline uint64_t ld_agent(const uint64_t* p) {
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Launches of up to kTreeMin working blocks count on one line (one atomic
 // round trip less on the critical path); larger ones use the shards.
 constexpr uint32_t kTreeMin = 256;
-__device__ inline uint32_t acc_shards(uint32_t workers) {
+__device__ __forceinline__ uint32_t acc_shards(uint32_t workers) {
   return workers > kTreeMin ? (uint32_t)kAccShards : 1u;
 }
 
@@ -282,7 +293,7 @@ __device__ inline uint32_t acc_shards(uint32_t workers) {
 // returned value is consumed so that the add has completed before the block
 // reports itself done).
 // With one shard the counts go to d.acc itself.
-__device__ inline void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint32_t live,
+__device__ __forceinline__ void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint32_t live,
                                uint32_t cnt) {
   const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
   if (v) {
@@ -294,7 +305,7 @@ __device__ inline void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint3
 }
 
 // Last block, one thread: moves the shard totals into d.acc and clears them.
-__device__ inline void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
+__device__ __forceinline__ void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
   if (nsh == 1) {
     d.acc = ld_agent(&d.acc);
     return;
@@ -306,7 +317,7 @@ __device__ inline void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
 }
 
 // live = low half, anticommuting count = high half; clears the accumulator.
-__device__ inline void take_acc(InstDyn& d) {
+__device__ __forceinline__ void take_acc(InstDyn& d) {
   const uint64_t v = d.acc;
   d.live = (uint32_t)v;
   d.count = (uint32_t)(v >> 32);
@@ -324,7 +335,7 @@ __device__ inline void take_acc(InstDyn& d) {
 // issued only after the level below returned, so no fence is needed.
 // `fence` adds one for a last block that reads plain stores of other blocks
 // (the multi-instance runner keeps it).
-__device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers,
+__device__ __forceinline__ bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t workers,
                                   bool fence = false) {
   if (workers <= 1) return true;       // block 0 did all the work itself
   __syncthreads();
@@ -357,14 +368,14 @@ __device__ inline bool last_block(uint32_t* sync, uint32_t* s_flag, uint32_t wor
 
 // Blocks beyond the tile count leave at once; block 0 always stays so that
 // the program counters advance even when no instance has work.
-__device__ inline uint32_t worker_count(uint32_t total) {
+__device__ __forceinline__ uint32_t worker_count(uint32_t total) {
   return total < gridDim.x ? (total ? total : 1u) : gridDim.x;
 }
 
 // Prefix of tiles over instances: s_pref[i] = first tile of instance i.
 // tiles(i) returns the tile count of instance i (0 when not served).
 template <class F>
-__device__ inline uint32_t plan_tiles(int ninst, F tiles, uint32_t* s_pref, uint32_t* s_tmp) {
+__device__ __forceinline__ uint32_t plan_tiles(int ninst, F tiles, uint32_t* s_pref, uint32_t* s_tmp) {
   constexpr int kPer = kMaxInst / kBlock;
   uint32_t loc[kPer];
   uint32_t sum = 0;
@@ -387,7 +398,7 @@ __device__ inline uint32_t plan_tiles(int ninst, F tiles, uint32_t* s_pref, uint
   return total;
 }
 
-__device__ inline int find_inst(const uint32_t* s_pref, int ninst, uint32_t t) {
+__device__ __forceinline__ int find_inst(const uint32_t* s_pref, int ninst, uint32_t t) {
   int lo = 0, hi = ninst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -397,9 +408,9 @@ __device__ inline int find_inst(const uint32_t* s_pref, int ninst, uint32_t t) {
 }
 
 template <int IT>
-__device__ inline uint32_t ceil_tiles(uint32_t n) { return (n + kBlock * IT - 1) / (kBlock * IT); }
+__device__ __forceinline__ uint32_t ceil_tiles(uint32_t n) { return (n + kBlock * IT - 1) / (kBlock * IT); }
 
-__device__ inline const Op* cur_op(const InstBuf& b, const InstDyn& d) {
+__device__ __forceinline__ const Op* cur_op(const InstBuf& b, const InstDyn& d) {
   return d.pc < b.prog_len ? &b.prog[d.pc] : nullptr;
 }
 
@@ -410,10 +421,14 @@ __device__ inline const Op* cur_op(const InstBuf& b, const InstDyn& d) {
 // Entries appended by the running gate (index >= Mstart) are skipped: no
 // gate ever looks up a string that the same gate appends, except the
 // appending thread itself, which knows it is absent.
-__device__ inline int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mstart,
-                                    const uint8_t* alive, const uint64_t* X,
-                                    const uint64_t* Z, const uint64_t* rx,
-                                    const uint64_t* rz) {
+// The candidate's liveness, key words and coefficient are loaded together
+// (a slot of the current generation always holds an index below cap), so a
+// probe costs one dependent round trip after the slot itself; *c receives
+// the found entry's coefficient.
+template <class V>
+__device__ __forceinline__ int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mstart,
+                                             const V& view, const uint64_t* rx,
+                                             const uint64_t* rz, double* c) {
   const int W = b.W;
   const uint32_t cap = b.cap;
   const uint64_t mask = (1ull << b.hg_bits) - 1;
@@ -422,11 +437,20 @@ __device__ inline int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mst
     const uint64_t v = b.gtab[s];
     if ((uint32_t)(v >> 32) != gen) return -1;
     const uint32_t idx = (uint32_t)v;
-    if (idx < Mstart && alive[idx]) {
+    const uint8_t a = view.al[idx];
+    uint64_t kx[kMaxW], kz[kMaxW];
+    PP_FOR_W(w, 0, W, kMaxW) {
+      kx[w] = view.X[(size_t)w * cap + idx];
+      kz[w] = view.Z[(size_t)w * cap + idx];
+    }
+    const double cj = view.getc(idx);
+    if (idx < Mstart && a) {
       bool eq = true;
-      for (int w = 0; w < W; ++w)
-        eq = eq && X[(size_t)w * cap + idx] == rx[w] && Z[(size_t)w * cap + idx] == rz[w];
-      if (eq) return idx;
+      PP_FOR_W(w, 0, W, kMaxW) eq = eq && kx[w] == rx[w] && kz[w] == rz[w];
+      if (eq) {
+        *c = cj;
+        return idx;
+      }
     }
     s = (s + 1) & mask;
   }
@@ -436,7 +460,7 @@ __device__ inline int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mst
 // Inserts index `idx` (insert-only: the caller guarantees that no live entry
 // with this key exists and that no thread compares keys of this generation
 // in the same launch, so no key is read here).
-__device__ inline void gt_insert(uint64_t* gtab, uint32_t bits, uint32_t gen, uint32_t idx,
+__device__ __forceinline__ void gt_insert(uint64_t* gtab, uint32_t bits, uint32_t gen, uint32_t idx,
                                  uint64_t h) {
   const uint64_t mask = (1ull << bits) - 1;
   uint64_t s = h >> (64 - bits);
@@ -459,7 +483,7 @@ __device__ inline void gt_insert(uint64_t* gtab, uint32_t bits, uint32_t gen, ui
 // acc += v with one integer atomic per non-zero limb; the carries returned
 // by the lower limbs are added into the next limb, so the final value is the
 // exact sum of all contributions whatever their order.
-__device__ inline void fx_atomic_add(uint64_t* acc, Fx v) {
+__device__ __forceinline__ void fx_atomic_add(uint64_t* acc, Fx v) {
   unsigned long long* a = (unsigned long long*)acc;
   uint64_t c0 = 0;
   if (v.l0) {
@@ -478,7 +502,7 @@ __device__ inline void fx_atomic_add(uint64_t* acc, Fx v) {
 
 // As fx_atomic_add, but every limb's atomic returns and the last value is
 // consumed, so the whole addition has completed when this returns.
-__device__ inline void fx_atomic_add_wait(uint64_t* acc, Fx v) {
+__device__ __forceinline__ void fx_atomic_add_wait(uint64_t* acc, Fx v) {
   unsigned long long* a = (unsigned long long*)acc;
   const uint64_t o0 = atomicAdd(&a[0], (unsigned long long)v.l0);
   const uint64_t c0 = (o0 + v.l0 < o0) ? 1u : 0u;
@@ -489,7 +513,7 @@ __device__ inline void fx_atomic_add_wait(uint64_t* acc, Fx v) {
   consume(atomicAdd(&a[2], (unsigned long long)(v.l2 + c1)));
 }
 
-__device__ inline Fx wave_sum_fx(Fx v) {
+__device__ __forceinline__ Fx wave_sum_fx(Fx v) {
   for (int o = 32; o > 0; o >>= 1) {
     Fx w;
     w.l0 = __shfl_xor(v.l0, o, 64);
@@ -505,14 +529,14 @@ __device__ inline Fx wave_sum_fx(Fx v) {
 // ---------------------------------------------------------------------------
 // Slots of the merge table used by a merge of the current d.M records:
 // at least twice the records (load factor <= 1/2).
-__device__ inline uint32_t merge_bits(const InstBuf& b, const InstDyn& d) {
+__device__ __forceinline__ uint32_t merge_bits(const InstBuf& b, const InstDyn& d) {
   const uint64_t need = 2ull * d.M;
   const uint32_t bits = need > 1 ? 64u - (uint32_t)__clzll((long long)(need - 1)) : 0u;
   return bits < 10u ? (10u < b.hm_bits ? 10u : b.hm_bits) : (bits < b.hm_bits ? bits : b.hm_bits);
 }
 
 // Find-or-insert of a 64-bit key; returns the slot.
-__device__ inline uint64_t mt_slot(uint64_t* mkey, uint32_t bits, uint64_t key) {
+__device__ __forceinline__ uint64_t mt_slot(uint64_t* mkey, uint32_t bits, uint64_t key) {
   const uint64_t mask = (1ull << bits) - 1;
   uint64_t s = mix64(key) >> (64 - bits);
   for (uint64_t probe = 0; probe <= mask; ++probe) {
@@ -528,7 +552,7 @@ __device__ inline uint64_t mt_slot(uint64_t* mkey, uint32_t bits, uint64_t key) 
   return kEmpty64;   // unreachable: the table is at most half full
 }
 
-__device__ inline void mt_add(const InstBuf& b, InstDyn& d, uint64_t key, Fx v) {
+__device__ __forceinline__ void mt_add(const InstBuf& b, InstDyn& d, uint64_t key, Fx v) {
   if (key == kEmpty64) {        // the one key equal to the empty marker
     fx_atomic_add(d.special_fx, v);
     atomicOr(&d.special, 1u);
@@ -541,7 +565,7 @@ __device__ inline void mt_add(const InstBuf& b, InstDyn& d, uint64_t key, Fx v) 
 // Adds (key, v) of every active lane, first combining lanes of one wave
 // that share a key (large orbits, e.g. S_n, collapse many records onto few
 // representatives).  Must be called by all lanes of the wave.
-__device__ inline void wave_merge_add(const InstBuf& b, InstDyn& d, bool act,
+__device__ __forceinline__ void wave_merge_add(const InstBuf& b, InstDyn& d, bool act,
                                       uint64_t key, Fx v) {
   const int lane = threadIdx.x & 63;
   for (int it = 0; it < 4; ++it) {
@@ -573,11 +597,11 @@ struct View {
   int W;
   bool f32;
   // coefficient i as FP64 (exact for either storage)
-  __device__ double getc(uint32_t i) const {
+  __device__ __forceinline__ double getc(uint32_t i) const {
     return f32 ? (double)static_cast<const float*>(C)[i] : static_cast<const double*>(C)[i];
   }
   // stores c, rounded to FP32 when the storage is FP32
-  __device__ void setc(uint32_t i, double c) const {
+  __device__ __forceinline__ void setc(uint32_t i, double c) const {
     if (f32)
       static_cast<float*>(C)[i] = (float)c;
     else
@@ -585,7 +609,7 @@ struct View {
   }
 };
 
-__device__ inline View view_of(const InstBuf& b, const InstDyn& d) {
+__device__ __forceinline__ View view_of(const InstBuf& b, const InstDyn& d) {
   View v;
   const uint32_t h = d.half, p = d.parity;
   v.X = b.x[h];
@@ -603,7 +627,7 @@ __device__ inline View view_of(const InstBuf& b, const InstDyn& d) {
 //   c_Q' = cos c_Q - sig sin c_R,   c_R' = cos c_R + sig sin c_Q.
 // In FP32 mode cos and sin are rounded to FP32 once and the products and
 // sums are FP32 operations; results are returned widened to FP64 (exact).
-__device__ inline void rotate_pair(bool f32, double cs, double sn, int sig, double cq, double cr,
+__device__ __forceinline__ void rotate_pair(bool f32, double cs, double sn, int sig, double cq, double cr,
                                    double* nq, double* nr) {
   if (f32) {
     const float c = (float)cs, s = (float)sn, q = (float)cq, r = (float)cr;
@@ -618,7 +642,7 @@ __device__ inline void rotate_pair(bool f32, double cs, double sn, int sig, doub
 }
 
 // Partner absent: c_Q' = cos c_Q and the new string R gets sig sin c_Q.
-__device__ inline void rotate_single(bool f32, double cs, double sn, int sig, double cq,
+__device__ __forceinline__ void rotate_single(bool f32, double cs, double sn, int sig, double cq,
                                      double* nq, double* child) {
   if (f32) {
     const float c = (float)cs, s = (float)sn, q = (float)cq;
@@ -632,8 +656,8 @@ __device__ inline void rotate_single(bool f32, double cs, double sn, int sig, do
   }
 }
 
-__device__ inline void load_key(const View& v, uint32_t i, uint64_t* x, uint64_t* z) {
-  for (int w = 0; w < v.W; ++w) {
+__device__ __forceinline__ void load_key(const View& v, uint32_t i, uint64_t* x, uint64_t* z) {
+  PP_FOR_W(w, 0, v.W, kMaxW) {
     x[w] = v.X[(size_t)w * v.cap + i];
     z[w] = v.Z[(size_t)w * v.cap + i];
   }
@@ -643,7 +667,7 @@ __device__ inline void load_key(const View& v, uint32_t i, uint64_t* x, uint64_t
 // GATE: one Pauli rotation (Prop. 1) + exact merge + truncation
 // ---------------------------------------------------------------------------
 // 0 = not served, 1 = run, 2 = would overflow (appends <= count)
-__device__ inline int gate_state(const InstBuf& b, const InstDyn& d) {
+__device__ __forceinline__ int gate_state(const InstBuf& b, const InstDyn& d) {
   if (d.status & ST_OVERFLOW) return 0;
   const Op* op = cur_op(b, d);
   if (!op || op->type != OP_GATE) return 0;
@@ -663,20 +687,20 @@ struct Smem {
   uint64_t pfx[3];
 };
 
-__device__ inline void pend_reset(Smem& sm) {
+__device__ __forceinline__ void pend_reset(Smem& sm) {
   sm.plive = sm.pcnt = 0;
   sm.pfx[0] = sm.pfx[1] = sm.pfx[2] = 0;
 }
 
 // Thread 0: adds the pending counts / sum to the instance and resets them.
-__device__ inline void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh) {
+__device__ __forceinline__ void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh) {
   add_acc(b, d, nsh, sm.plive, sm.pcnt);
   if (sm.pfx[0] | sm.pfx[1] | sm.pfx[2]) fx_atomic_add_wait(d.expect_fx, Fx{sm.pfx[0], sm.pfx[1], sm.pfx[2]});
   pend_reset(sm);
 }
 
 template <int IT>
-__device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Smem& sm) {
+__device__ __forceinline__ void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Smem& sm) {
   uint32_t* s_tmp = sm.tmp;
   uint32_t* s_base = &sm.base;
   const View v = view_of(b, d);
@@ -687,11 +711,11 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
   const int wmax = op.wmax;
   const bool full = op.full_check != 0;
   uint64_t px[kMaxW], pz[kMaxW], nxm[kMaxW], nzm[kMaxW];
-  for (int w = 0; w < W; ++w) { px[w] = op.px[w]; pz[w] = op.pz[w]; }
+  PP_FOR_W(w, 0, W, kMaxW) { px[w] = op.px[w]; pz[w] = op.pz[w]; }
   const bool has_next = op.next_gate != kNone32;
   if (has_next) {
     const Op& nx = b.prog[op.next_gate];
-    for (int w = 0; w < W; ++w) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
+    PP_FOR_W(w, 0, W, kMaxW) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
   }
   uint32_t my_live = 0, my_cnt = 0;
   uint64_t chx[IT][kMaxW], chz[IT][kMaxW];
@@ -711,29 +735,30 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
     chv[k] = false;
     const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
     if (i >= M) continue;
-    if (!v.al[i]) { v.aln[i] = 0; continue; }
+    // liveness, key and coefficient of entry i are loaded together (i < M <= cap)
+    const uint8_t alive_i = v.al[i];
     uint64_t qx[kMaxW], qz[kMaxW];
     load_key(v, i, qx, qz);
+    const double ci = v.getc(i);
+    if (!alive_i) { v.aln[i] = 0; continue; }
     if (!anticommutes(qx, qz, px, pz, W)) {        // [P, Q] = 0: unchanged
       bool keep = true;
-      if (full) {
-        const double c = v.getc(i);
-        keep = fabs(c) >= eps && !heavy(qx, qz);
-      }
+      if (full) keep = fabs(ci) >= eps && !heavy(qx, qz);
       v.aln[i] = keep ? 1 : 0;
       if (keep) tally(qx, qz);
       continue;
     }
     uint64_t rx[kMaxW], rz[kMaxW];
-    for (int w = 0; w < W; ++w) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
+    PP_FOR_W(w, 0, W, kMaxW) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
     const int sig = product_sign(px, pz, qx, qz, rx, rz, W);   // i P Q = sig R
-    const int64_t j = gt_lookup(b, gen, M, v.al, v.X, v.Z, rx, rz);
+    double cj = 0.0;
+    const int64_t j = gt_lookup(b, gen, M, v, rx, rz, &cj);
     if (j >= 0) {
       if ((uint32_t)j < i) continue;                 // the partner's thread leads
       // Both Q and R = PQ live: the gate acts on span{Q, R} as a rotation.
       // i P R = -sig Q.
       double nq, nr;
-      rotate_pair(v.f32, cs, sn, sig, v.getc(i), v.getc((uint32_t)j), &nq, &nr);
+      rotate_pair(v.f32, cs, sn, sig, ci, cj, &nq, &nr);
       v.setc(i, nq);
       v.setc((uint32_t)j, nr);
       const bool kq = fabs(nq) >= eps && !(full && heavy(qx, qz));
@@ -744,14 +769,14 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
       if (kr) tally(rx, rz);
     } else {
       double nq, child;
-      rotate_single(v.f32, cs, sn, sig, v.getc(i), &nq, &child);
+      rotate_single(v.f32, cs, sn, sig, ci, &nq, &child);
       v.setc(i, nq);
       const bool kq = fabs(nq) >= eps && !(full && heavy(qx, qz));
       v.aln[i] = kq ? 1 : 0;
       if (kq) tally(qx, qz);
       if (fabs(child) >= eps && !heavy(rx, rz)) {
         chv[k] = true;
-        for (int w = 0; w < W; ++w) { chx[k][w] = rx[w]; chz[k][w] = rz[w]; }
+        PP_FOR_W(w, 0, W, kMaxW) { chx[k][w] = rx[w]; chz[k][w] = rz[w]; }
         chc[k] = child;
         tally(rx, rz);
       }
@@ -771,7 +796,7 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
     if (!chv[k]) continue;
     const uint32_t pos = base + off++;
     if (pos >= v.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }   // guard
-    for (int w = 0; w < W; ++w) {
+    PP_FOR_W(w, 0, W, kMaxW) {
       v.X[(size_t)w * v.cap + pos] = chx[k][w];
       v.Z[(size_t)w * v.cap + pos] = chz[k][w];
     }
@@ -799,8 +824,11 @@ __device__ inline void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Sm
 // instance whose current op index is a launch argument, so a captured
 // sequence of solo launches replays a fixed list of operations.
 // ---------------------------------------------------------------------------
+// Launch argument of the one-instance kernels.  The instance's buffer
+// descriptor travels by value (kernel-argument loads, no dependent global
+// load before the program can be read).
 struct Solo {
-  const InstBuf* b;
+  InstBuf b;
   InstDyn* d;
   uint32_t* sync;
   uint32_t k;          // index of the op this launch executes
@@ -815,15 +843,15 @@ struct NextGate {
     has = op.next_gate != kNone32;
     if (has) {
       const Op& nx = b.prog[op.next_gate];
-      for (int w = 0; w < b.W; ++w) { x[w] = nx.px[w]; z[w] = nx.pz[w]; }
+      PP_FOR_W(w, 0, b.W, kMaxW) { x[w] = nx.px[w]; z[w] = nx.pz[w]; }
     }
   }
-  __device__ bool anti(const uint64_t* qx, const uint64_t* qz, int W) const {
+  __device__ __forceinline__ bool anti(const uint64_t* qx, const uint64_t* qz, int W) const {
     return has && anticommutes(qx, qz, x, z, W);
   }
 };
 
-__device__ inline void add_counts(InstDyn&, uint32_t live, uint32_t cnt, Smem& sm) {
+__device__ __forceinline__ void add_counts(InstDyn&, uint32_t live, uint32_t cnt, Smem& sm) {
   const uint32_t bl = block_sum_u32(live, sm.tmp);
   const uint32_t bc = block_sum_u32(cnt, sm.tmp);
   if (threadIdx.x == 0) {
@@ -833,14 +861,14 @@ __device__ inline void add_counts(InstDyn&, uint32_t live, uint32_t cnt, Smem& s
 }
 
 struct GateKind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) { return gate_state(b, d); }
-  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) { return gate_state(b, d); }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     gate_tile<IT>(b, d, t, sm);
   }
-  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
     const Op& op = b.prog[d.pc];
     d.propagated += d.live;
     d.merged += (uint64_t)d.live + d.count;
@@ -856,7 +884,7 @@ struct GateKind {
 };
 
 // MERGE, narrow keys: one pass, representative -> hash table -> exact sums
-__device__ inline bool merge_served(const InstBuf& b, const InstDyn& d, bool narrow,
+__device__ __forceinline__ bool merge_served(const InstBuf& b, const InstDyn& d, bool narrow,
                                     uint32_t phase) {
   if (d.status & ST_OVERFLOW) return false;
   const Op* op = cur_op(b, d);
@@ -865,14 +893,25 @@ __device__ inline bool merge_served(const InstBuf& b, const InstDyn& d, bool nar
   return (b.narrow != 0) == narrow && d.mphase == phase;
 }
 
+__device__ __forceinline__ bool use_part(const InstBuf& b, const InstDyn& d) {
+  return b.pkey != nullptr && !b.nopart && b.narrow && b.group != 2 && d.M >= kPartMin;
+}
+
+__device__ __forceinline__ uint32_t part_of(uint64_t key) { return (uint32_t)(mix64(key) >> 56); }
+
+__device__ __forceinline__ uint32_t part_slot(uint64_t key) {
+  return (uint32_t)(mix64(key) >> 20) & (uint32_t)(kPartSlots - 1);
+}
+
+
 struct MergeNarrowKind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) {
-    return merge_served(b, d, true, 0) ? 1 : 0;
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
+    return (merge_served(b, d, true, 0) && !use_part(b, d)) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
     const View v = view_of(b, d);
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
@@ -891,7 +930,7 @@ struct MergeNarrowKind {
       wave_merge_add(b, d, act, key, c);
     }
   }
-  __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
     d.merged += d.live;
     d.mphase = 1;
   }
@@ -902,13 +941,13 @@ struct MergeNarrowKind {
 // the owner's (a mismatch is a hash collision: the merge restarts with
 // another seed) and adds its coefficient.
 struct MergeWide1Kind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return merge_served(b, d, false, 0) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
     const View v = view_of(b, d);
     const int W = b.W;
     const uint64_t seed = d.seed;
@@ -920,7 +959,7 @@ struct MergeWide1Kind {
       uint64_t qx[kMaxW], qz[kMaxW], rx[kMaxW], rz[kMaxW];
       load_key(v, i, qx, qz);
       rep_string(b, qx, qz, rx, rz);
-      for (int w = 0; w < W; ++w) {
+      PP_FOR_W(w, 0, W, kMaxW) {
         b.wrep[(size_t)w * b.cap + i] = rx[w];
         b.wrep[(size_t)(W + w) * b.cap + i] = rz[w];
       }
@@ -929,20 +968,20 @@ struct MergeWide1Kind {
       b.wslot[i] = (uint32_t)mt_slot(b.mkey, merge_bits(b, d), h);
     }
   }
-  __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
     d.merged += d.live;
     d.mphase = 1;
   }
 };
 
 struct MergeWide2Kind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return merge_served(b, d, false, 1) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem&) {
     const View v = view_of(b, d);
     const int W = b.W;
 #pragma unroll
@@ -955,7 +994,7 @@ struct MergeWide2Kind {
       const uint32_t owner = (o == kNone32) ? i : o;
       bool same = true;
       if (owner != i)
-        for (int w = 0; w < 2 * W; ++w)
+        PP_FOR_W(w, 0, 2 * W, 2 * kMaxW)
           same = same && b.wrep[(size_t)w * b.cap + i] == b.wrep[(size_t)w * b.cap + owner];
       if (same) {
         bool range = false;
@@ -966,17 +1005,17 @@ struct MergeWide2Kind {
       }
     }
   }
-  __device__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
     d.mphase = 2;
   }
 };
 
 // Writes one output term at the cursor position `pos` of the other half.
-__device__ inline void emit_term(const InstBuf& b, const InstDyn& d, uint32_t pos,
+__device__ __forceinline__ void emit_term(const InstBuf& b, const InstDyn& d, uint32_t pos,
                                  const uint64_t* x, const uint64_t* z, double c) {
   const uint32_t h = d.half ^ 1u;
   const int W = b.W;
-  for (int w = 0; w < W; ++w) {
+  PP_FOR_W(w, 0, W, kMaxW) {
     b.x[h][(size_t)w * b.cap + pos] = x[w];
     b.z[h][(size_t)w * b.cap + pos] = z[w];
   }
@@ -990,7 +1029,7 @@ __device__ inline void emit_term(const InstBuf& b, const InstDyn& d, uint32_t po
 }
 
 // After a merge or compaction: the other half becomes current.
-__device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
+__device__ __forceinline__ void finish_rebuild(const InstBuf& b, InstDyn& d) {
   const Op& op = b.prog[d.pc];
   d.merge_in += d.live;
   d.merge_out += d.nuniq;
@@ -1003,21 +1042,23 @@ __device__ inline void finish_rebuild(const InstBuf& b, InstDyn& d) {
   d.count_for = op.next_gate;
   d.nuniq = 0;
   d.mphase = 0;
+  d.pglobal = 0;
   d.pc += 1;
 }
 
 // Collect: every occupied merge slot becomes one representative of the new
 // half; slots are cleared for the next merge.
 struct CollectKind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return (merge_served(b, d, true, 1) || merge_served(b, d, false, 2)) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf& b, const InstDyn& d) {
+  __device__ __forceinline__ static uint32_t elems(const InstBuf& b, const InstDyn& d) {
+    if (b.narrow && use_part(b, d) && !d.pglobal) return 0u;   // all emitted by pass 2
     return 1u << merge_bits(b, d);
   }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const bool collided = (d.status & ST_COLLISION) != 0;
     const uint32_t nslots = 1u << merge_bits(b, d);
     const int W = b.W;
@@ -1038,7 +1079,7 @@ struct CollectKind {
           narrow_decode(b, key, ox[k], oz[k]);
         } else {
           const uint32_t o = b.mown[s];
-          for (int w = 0; w < W; ++w) {
+          PP_FOR_W(w, 0, W, kMaxW) {
             ox[k][w] = b.wrep[(size_t)w * b.cap + o];
             oz[k][w] = b.wrep[(size_t)(W + w) * b.cap + o];
           }
@@ -1069,7 +1110,7 @@ struct CollectKind {
     }
     add_counts(d, mine, my_cnt, sm);
   }
-  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
     if (d.status & ST_COLLISION) {     // retry this merge with another seed
       d.status &= ~ST_COLLISION;
       d.special = 0;
@@ -1101,22 +1142,298 @@ struct CollectKind {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Partitioned exact merge (narrow keys, at least kPartMin records, one
+// instance).  Pass 1 takes tiles of kPartTile records, computes each live
+// record's representative key and its partition (top 8 bits of a mix of
+// the key), counting-sorts the tile by partition in LDS and writes it back
+// to the staging buffer at the tile's own place, with the tile's partition
+// offsets: no global atomics.  Pass 2 gives each partition to one block,
+// which gathers the partition's records from every tile and adds them into
+// an LDS table of exact fixed-point sums, then emits one term per key.  A
+// partition with more than kPartFill distinct keys discards its table (the
+// decision is taken after a barrier, so no key is split between the two
+// paths) and adds its records to the global merge table instead; the
+// collect pass then emits those.
+// ---------------------------------------------------------------------------
+struct PartSortKind {
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
+    return (merge_served(b, d, true, 0) && use_part(b, d)) ? 1 : 0;
+  }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  template <int IT>
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
+    static_assert(IT * kBlock == kPartTile && kBlock == kParts, "tile and partition shape");
+    __shared__ uint64_t s_key[kPartTile];
+    __shared__ double s_c[kPartTile];
+    __shared__ uint32_t s_cnt[kParts];
+    const View v = view_of(b, d);
+    s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t key[IT];
+    double c[IT];
+    uint32_t at[IT];                       // partition << 16 | rank, or kNone32
+    bool range = false;
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      at[k] = kNone32;
+      const uint32_t i = t * kPartTile + k * kBlock + threadIdx.x;
+      if (i >= d.M || !v.al[i]) continue;
+      uint64_t qx[kMaxW], qz[kMaxW];
+      load_key(v, i, qx, qz);
+      key[k] = narrow_key(b, qx, qz);
+      c[k] = v.getc(i);
+      if (key[k] == kEmpty64) {            // the one key equal to the empty marker
+        fx_atomic_add(d.special_fx, fx_from_double(c[k], &range));
+        atomicOr(&d.special, 1u);
+        continue;
+      }
+      const uint32_t p = part_of(key[k]);
+      at[k] = (p << 16) | atomicAdd(&s_cnt[p], 1u);
+    }
+    if (range) atomicOr(&d.status, ST_RANGE);
+    __syncthreads();
+    uint32_t total;
+    const uint32_t off = block_scan(s_cnt[threadIdx.x], sm.tmp, &total);
+    uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
+    pre[threadIdx.x] = (uint16_t)off;
+    if (threadIdx.x == 0) pre[kParts] = (uint16_t)total;
+    __syncthreads();
+    s_cnt[threadIdx.x] = off;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      if (at[k] == kNone32) continue;
+      const uint32_t pos = s_cnt[at[k] >> 16] + (at[k] & 0xffffu);
+      s_key[pos] = key[k];
+      s_c[pos] = c[k];
+    }
+    __syncthreads();
+    const size_t base = (size_t)t * kPartTile;
+    for (uint32_t j = threadIdx.x; j < total; j += kBlock) {
+      b.pkey[base + j] = s_key[j];
+      b.pcoef[base + j] = s_c[j];
+    }
+    __syncthreads();                       // LDS is reused by the next tile
+  }
+  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
+    d.merged += d.live;
+    d.pglobal = 0;
+    d.mphase = 1;
+  }
+};
+
+// Adds (key, v) to a partition's LDS table; false when v's key is new and
+// the table already holds kPartFill keys (the caller flushes and retries).
+// At most kPartFill + kBlock keys are ever inserted, so a probe always ends.
+__device__ __forceinline__ bool part_try_add(uint64_t* tk, uint64_t* tf, uint32_t* fill,
+                                             uint64_t key, Fx v) {
+  uint32_t s = part_slot(key);
+  for (int probe = 0; probe < kPartSlots; ++probe) {
+    uint64_t k = tk[s];
+    if (k == kEmpty64) {
+      if (*(volatile uint32_t*)fill >= (uint32_t)kPartFill) return false;
+      k = atomicCAS((unsigned long long*)&tk[s], (unsigned long long)kEmpty64,
+                    (unsigned long long)key);
+      if (k == kEmpty64) {
+        atomicAdd(fill, 1u);
+        k = key;
+      }
+    }
+    if (k == key) {
+      fx_atomic_add(&tf[3 * s], v);
+      return true;
+    }
+    s = (s + 1) & (uint32_t)(kPartSlots - 1);
+  }
+  return false;
+}
+
+// All threads: moves every key of the LDS table into the global merge table
+// and empties the LDS table.
+__device__ __forceinline__ void part_flush(const InstBuf& b, InstDyn& d, uint64_t* tk, uint64_t* tf,
+                                           uint32_t* fill) {
+  for (int q = threadIdx.x; q < kPartSlots; q += kBlock) {
+    const uint64_t key = tk[q];
+    if (key != kEmpty64) {
+      mt_add(b, d, key, Fx{tf[3 * q], tf[3 * q + 1], tf[3 * q + 2]});
+      tk[q] = kEmpty64;
+      tf[3 * q] = tf[3 * q + 1] = tf[3 * q + 2] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *fill = 0;
+  __syncthreads();
+}
+
+struct PartAggKind {
+  static constexpr int kBatch = 8;         // records loaded before they are added
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
+    return (merge_served(b, d, true, 1) && use_part(b, d)) ? 1 : 0;
+  }
+  // one tile (of kBlock elements at one item per thread) per partition
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn&) { return kParts * kBlock; }
+
+  // Walks partition p: each thread takes p's segment of every kBlock-th tile
+  // and loads up to kBatch records of it at a time (in flight together);
+  // a non-null `stop` (an LDS flag) ends the walk once it is set.
+  template <class F>
+  __device__ __forceinline__ static void each_record(const InstBuf& b, const InstDyn& d, uint32_t p,
+                                                     F f, const uint32_t* stop) {
+    const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
+    for (uint32_t t = threadIdx.x; t < T; t += kBlock) {
+      const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
+      const uint32_t lo = pre[p], hi = pre[p + 1];
+      const size_t base = (size_t)t * kPartTile;
+      for (uint32_t r = lo; r < hi; r += kBatch) {
+        if (stop && *(const volatile uint32_t*)stop) return;
+        uint64_t k[kBatch];
+        double c[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          if (r + q < hi) {
+            k[q] = b.pkey[base + r + q];
+            c[q] = b.pcoef[base + r + q];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+          if (r + q < hi) f(k[q], c[q]);
+      }
+    }
+  }
+
+  // Partition p.  First pass: every thread adds its records into the
+  // block's LDS table, stopping as soon as a key finds no room.  If that
+  // happened (more than kPartFill keys), the table is cleared and the
+  // partition is summed again with the table as a write-combining cache:
+  // the threads advance in rounds of up to kBatch records; a round that
+  // finds the table full flushes it into the global merge table and retries
+  // its leftovers; the last table is flushed too, so every key of such a
+  // partition ends in the global table, never split.  Otherwise the block
+  // emits one term per key.
+  template <int IT>
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t p, Smem& sm) {
+    __shared__ uint64_t s_tk[kPartSlots];
+    __shared__ uint64_t s_tf[3 * kPartSlots];
+    __shared__ uint32_t s_fill, s_over;
+    auto clear = [&]() {
+      for (int q = threadIdx.x; q < kPartSlots; q += kBlock) {
+        s_tk[q] = kEmpty64;
+        s_tf[3 * q] = s_tf[3 * q + 1] = s_tf[3 * q + 2] = 0;
+      }
+      if (threadIdx.x == 0) s_fill = 0;
+      __syncthreads();
+    };
+    if (threadIdx.x == 0) s_over = 0;
+    clear();
+    bool range = false;
+    each_record(b, d, p, [&](uint64_t key, double c) {
+      if (!part_try_add(s_tk, s_tf, &s_fill, key, fx_from_double(c, &range))) atomicExch(&s_over, 1u);
+    }, &s_over);
+    __syncthreads();
+    const bool flushed = s_over != 0;
+    if (flushed) {                         // block-uniform
+      clear();
+      const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
+      uint32_t t = threadIdx.x, r = 0, hi = 0;
+      auto seek = [&]() {                  // next tile with records of p
+        while (t < T) {
+          const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
+          r = pre[p];
+          hi = pre[p + 1];
+          if (r < hi) return;
+          t += kBlock;
+        }
+      };
+      seek();
+      while (true) {
+        uint64_t k[kBatch];
+        Fx v[kBatch];
+        uint32_t got = 0;
+        if (t < T) {
+          const size_t base = (size_t)t * kPartTile;
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q) {
+            if (r + q < hi) {
+              k[q] = b.pkey[base + r + q];
+              v[q] = fx_from_double(b.pcoef[base + r + q], &range);
+              got = q + 1;
+            }
+          }
+          r += got;
+          if (r >= hi) {
+            t += kBlock;
+            seek();
+          }
+        }
+        uint32_t fail = 0;
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+          if ((uint32_t)q < got && !part_try_add(s_tk, s_tf, &s_fill, k[q], v[q])) fail |= 1u << q;
+        if (__syncthreads_or(fail != 0)) {
+          part_flush(b, d, s_tk, s_tf, &s_fill);
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q)    // at most kBlock * kBatch <= kPartFill keys
+            if ((fail >> q) & 1u) part_try_add(s_tk, s_tf, &s_fill, k[q], v[q]);
+        }
+        if (!__syncthreads_or(t < T)) break;
+      }
+    }
+    if (range) atomicOr(&d.status, ST_RANGE);
+    __syncthreads();
+    if (flushed) {                         // block-uniform
+      part_flush(b, d, s_tk, s_tf, &s_fill);
+      if (threadIdx.x == 0) atomicOr(&d.pglobal, 1u);
+      return;
+    }
+    // emit one term per key
+    constexpr int kPer = kPartSlots / kBlock;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) mine += s_tk[q * kBlock + threadIdx.x] != kEmpty64 ? 1u : 0u;
+    uint32_t tot;
+    uint32_t off = block_scan(mine, sm.tmp, &tot);
+    if (threadIdx.x == 0) sm.base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    __syncthreads();
+    const uint32_t base = sm.base;
+    const NextGate ng(b, b.prog[d.pc]);
+    uint32_t my_cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t sl = q * kBlock + threadIdx.x;
+      const uint64_t key = s_tk[sl];
+      if (key == kEmpty64) continue;
+      const uint32_t pos = base + off++;
+      if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
+      uint64_t x[kMaxW], z[kMaxW];
+      narrow_decode(b, key, x, z);
+      emit_term(b, d, pos, x, z, fx_to_double(Fx{s_tf[3 * sl], s_tf[3 * sl + 1], s_tf[3 * sl + 2]}));
+      if (ng.anti(x, z, b.W)) ++my_cnt;
+    }
+    add_counts(d, mine, my_cnt, sm);
+  }
+  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn&, uint32_t, Smem&) {}
+};
+
 // MERGE for plain PP: the set is already free of duplicates, so the merge
 // only drops dead entries (compaction into the other half).
-__device__ inline bool compact_served(const InstBuf& b, const InstDyn& d) {
+__device__ __forceinline__ bool compact_served(const InstBuf& b, const InstDyn& d) {
   if (d.status & ST_OVERFLOW) return false;
   const Op* op = cur_op(b, d);
   return op && op->type == OP_MERGE && b.group == 0 && !op->force_full;
 }
 
 struct CompactKind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return compact_served(b, d) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const View v = view_of(b, d);
     const int W = b.W;
     const NextGate ng(b, b.prog[d.pc]);
@@ -1146,7 +1463,7 @@ struct CompactKind {
     }
     add_counts(d, mine, my_cnt, sm);
   }
-  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
     d.merged += d.live;
     d.nuniq = ld_agent(&d.nuniq);
     finish_rebuild(b, d);
@@ -1154,7 +1471,7 @@ struct CompactKind {
 };
 
 // DAMP / TRUNC / COUNT / EXPECT: one streaming pass over the live terms
-__device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
+__device__ __forceinline__ bool scan_served(const InstBuf& b, const InstDyn& d) {
   if (d.status & ST_OVERFLOW) return false;
   const Op* op = cur_op(b, d);
   if (!op) return false;
@@ -1163,13 +1480,13 @@ __device__ inline bool scan_served(const InstBuf& b, const InstDyn& d) {
 }
 
 struct ScanKind {
-  __device__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ static int state(const InstBuf& b, const InstDyn& d) {
+  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return scan_served(b, d) ? 1 : 0;
   }
-  __device__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
-  __device__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const View v = view_of(b, d);
     const int W = b.W, n = b.n;
     const Op& op = b.prog[d.pc];
@@ -1219,7 +1536,7 @@ struct ScanKind {
     }
     add_counts(d, my_live, my_cnt, sm);
   }
-  __device__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
+  __device__ __forceinline__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
     const Op& op = b.prog[d.pc];
     if (op.type == OP_EXPECT) {
       const Fx f{ld_agent(&d.expect_fx[0]), ld_agent(&d.expect_fx[1]),
@@ -1237,7 +1554,7 @@ struct ScanKind {
 // runners
 // ---------------------------------------------------------------------------
 template <class K, int IT>
-__device__ inline void run_multi(const Ctx& C, Smem& sm, uint32_t* s_pref) {
+__device__ __forceinline__ void run_multi(const Ctx& C, Smem& sm, uint32_t* s_pref) {
   const int ninst = *C.ninst;
   const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
     const InstBuf& b = *C.bufs[i];
@@ -1276,8 +1593,8 @@ __device__ inline void run_multi(const Ctx& C, Smem& sm, uint32_t* s_pref) {
 }
 
 template <class K, int IT>
-__device__ inline void run_solo(const Solo& S, Smem& sm) {
-  const InstBuf& b = *S.b;
+__device__ __forceinline__ void run_solo(const Solo& S, Smem& sm) {
+  const InstBuf& b = S.b;
   InstDyn& d = *S.d;
   if (d.pc != S.k) return;                 // an earlier op did not complete
   const int st = K::state(b, d);
@@ -1321,6 +1638,16 @@ PP_KERNEL_PAIR(k_merge_collect, CollectKind)
 PP_KERNEL_PAIR(k_compact, CompactKind)
 PP_KERNEL_PAIR(k_scan_op, ScanKind)
 
+// the partitioned merge runs on the one-instance path only
+__global__ __launch_bounds__(kBlock) void k_part_sort_solo(Solo S) {
+  __shared__ Smem sm;
+  run_solo<PartSortKind, kPartTile / kBlock>(S, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_part_agg_solo(Solo S) {
+  __shared__ Smem sm;
+  run_solo<PartAggKind, 1>(S, sm);
+}
+
 // ---------------------------------------------------------------------------
 // Host-driven growth / compaction of one instance into a new store.
 // ---------------------------------------------------------------------------
@@ -1358,7 +1685,7 @@ __global__ __launch_bounds__(kBlock) void k_grow(InstBuf src, InstBuf dst, InstD
       if (pos >= dst.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
       uint64_t x[kMaxW], z[kMaxW];
       load_key(v, i, x, z);
-      for (int w = 0; w < W; ++w) {
+      PP_FOR_W(w, 0, W, kMaxW) {
         dst.x[0][(size_t)w * dst.cap + pos] = x[w];
         dst.z[0][(size_t)w * dst.cap + pos] = z[w];
       }

@@ -62,6 +62,15 @@ constexpr int kLineU32 = 32;
 constexpr size_t kSyncBytes = (1 + kSyncShards) * kLineU32 * sizeof(uint32_t);
 constexpr size_t kAccBytes = kAccShards * kLineU64 * sizeof(uint64_t);
 
+// Partitioned merge: used for narrow-key merges of at least kPartMin
+// records; tiles of kPartTile records, kParts partitions, LDS tables of
+// kPartSlots slots of which at most kPartFill may be filled.
+constexpr uint32_t kPartMin = 1u << 18;
+constexpr int kPartTile = 4096;
+constexpr int kParts = 256;
+constexpr int kPartSlots = 4096;
+constexpr int kPartFill = 3072;
+
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
 
@@ -92,6 +101,11 @@ struct InstBuf {
   uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
   uint32_t* wslot;
   uint64_t* accs;        // kAccShards count accumulators (live | count << 32)
+  // partitioned merge (narrow keys, large sets): records staged per tile of
+  // kPartTile, sorted by partition, with each tile's partition offsets
+  uint64_t* pkey;        // [tiles * kPartTile] representative keys
+  double* pcoef;         // [tiles * kPartTile] coefficients (FP64)
+  uint16_t* ppre;        // [tiles][kParts + 1] exclusive offsets per partition
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;
@@ -102,6 +116,7 @@ struct InstBuf {
   int32_t group;
   uint32_t narrow;       // merge keys fit 64 bits exactly
   uint32_t f32;          // coefficients stored and rotated in FP32
+  uint32_t nopart;       // the partitioned merge's kernels are not launched
 };
 
 struct InstDyn {
@@ -130,7 +145,7 @@ struct InstDyn {
   uint32_t seed;         // wide-merge hash seed (bumped on a collision)
   uint32_t special;
   uint32_t failed_pc;
-  uint32_t pad;
+  uint32_t pglobal;      // partitioned merge: some partition used the table
 };
 
 }  // namespace pp

@@ -28,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pp_oracle.cpp")
 _LIB = os.path.join(_HERE, "libpp_oracle.so")
 
-GROUP_CODE = {"none": 0, "Zn": 1, "Sn": 2}
+GROUP_CODE = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3}
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _f64p = ctypes.POINTER(ctypes.c_double)

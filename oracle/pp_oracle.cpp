@@ -125,7 +125,14 @@ Pauli translate(const Pauli& s, int j, int n) {
   return t;
 }
 
-enum Group { kNone = 0, kTranslation = 1, kPermutation = 2 };
+enum Group { kNone = 0, kTranslation = 1, kPermutation = 2, kDihedral = 3 };
+
+// Reflection of the ring: qubit q of the result carries qubit n-1-q of s.
+Pauli reflect(const Pauli& s, int n) {
+  Pauli t;
+  for (int q = 0; q < n; ++q) set_letter(t, q, get_letter(s, n - 1 - q));
+  return t;
+}
 
 // Algorithm 2: the representative is the argmin of int(T^j s), j = 0..n-1.
 Pauli canon_translation(const Pauli& s, int n) {
@@ -155,9 +162,24 @@ Pauli canon_permutation(const Pauli& s, int n) {
   return r;
 }
 
+// Dihedral group D_n (translations and the reflection of the ring), the
+// first wider group the paper's outlook names: the representative is the
+// argmin of int(g s) over all 2n elements g = T^j and T^j R.
+Pauli canon_dihedral(const Pauli& s, int n) {
+  const Pauli r = reflect(s, n);
+  Pauli best = s;
+  for (int j = 0; j < n; ++j) {
+    const Pauli a = translate(s, j, n), b = translate(r, j, n);
+    if (int_less(a, best, n)) best = a;
+    if (int_less(b, best, n)) best = b;
+  }
+  return best;
+}
+
 Pauli canon(const Pauli& s, int n, int group) {
   if (group == kTranslation) return canon_translation(s, n);
   if (group == kPermutation) return canon_permutation(s, n);
+  if (group == kDihedral) return canon_dihedral(s, n);
   return s;
 }
 

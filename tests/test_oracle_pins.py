@@ -437,3 +437,77 @@ def test_orbit_sum_is_exactly_rounded():
         o.add(*W.from_letters(s), c)
     o.merge()
     assert o.as_dict() == {W.from_letters("XIII"): 1.0}
+
+
+# ----------------------------------------------------------------------------
+# Dihedral group D_n (translations and the reflection of the ring)
+# ----------------------------------------------------------------------------
+def bracelets(n, k=4):
+    """Burnside count of k-colourings of an n-cycle up to rotation and
+    reflection (the orbit count of D_n on n-qubit Pauli strings)."""
+    neck = sum(k ** math.gcd(j, n) for j in range(1, n + 1))       # n * necklaces
+    refl = (n // 2) * (k ** (n // 2 + 1) + k ** (n // 2)) if n % 2 == 0 else n * k ** ((n + 1) // 2)
+    return (neck + refl) // (2 * n)
+
+
+def test_bracelet_formula_small_values():
+    # the formula against plain enumeration of colourings (no Pauli code)
+    for n in range(1, 7):
+        seen = set()
+        for s in itertools.product(range(4), repeat=n):
+            rots = [s[j:] + s[:j] for j in range(n)]
+            seen.add(min(rots + [tuple(reversed(r)) for r in rots]))
+        assert len(seen) == bracelets(n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dihedral_representative_count(n):
+    reps = set()
+    for s in itertools.product("IXYZ", repeat=n):
+        reps.add(O.canon(n, "Dn", *W.from_letters("".join(s))))
+    assert len(reps) == bracelets(n)
+
+
+@pytest.mark.parametrize("n", [4, 7, 16, 31, 32, 33, 48, 64])
+def test_dihedral_representative_is_orbit_minimum(n):
+    rng = random.Random(100 + n)
+    for trial in range(30):
+        s = random_string(rng, n, None if trial % 2 else rng.randint(0, min(n, 9)))
+        rx, rz = O.canon(n, "Dn", *W.from_letters(s))
+        # the orbit written out with letters: rotations of s and of s reversed
+        orbit = [rotate_letters(s, j) for j in range(n)] + \
+                [rotate_letters(s[::-1], j) for j in range(n)]
+        best = min(orbit, key=lambda t: int_value(*W.from_letters(t), n))
+        assert W.to_letters(rx, rz, n) == best
+        assert O.canon(n, "Dn", rx, rz) == (rx, rz)                  # idempotent
+        g = orbit[rng.randrange(2 * n)]
+        assert O.canon(n, "Dn", *W.from_letters(g)) == (rx, rz)      # invariant
+        # never above the translation representative
+        tx, tz = O.canon(n, "Zn", *W.from_letters(s))
+        assert int_value(rx, rz, n) <= int_value(tx, tz, n)
+
+
+@pytest.mark.parametrize("n,obs", [(4, "Z"), (5, "XX")])
+def test_dihedral_pp_matches_dense_orbit_sums(n, obs):
+    ob = W.sum_single(n, "Z") if obs == "Z" else W.sum_ring_pairs(n, "X")
+    prog = small_ring(n, obs=ob, bloch=W.random_bloch(2 * n))
+    res = O.run_program(prog, group="Dn")
+    Od = dense.heisenberg(prog)
+    coeffs = {k: v.real for k, v in dense.pauli_coefficients(Od, n).items()}
+    want = orbit_sums(coeffs, n, "Dn")
+    assert_terms_match(res.terms, {k: v for k, v in want.items() if abs(v) > 1e-13})
+    assert abs(res.expectation - dense.expectation(Od, prog.bloch, n)) < 1e-12
+
+
+def test_theorem1_dihedral_equals_plain_and_translation():
+    """The ring XXZ layers are reflection-symmetric, so D_n merging keeps the
+    plain expectation (Theorem 1) with at most as many representatives as
+    Z_n merging, and at least ceil(N / 2n)."""
+    for n, steps in ((9, 3), (10, 2)):
+        prog = W.xxz_ring(n, steps, 0.21, 1.3, obs=W.sum_ring_pairs(n, "X"),
+                          bloch=W.random_bloch(n))
+        d = O.run_program(prog, group="Dn", keep_terms=False)
+        z = O.run_program(prog, group="Zn", keep_terms=False)
+        b = O.run_program(prog, group="none", keep_terms=False)
+        assert abs(d.expectation - b.expectation) < 1e-12 * max(1, abs(b.expectation))
+        assert math.ceil(b.sizes[-1] / (2 * n)) <= d.sizes[-1] <= z.sizes[-1] <= b.sizes[-1]

@@ -13,7 +13,7 @@ value = (propagated + merged) terms / second, the paper's two work units
 the device and equal to the oracle's counts (tests/test_gpu_parity.py).
 
 The JSON line also carries: the same circuit without symmetry merging
-(plain PP), the roofline of the dominant kernel (per-kernel durations from
+(plain PP) and merged under the dihedral group D_n, the roofline of the dominant kernel (per-kernel durations from
 HIP events recorded on the library's stream over the timed steps; HBM
 traffic from the committed rocprofv3 counter summary when it matches the
 current kernel sources), the exact-merge pass on a large record stream, the
@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-merge-pass", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-dihedral", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--event-every", type=int, default=4,
                     help="time every N-th run of back-to-back launches of one kernel "
@@ -393,6 +394,16 @@ def main():
                          terms_per_step=(ptot["propagated"] + ptot["merged"]) // psteps,
                          expectation=pe)
             print(f"[bench] plain PP done", file=sys.stderr, flush=True)
+        dihedral = None
+        if not args.no_dihedral:
+            run_steps(prog, "Dn", 1, stream, alloc, False)
+            dsteps = max(1, args.steps // 2)
+            dw, dtot, _, de = run_steps(prog, "Dn", dsteps, stream, alloc, False)
+            dihedral = dict(value=(dtot["propagated"] + dtot["merged"]) / dw, unit="terms/s",
+                            ms_per_step=round(dw / dsteps * 1e3, 3),
+                            terms_per_step=(dtot["propagated"] + dtot["merged"]) // dsteps,
+                            expectation=de)
+            print(f"[bench] dihedral done", file=sys.stderr, flush=True)
         traffic, traffic_src = pmc_traffic(None)
         roof["traffic"] = round(traffic, 1) if traffic is not None else None
         roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
@@ -436,6 +447,7 @@ def main():
                    "n": 32, "sublayers": 60, "gates": 1920,
                    "terms_per_step": units // args.steps, "expectation": e},
         "plain_pp": plain,
+        "dihedral_pp": dihedral,
         "roofline": roof,
         "kernels": kernels,
         "variants": variants,

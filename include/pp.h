@@ -26,10 +26,14 @@
  *   (Definition "lowest integer representation", Appendix E.2): I->0, X->1,
  *   Y->2, Z->3 as the base-4 digit of weight 4^q for qubit q.  For Z_n this
  *   is the minimum over the n cyclic translations (Algorithm 2); for S_n it
- *   is Z^{nZ} Y^{nY} X^{nX} I^{rest} from qubit 0 upward (Algorithm 3).
- *   Merging adds the coefficients of the distinct strings of one orbit.
+ *   is Z^{nZ} Y^{nY} X^{nX} I^{rest} from qubit 0 upward (Algorithm 3); for
+ *   the dihedral group D_n (translations and the reflection q -> n-1-q of
+ *   the ring, a wider group of the kind the paper's outlook names) it is
+ *   the smaller of the Z_n representatives of the string and of its
+ *   reflection.  Merging adds the coefficients of the distinct strings of
+ *   one orbit.
  * - Supported sizes: PP_GROUP_NONE and PP_GROUP_PERMUTATION for 1 <= n <= 128,
- *   PP_GROUP_TRANSLATION for 2 <= n <= 64.
+ *   PP_GROUP_TRANSLATION and PP_GROUP_DIHEDRAL for 2 <= n <= 64.
  *
  * Memory, streams, ownership
  * --------------------------
@@ -70,7 +74,8 @@ typedef struct pp_program pp_program;
 enum {
   PP_GROUP_NONE = 0,         /* plain Pauli propagation (no symmetry merge) */
   PP_GROUP_TRANSLATION = 1,  /* cyclic translations Z_n                     */
-  PP_GROUP_PERMUTATION = 2   /* qubit permutations S_n                      */
+  PP_GROUP_PERMUTATION = 2,  /* qubit permutations S_n                      */
+  PP_GROUP_DIHEDRAL = 3      /* ring translations and reflection D_n        */
 };
 
 /*
@@ -128,8 +133,8 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype,
  * (inner_eps = 0 and inner_max_weight < 0 switch these off).
  * merge_every must be 1.  For a handle whose group is not
  * PP_GROUP_NONE the gate multiset must be closed under the group (every
- * translate / permutation of each gate present with the same angle),
- * otherwise PP_ENOTSYM.
+ * translate / reflection / permutation of each gate present with the same
+ * angle), otherwise PP_ENOTSYM.
  */
 int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
                    const double* theta, size_t n_gates, int merge_every,

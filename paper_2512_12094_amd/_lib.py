@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpp.so")
 
-PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2}
+PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3}
 PP_F64 = 0
 PP_F32_COMPENSATED = 1
 DTYPES = {"f64": PP_F64, "f32": PP_F32_COMPENSATED}

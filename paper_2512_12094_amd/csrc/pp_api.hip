@@ -543,7 +543,7 @@ void set_next_gates(std::vector<Op>& ops) {
 }
 
 bool valid_group_n(int group, int n) {
-  if (group == PP_GROUP_TRANSLATION) return n >= 2 && n <= 64;
+  if (group == PP_GROUP_TRANSLATION || group == PP_GROUP_DIHEDRAL) return n >= 2 && n <= 64;
   if (group == PP_GROUP_NONE || group == PP_GROUP_PERMUTATION) return n >= 1 && n <= 128;
   return false;
 }
@@ -566,10 +566,16 @@ int check_symmetric(const pp_state* s, const uint64_t* gx, const uint64_t* gz,
   auto key = [&](const uint64_t* x, const uint64_t* z, double t) {
     return Key(x[0], W > 1 ? x[1] : 0, z[0], W > 1 ? z[1] : 0, t);
   };
-  if (s->group == PP_GROUP_TRANSLATION) {
+  if (s->group == PP_GROUP_TRANSLATION || s->group == PP_GROUP_DIHEDRAL) {
     std::map<Key, long> mult;
     for (size_t k = 0; k < K; ++k) mult[key(gx + k * W, gz + k * W, theta[k])] += 1;
     const uint64_t mask = n == 64 ? ~0ull : ((1ull << n) - 1);
+    auto reflect = [&](uint64_t v) {     // qubit q -> n-1-q
+      uint64_t r = 0;
+      for (int q = 0; q < n; ++q)
+        if ((v >> q) & 1) r |= 1ull << (n - 1 - q);
+      return r;
+    };
     for (const auto& [k, m] : mult) {
       const uint64_t x = std::get<0>(k), z = std::get<2>(k);
       const uint64_t tx = ((x >> 1) | (x << (n - 1))) & mask;   // T shifts left
@@ -578,6 +584,12 @@ int check_symmetric(const pp_state* s, const uint64_t* gx, const uint64_t* gz,
       auto it = mult.find(key(t1, t2, std::get<4>(k)));
       if (it == mult.end() || it->second != m)
         return fail(PP_ENOTSYM, "gate layer is not closed under translations");
+      if (s->group == PP_GROUP_DIHEDRAL) {
+        const uint64_t r1[1] = {reflect(x)}, r2[1] = {reflect(z)};
+        auto jt = mult.find(key(r1, r2, std::get<4>(k)));
+        if (jt == mult.end() || jt->second != m)
+          return fail(PP_ENOTSYM, "gate layer is not closed under the reflection");
+      }
     }
   } else if (s->group == PP_GROUP_PERMUTATION) {
     std::map<std::tuple<int, int, int, double>, long> cls;

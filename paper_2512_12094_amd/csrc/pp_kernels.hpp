@@ -160,6 +160,23 @@ __device__ __forceinline__ void canon_translation(uint64_t x, uint64_t z, int n,
   *rz = bz;
 }
 
+// Dihedral group D_n: the smaller of the translation representatives of the
+// string and of its reflection (qubit q -> n-1-q), i.e. the minimum over all
+// 2n translations and reflected translations.
+__device__ __forceinline__ void canon_dihedral(uint64_t x, uint64_t z, int n, uint64_t* rx,
+                                               uint64_t* rz) {
+  uint64_t ax, az, bx, bz;
+  canon_translation(x, z, n, &ax, &az);
+  const uint64_t xr = __brevll(x) >> (64 - n), zr = __brevll(z) >> (64 - n);
+  canon_translation(xr, zr, n, &bx, &bz);
+  if (int_less1(bx, bz, ax, az)) {
+    ax = bx;
+    az = bz;
+  }
+  *rx = ax;
+  *rz = az;
+}
+
 // Algorithm 3: counts of X, Y, Z letters.
 __device__ __forceinline__ void perm_counts(const uint64_t* x, const uint64_t* z, int W,
                                    uint32_t* nx, uint32_t* ny, uint32_t* nz) {
@@ -200,6 +217,7 @@ __device__ __forceinline__ uint64_t narrow_key(const InstBuf& b, const uint64_t*
   }
   uint64_t rx = x[0], rz = z[0];
   if (b.group == 1) canon_translation(x[0], z[0], b.n, &rx, &rz);
+  if (b.group == 3) canon_dihedral(x[0], z[0], b.n, &rx, &rz);
   return rx | (rz << 32);   // n <= 32
 }
 
@@ -218,8 +236,11 @@ __device__ __forceinline__ void narrow_decode(const InstBuf& b, uint64_t key, ui
 // Representative as a string (wide path: Z_n with n <= 64, or identity).
 __device__ __forceinline__ void rep_string(const InstBuf& b, const uint64_t* x, const uint64_t* z,
                                   uint64_t* rx, uint64_t* rz) {
-  if (b.group == 1) {
-    canon_translation(x[0], z[0], b.n, rx, rz);
+  if (b.group == 1 || b.group == 3) {
+    if (b.group == 1)
+      canon_translation(x[0], z[0], b.n, rx, rz);
+    else
+      canon_dihedral(x[0], z[0], b.n, rx, rz);
     PP_FOR_W(w, 1, b.W, kMaxW) { rx[w] = 0; rz[w] = 0; }
   } else if (b.group == 2) {
     uint32_t nx, ny, nz;

@@ -30,6 +30,7 @@ import numpy as np
 GROUP_NONE = "none"
 GROUP_ZN = "Zn"   # cyclic translation (Example: translation symmetry Z_n)
 GROUP_SN = "Sn"   # qubit permutations (Example: permutation symmetry S_n)
+GROUP_DN = "Dn"   # ring translations and reflection (dihedral D_n)
 
 
 @dataclass(frozen=True)

@@ -258,3 +258,55 @@ def test_program_path_matches_oracle(gpu, which):
                                    allocator=gpu["alloc"], keep_terms=True)
     ref = O.run_program(prog, group=group)
     check(res, ref, prog, what=f"program {which}")
+
+
+# ----------------------------------------------------------------------------
+# Dihedral group D_n
+# ----------------------------------------------------------------------------
+def test_dihedral_config1(gpu):
+    """Config 1's circuit merged under D_8: untruncated, so the set is fixed
+    by integer algebra and must match bit for bit."""
+    prog = W.config1().with_group("Dn")
+    res, ref = run_both(gpu, prog)
+    n = check(res, ref, prog, what="c1 Dn")
+    assert n == len(ref.terms) and set(res.terms) == set(ref.terms)
+
+
+def test_dihedral_config2_prefix(gpu):
+    prog = W.config2().with_group("Dn")
+    res, ref = run_both(gpu, prog, max_sub=12)
+    check(res, ref, prog, what="c2 Dn")
+
+
+def test_dihedral_wide_and_program_path(gpu):
+    """n = 48 (keys wider than 64 bits) through the one-program path."""
+    from paper_2512_12094_amd import driver
+    prog = W.xxz_ring(48, 2, 0.3, 1.4, eps=1e-6, obs=W.sum_ring_pairs(48, "X"),
+                      bloch=W.random_bloch(48), group="Dn", name="d48")
+    print("[case] program d48 Dn", flush=True)
+    res = driver.propagate_program(prog, stream=gpu["handle"], allocator=gpu["alloc"],
+                                   keep_terms=True)
+    ref = O.run_program(prog)
+    check(res, ref, prog, what="d48")
+
+
+def test_dihedral_rejects_chiral_layer(gpu):
+    """X_b Y_{b+1} on every bond is closed under translations but its
+    reflection Y_b X_{b+1} is absent: PP_ENOTSYM under D_n, fine under Z_n."""
+    from paper_2512_12094_amd import _lib as L
+    n = 8
+    gx = np.array([[(1 << b) | (1 << ((b + 1) % n))] for b in range(n)], dtype=np.uint64)
+    gz = np.array([[1 << ((b + 1) % n)] for b in range(n)], dtype=np.uint64)
+    th = np.full(n, 0.1)
+    x, z = W.one_site("Z", 0)
+    for group, ok in (("Zn", True), ("Dn", False)):
+        h = L.pp_create(n, group, np.array([[x]], dtype=np.uint64),
+                        np.array([[z]], dtype=np.uint64), np.array([1.0]), gpu["handle"],
+                        gpu["alloc"])
+        try:
+            L.pp_apply_layer(h, gx, gz, th, 1)
+            assert ok, group
+        except L.PPError as e:
+            assert not ok and e.code == -2, (group, e)
+        finally:
+            L.pp_destroy(h)

@@ -310,3 +310,22 @@ def test_dihedral_rejects_chiral_layer(gpu):
             assert not ok and e.code == -2, (group, e)
         finally:
             L.pp_destroy(h)
+
+
+def test_tilted_ising_saturates_below_necklace_count(gpu):
+    """Tilted-field Ising ring (Sec. IV), untruncated, merged after every
+    sub-layer: the GPU's set after every layer matches the oracle's size and
+    stays below the necklace count minus one (the identity is never produced
+    from a traceless observable), and the final set matches exactly."""
+    from paper_2512_12094_amd import driver
+    n = 8
+    prog = W.tilted_ising_ring(n, 8, 0.4)
+    print("[case] tilted Ising n=8", flush=True)
+    res = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"],
+                           record_sizes=True)
+    ref = O.run_program(prog)
+    neck = sum(4 ** math.gcd(j, n) for j in range(1, n + 1)) // n
+    assert max(res.sizes) <= neck - 1 and (0, 0) not in res.terms
+    assert res.sizes == ref.sizes and res.sizes[-1] == len(ref.terms)
+    n_cmp = check(res, ref, prog, what="ising")
+    assert n_cmp == len(ref.terms)

@@ -29,6 +29,7 @@ _SRC = os.path.join(_HERE, "pp_oracle.cpp")
 _LIB = os.path.join(_HERE, "libpp_oracle.so")
 
 GROUP_CODE = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3}
+TORUS = "T2"   # translations of an lx x ly torus (the width travels separately)
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -67,6 +68,9 @@ def lib():
         L.orc_export.argtypes = [ctypes.c_void_p, _u64p, _u64p, _f64p]
         L.orc_counters.argtypes = [ctypes.c_void_p, _u64p, _u64p]
         L.orc_canon.argtypes = [ctypes.c_int, ctypes.c_int, _u64p, _u64p, _u64p, _u64p]
+        L.orc_canon_torus.argtypes = [ctypes.c_int, ctypes.c_int, _u64p, _u64p, _u64p, _u64p]
+        L.orc_create_torus.restype = ctypes.c_void_p
+        L.orc_create_torus.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_multiply.restype = ctypes.c_int
         L.orc_multiply.argtypes = [ctypes.c_int] + [_u64p] * 6
         L.orc_exact_sum.restype = ctypes.c_double
@@ -85,10 +89,14 @@ def _join(ws) -> int:
     return sum(int(w) << (64 * i) for i, w in enumerate(ws))
 
 
-def canon(n: int, group: str, x: int, z: int):
+def canon(n: int, group: str, x: int, z: int, lx: int = 0):
+    """Representative of (x, z); group TORUS needs the torus width lx."""
     W = (n + 63) // 64
     rx, rz = (ctypes.c_uint64 * W)(), (ctypes.c_uint64 * W)()
-    lib().orc_canon(n, GROUP_CODE[group], _words(x, W), _words(z, W), rx, rz)
+    if group == TORUS:
+        lib().orc_canon_torus(lx, n // lx, _words(x, W), _words(z, W), rx, rz)
+    else:
+        lib().orc_canon(n, GROUP_CODE[group], _words(x, W), _words(z, W), rx, rz)
     return _join(rx), _join(rz)
 
 
@@ -115,9 +123,12 @@ def int_less(n: int, a, b) -> bool:
 class Oracle:
     """One propagation handle (a std::map of strings to FP64 coefficients)."""
 
-    def __init__(self, n: int, group: str):
+    def __init__(self, n: int, group: str, lx: int = 0):
         self.n, self.group, self.W = n, group, (n + 63) // 64
-        self.h = lib().orc_create(n, GROUP_CODE[group])
+        if group == TORUS:
+            self.h = lib().orc_create_torus(lx, n // lx if lx else 0)
+        else:
+            self.h = lib().orc_create(n, GROUP_CODE[group])
         if not self.h:
             raise ValueError(f"unsupported n={n}")
 
@@ -186,7 +197,7 @@ def run_program(prog, group: str | None = None, max_sublayers: int | None = None
     early (a bounded prefix, for timing samples)."""
     group = prog.group if group is None else group
     t0 = time.perf_counter()
-    o = Oracle(prog.n, group)
+    o = Oracle(prog.n, group, prog.meta.get("lx", 0))
     for (x, z, c) in prog.obs:
         o.add(x, z, c)
     o.merge()                                   # Algorithm 1, step 1

@@ -125,7 +125,17 @@ Pauli translate(const Pauli& s, int j, int n) {
   return t;
 }
 
-enum Group { kNone = 0, kTranslation = 1, kPermutation = 2, kDihedral = 3 };
+enum Group { kNone = 0, kTranslation = 1, kPermutation = 2, kDihedral = 3, kTorus = 4 };
+
+// 2D translation on an lx x ly torus, qubit q = x + lx*y: qubit (x, y) of
+// the result carries qubit ((x+a) mod lx, (y+b) mod ly) of s.
+Pauli translate2d(const Pauli& s, int a, int b, int lx, int ly) {
+  Pauli t;
+  for (int y = 0; y < ly; ++y)
+    for (int x = 0; x < lx; ++x)
+      set_letter(t, x + lx * y, get_letter(s, (x + a) % lx + lx * ((y + b) % ly)));
+  return t;
+}
 
 // Reflection of the ring: qubit q of the result carries qubit n-1-q of s.
 Pauli reflect(const Pauli& s, int n) {
@@ -176,10 +186,25 @@ Pauli canon_dihedral(const Pauli& s, int n) {
   return best;
 }
 
-Pauli canon(const Pauli& s, int n, int group) {
+// Translations of the torus Z_lx x Z_ly (a 2D lattice of the kind the
+// paper's Fig. 3 merges over): the representative is the argmin of
+// int(T_(a,b) s) over all lx*ly translations.
+Pauli canon_torus(const Pauli& s, int n, int lx) {
+  const int ly = n / lx;
+  Pauli best = s;
+  for (int b = 0; b < ly; ++b)
+    for (int a = 0; a < lx; ++a) {
+      const Pauli t = translate2d(s, a, b, lx, ly);
+      if (int_less(t, best, n)) best = t;
+    }
+  return best;
+}
+
+Pauli canon(const Pauli& s, int n, int group, int lx = 0) {
   if (group == kTranslation) return canon_translation(s, n);
   if (group == kPermutation) return canon_permutation(s, n);
   if (group == kDihedral) return canon_dihedral(s, n);
+  if (group == kTorus) return canon_torus(s, n, lx);
   return s;
 }
 
@@ -223,6 +248,7 @@ double exact_sum(const std::vector<double>& xs) {
 struct Oracle {
   int n = 0;
   int group = kNone;
+  int lx = 0;                // torus width (group kTorus)
   std::map<Pauli, double> terms;
   uint64_t propagated = 0;   // sum over gates of the terms tested
   uint64_t merged = 0;       // sum over merge points of the records entering
@@ -254,10 +280,20 @@ void truncate_map(std::map<Pauli, double>& m, int n, double eps, int wmax) {
 extern "C" {
 
 void* orc_create(int n, int group) {
-  if (n < 1 || n > 64 * kMaxWords) return nullptr;
+  if (n < 1 || n > 64 * kMaxWords || group == kTorus) return nullptr;
   auto* o = new Oracle;
   o->n = n;
   o->group = group;
+  return o;
+}
+
+// A handle merging under the translations of an lx x ly torus.
+void* orc_create_torus(int lx, int ly) {
+  if (lx < 1 || ly < 1 || lx * ly > 64 * kMaxWords) return nullptr;
+  auto* o = new Oracle;
+  o->n = lx * ly;
+  o->group = kTorus;
+  o->lx = lx;
   return o;
 }
 
@@ -277,7 +313,7 @@ void orc_merge(void* h) {
   auto* o = static_cast<Oracle*>(h);
   o->merged += o->terms.size();
   std::map<Pauli, std::vector<double>> addends;
-  for (const auto& [s, c] : o->terms) addends[canon(s, o->n, o->group)].push_back(c);
+  for (const auto& [s, c] : o->terms) addends[canon(s, o->n, o->group, o->lx)].push_back(c);
   std::map<Pauli, double> merged;
   for (const auto& [r, v] : addends) merged[r] = exact_sum(v);
   o->terms.swap(merged);
@@ -371,6 +407,16 @@ void orc_counters(void* h, uint64_t* propagated, uint64_t* merged) {
 }
 
 // Single-string helpers for the tests.
+void orc_canon_torus(int lx, int ly, const uint64_t* x, const uint64_t* z, uint64_t* rx,
+                     uint64_t* rz) {
+  const int n = lx * ly;
+  const Pauli r = canon(load(x, z, n), n, kTorus, lx);
+  for (int w = 0; w < (n + 63) / 64; ++w) {
+    rx[w] = r.x[w];
+    rz[w] = r.z[w];
+  }
+}
+
 void orc_canon(int n, int group, const uint64_t* x, const uint64_t* z,
                uint64_t* rx, uint64_t* rz) {
   const Pauli r = canon(load(x, z, n), n, group);

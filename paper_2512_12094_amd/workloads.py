@@ -25,12 +25,15 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
+import math
+
 import numpy as np
 
 GROUP_NONE = "none"
 GROUP_ZN = "Zn"   # cyclic translation (Example: translation symmetry Z_n)
 GROUP_SN = "Sn"   # qubit permutations (Example: permutation symmetry S_n)
 GROUP_DN = "Dn"   # ring translations and reflection (dihedral D_n)
+GROUP_T2 = "T2"   # translations of an lx x ly torus (width in meta["lx"])
 
 
 @dataclass(frozen=True)
@@ -199,6 +202,37 @@ def tilted_ising_ring(n: int, steps: int, dt: float, gx: float = 1.4,
     mid = (n + 1) // 2 - 1   # qubit ceil(n/2) in 1-based numbering
     return Program("ising", n, GROUP_ZN, [(*one_site("Z", mid), 1.0)], subs,
                    ZERO_STATE, dict(steps=steps, dt=dt, gx=gx, gz=gz))
+
+
+def torus_distance(i: int, j: int, lx: int, ly: int) -> float:
+    """Minimum-image Euclidean distance between sites i and j of an lx x ly
+    torus (site q = x + lx*y), so every coupling is translation invariant."""
+    dx = abs(i % lx - j % lx)
+    dy = abs(i // lx - j // lx)
+    dx, dy = min(dx, lx - dx), min(dy, ly - dy)
+    return math.hypot(dx, dy)
+
+
+def power_law_xxz_torus(lx: int, ly: int, steps: int, dt: float, *, delta: float = -1.8,
+                        jperp: float = 1.0, alpha: float = 3.0, eps=0.0, wmax=-1,
+                        obs=None, bloch=ZERO_STATE, name="xxz_torus") -> Program:
+    """Trotterised power-law XXZ model on an lx x ly torus:
+    H = sum_{i<j} J_ij (jperp (X_iX_j + Y_iY_j) + delta Z_iZ_j) with
+    J_ij = 1 / d_ij^alpha (minimum-image distance).  Per step three
+    sub-layers, XX, YY, ZZ over all pairs i<j (lexicographic); the rotation
+    exp(-i dt J P_iP_j) is R_PP(2 dt J)."""
+    n = lx * ly
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    J = {p: 1.0 / torus_distance(p[0], p[1], lx, ly) ** alpha for p in pairs}
+    subs = []
+    for _ in range(steps):
+        for kind, scale in (("X", jperp), ("Y", jperp), ("Z", delta)):
+            subs.append(SubLayer([Gate(*two_site(kind, i, j), 2.0 * dt * scale * J[(i, j)])
+                                  for (i, j) in pairs], eps=eps, wmax=wmax))
+    obs = sum_single(n, "Z") if obs is None else obs
+    return Program(name, n, GROUP_T2, obs, subs, bloch,
+                   dict(lx=lx, ly=ly, steps=steps, dt=dt, delta=delta, jperp=jperp,
+                        alpha=alpha, eps=eps))
 
 
 def config1() -> Program:

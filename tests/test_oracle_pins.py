@@ -511,3 +511,76 @@ def test_theorem1_dihedral_equals_plain_and_translation():
         b = O.run_program(prog, group="none", keep_terms=False)
         assert abs(d.expectation - b.expectation) < 1e-12 * max(1, abs(b.expectation))
         assert math.ceil(b.sizes[-1] / (2 * n)) <= d.sizes[-1] <= z.sizes[-1] <= b.sizes[-1]
+
+
+# ----------------------------------------------------------------------------
+# 2D translations Z_lx x Z_ly of a torus
+# ----------------------------------------------------------------------------
+def torus_shift(s, a, b, lx, ly):
+    """Letters: site (x, y) of the result carries site (x+a, y+b) of s."""
+    return "".join(s[(x + a) % lx + lx * ((y + b) % ly)] for y in range(ly) for x in range(lx))
+
+
+def torus_orbit_count(lx, ly, k=4):
+    """Burnside: average over the lx*ly translations of k^(number of cycles
+    of the site permutation), the cycles found by following the map."""
+    n = lx * ly
+    total = 0
+    for a in range(lx):
+        for b in range(ly):
+            seen, cycles = set(), 0
+            for q in range(n):
+                if q in seen:
+                    continue
+                cycles += 1
+                while q not in seen:
+                    seen.add(q)
+                    q = (q % lx + a) % lx + lx * ((q // lx + b) % ly)
+            total += k ** cycles
+    return total // n
+
+
+@pytest.mark.parametrize("lx,ly", [(2, 2), (2, 3), (3, 3), (2, 4), (4, 2)])
+def test_torus_representative_count(lx, ly):
+    n = lx * ly
+    reps = set()
+    for s in itertools.product("IXYZ", repeat=n):
+        reps.add(O.canon(n, "T2", *W.from_letters("".join(s)), lx=lx))
+    assert len(reps) == torus_orbit_count(lx, ly)
+
+
+@pytest.mark.parametrize("lx,ly", [(3, 4), (4, 4), (6, 6), (8, 8)])
+def test_torus_representative_is_orbit_minimum(lx, ly):
+    n = lx * ly
+    rng = random.Random(lx * 100 + ly)
+    for trial in range(20):
+        s = random_string(rng, n, None if trial % 2 else rng.randint(0, min(n, 9)))
+        rx, rz = O.canon(n, "T2", *W.from_letters(s), lx=lx)
+        orbit = [torus_shift(s, a, b, lx, ly) for a in range(lx) for b in range(ly)]
+        best = min(orbit, key=lambda t: int_value(*W.from_letters(t), n))
+        assert W.to_letters(rx, rz, n) == best
+        assert O.canon(n, "T2", rx, rz, lx=lx) == (rx, rz)
+        g = orbit[rng.randrange(len(orbit))]
+        assert O.canon(n, "T2", *W.from_letters(g), lx=lx) == (rx, rz)
+
+
+def test_torus_pp_matches_dense_orbit_sums():
+    prog = W.power_law_xxz_torus(2, 3, 1, 0.15, obs=W.sum_single(6, "Z"),
+                                 bloch=W.random_bloch(6))
+    res = O.run_program(prog)
+    Od = dense.heisenberg(prog)
+    coeffs = {k: v.real for k, v in dense.pauli_coefficients(Od, 6).items()}
+    sums = {}
+    for (x, z), c in coeffs.items():
+        r = O.canon(6, "T2", x, z, lx=2)
+        sums[r] = sums.get(r, 0.0) + c
+    assert_terms_match(res.terms, {k: v for k, v in sums.items() if abs(v) > 1e-13})
+    assert abs(res.expectation - dense.expectation(Od, prog.bloch, 6)) < 1e-12
+
+
+def test_theorem1_torus_equals_plain():
+    prog = W.power_law_xxz_torus(3, 3, 1, 0.1, bloch=W.random_bloch(9))
+    t = O.run_program(prog, keep_terms=False)
+    b = O.run_program(prog, group="none", keep_terms=False)
+    assert abs(t.expectation - b.expectation) < 1e-12 * max(1, abs(b.expectation))
+    assert math.ceil(b.sizes[-1] / 9) <= t.sizes[-1] <= b.sizes[-1]

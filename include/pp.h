@@ -30,10 +30,13 @@
  *   the dihedral group D_n (translations and the reflection q -> n-1-q of
  *   the ring, a wider group of the kind the paper's outlook names) it is
  *   the smaller of the Z_n representatives of the string and of its
- *   reflection.  Merging adds the coefficients of the distinct strings of
- *   one orbit.
+ *   reflection; for PP_GROUP_TORUS (qubit q = x + lx*y of an lx x ly torus,
+ *   the lattice setting of the paper's Fig. 3) it is the minimum over the
+ *   lx*ly translations (x, y) -> (x + a, y + b).  Merging adds the
+ *   coefficients of the distinct strings of one orbit.
  * - Supported sizes: PP_GROUP_NONE and PP_GROUP_PERMUTATION for 1 <= n <= 128,
- *   PP_GROUP_TRANSLATION and PP_GROUP_DIHEDRAL for 2 <= n <= 64.
+ *   PP_GROUP_TRANSLATION and PP_GROUP_DIHEDRAL for 2 <= n <= 64,
+ *   PP_GROUP_TORUS for 2 <= lx*ly <= 64.
  *
  * Memory, streams, ownership
  * --------------------------
@@ -75,7 +78,8 @@ enum {
   PP_GROUP_NONE = 0,         /* plain Pauli propagation (no symmetry merge) */
   PP_GROUP_TRANSLATION = 1,  /* cyclic translations Z_n                     */
   PP_GROUP_PERMUTATION = 2,  /* qubit permutations S_n                      */
-  PP_GROUP_DIHEDRAL = 3      /* ring translations and reflection D_n        */
+  PP_GROUP_DIHEDRAL = 3,     /* ring translations and reflection D_n        */
+  PP_GROUP_TORUS = 4         /* translations of a 2D torus (pp_create_torus) */
 };
 
 /*
@@ -121,6 +125,18 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype,
               const uint64_t* obs_x, const uint64_t* obs_z,
               const double* obs_coef, size_t n_obs, void* hip_stream,
               const pp_allocator* alloc);
+
+/*
+ * pp_create_torus -- pp_create for the translation group of an lx x ly
+ * torus (group PP_GROUP_TORUS, n_qubits = lx * ly, qubit q = x + lx*y).
+ * Arguments, layout, ownership and errors as for pp_create; PP_EINVAL
+ * unless 2 <= lx*ly <= 64.  Gate layers applied to the handle must be
+ * closed under both unit translations (PP_ENOTSYM otherwise).
+ */
+int pp_create_torus(pp_state** out, int lx, int ly, int dtype,
+                    const uint64_t* obs_x, const uint64_t* obs_z,
+                    const double* obs_coef, size_t n_obs, void* hip_stream,
+                    const pp_allocator* alloc);
 
 /*
  * pp_apply_layer -- Algorithm 1, step 2a, for one symmetric (sub-)layer.

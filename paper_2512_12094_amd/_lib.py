@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpp.so")
 
-PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3}
+PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3, "T2": 4}
 PP_F64 = 0
 PP_F32_COMPENSATED = 1
 DTYPES = {"f64": PP_F64, "f32": PP_F32_COMPENSATED}
@@ -56,6 +56,9 @@ def lib():
     L.pp_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                             _u64p, _u64p, _f64p, ctypes.c_size_t, _vp,
                             ctypes.POINTER(PPAllocator)]
+    L.pp_create_torus.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  _u64p, _u64p, _f64p, ctypes.c_size_t, _vp,
+                                  ctypes.POINTER(PPAllocator)]
     L.pp_apply_layer.argtypes = [_vp, _u64p, _u64p, _f64p, ctypes.c_size_t, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_int]
     L.pp_merge_canonicalize.argtypes = [_vp]
@@ -146,6 +149,20 @@ def pp_create(n, group, obs_x, obs_z, obs_coef, stream=0, allocator=None, dtype=
     al = ctypes.byref(allocator.struct) if allocator is not None else None
     _check(lib().pp_create(ctypes.byref(h), n, PP_GROUP.get(group, group),
                            DTYPES.get(dtype, dtype), xp, zp, cp, len(c), _vp(stream or None), al))
+    return h
+
+
+def pp_create_torus(lx, ly, obs_x, obs_z, obs_coef, stream=0, allocator=None, dtype="f64"):
+    """pp_create for the translations of an lx x ly torus (n = lx * ly)."""
+    n = lx * ly
+    W = (n + 63) // 64
+    x, xp = _u64(np.asarray(obs_x, dtype=np.uint64).reshape(-1, W))
+    z, zp = _u64(np.asarray(obs_z, dtype=np.uint64).reshape(-1, W))
+    c, cp = _f64(obs_coef)
+    h = _vp()
+    al = ctypes.byref(allocator.struct) if allocator is not None else None
+    _check(lib().pp_create_torus(ctypes.byref(h), lx, ly, DTYPES.get(dtype, dtype), xp, zp, cp,
+                                 len(c), _vp(stream or None), al))
     return h
 
 

@@ -101,6 +101,7 @@ struct pp_state {
   // two events, and the interval is shared by the run's launches (0 = off)
   int prof_every = 0;
   uint32_t m_hint = 0;     // term count last read back (picks tile sizes)
+  int lx = 0;              // torus width (PP_GROUP_TORUS)
   uint64_t prof_seen[PP_KERNEL_KINDS] = {};
   struct Pend {
     int k;
@@ -591,6 +592,27 @@ int check_symmetric(const pp_state* s, const uint64_t* gx, const uint64_t* gz,
           return fail(PP_ENOTSYM, "gate layer is not closed under the reflection");
       }
     }
+  } else if (s->group == PP_GROUP_TORUS) {
+    // closed under the two generators: x + 1 within each row, y + 1
+    std::map<Key, long> mult;
+    for (size_t k = 0; k < K; ++k) mult[key(gx + k * W, gz + k * W, theta[k])] += 1;
+    const int lx = s->lx, ly = n / lx;
+    auto shift = [&](uint64_t v, int a, int b) {   // qubit (x,y) <- (x+a, y+b)
+      uint64_t r = 0;
+      for (int y = 0; y < ly; ++y)
+        for (int x = 0; x < lx; ++x)
+          if ((v >> ((x + a) % lx + lx * ((y + b) % ly))) & 1) r |= 1ull << (x + lx * y);
+      return r;
+    };
+    for (const auto& [k, m] : mult) {
+      const uint64_t x = std::get<0>(k), z = std::get<2>(k);
+      for (int g = 0; g < 2; ++g) {
+        const uint64_t t1[1] = {shift(x, g == 0, g == 1)}, t2[1] = {shift(z, g == 0, g == 1)};
+        auto it = mult.find(key(t1, t2, std::get<4>(k)));
+        if (it == mult.end() || it->second != m)
+          return fail(PP_ENOTSYM, "gate layer is not closed under the torus translations");
+      }
+    }
   } else if (s->group == PP_GROUP_PERMUTATION) {
     std::map<std::tuple<int, int, int, double>, long> cls;
     std::map<Key, long> mult;
@@ -676,14 +698,14 @@ void pp_destroy(pp_state* s) {
   delete s;
 }
 
-int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t* obs_x,
-              const uint64_t* obs_z, const double* obs_coef, size_t n_obs, void* hip_stream,
-              const pp_allocator* alloc) {
+namespace {
+
+// pp_create and pp_create_torus (lx = torus width, 0 for the other groups).
+int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
+                  const uint64_t* obs_x, const uint64_t* obs_z, const double* obs_coef,
+                  size_t n_obs, void* hip_stream, const pp_allocator* alloc) {
   if (!out) return fail(PP_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!valid_group_n(group, n_qubits))
-    return fail(PP_EINVAL, "unsupported (group, n_qubits) = (" + std::to_string(group) + ", " +
-                               std::to_string(n_qubits) + ")");
   if (dtype != PP_F64 && dtype != PP_F32_COMPENSATED)
     return fail(PP_EINVAL, "dtype must be PP_F64 or PP_F32_COMPENSATED");
   if (n_obs && (!obs_x || !obs_z || !obs_coef)) return fail(PP_EINVAL, "observable is NULL");
@@ -710,6 +732,8 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   s->buf.group = group;
   s->buf.narrow = (group == PP_GROUP_PERMUTATION || n_qubits <= 32) ? 1u : 0u;
   s->buf.f32 = dtype == PP_F32_COMPENSATED ? 1u : 0u;
+  s->buf.lx = lx;
+  s->lx = lx;
 
   HIP_TRY(hipHostMalloc((void**)&s->h_dyn, sizeof(InstDyn), hipHostMallocDefault));
   s->d_buf = (InstBuf*)dev_alloc(s.get(), sizeof(InstBuf));
@@ -774,6 +798,27 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
   if ((rc = run_ops(s.get(), ops, {}, {}, false))) return bail(rc);
   *out = s.release();
   return PP_OK;
+}
+
+}  // namespace
+
+int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t* obs_x,
+              const uint64_t* obs_z, const double* obs_coef, size_t n_obs, void* hip_stream,
+              const pp_allocator* alloc) {
+  if (!valid_group_n(group, n_qubits))
+    return fail(PP_EINVAL, "unsupported (group, n_qubits) = (" + std::to_string(group) + ", " +
+                               std::to_string(n_qubits) + ")");
+  return create_handle(out, n_qubits, group, 0, dtype, obs_x, obs_z, obs_coef, n_obs, hip_stream,
+                       alloc);
+}
+
+int pp_create_torus(pp_state** out, int lx, int ly, int dtype, const uint64_t* obs_x,
+                    const uint64_t* obs_z, const double* obs_coef, size_t n_obs,
+                    void* hip_stream, const pp_allocator* alloc) {
+  if (lx < 1 || ly < 1 || lx * ly < 2 || lx * ly > 64)
+    return fail(PP_EINVAL, "unsupported torus " + std::to_string(lx) + " x " + std::to_string(ly));
+  return create_handle(out, lx * ly, PP_GROUP_TORUS, lx, dtype, obs_x, obs_z, obs_coef, n_obs,
+                       hip_stream, alloc);
 }
 
 int pp_work_counters(pp_state* s, uint64_t out[6]) {

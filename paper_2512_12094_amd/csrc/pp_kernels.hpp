@@ -177,6 +177,38 @@ __device__ __forceinline__ void canon_dihedral(uint64_t x, uint64_t z, int n, ui
   *rz = az;
 }
 
+// Translations of an lx x ly torus (qubit q = x + lx*y, n = lx*ly <= 64):
+// the minimum over all shifts.  Shifting by b rows is a rotation of the
+// whole mask by b*lx bits; shifting every row by a columns moves the bits
+// with x >= a down by a and wraps the others, with masks replicated over the
+// rows.
+__device__ __forceinline__ void canon_torus(uint64_t x, uint64_t z, int n, int lx, uint64_t* rx,
+                                            uint64_t* rz) {
+  const int ly = n / lx;
+  const uint64_t mask = (n == 64) ? ~0ull : ((1ull << n) - 1);
+  uint64_t rep = 0;                        // bit 0 of every row
+  for (int y = 0; y < ly; ++y) rep |= 1ull << (lx * y);
+  uint64_t bx = x, bz = z;
+  for (int b = 0; b < ly; ++b) {
+    const uint64_t yx = rotr_n(x, b * lx, n, mask), yz = rotr_n(z, b * lx, n, mask);
+    for (int a = 0; a < lx; ++a) {
+      uint64_t tx = yx, tz = yz;
+      if (a) {
+        const uint64_t low = (((1ull << (lx - a)) - 1) * rep) & mask;   // columns < lx - a
+        const uint64_t high = mask & ~low;
+        tx = ((yx >> a) & low) | ((yx << (lx - a)) & high);
+        tz = ((yz >> a) & low) | ((yz << (lx - a)) & high);
+      }
+      if (int_less1(tx, tz, bx, bz)) {
+        bx = tx;
+        bz = tz;
+      }
+    }
+  }
+  *rx = bx;
+  *rz = bz;
+}
+
 // Algorithm 3: counts of X, Y, Z letters.
 __device__ __forceinline__ void perm_counts(const uint64_t* x, const uint64_t* z, int W,
                                    uint32_t* nx, uint32_t* ny, uint32_t* nz) {
@@ -218,6 +250,7 @@ __device__ __forceinline__ uint64_t narrow_key(const InstBuf& b, const uint64_t*
   uint64_t rx = x[0], rz = z[0];
   if (b.group == 1) canon_translation(x[0], z[0], b.n, &rx, &rz);
   if (b.group == 3) canon_dihedral(x[0], z[0], b.n, &rx, &rz);
+  if (b.group == 4) canon_torus(x[0], z[0], b.n, b.lx, &rx, &rz);
   return rx | (rz << 32);   // n <= 32
 }
 
@@ -236,11 +269,13 @@ __device__ __forceinline__ void narrow_decode(const InstBuf& b, uint64_t key, ui
 // Representative as a string (wide path: Z_n with n <= 64, or identity).
 __device__ __forceinline__ void rep_string(const InstBuf& b, const uint64_t* x, const uint64_t* z,
                                   uint64_t* rx, uint64_t* rz) {
-  if (b.group == 1 || b.group == 3) {
+  if (b.group == 1 || b.group == 3 || b.group == 4) {
     if (b.group == 1)
       canon_translation(x[0], z[0], b.n, rx, rz);
-    else
+    else if (b.group == 3)
       canon_dihedral(x[0], z[0], b.n, rx, rz);
+    else
+      canon_torus(x[0], z[0], b.n, b.lx, rx, rz);
     PP_FOR_W(w, 1, b.W, kMaxW) { rx[w] = 0; rz[w] = 0; }
   } else if (b.group == 2) {
     uint32_t nx, ny, nz;

@@ -117,6 +117,7 @@ struct InstBuf {
   uint32_t narrow;       // merge keys fit 64 bits exactly
   uint32_t f32;          // coefficients stored and rotated in FP32
   uint32_t nopart;       // the partitioned merge's kernels are not launched
+  int32_t lx;            // torus width (group 4: translations of lx x n/lx)
 };
 
 struct InstDyn {

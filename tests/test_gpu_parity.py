@@ -329,3 +329,48 @@ def test_tilted_ising_saturates_below_necklace_count(gpu):
     assert res.sizes == ref.sizes and res.sizes[-1] == len(ref.terms)
     n_cmp = check(res, ref, prog, what="ising")
     assert n_cmp == len(ref.terms)
+
+
+# ----------------------------------------------------------------------------
+# 2D translations of a torus
+# ----------------------------------------------------------------------------
+def test_torus_untruncated_3x3(gpu):
+    prog = W.power_law_xxz_torus(3, 3, 1, 0.2, bloch=W.random_bloch(9))
+    res, ref = run_both(gpu, prog)
+    n = check(res, ref, prog, what="torus 3x3")
+    assert n == len(ref.terms) and set(res.terms) == set(ref.terms)
+
+
+def test_torus_truncated_4x4(gpu):
+    prog = W.power_law_xxz_torus(4, 4, 1, 0.1, eps=1e-4, bloch=W.random_bloch(16))
+    res, ref = run_both(gpu, prog)
+    check(res, ref, prog, what="torus 4x4")
+
+
+def test_torus_6x6_wide_program_path(gpu):
+    """n = 36: keys wider than 64 bits; one device program."""
+    from paper_2512_12094_amd import driver
+    prog = W.power_law_xxz_torus(6, 6, 1, 0.05, eps=1e-3, bloch=W.random_bloch(36))
+    print("[case] program torus 6x6", flush=True)
+    res = driver.propagate_program(prog, stream=gpu["handle"], allocator=gpu["alloc"],
+                                   keep_terms=True)
+    ref = O.run_program(prog)
+    check(res, ref, prog, what="torus 6x6")
+
+
+def test_torus_rejects_row_only_layer(gpu):
+    """XX on the bonds of row 0 only: closed under x shifts, not under y."""
+    from paper_2512_12094_amd import _lib as L
+    lx, ly = 4, 3
+    gx = np.array([[(1 << a) | (1 << ((a + 1) % lx))] for a in range(lx)], dtype=np.uint64)
+    gz = np.zeros((lx, 1), dtype=np.uint64)
+    x, z = W.one_site("Z", 0)
+    h = L.pp_create_torus(lx, ly, np.array([[x]], dtype=np.uint64),
+                          np.array([[z]], dtype=np.uint64), np.array([1.0]), gpu["handle"],
+                          gpu["alloc"])
+    try:
+        with pytest.raises(L.PPError) as e:
+            L.pp_apply_layer(h, gx, gz, np.full(lx, 0.1), 1)
+        assert e.value.code == -2
+    finally:
+        L.pp_destroy(h)

@@ -30,6 +30,7 @@ _LIB = os.path.join(_HERE, "libpp_oracle.so")
 
 GROUP_CODE = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3}
 TORUS = "T2"   # translations of an lx x ly torus (the width travels separately)
+EXPLICIT = "G"  # a group given by its list of qubit permutations
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -69,6 +70,10 @@ def lib():
         L.orc_counters.argtypes = [ctypes.c_void_p, _u64p, _u64p]
         L.orc_canon.argtypes = [ctypes.c_int, ctypes.c_int, _u64p, _u64p, _u64p, _u64p]
         L.orc_canon_torus.argtypes = [ctypes.c_int, ctypes.c_int, _u64p, _u64p, _u64p, _u64p]
+        L.orc_create_group.restype = ctypes.c_void_p
+        L.orc_create_group.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
+        L.orc_canon_group.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                      _u64p, _u64p, _u64p, _u64p]
         L.orc_create_torus.restype = ctypes.c_void_p
         L.orc_create_torus.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_multiply.restype = ctypes.c_int
@@ -89,11 +94,20 @@ def _join(ws) -> int:
     return sum(int(w) << (64 * i) for i, w in enumerate(ws))
 
 
-def canon(n: int, group: str, x: int, z: int, lx: int = 0):
-    """Representative of (x, z); group TORUS needs the torus width lx."""
+def _perm_array(perms, n):
+    a = np.ascontiguousarray(np.asarray(perms, dtype=np.uint8).reshape(-1, n))
+    return a, len(a)
+
+
+def canon(n: int, group: str, x: int, z: int, lx: int = 0, perms=None):
+    """Representative of (x, z); group TORUS needs the torus width lx,
+    group EXPLICIT the element list perms (rows of n qubit indices)."""
     W = (n + 63) // 64
     rx, rz = (ctypes.c_uint64 * W)(), (ctypes.c_uint64 * W)()
-    if group == TORUS:
+    if group == EXPLICIT:
+        a, m = _perm_array(perms, n)
+        lib().orc_canon_group(n, a.ctypes.data, m, _words(x, W), _words(z, W), rx, rz)
+    elif group == TORUS:
         lib().orc_canon_torus(lx, n // lx, _words(x, W), _words(z, W), rx, rz)
     else:
         lib().orc_canon(n, GROUP_CODE[group], _words(x, W), _words(z, W), rx, rz)
@@ -123,9 +137,12 @@ def int_less(n: int, a, b) -> bool:
 class Oracle:
     """One propagation handle (a std::map of strings to FP64 coefficients)."""
 
-    def __init__(self, n: int, group: str, lx: int = 0):
+    def __init__(self, n: int, group: str, lx: int = 0, perms=None):
         self.n, self.group, self.W = n, group, (n + 63) // 64
-        if group == TORUS:
+        if group == EXPLICIT:
+            a, m = _perm_array(perms, n)
+            self.h = lib().orc_create_group(n, a.ctypes.data, m)
+        elif group == TORUS:
             self.h = lib().orc_create_torus(lx, n // lx if lx else 0)
         else:
             self.h = lib().orc_create(n, GROUP_CODE[group])
@@ -197,7 +214,7 @@ def run_program(prog, group: str | None = None, max_sublayers: int | None = None
     early (a bounded prefix, for timing samples)."""
     group = prog.group if group is None else group
     t0 = time.perf_counter()
-    o = Oracle(prog.n, group, prog.meta.get("lx", 0))
+    o = Oracle(prog.n, group, prog.meta.get("lx", 0), prog.meta.get("perms"))
     for (x, z, c) in prog.obs:
         o.add(x, z, c)
     o.merge()                                   # Algorithm 1, step 1

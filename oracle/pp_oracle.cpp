@@ -125,7 +125,26 @@ Pauli translate(const Pauli& s, int j, int n) {
   return t;
 }
 
-enum Group { kNone = 0, kTranslation = 1, kPermutation = 2, kDihedral = 3, kTorus = 4 };
+enum Group { kNone = 0, kTranslation = 1, kPermutation = 2, kDihedral = 3, kTorus = 4,
+             kExplicit = 5 };
+
+// A qubit permutation g as a list: qubit q of g.s carries qubit perm[q] of s.
+Pauli permute(const Pauli& s, const uint8_t* perm, int n) {
+  Pauli t;
+  for (int q = 0; q < n; ++q) set_letter(t, q, get_letter(s, perm[q]));
+  return t;
+}
+
+// Any finite group of qubit permutations given by its element list: the
+// representative is the argmin of int(g s) over the listed elements.
+Pauli canon_explicit(const Pauli& s, int n, const std::vector<uint8_t>& perms) {
+  Pauli best = s;
+  for (size_t g = 0; g * n < perms.size(); ++g) {
+    const Pauli t = permute(s, &perms[g * n], n);
+    if (int_less(t, best, n)) best = t;
+  }
+  return best;
+}
 
 // 2D translation on an lx x ly torus, qubit q = x + lx*y: qubit (x, y) of
 // the result carries qubit ((x+a) mod lx, (y+b) mod ly) of s.
@@ -249,6 +268,7 @@ struct Oracle {
   int n = 0;
   int group = kNone;
   int lx = 0;                // torus width (group kTorus)
+  std::vector<uint8_t> perms;  // group kExplicit: elements x n
   std::map<Pauli, double> terms;
   uint64_t propagated = 0;   // sum over gates of the terms tested
   uint64_t merged = 0;       // sum over merge points of the records entering
@@ -287,6 +307,27 @@ void* orc_create(int n, int group) {
   return o;
 }
 
+// A handle merging under the group whose m elements are the rows of perms
+// (m x n, row g: qubit q of g.s carries qubit perms[g*n + q] of s).
+void* orc_create_group(int n, const uint8_t* perms, size_t m) {
+  if (n < 1 || n > 64 * kMaxWords || m == 0) return nullptr;
+  auto* o = new Oracle;
+  o->n = n;
+  o->group = kExplicit;
+  o->perms.assign(perms, perms + m * n);
+  return o;
+}
+
+void orc_canon_group(int n, const uint8_t* perms, size_t m, const uint64_t* x,
+                     const uint64_t* z, uint64_t* rx, uint64_t* rz) {
+  const std::vector<uint8_t> p(perms, perms + m * n);
+  const Pauli r = canon_explicit(load(x, z, n), n, p);
+  for (int w = 0; w < (n + 63) / 64; ++w) {
+    rx[w] = r.x[w];
+    rz[w] = r.z[w];
+  }
+}
+
 // A handle merging under the translations of an lx x ly torus.
 void* orc_create_torus(int lx, int ly) {
   if (lx < 1 || ly < 1 || lx * ly > 64 * kMaxWords) return nullptr;
@@ -313,7 +354,9 @@ void orc_merge(void* h) {
   auto* o = static_cast<Oracle*>(h);
   o->merged += o->terms.size();
   std::map<Pauli, std::vector<double>> addends;
-  for (const auto& [s, c] : o->terms) addends[canon(s, o->n, o->group, o->lx)].push_back(c);
+  for (const auto& [s, c] : o->terms)
+    addends[o->group == kExplicit ? canon_explicit(s, o->n, o->perms)
+                                  : canon(s, o->n, o->group, o->lx)].push_back(c);
   std::map<Pauli, double> merged;
   for (const auto& [r, v] : addends) merged[r] = exact_sum(v);
   o->terms.swap(merged);

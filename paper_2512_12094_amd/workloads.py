@@ -34,6 +34,7 @@ GROUP_ZN = "Zn"   # cyclic translation (Example: translation symmetry Z_n)
 GROUP_SN = "Sn"   # qubit permutations (Example: permutation symmetry S_n)
 GROUP_DN = "Dn"   # ring translations and reflection (dihedral D_n)
 GROUP_T2 = "T2"   # translations of an lx x ly torus (width in meta["lx"])
+GROUP_G = "G"     # any group of qubit permutations (element list in meta["perms"])
 
 
 @dataclass(frozen=True)
@@ -233,6 +234,39 @@ def power_law_xxz_torus(lx: int, ly: int, steps: int, dt: float, *, delta: float
     return Program(name, n, GROUP_T2, obs, subs, bloch,
                    dict(lx=lx, ly=ly, steps=steps, dt=dt, delta=delta, jperp=jperp,
                         alpha=alpha, eps=eps))
+
+
+# ----------------------------------------------------------------------------
+# Groups as explicit element lists: row g lists, for each qubit q, the qubit
+# of s that qubit q of g.s carries (index permutations only).
+# ----------------------------------------------------------------------------
+def elements_ring(n: int) -> List[List[int]]:
+    """The n translations T^j of a ring."""
+    return [[(q + j) % n for q in range(n)] for j in range(n)]
+
+
+def elements_dihedral(n: int) -> List[List[int]]:
+    """The 2n elements T^j and T^j R (R: q -> n-1-q) of D_n."""
+    rots = elements_ring(n)
+    return rots + [[n - 1 - r[q] for q in range(n)] for r in rots]
+
+
+def elements_torus(lx: int, ly: int) -> List[List[int]]:
+    return [[(q % lx + a) % lx + lx * ((q // lx + b) % ly) for q in range(lx * ly)]
+            for b in range(ly) for a in range(lx)]
+
+
+def elements_symmetric(n: int) -> List[List[int]]:
+    import itertools
+    return [list(p) for p in itertools.permutations(range(n))]
+
+
+def with_explicit_group(prog: Program, perms) -> Program:
+    """The same circuit merged under the group with element list perms."""
+    meta = dict(prog.meta)
+    meta["perms"] = [list(map(int, r)) for r in perms]
+    return Program(prog.name + "[G]", prog.n, GROUP_G, list(prog.obs), prog.sublayers,
+                   prog.bloch, meta)
 
 
 def config1() -> Program:

@@ -584,3 +584,79 @@ def test_theorem1_torus_equals_plain():
     b = O.run_program(prog, group="none", keep_terms=False)
     assert abs(t.expectation - b.expectation) < 1e-12 * max(1, abs(b.expectation))
     assert math.ceil(b.sizes[-1] / 9) <= t.sizes[-1] <= b.sizes[-1]
+
+
+# ----------------------------------------------------------------------------
+# Any finite group of qubit permutations, given by its element list
+# ----------------------------------------------------------------------------
+def burnside_count(perms, k=4):
+    """(1/|G|) sum_g k^(cycles of g), cycles found by following each map."""
+    total = 0
+    for p in perms:
+        seen, cycles = set(), 0
+        for q in range(len(p)):
+            if q in seen:
+                continue
+            cycles += 1
+            while q not in seen:
+                seen.add(q)
+                q = p[q]
+        total += k ** cycles
+    assert total % len(perms) == 0
+    return total // len(perms)
+
+
+def klein_four():
+    return [[0, 1, 2, 3], [1, 0, 3, 2], [2, 3, 0, 1], [3, 2, 1, 0]]
+
+
+def cyclic_6_on_5():
+    """The cyclic group generated by (0 1 2)(3 4), order 6."""
+    g = [1, 2, 0, 4, 3]
+    els, cur = [], list(range(5))
+    for _ in range(6):
+        els.append(cur)
+        cur = [cur[g[q]] for q in range(5)]
+    return els
+
+
+@pytest.mark.parametrize("name", ["klein4", "c6on5", "s3", "d5", "torus2x3"])
+def test_explicit_group_representative_count(name):
+    perms, n = {"klein4": (klein_four(), 4), "c6on5": (cyclic_6_on_5(), 5),
+                "s3": (W.elements_symmetric(3), 3), "d5": (W.elements_dihedral(5), 5),
+                "torus2x3": (W.elements_torus(2, 3), 6)}[name]
+    reps = set()
+    for s in itertools.product("IXYZ", repeat=n):
+        reps.add(O.canon(n, "G", *W.from_letters("".join(s)), perms=perms))
+    assert len(reps) == burnside_count(perms)
+
+
+def test_explicit_group_agrees_with_the_named_groups():
+    rng = random.Random(3)
+    for n in (5, 12, 32, 40):
+        for _ in range(10):
+            s = random_string(rng, n)
+            xz = W.from_letters(s)
+            assert O.canon(n, "G", *xz, perms=W.elements_ring(n)) == O.canon(n, "Zn", *xz)
+            assert O.canon(n, "G", *xz, perms=W.elements_dihedral(n)) == O.canon(n, "Dn", *xz)
+    for lx, ly in ((3, 4), (6, 6)):
+        for _ in range(10):
+            s = random_string(rng, lx * ly)
+            xz = W.from_letters(s)
+            assert O.canon(lx * ly, "G", *xz, perms=W.elements_torus(lx, ly)) == \
+                O.canon(lx * ly, "T2", *xz, lx=lx)
+    for n in (3, 5):
+        for s in itertools.islice(itertools.product("IXYZ", repeat=n), 0, None, 7):
+            xz = W.from_letters("".join(s))
+            assert O.canon(n, "G", *xz, perms=W.elements_symmetric(n)) == O.canon(n, "Sn", *xz)
+
+
+def test_theorem1_explicit_group():
+    """The ring circuit merged under D_n given as a list: the same sets and
+    expectation as D_n, and the plain expectation (Theorem 1)."""
+    prog = W.xxz_ring(9, 2, 0.21, 1.3, obs=W.sum_ring_pairs(9, "X"), bloch=W.random_bloch(9))
+    g = O.run_program(W.with_explicit_group(prog, W.elements_dihedral(9)))
+    d = O.run_program(prog, group="Dn")
+    b = O.run_program(prog, group="none", keep_terms=False)
+    assert g.terms == d.terms and g.expectation == d.expectation
+    assert abs(g.expectation - b.expectation) < 1e-12 * max(1, abs(b.expectation))

@@ -32,11 +32,14 @@
  *   the smaller of the Z_n representatives of the string and of its
  *   reflection; for PP_GROUP_TORUS (qubit q = x + lx*y of an lx x ly torus,
  *   the lattice setting of the paper's Fig. 3) it is the minimum over the
- *   lx*ly translations (x, y) -> (x + a, y + b).  Merging adds the
- *   coefficients of the distinct strings of one orbit.
+ *   lx*ly translations (x, y) -> (x + a, y + b); for PP_GROUP_EXPLICIT (any
+ *   finite group of qubit permutations, given by its element list) it is the
+ *   minimum over the listed images (Algorithm 2 generalised).  Merging adds
+ *   the coefficients of the distinct strings of one orbit.
  * - Supported sizes: PP_GROUP_NONE and PP_GROUP_PERMUTATION for 1 <= n <= 128,
  *   PP_GROUP_TRANSLATION and PP_GROUP_DIHEDRAL for 2 <= n <= 64,
- *   PP_GROUP_TORUS for 2 <= lx*ly <= 64.
+ *   PP_GROUP_TORUS for 2 <= lx*ly <= 64, PP_GROUP_EXPLICIT for 2 <= n <= 64
+ *   with at most 1024 group elements.
  *
  * Memory, streams, ownership
  * --------------------------
@@ -79,7 +82,8 @@ enum {
   PP_GROUP_TRANSLATION = 1,  /* cyclic translations Z_n                     */
   PP_GROUP_PERMUTATION = 2,  /* qubit permutations S_n                      */
   PP_GROUP_DIHEDRAL = 3,     /* ring translations and reflection D_n        */
-  PP_GROUP_TORUS = 4         /* translations of a 2D torus (pp_create_torus) */
+  PP_GROUP_TORUS = 4,        /* translations of a 2D torus (pp_create_torus) */
+  PP_GROUP_EXPLICIT = 5      /* any permutation group (pp_create_group)     */
 };
 
 /*
@@ -135,6 +139,23 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype,
  */
 int pp_create_torus(pp_state** out, int lx, int ly, int dtype,
                     const uint64_t* obs_x, const uint64_t* obs_z,
+                    const double* obs_coef, size_t n_obs, void* hip_stream,
+                    const pp_allocator* alloc);
+
+/*
+ * pp_create_group -- pp_create for any finite group of qubit permutations
+ * (PP_GROUP_EXPLICIT).  perms (host, n_elems rows of n_qubits bytes,
+ * row-major) lists every element g: qubit q of g.s carries qubit
+ * perms[g*n_qubits + q] of s.  The list must be a group: every row a
+ * permutation of 0..n_qubits-1, the identity present, closed under
+ * composition, no row repeated; otherwise PP_EINVAL (also unless
+ * 2 <= n_qubits <= 64 and 1 <= n_elems <= 1024).  The list is copied to the
+ * device before the call returns.  Other arguments as for pp_create.
+ * Gate layers applied to the handle must be closed under every element
+ * (PP_ENOTSYM otherwise).
+ */
+int pp_create_group(pp_state** out, int n_qubits, const uint8_t* perms, size_t n_elems,
+                    int dtype, const uint64_t* obs_x, const uint64_t* obs_z,
                     const double* obs_coef, size_t n_obs, void* hip_stream,
                     const pp_allocator* alloc);
 

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpp.so")
 
-PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3, "T2": 4}
+PP_GROUP = {"none": 0, "Zn": 1, "Sn": 2, "Dn": 3, "T2": 4, "G": 5}
 PP_F64 = 0
 PP_F32_COMPENSATED = 1
 DTYPES = {"f64": PP_F64, "f32": PP_F32_COMPENSATED}
@@ -56,6 +56,9 @@ def lib():
     L.pp_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                             _u64p, _u64p, _f64p, ctypes.c_size_t, _vp,
                             ctypes.POINTER(PPAllocator)]
+    L.pp_create_group.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t,
+                                  ctypes.c_int, _u64p, _u64p, _f64p, ctypes.c_size_t, _vp,
+                                  ctypes.POINTER(PPAllocator)]
     L.pp_create_torus.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   _u64p, _u64p, _f64p, ctypes.c_size_t, _vp,
                                   ctypes.POINTER(PPAllocator)]
@@ -149,6 +152,22 @@ def pp_create(n, group, obs_x, obs_z, obs_coef, stream=0, allocator=None, dtype=
     al = ctypes.byref(allocator.struct) if allocator is not None else None
     _check(lib().pp_create(ctypes.byref(h), n, PP_GROUP.get(group, group),
                            DTYPES.get(dtype, dtype), xp, zp, cp, len(c), _vp(stream or None), al))
+    return h
+
+
+def pp_create_group(n, perms, obs_x, obs_z, obs_coef, stream=0, allocator=None, dtype="f64"):
+    """pp_create for the group whose elements are the rows of perms (each a
+    list of n qubit indices: qubit q of g.s carries qubit perms[g][q] of s)."""
+    W = (n + 63) // 64
+    p = np.ascontiguousarray(np.asarray(perms, dtype=np.uint8).reshape(-1, n))
+    x, xp = _u64(np.asarray(obs_x, dtype=np.uint64).reshape(-1, W))
+    z, zp = _u64(np.asarray(obs_z, dtype=np.uint64).reshape(-1, W))
+    c, cp = _f64(obs_coef)
+    h = _vp()
+    al = ctypes.byref(allocator.struct) if allocator is not None else None
+    _check(lib().pp_create_group(ctypes.byref(h), n, p.ctypes.data_as(_vp), len(p),
+                                 DTYPES.get(dtype, dtype), xp, zp, cp, len(c),
+                                 _vp(stream or None), al))
     return h
 
 

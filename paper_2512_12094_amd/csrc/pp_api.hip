@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -102,6 +103,8 @@ struct pp_state {
   int prof_every = 0;
   uint32_t m_hint = 0;     // term count last read back (picks tile sizes)
   int lx = 0;              // torus width (PP_GROUP_TORUS)
+  std::vector<uint8_t> gperm;   // PP_GROUP_EXPLICIT: element list (host copy)
+  uint8_t* d_gperm = nullptr;   // and its device copy
   uint64_t prof_seen[PP_KERNEL_KINDS] = {};
   struct Pend {
     int k;
@@ -613,6 +616,25 @@ int check_symmetric(const pp_state* s, const uint64_t* gx, const uint64_t* gz,
           return fail(PP_ENOTSYM, "gate layer is not closed under the torus translations");
       }
     }
+  } else if (s->group == PP_GROUP_EXPLICIT) {
+    std::map<Key, long> mult;
+    for (size_t k = 0; k < K; ++k) mult[key(gx + k * W, gz + k * W, theta[k])] += 1;
+    const size_t m = s->gperm.size() / n;
+    for (const auto& [k, mu] : mult) {
+      const uint64_t x = std::get<0>(k), z = std::get<2>(k);
+      for (size_t g = 0; g < m; ++g) {
+        const uint8_t* p = &s->gperm[g * n];
+        uint64_t tx = 0, tz = 0;
+        for (int q = 0; q < n; ++q) {
+          tx |= ((x >> p[q]) & 1ull) << q;
+          tz |= ((z >> p[q]) & 1ull) << q;
+        }
+        const uint64_t t1[1] = {tx}, t2[1] = {tz};
+        auto it = mult.find(key(t1, t2, std::get<4>(k)));
+        if (it == mult.end() || it->second != mu)
+          return fail(PP_ENOTSYM, "gate layer is not closed under the group");
+      }
+    }
   } else if (s->group == PP_GROUP_PERMUTATION) {
     std::map<std::tuple<int, int, int, double>, long> cls;
     std::map<Key, long> mult;
@@ -685,6 +707,7 @@ void pp_destroy(pp_state* s) {
   dev_free(s, s->d_dynp);
   dev_free(s, s->d_ninst);
   dev_free(s, s->d_sync);
+  dev_free(s, s->d_gperm);
   if (s->h_dyn) (void)hipHostFree(s->h_dyn);
   for (auto& st : s->ring) {
     if (st.h) (void)hipHostFree(st.h);
@@ -703,7 +726,8 @@ namespace {
 // pp_create and pp_create_torus (lx = torus width, 0 for the other groups).
 int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
                   const uint64_t* obs_x, const uint64_t* obs_z, const double* obs_coef,
-                  size_t n_obs, void* hip_stream, const pp_allocator* alloc) {
+                  size_t n_obs, void* hip_stream, const pp_allocator* alloc,
+                  const std::vector<uint8_t>* gperm = nullptr) {
   if (!out) return fail(PP_EINVAL, "out is NULL");
   *out = nullptr;
   if (dtype != PP_F64 && dtype != PP_F32_COMPENSATED)
@@ -752,6 +776,16 @@ int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
     pp_destroy(s.release());
     return code;
   };
+  if (gperm) {                            // the group's element list, on the device
+    s->gperm = *gperm;
+    s->d_gperm = (uint8_t*)dev_alloc(s.get(), s->gperm.size());
+    if (!s->d_gperm) return bail(fail(PP_ENOMEM, "group element list allocation failed"));
+    if (hipMemcpyAsync(s->d_gperm, s->gperm.data(), s->gperm.size(), hipMemcpyHostToDevice,
+                       s->stream))
+      return bail(fail(PP_EDEVICE, "group element list upload failed"));
+    s->buf.gperm = s->d_gperm;
+    s->buf.gsize = (uint32_t)(s->gperm.size() / n_qubits);
+  }
   if (hipMemcpyAsync(s->d_bufp, &s->d_buf, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
       hipMemcpyAsync(s->d_dynp, &s->d_dyn, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
       hipMemcpyAsync(s->d_ninst, &one, sizeof(int), hipMemcpyHostToDevice, s->stream) ||
@@ -810,6 +844,38 @@ int pp_create(pp_state** out, int n_qubits, int group, int dtype, const uint64_t
                                std::to_string(n_qubits) + ")");
   return create_handle(out, n_qubits, group, 0, dtype, obs_x, obs_z, obs_coef, n_obs, hip_stream,
                        alloc);
+}
+
+int pp_create_group(pp_state** out, int n_qubits, const uint8_t* perms, size_t n_elems,
+                    int dtype, const uint64_t* obs_x, const uint64_t* obs_z,
+                    const double* obs_coef, size_t n_obs, void* hip_stream,
+                    const pp_allocator* alloc) {
+  const int n = n_qubits;
+  if (n < 2 || n > 64) return fail(PP_EINVAL, "explicit groups need 2 <= n_qubits <= 64");
+  if (!perms || n_elems < 1 || n_elems > 1024)
+    return fail(PP_EINVAL, "the element list needs 1..1024 rows");
+  std::set<std::vector<uint8_t>> rows;
+  for (size_t g = 0; g < n_elems; ++g) {
+    std::vector<uint8_t> r(perms + g * n, perms + (g + 1) * n);
+    std::vector<uint8_t> seen(n, 0);
+    for (uint8_t q : r) {
+      if (q >= n || seen[q]) return fail(PP_EINVAL, "row " + std::to_string(g) + " is not a permutation");
+      seen[q] = 1;
+    }
+    if (!rows.insert(r).second) return fail(PP_EINVAL, "repeated group element");
+  }
+  std::vector<uint8_t> id(n);
+  for (int q = 0; q < n; ++q) id[q] = (uint8_t)q;
+  if (!rows.count(id)) return fail(PP_EINVAL, "the identity is not in the element list");
+  std::vector<uint8_t> c(n);
+  for (const auto& a : rows)                // (a.(b.s))[q] = s[b[a[q]]]
+    for (const auto& b : rows) {
+      for (int q = 0; q < n; ++q) c[q] = b[a[q]];
+      if (!rows.count(c)) return fail(PP_EINVAL, "the element list is not closed under composition");
+    }
+  const std::vector<uint8_t> flat(perms, perms + n_elems * n);
+  return create_handle(out, n, PP_GROUP_EXPLICIT, 0, dtype, obs_x, obs_z, obs_coef, n_obs,
+                       hip_stream, alloc, &flat);
 }
 
 int pp_create_torus(pp_state** out, int lx, int ly, int dtype, const uint64_t* obs_x,

@@ -209,6 +209,30 @@ __device__ __forceinline__ void canon_torus(uint64_t x, uint64_t z, int n, int l
   *rz = bz;
 }
 
+// Any finite group of qubit permutations given by its element list (n <= 64):
+// the minimum over the listed images, image g taking qubit gperm[g*n + q] of
+// the string to qubit q.
+__device__ __forceinline__ void canon_explicit(uint64_t x, uint64_t z, int n,
+                                               const uint8_t* gperm, uint32_t gsize,
+                                               uint64_t* rx, uint64_t* rz) {
+  uint64_t bx = x, bz = z;
+  for (uint32_t g = 0; g < gsize; ++g) {
+    const uint8_t* p = gperm + (size_t)g * n;
+    uint64_t tx = 0, tz = 0;
+    for (int q = 0; q < n; ++q) {
+      const int src = p[q];
+      tx |= ((x >> src) & 1ull) << q;
+      tz |= ((z >> src) & 1ull) << q;
+    }
+    if (int_less1(tx, tz, bx, bz)) {
+      bx = tx;
+      bz = tz;
+    }
+  }
+  *rx = bx;
+  *rz = bz;
+}
+
 // Algorithm 3: counts of X, Y, Z letters.
 __device__ __forceinline__ void perm_counts(const uint64_t* x, const uint64_t* z, int W,
                                    uint32_t* nx, uint32_t* ny, uint32_t* nz) {
@@ -251,6 +275,7 @@ __device__ __forceinline__ uint64_t narrow_key(const InstBuf& b, const uint64_t*
   if (b.group == 1) canon_translation(x[0], z[0], b.n, &rx, &rz);
   if (b.group == 3) canon_dihedral(x[0], z[0], b.n, &rx, &rz);
   if (b.group == 4) canon_torus(x[0], z[0], b.n, b.lx, &rx, &rz);
+  if (b.group == 5) canon_explicit(x[0], z[0], b.n, b.gperm, b.gsize, &rx, &rz);
   return rx | (rz << 32);   // n <= 32
 }
 
@@ -269,13 +294,15 @@ __device__ __forceinline__ void narrow_decode(const InstBuf& b, uint64_t key, ui
 // Representative as a string (wide path: Z_n with n <= 64, or identity).
 __device__ __forceinline__ void rep_string(const InstBuf& b, const uint64_t* x, const uint64_t* z,
                                   uint64_t* rx, uint64_t* rz) {
-  if (b.group == 1 || b.group == 3 || b.group == 4) {
+  if (b.group == 1 || b.group == 3 || b.group == 4 || b.group == 5) {
     if (b.group == 1)
       canon_translation(x[0], z[0], b.n, rx, rz);
     else if (b.group == 3)
       canon_dihedral(x[0], z[0], b.n, rx, rz);
-    else
+    else if (b.group == 4)
       canon_torus(x[0], z[0], b.n, b.lx, rx, rz);
+    else
+      canon_explicit(x[0], z[0], b.n, b.gperm, b.gsize, rx, rz);
     PP_FOR_W(w, 1, b.W, kMaxW) { rx[w] = 0; rz[w] = 0; }
   } else if (b.group == 2) {
     uint32_t nx, ny, nz;

@@ -118,6 +118,8 @@ struct InstBuf {
   uint32_t f32;          // coefficients stored and rotated in FP32
   uint32_t nopart;       // the partitioned merge's kernels are not launched
   int32_t lx;            // torus width (group 4: translations of lx x n/lx)
+  const uint8_t* gperm;  // group 5: gsize rows of n qubit indices
+  uint32_t gsize;
 };
 
 struct InstDyn {

@@ -80,9 +80,11 @@ class PauliSet:
     """A handle (pp_state) with the observable loaded and merged."""
 
     def __init__(self, n: int, group: str, obs_x, obs_z, obs_c, stream: int = 0,
-                 allocator=None, dtype: str = "f64", lx: int = 0):
+                 allocator=None, dtype: str = "f64", lx: int = 0, perms=None):
         self.n, self.group, self.W, self.dtype = n, group, n_words(n), dtype
-        if group == "T2":
+        if group == "G":
+            self.h = L.pp_create_group(n, perms, obs_x, obs_z, obs_c, stream, allocator, dtype)
+        elif group == "T2":
             self.h = L.pp_create_torus(lx, n // lx, obs_x, obs_z, obs_c, stream, allocator,
                                        dtype)
         else:
@@ -94,7 +96,7 @@ class PauliSet:
                      allocator=None, dtype: str = "f64"):
         x, z, c = observable_arrays(prog)
         return cls(prog.n, prog.group if group is None else group, x, z, c, stream, allocator,
-                   dtype, prog.meta.get("lx", 0))
+                   dtype, prog.meta.get("lx", 0), prog.meta.get("perms"))
 
     def apply_layer(self, la: LayerArrays):
         L.pp_apply_layer(self.h, la.gx, la.gz, la.theta, self.W, 1, la.eps, la.wmax)

@@ -261,6 +261,19 @@ def elements_symmetric(n: int) -> List[List[int]]:
     return [list(p) for p in itertools.permutations(range(n))]
 
 
+def permute_mask(v: int, perm) -> int:
+    """Relabels the qubits of a bit mask: bit q of the result is bit
+    perm[q] of v."""
+    return sum(((v >> src) & 1) << q for q, src in enumerate(perm))
+
+
+def symmetrize(gates: List[Gate], perms) -> List[Gate]:
+    """Every gate's image under every listed group element (a multiset
+    closed under the group)."""
+    return [Gate(permute_mask(g.x, p), permute_mask(g.z, p), g.theta)
+            for g in gates for p in perms]
+
+
 def with_explicit_group(prog: Program, perms) -> Program:
     """The same circuit merged under the group with element list perms."""
     meta = dict(prog.meta)

@@ -54,3 +54,22 @@ def test_argument_errors_need_no_gpu():
     assert L.pp_set_tuning(3, 0, 0, 0, 0) == -1
     assert L.pp_set_tuning(0, 16, 0, 0, 0) == -1
     assert L.pp_set_tuning(0, 0, 0, 0, 65) == -1
+
+
+def test_explicit_group_list_is_validated_on_the_host():
+    """pp_create_group rejects lists that are not a group before any device
+    work (no GPU needed)."""
+    import numpy as np
+    from paper_2512_12094_amd import _lib as L
+    one = dict(obs_x=np.array([[1]], dtype=np.uint64), obs_z=np.array([[0]], dtype=np.uint64),
+               obs_coef=np.array([1.0]))
+    bad = {
+        "not a permutation": [[0, 1, 2], [0, 0, 2]],
+        "no identity": [[1, 2, 0], [2, 0, 1]],
+        "not closed": [[0, 1, 2], [1, 2, 0]],
+        "repeated": [[0, 1, 2], [0, 1, 2]],
+    }
+    for why, perms in bad.items():
+        with pytest.raises(L.PPError) as e:
+            L.pp_create_group(3, perms, **one)
+        assert e.value.code == -1, why

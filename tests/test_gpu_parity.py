@@ -374,3 +374,68 @@ def test_torus_rejects_row_only_layer(gpu):
         assert e.value.code == -2
     finally:
         L.pp_destroy(h)
+
+
+# ----------------------------------------------------------------------------
+# Any permutation group given by its element list
+# ----------------------------------------------------------------------------
+def test_explicit_dihedral_list_equals_dihedral_handle(gpu):
+    from paper_2512_12094_amd import driver
+    base = W.config1()
+    prog = W.with_explicit_group(base, W.elements_dihedral(8))
+    print("[case] explicit D_8 list", flush=True)
+    g = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"])
+    d = driver.propagate(base, group="Dn", stream=gpu["handle"], allocator=gpu["alloc"])
+    assert g.terms == d.terms and g.expectation == d.expectation
+    ref = O.run_program(prog)
+    check(g, ref, prog, what="explicit D8")
+
+
+def test_explicit_symmetric_group_equals_permutation_handle(gpu):
+    """S_5 as its 120 elements: the same representatives as Algorithm 3."""
+    from paper_2512_12094_amd import driver
+    base = W.heisenberg_all_to_all(5, 2, 0.2, obs=W.sum_single(5, "Z"), bloch=W.random_bloch(5))
+    prog = W.with_explicit_group(base, W.elements_symmetric(5))
+    print("[case] explicit S_5 list", flush=True)
+    g = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"])
+    p = driver.propagate(base, stream=gpu["handle"], allocator=gpu["alloc"])
+    assert g.terms == p.terms and g.expectation == p.expectation
+
+
+def test_explicit_cyclic_group_on_a_symmetrised_circuit(gpu):
+    """A cyclic group of order 6 on 5 qubits, (0 1 2)(3 4): a circuit made
+    closed under it by taking every gate's images; vs the oracle."""
+    from paper_2512_12094_amd import driver
+    gen = [1, 2, 0, 4, 3]
+    perms, cur = [], list(range(5))
+    for _ in range(6):
+        perms.append(cur)
+        cur = [cur[gen[q]] for q in range(5)]
+    seeds = [W.Gate(*W.two_site("X", 0, 3), 0.3), W.Gate(*W.two_site("Z", 1, 4), 0.2),
+             W.Gate(*W.one_site("Y", 0), 0.25)]
+    subs = [W.SubLayer(W.symmetrize([s], perms)) for s in seeds] * 2
+    obs = [(*W.one_site("Z", q), 1.0) for q in range(5)]
+    prog = W.Program("c6", 5, "G", obs, subs, W.random_bloch(7), dict(perms=perms))
+    print("[case] explicit cyclic group of order 6", flush=True)
+    res = driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"])
+    ref = O.run_program(prog)
+    n = check(res, ref, prog, what="c6")
+    assert n == len(ref.terms)
+    plain = O.run_program(prog, group="none", keep_terms=False)
+    assert abs(res.expectation - plain.expectation) < 1e-12 * max(1, abs(plain.expectation))
+
+
+def test_explicit_group_rejects_open_layer(gpu):
+    from paper_2512_12094_amd import _lib as L
+    perms = W.elements_dihedral(6)
+    x, z = W.one_site("Z", 0)
+    h = L.pp_create_group(6, perms, np.array([[x]], dtype=np.uint64),
+                          np.array([[z]], dtype=np.uint64), np.array([1.0]), gpu["handle"],
+                          gpu["alloc"])
+    gx = np.array([[W.two_site("X", 0, 1)[0]]], dtype=np.uint64)
+    try:
+        with pytest.raises(L.PPError) as e:
+            L.pp_apply_layer(h, gx, np.zeros((1, 1), dtype=np.uint64), np.array([0.1]), 1)
+        assert e.value.code == -2
+    finally:
+        L.pp_destroy(h)

@@ -327,6 +327,20 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
                   int gates_per_step);
 int pp_get_tuning(int out[5]);
 
+/*
+ * Gate fusion (process-wide, default on): when a sub-layer has two
+ * consecutive rotations whose Pauli strings commute and differ, one launch
+ * applies both (each with its own exact merge and truncation, in circuit
+ * order, as Algorithm 2 prescribes per gate).  Results, counters and
+ * expectations are identical with fusion off; only the launch count
+ * changes.  A fused pair needs store room for 2 (live + anticommuting)
+ * terms where a single gate needs live + anticommuting, so near
+ * pp_set_max_terms a fused run can report PP_ECAPACITY one gate earlier.
+ * Applies to pp_apply_layer and pp_program_create calls made afterwards.
+ * enable: 0 or 1, else PP_EINVAL.
+ */
+int pp_set_gate_fusion(int enable);
+
 #ifdef __cplusplus
 }
 #endif

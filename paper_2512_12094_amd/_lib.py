@@ -87,6 +87,7 @@ def lib():
     L.pp_batch_step.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_size_t, _vp,
                                 ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p]
     L.pp_set_tuning.argtypes = [ctypes.c_int] * 5
+    L.pp_set_gate_fusion.argtypes = [ctypes.c_int]
     L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     _lib = L
     return L
@@ -313,6 +314,10 @@ TUNING_KEYS = ["gate_items", "stream_items", "max_blocks", "graph_steps", "gates
 def pp_set_tuning(gate_items=0, stream_items=0, max_blocks=0, graph_steps=0, gates_per_step=0):
     _check(lib().pp_set_tuning(gate_items, stream_items, max_blocks, graph_steps,
                                gates_per_step))
+
+
+def pp_set_gate_fusion(enable):
+    _check(lib().pp_set_gate_fusion(int(enable)))
 
 
 def pp_get_tuning():

@@ -41,6 +41,7 @@ struct Tuning {
   int gates_per_step = 4; // gate launches per batched step
 };
 Tuning g_tune;
+int g_fuse = 1;           // pp_set_gate_fusion: pair commuting gates of a sub-layer
 int g_prof_default = 0;   // pp_profile(NULL, every): new handles start timed
 
 #define HIP_TRY(expr)                                                            \
@@ -86,6 +87,7 @@ struct pp_state {
   size_t tab_cap = 0;
   InstDyn* h_dyn = nullptr;            // pinned
   const pp_program* batch_prog = nullptr;
+  const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
   InstDyn* solo_slots = nullptr;       // pinned status slots of solo_program
   hipEvent_t solo_ev[2] = {nullptr, nullptr};
@@ -316,10 +318,10 @@ int stream_items(bool big) {
   return big ? std::max(g_tune.stream_items, kBigItems) : g_tune.stream_items;
 }
 
-SoloFn solo_of(int kind, bool big) {
+SoloFn solo_of(int kind, bool big, bool two_gate = false) {
   const int gi = gate_items(big), si = stream_items(big);
   switch (kind) {
-    case PP_K_GATE: return PP_PICK(k_gate_solo, gi);
+    case PP_K_GATE: return two_gate ? PP_PICK(k_gate2_solo, gi) : PP_PICK(k_gate_solo, gi);
     case PP_K_MERGE_NARROW: return PP_PICK(k_merge_narrow_solo, si);
     case PP_K_MERGE_WIDE1: return PP_PICK(k_merge_wide1_solo, si);
     case PP_K_MERGE_WIDE2: return PP_PICK(k_merge_wide2_solo, si);
@@ -335,10 +337,14 @@ int items_of(int kind, bool big = false) {
   return kind == PP_K_GATE ? gate_items(big) : stream_items(big);
 }
 
-// Grows (or just compacts) the store so that live + count + slack fits.
+// Grows (or just compacts) the store so that the op that stopped fits:
+// live + count entries for a gate, 2 (live + count) for a two-gate op (its
+// second rotation may append one string per term live after the first).
 int grow(pp_state* s) {
   const InstDyn& d = *s->h_dyn;
-  const uint64_t need = (uint64_t)d.live + d.count;
+  const std::vector<Op>* ops = s->batch_prog ? &s->batch_prog->ops : s->run_ops_list;
+  const bool two = ops && d.pc < ops->size() && (*ops)[d.pc].type == OP_GATE2;
+  const uint64_t need = ((uint64_t)d.live + d.count) * (two ? 2 : 1);
   // same capacity (a compaction) when the live terms leave enough room;
   // the headroom shrinks from 4x to 1.5x for very large sets
   const uint64_t head = need < (1ull << 24) ? 4 * need : need < (1ull << 27) ? 2 * need
@@ -390,6 +396,7 @@ int ensure_ops(pp_state* s, size_t nops, size_t ntab) {
 void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
   switch (op.type) {
     case OP_GATE:
+    case OP_GATE2:
       out->push_back(PP_K_GATE);
       break;
     case OP_MERGE:
@@ -444,7 +451,8 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      hipLaunchKernelGGL(solo_of(kind, big), dim3(grid), dim3(kBlock), 0, s->stream, S);
+      hipLaunchKernelGGL(solo_of(kind, big, ops[k].type == OP_GATE2), dim3(grid), dim3(kBlock), 0,
+                         s->stream, S);
       ++run_len;
     }
   }
@@ -472,6 +480,11 @@ int run_ops(pp_state* s, std::vector<Op> ops, const std::vector<double>& tab,
   s->buf.prog_len = (uint32_t)ops.size();
   s->buf.nopart = 0;
   s->batch_prog = nullptr;
+  s->run_ops_list = &ops;
+  struct Reset {
+    pp_state* s;
+    ~Reset() { s->run_ops_list = nullptr; }
+  } reset{s};
   {
     // ops, tables and the buffer descriptor go through pinned staging
     auto& st = s->ring[s->ring_pos++ % 4];
@@ -499,7 +512,7 @@ int run_ops(pp_state* s, std::vector<Op> ops, const std::vector<double>& tab,
   hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, s->stream, s->d_dyn, 0u);
   if ((rc = launch_ops(s, ops, 0))) return rc;
   bool can_overflow = false;
-  for (const auto& op : ops) can_overflow |= op.type == OP_GATE || op.type == OP_MERGE;
+  for (const auto& op : ops) can_overflow |= op.type == OP_GATE || op.type == OP_GATE2 || op.type == OP_MERGE;
   if (nosync && !can_overflow) return PP_OK;
   for (int guard = 0; guard < 1000; ++guard) {
     if ((rc = read_dyn(s))) return rc;
@@ -542,8 +555,50 @@ void set_next_gates(std::vector<Op>& ops) {
   uint32_t next = kNone32;
   for (size_t k = ops.size(); k-- > 0;) {
     ops[k].next_gate = next;
-    if (ops[k].type == OP_GATE) next = (uint32_t)k;
+    if (ops[k].type == OP_GATE || ops[k].type == OP_GATE2) next = (uint32_t)k;
   }
+}
+
+// Gate ops ops[from..] (consecutive gates of one sub-layer) become two-gate
+// ops where neighbours commute and differ: gate k+1 then rides with gate k.
+// Only the first gate of a sub-layer carries the full re-check, so the
+// second of a pair never does.
+void fuse_gates(std::vector<Op>& ops, size_t from, int W) {
+  if (!g_fuse) return;
+  std::vector<Op> out;
+  size_t k = from;
+  while (k < ops.size()) {
+    const Op& a = ops[k];
+    bool pair = k + 1 < ops.size();
+    if (pair) {
+      const Op& b = ops[k + 1];
+      int odd = 0;
+      bool same = true;
+      for (int w = 0; w < W; ++w) {
+        odd += __builtin_popcountll((a.px[w] & b.pz[w]) ^ (a.pz[w] & b.px[w]));
+        same = same && a.px[w] == b.px[w] && a.pz[w] == b.pz[w];
+      }
+      pair = a.type == OP_GATE && b.type == OP_GATE && !b.full_check && !(odd & 1) && !same &&
+             a.eps == b.eps && a.wmax == b.wmax;
+    }
+    if (!pair) {
+      out.push_back(a);
+      ++k;
+      continue;
+    }
+    Op f = a;
+    f.type = OP_GATE2;
+    for (int w = 0; w < W; ++w) {
+      f.px2[w] = ops[k + 1].px[w];
+      f.pz2[w] = ops[k + 1].pz[w];
+    }
+    f.cs2 = ops[k + 1].cs;
+    f.sn2 = ops[k + 1].sn;
+    out.push_back(f);
+    k += 2;
+  }
+  ops.resize(from);
+  ops.insert(ops.end(), out.begin(), out.end());
 }
 
 bool valid_group_n(int group, int n) {
@@ -682,6 +737,12 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
   if (max_blocks) g_tune.max_blocks = max_blocks;
   if (graph_steps) g_tune.graph_steps = graph_steps;
   if (gates_per_step) g_tune.gates_per_step = gates_per_step;
+  return PP_OK;
+}
+
+int pp_set_gate_fusion(int enable) {
+  if (enable != 0 && enable != 1) return fail(PP_EINVAL, "enable must be 0 or 1");
+  g_fuse = enable;
   return PP_OK;
 }
 
@@ -968,6 +1029,7 @@ int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
     op.full_check = k == 0;
     ops.push_back(op);
   }
+  fuse_gates(ops, 1, W);
   set_next_gates(ops);
   return run_ops(s, ops, {}, {}, false);
 }
@@ -1117,6 +1179,7 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
       for (int w = 0; w <= n_qubits; ++w) tab.push_back(std::pow(1.0 - depol_p[j], (double)w));
       ops.push_back(make_op(OP_DAMP));
     }
+    const size_t first_gate = ops.size();
     for (size_t k = sub_start[j]; k < sub_start[j + 1]; ++k) {
       Op op = make_op(OP_GATE);
       for (int w = 0; w < W; ++w) {
@@ -1130,6 +1193,7 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
       op.full_check = k == sub_start[j];
       ops.push_back(op);
     }
+    fuse_gates(ops, first_gate, W);
     ops.push_back(make_op(OP_MERGE));
     if (eps[j] > 0.0 || max_weight[j] >= 0) {
       Op op = make_op(OP_TRUNC);

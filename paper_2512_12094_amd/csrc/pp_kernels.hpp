@@ -375,28 +375,34 @@ __device__ __forceinline__ uint32_t acc_shards(uint32_t workers) {
 // blockIdx % nsh (called by thread 0 once per block and instance; the
 // returned value is consumed so that the add has completed before the block
 // reports itself done).
-// With one shard the counts go to d.acc itself.
+// With one shard the counts go to d.acc (which = 0) or d.acc2 (which = 1)
+// itself; otherwise to the shards of accumulator `which`.
 __device__ __forceinline__ void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint32_t live,
-                               uint32_t cnt) {
+                                        uint32_t cnt, int which = 0) {
   const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
   if (v) {
-    unsigned long long* a = nsh == 1
-        ? (unsigned long long*)&d.acc
-        : (unsigned long long*)&b.accs[(blockIdx.x % nsh) * kLineU64];
+    unsigned long long* a =
+        nsh == 1 ? (unsigned long long*)(which ? &d.acc2 : &d.acc)
+                 : (unsigned long long*)&b.accs[(which * kAccShards + blockIdx.x % nsh) * kLineU64];
     consume(atomicAdd(a, (unsigned long long)v));
   }
 }
 
-// Last block, one thread: moves the shard totals into d.acc and clears them.
+// Last block, one thread: moves the shard totals into d.acc / d.acc2 and
+// clears them.
 __device__ __forceinline__ void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
   if (nsh == 1) {
     d.acc = ld_agent(&d.acc);
+    d.acc2 = ld_agent(&d.acc2);
     return;
   }
-  uint64_t v = 0;
-  for (uint32_t s = 0; s < nsh; ++s)
+  uint64_t v = 0, v2 = 0;
+  for (uint32_t s = 0; s < nsh; ++s) {
     v += atomicExch((unsigned long long*)&b.accs[s * kLineU64], 0ull);
+    v2 += atomicExch((unsigned long long*)&b.accs[(kAccShards + s) * kLineU64], 0ull);
+  }
   d.acc += v;
+  d.acc2 += v2;
 }
 
 // live = low half, anticommuting count = high half; clears the accumulator.
@@ -753,9 +759,12 @@ __device__ __forceinline__ void load_key(const View& v, uint32_t i, uint64_t* x,
 __device__ __forceinline__ int gate_state(const InstBuf& b, const InstDyn& d) {
   if (d.status & ST_OVERFLOW) return 0;
   const Op* op = cur_op(b, d);
-  if (!op || op->type != OP_GATE) return 0;
+  if (!op || (op->type != OP_GATE && op->type != OP_GATE2)) return 0;
   if (d.count_for != d.pc) return 2;
-  if ((uint64_t)d.M + d.count > b.cap) return 2;
+  // appends: at most the live terms anticommuting with the (first) rotation;
+  // a second rotation appends at most the terms live after the first
+  const uint64_t bound = op->type == OP_GATE ? d.count : (uint64_t)d.live + 2ull * d.count;
+  if ((uint64_t)d.M + bound > b.cap) return 2;
   return 1;
 }
 
@@ -765,19 +774,21 @@ struct Smem {
   uint32_t flag;
   uint64_t wfx[kWaves][3];
   // counts and expectation partial sum of this block's tiles of one
-  // instance, kept by thread 0 and added to the instance once (flush)
-  uint32_t plive, pcnt;
+  // instance, kept by thread 0 and added to the instance once (flush);
+  // plive2 / pcnt2: a two-gate op's counts between its gates
+  uint32_t plive, pcnt, plive2, pcnt2;
   uint64_t pfx[3];
 };
 
 __device__ __forceinline__ void pend_reset(Smem& sm) {
-  sm.plive = sm.pcnt = 0;
+  sm.plive = sm.pcnt = sm.plive2 = sm.pcnt2 = 0;
   sm.pfx[0] = sm.pfx[1] = sm.pfx[2] = 0;
 }
 
 // Thread 0: adds the pending counts / sum to the instance and resets them.
 __device__ __forceinline__ void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh) {
   add_acc(b, d, nsh, sm.plive, sm.pcnt);
+  add_acc(b, d, nsh, sm.plive2, sm.pcnt2, 1);
   if (sm.pfx[0] | sm.pfx[1] | sm.pfx[2]) fx_atomic_add_wait(d.expect_fx, Fx{sm.pfx[0], sm.pfx[1], sm.pfx[2]});
   pend_reset(sm);
 }
@@ -895,6 +906,205 @@ __device__ __forceinline__ void gate_tile(const InstBuf& b, InstDyn& d, uint32_t
   }
 }
 
+// Two commuting rotations, P then P2, in one pass (OP_GATE2).  The strings
+// Q, PQ, P2Q and PP2Q of a group only mix among themselves under the two
+// gates, and since P and P2 commute all four share Q's anticommutation with
+// each.  So the group's lowest-index live member applies the first gate,
+// its exact merge and its truncation, then the second gate, its merge and
+// its truncation, to the whole group in registers: the same arithmetic in
+// the same order as two one-gate passes, with one lookup round and one
+// launch.  Members m = b1 + 2 b2 (b1: times P, b2: times P2) exist for
+// b1 <= a1 and b2 <= a2 (a1, a2: Q anticommutes with P, P2).  New strings
+// are appended after each row of the tile (at most three per thread), which
+// keeps them out of registers across rows.
+template <int IT>
+__device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Smem& sm) {
+  uint32_t* s_tmp = sm.tmp;
+  uint32_t* s_base = &sm.base;
+  const View v = view_of(b, d);
+  const Op& op = b.prog[d.pc];
+  const int W = v.W;
+  const uint32_t M = d.M, gen = d.gen;
+  const double eps = op.eps;
+  const int wmax = op.wmax;
+  const bool full = op.full_check != 0;
+  uint64_t px[2][kMaxW], pz[2][kMaxW], nxm[kMaxW], nzm[kMaxW];
+  PP_FOR_W(w, 0, W, kMaxW) {
+    px[0][w] = op.px[w];
+    pz[0][w] = op.pz[w];
+    px[1][w] = op.px2[w];
+    pz[1][w] = op.pz2[w];
+  }
+  const double cs[2] = {op.cs, op.cs2}, sn[2] = {op.sn, op.sn2};
+  const bool has_next = op.next_gate != kNone32;
+  if (has_next) {
+    const Op& nx = b.prog[op.next_gate];
+    PP_FOR_W(w, 0, W, kMaxW) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
+  }
+  uint32_t my_live = 0, my_cnt = 0, my_live1 = 0, my_anti2 = 0;
+
+  auto heavy = [&](const uint64_t* x, const uint64_t* z) {
+    return wmax >= 0 && weight(x, z, W) > wmax;
+  };
+  auto tally = [&](const uint64_t* x, const uint64_t* z) {
+    ++my_live;
+    if (has_next && anticommutes(x, z, nxm, nzm, W)) ++my_cnt;
+  };
+
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    uint64_t mx[4][kMaxW], mz[4][kMaxW];
+    double c[4];
+    bool ex[4], was[4], pres[4];
+    int64_t idx[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ex[m] = was[m] = pres[m] = false;
+      idx[m] = -1;
+      c[m] = 0.0;
+    }
+    const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
+    // does this thread lead a group of members to update? (untouched live
+    // terms are finished at once)
+    bool lead = false;
+    if (i < M) {
+      const uint8_t alive_i = v.al[i];
+      load_key(v, i, mx[0], mz[0]);
+      c[0] = v.getc(i);
+      if (!alive_i) {
+        v.aln[i] = 0;
+      } else {
+        const bool a1 = anticommutes(mx[0], mz[0], px[0], pz[0], W);
+        const bool a2 = anticommutes(mx[0], mz[0], px[1], pz[1], W);
+        if (!a1 && !a2) {
+          bool keep = true;
+          if (full) keep = fabs(c[0]) >= eps && !heavy(mx[0], mz[0]);
+          v.aln[i] = keep ? 1 : 0;
+          if (keep) {
+            ++my_live1;
+            tally(mx[0], mz[0]);
+          }
+        } else {
+          ex[0] = true;
+          ex[1] = a1;
+          ex[2] = a2;
+          ex[3] = a1 && a2;
+          PP_FOR_W(w, 0, W, kMaxW) {
+            mx[1][w] = mx[0][w] ^ px[0][w];
+            mz[1][w] = mz[0][w] ^ pz[0][w];
+            mx[2][w] = mx[0][w] ^ px[1][w];
+            mz[2][w] = mz[0][w] ^ pz[1][w];
+            mx[3][w] = mx[1][w] ^ px[1][w];
+            mz[3][w] = mz[1][w] ^ pz[1][w];
+          }
+          idx[0] = i;
+          was[0] = true;
+          lead = true;
+#pragma unroll
+          for (int m = 1; m < 4; ++m) {
+            if (ex[m]) idx[m] = gt_lookup(b, gen, M, v, mx[m], mz[m], &c[m]);
+            was[m] = idx[m] >= 0;
+            if (was[m] && (uint32_t)idx[m] < i) lead = false;   // a lower member leads
+          }
+        }
+      }
+    }
+    if (lead) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) pres[m] = was[m];
+      // gate g acts on the pairs (A, A + step): step 1 for P, 2 for P2
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const bool acts = g == 0 ? ex[1] : ex[2];
+        const bool chk = g == 0 && full;   // the sub-layer's first gate re-checks all
+        if (!acts) {
+          if (chk)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+              if (pres[m]) pres[m] = fabs(c[m]) >= eps && !heavy(mx[m], mz[m]);
+        } else {
+          const int step = g == 0 ? 1 : 2;
+#pragma unroll
+          for (int A = 0; A < 4; ++A) {
+            if ((A & step) || !ex[A] || !ex[A + step]) continue;
+            const int B = A + step;
+            const int sig = product_sign(px[g], pz[g], mx[A], mz[A], mx[B], mz[B], W);  // i P A = sig B
+            if (pres[A] && pres[B]) {
+              double nA, nB;
+              rotate_pair(v.f32, cs[g], sn[g], sig, c[A], c[B], &nA, &nB);
+              c[A] = nA;
+              c[B] = nB;
+              pres[A] = fabs(nA) >= eps && !(chk && heavy(mx[A], mz[A]));
+              pres[B] = fabs(nB) >= eps && !(chk && heavy(mx[B], mz[B]));
+            } else if (pres[A] || pres[B]) {
+              // i P B = -sig A: the source's sign is sig from A, -sig from B
+              const int S = pres[A] ? A : B, T = pres[A] ? B : A;
+              double nS, child;
+              rotate_single(v.f32, cs[g], sn[g], pres[A] ? sig : -sig, c[S], &nS, &child);
+              c[S] = nS;
+              pres[S] = fabs(nS) >= eps && !(chk && heavy(mx[S], mz[S]));
+              if (fabs(child) >= eps && !heavy(mx[T], mz[T])) {
+                c[T] = child;
+                pres[T] = true;
+              }
+            }
+          }
+        }
+        if (g == 0)
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (pres[m]) {
+              ++my_live1;
+              if (ex[2]) ++my_anti2;   // every member anticommutes with P2 iff Q does
+            }
+      }
+      // members that were live keep their slot; tally the survivors
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (was[m]) {
+          v.setc((uint32_t)idx[m], c[m]);
+          v.aln[idx[m]] = pres[m] ? 1 : 0;
+        }
+        if (pres[m]) tally(mx[m], mz[m]);
+      }
+    }
+    // append the new members of this row: one atomic per block and row
+    uint32_t mine = 0;
+#pragma unroll
+    for (int m = 1; m < 4; ++m) mine += (lead && pres[m] && !was[m]) ? 1u : 0u;
+    uint32_t total;
+    uint32_t off = block_scan(mine, s_tmp, &total);
+    if (total) {
+      if (threadIdx.x == 0) *s_base = atomicAdd(&d.Mnext, total);
+      __syncthreads();
+      const uint32_t base = *s_base;
+#pragma unroll
+      for (int m = 1; m < 4; ++m) {
+        if (!(lead && pres[m] && !was[m])) continue;
+        const uint32_t pos = base + off++;
+        if (pos >= v.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }   // guard
+        PP_FOR_W(w, 0, W, kMaxW) {
+          v.X[(size_t)w * v.cap + pos] = mx[m][w];
+          v.Z[(size_t)w * v.cap + pos] = mz[m][w];
+        }
+        v.setc(pos, c[m]);
+        v.aln[pos] = 1;
+        gt_insert(b.gtab, b.hg_bits, gen, pos, hash_key(mx[m], mz[m], W, 0));
+      }
+    }
+  }
+  const uint32_t bl = block_sum_u32(my_live, s_tmp);
+  const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
+  const uint32_t bl1 = block_sum_u32(my_live1, s_tmp);
+  const uint32_t ba2 = block_sum_u32(my_anti2, s_tmp);
+  if (threadIdx.x == 0) {
+    sm.plive += bl;
+    sm.pcnt += bc;
+    sm.plive2 += bl1;
+    sm.pcnt2 += ba2;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel kinds.  Each kind provides
 //   state(b, d)   0: instance not served by this kernel now, 1: run,
@@ -943,19 +1153,38 @@ __device__ __forceinline__ void add_counts(InstDyn&, uint32_t live, uint32_t cnt
   }
 }
 
-struct GateKind {
+// Mode 0 runs either gate op (the multi-instance kernel, whose instances may
+// stand at either); the one-instance kernels are built per op type (1: one
+// gate, 2: two gates), so the one-gate kernel keeps its smaller register
+// footprint.
+template <int Mode>
+struct GateKindT {
   __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) { return gate_state(b, d); }
+  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
+    const int st = gate_state(b, d);
+    if (Mode && st && (b.prog[d.pc].type == OP_GATE2) != (Mode == 2)) return 0;
+    return st;
+  }
   __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
   __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
-    gate_tile<IT>(b, d, t, sm);
+    if (Mode == 2 || (Mode == 0 && b.prog[d.pc].type == OP_GATE2))
+      gate2_tile<IT>(b, d, t, sm);
+    else
+      gate_tile<IT>(b, d, t, sm);
   }
   __device__ __forceinline__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
     const Op& op = b.prog[d.pc];
     d.propagated += d.live;
     d.merged += (uint64_t)d.live + d.count;
     d.anti_total += d.count;
+    if (op.type == OP_GATE2) {            // the second rotation's work units
+      const uint64_t live1 = (uint32_t)d.acc2, anti2 = d.acc2 >> 32;
+      d.propagated += live1;
+      d.merged += live1 + anti2;
+      d.anti_total += anti2;
+      d.acc2 = 0;
+    }
     d.appended += ld_agent(&d.Mnext) - d.M;
     d.M = ld_agent(&d.Mnext);
     d.Mnext = d.M;
@@ -1713,7 +1942,23 @@ __device__ __forceinline__ void run_solo(const Solo& S, Smem& sm) {
     run_solo<Kind, IT>(S, sm);                                                       \
   }
 
-PP_KERNEL_PAIR(k_gate, GateKind)
+using GateKind = GateKindT<0>;
+template <int IT>
+__global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ Smem sm;
+  run_multi<GateKind, IT>(C, sm, s_pref);
+}
+template <int IT>
+__global__ __launch_bounds__(kBlock) void k_gate_solo(Solo S) {
+  __shared__ Smem sm;
+  run_solo<GateKindT<1>, IT>(S, sm);
+}
+template <int IT>
+__global__ __launch_bounds__(kBlock) void k_gate2_solo(Solo S) {
+  __shared__ Smem sm;
+  run_solo<GateKindT<2>, IT>(S, sm);
+}
 PP_KERNEL_PAIR(k_merge_narrow, MergeNarrowKind)
 PP_KERNEL_PAIR(k_merge_wide1, MergeWide1Kind)
 PP_KERNEL_PAIR(k_merge_wide2, MergeWide2Kind)

@@ -47,6 +47,8 @@ enum OpType : uint32_t {
   OP_TRUNC = 4,    // drop |c| < eps or weight > wmax
   OP_COUNT = 5,    // only recount (live, anticommuting with next gate)
   OP_EXPECT = 6,   // expectation in a symmetric product state
+  OP_GATE2 = 7,    // two commuting rotations (P, then P2), each followed by
+                   // the exact merge and truncation, in one pass
 };
 
 enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u, ST_FAILED = 8u };
@@ -60,7 +62,7 @@ constexpr int kSyncShards = 16;
 constexpr int kLineU64 = 16;
 constexpr int kLineU32 = 32;
 constexpr size_t kSyncBytes = (1 + kSyncShards) * kLineU32 * sizeof(uint32_t);
-constexpr size_t kAccBytes = kAccShards * kLineU64 * sizeof(uint64_t);
+constexpr size_t kAccBytes = 2 * kAccShards * kLineU64 * sizeof(uint64_t);   // acc, acc2
 
 // Partitioned merge: used for narrow-key merges of at least kPartMin
 // records; tiles of kPartTile records, kParts partitions, LDS tables of
@@ -84,6 +86,9 @@ struct Op {
   uint64_t px[kMaxW];    // GATE: the rotation's Pauli string
   uint64_t pz[kMaxW];
   double cs, sn;         // GATE: cos(theta), sin(theta)
+  uint64_t px2[kMaxW];   // GATE2: the second rotation (commutes with the first)
+  uint64_t pz2[kMaxW];
+  double cs2, sn2;
   double eps;            // GATE/TRUNC: coefficient threshold (0: off)
   const double* table;   // DAMP: (1-p)^w for w = 0..n;
                          // EXPECT: bx^k, by^k, bz^k for k = 0..n (3 blocks)
@@ -100,7 +105,7 @@ struct InstBuf {
   uint32_t* mown;
   uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
   uint32_t* wslot;
-  uint64_t* accs;        // kAccShards count accumulators (live | count << 32)
+  uint64_t* accs;        // 2 x kAccShards count accumulators (acc, then acc2)
   // partitioned merge (narrow keys, large sets): records staged per tile of
   // kPartTile, sorted by partition, with each tile's partition offsets
   uint64_t* pkey;        // [tiles * kPartTile] representative keys
@@ -130,6 +135,7 @@ struct InstDyn {
   uint64_t merge_in;     // records entering symmetry merges / compactions
   uint64_t merge_out;    // representatives leaving them
   uint64_t acc;          // counts folded from the shards by the last block
+  uint64_t acc2;         // GATE2: live | anticommuting << 32 between its gates
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
   uint64_t expect_fx[3];    // exact expectation accumulator
  double expect;

@@ -68,10 +68,13 @@ def parse():
 
 
 def gate_bytes(wc, W=1):
-    """Algorithmic bytes of the gate kernel: every live term's key is read
-    (16W B); every anticommuting term's coefficient is read and written
-    (16 B); every appended child is written (16W + 8 B)."""
-    return 16 * W * wc["propagated"] + 16 * wc["anticommuting"] + (16 * W + 8) * wc["appended"]
+    """Algorithmic bytes of the gate kernel: every live term entering a launch
+    has its key read (16W B; a launch of two fused rotations reads it once);
+    every entering term that a rotation of the launch touches has its
+    coefficient read and written (16 B); every appended string is written
+    (16W + 8 B)."""
+    return (16 * W * wc["gate_key_reads"] + 16 * wc["gate_coef_rw"] +
+            (16 * W + 8) * wc["appended"])
 
 
 def merge_bytes(wc, W=1):
@@ -89,7 +92,7 @@ def run_steps(prog, group, steps, stream, alloc, profile, mode="program"):
     layers = driver.heisenberg_layers(prog)
     dp = driver.device_program(prog) if mode == "program" else None
     totals = dict(propagated=0, merged=0, anticommuting=0, appended=0, merge_in=0,
-                  merge_out=0)
+                  merge_out=0, gate_key_reads=0, gate_coef_rw=0)
     kern = {k: [0, 0.0] for k in L.KERNELS}
     L.pp_profile(None, int(profile))
     e = None
@@ -370,7 +373,9 @@ def main():
         units = tot["propagated"] + tot["merged"]
         value = units / wall
         gate_n, gate_ms = kern["gate"]             # sampled launches and their time
-        gates_run = prog.n_gates * args.steps       # every gate op runs once per step
+        from paper_2512_12094_amd import driver
+        per_step = L.pp_program_info(driver.device_program(prog).h)["gate_launches"]
+        gates_run = per_step * args.steps           # every gate op runs once per step
         gb = gate_bytes(tot)
         avg_s = gate_ms * 1e-3 / max(gate_n, 1)
         bpl = gb / gates_run
@@ -379,7 +384,8 @@ def main():
                     frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 5), traffic=None,
                     avg_launch_us=round(avg_s * 1e6, 3), timed_launches=gate_n,
                     launches=gates_run, bytes_per_launch=round(bpl, 1),
-                    est_kernel_ms_per_step=round(avg_s * 1e3 * prog.n_gates, 3))
+                    rotations_per_launch=round(prog.n_gates / per_step, 3),
+                    est_kernel_ms_per_step=round(avg_s * 1e3 * per_step, 3))
         kernels = {k: dict(launches=n, ms=round(ms, 3)) for k, (n, ms) in kern.items() if n}
         variants = dict(ms_per_step_without_events=round(wall_np / args.steps * 1e3, 3),
                         ms_per_step_one_call_per_op=round(wall_calls / args.steps * 1e3, 3))

@@ -227,10 +227,15 @@ int pp_counters(pp_state* s, uint64_t out[2]);
  * out[2] = sum over gates of the live terms that anticommute with the gate,
  * out[3] = strings appended by gates (children whose partner was absent),
  * out[4] = records entering symmetry merges / compactions,
- * out[5] = representatives leaving them.  These are the unit counts of the
- * algorithmic-bytes model of each kernel.
+ * out[5] = representatives leaving them,
+ * out[6] = sum over gate launches of the live terms entering the launch
+ *          (keys read; a fused launch of two gates reads each key once),
+ * out[7] = sum over gate launches of the entering terms that anticommute
+ *          with one of its rotations (coefficients read and written once).
+ * Without fusion out[6] = out[0] and out[7] = out[2].  These are the unit
+ * counts of the algorithmic-bytes model of each kernel.
  */
-int pp_work_counters(pp_state* s, uint64_t out[6]);
+int pp_work_counters(pp_state* s, uint64_t out[8]);
 
 /* Kernel kinds for per-kernel timing. */
 enum {
@@ -288,6 +293,13 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub,
                       const double* eps, const int* max_weight,
                       const double* depol_p, const double bloch_xyz[3]);
 void pp_program_destroy(pp_program* p);
+
+/*
+ * Shape of a created program: out[0] = device operations, out[1] = gate
+ * launches per run (a fused pair of rotations is one launch), out[2] =
+ * rotations.  NULL arguments: PP_EINVAL.
+ */
+int pp_program_info(const pp_program* p, uint64_t out[3]);
 
 /*
  * Runs programs[i] on states[i] for i < n (n <= 1024), all instances

@@ -82,6 +82,7 @@ def lib():
                                     _f64p, ctypes.POINTER(ctypes.c_int), _f64p, _f64p]
     L.pp_program_destroy.argtypes = [_vp]
     L.pp_program_destroy.restype = None
+    L.pp_program_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64)]
     L.pp_batch_run.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_size_t, _vp,
                                _f64p]
     L.pp_batch_step.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_size_t, _vp,
@@ -239,9 +240,10 @@ KERNELS = ["gate", "merge_narrow", "merge_wide1", "merge_wide2", "merge_collect"
 
 
 def pp_work_counters(h):
-    out = (ctypes.c_uint64 * 6)()
+    out = (ctypes.c_uint64 * 8)()
     _check(lib().pp_work_counters(h, out))
-    keys = ["propagated", "merged", "anticommuting", "appended", "merge_in", "merge_out"]
+    keys = ["propagated", "merged", "anticommuting", "appended", "merge_in", "merge_out",
+            "gate_key_reads", "gate_coef_rw"]
     return {k: int(v) for k, v in zip(keys, out)}
 
 
@@ -281,6 +283,12 @@ def pp_program_create(n, sub_start, gate_x, gate_z, theta, eps, max_weight, depo
         ctypes.byref(h), n, len(ss) - 1, ss.ctypes.data_as(ctypes.POINTER(ctypes.c_size_t)),
         xp, zp, tp, ep, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), pq, bp))
     return h
+
+
+def pp_program_info(h):
+    out = (ctypes.c_uint64 * 3)()
+    _check(lib().pp_program_info(h, out))
+    return dict(ops=int(out[0]), gate_launches=int(out[1]), gates=int(out[2]))
 
 
 def pp_program_destroy(h):

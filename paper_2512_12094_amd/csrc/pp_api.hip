@@ -948,7 +948,7 @@ int pp_create_torus(pp_state** out, int lx, int ly, int dtype, const uint64_t* o
                        hip_stream, alloc);
 }
 
-int pp_work_counters(pp_state* s, uint64_t out[6]) {
+int pp_work_counters(pp_state* s, uint64_t out[8]) {
   if (!s || !out) return fail(PP_EINVAL, "NULL argument");
   int rc = read_dyn(s);
   if (rc) return rc;
@@ -959,6 +959,8 @@ int pp_work_counters(pp_state* s, uint64_t out[6]) {
   out[3] = d.appended;
   out[4] = d.merge_in;
   out[5] = d.merge_out;
+  out[6] = d.key_reads;
+  out[7] = d.coef_rw;
   return PP_OK;
 }
 
@@ -1227,6 +1229,16 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
     return fail(PP_EDEVICE, "program upload failed");
   }
   *out = p.release();
+  return PP_OK;
+}
+
+int pp_program_info(const pp_program* p, uint64_t out[3]) {
+  if (!p || !out) return fail(PP_EINVAL, "NULL argument");
+  uint64_t gates = 0;
+  for (const auto& op : p->ops) gates += op.type == OP_GATE || op.type == OP_GATE2;
+  out[0] = p->ops.size();
+  out[1] = gates;
+  out[2] = p->n_gates;
   return PP_OK;
 }
 

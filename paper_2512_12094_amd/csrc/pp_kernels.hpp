@@ -375,34 +375,38 @@ __device__ __forceinline__ uint32_t acc_shards(uint32_t workers) {
 // blockIdx % nsh (called by thread 0 once per block and instance; the
 // returned value is consumed so that the add has completed before the block
 // reports itself done).
-// With one shard the counts go to d.acc (which = 0) or d.acc2 (which = 1)
+// With one shard the counts go to d.acc, d.acc2 or d.acc3 (which = 0, 1, 2)
 // itself; otherwise to the shards of accumulator `which`.
 __device__ __forceinline__ void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint32_t live,
                                         uint32_t cnt, int which = 0) {
   const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
   if (v) {
+    uint64_t* one = which == 0 ? &d.acc : which == 1 ? &d.acc2 : &d.acc3;
     unsigned long long* a =
-        nsh == 1 ? (unsigned long long*)(which ? &d.acc2 : &d.acc)
+        nsh == 1 ? (unsigned long long*)one
                  : (unsigned long long*)&b.accs[(which * kAccShards + blockIdx.x % nsh) * kLineU64];
     consume(atomicAdd(a, (unsigned long long)v));
   }
 }
 
-// Last block, one thread: moves the shard totals into d.acc / d.acc2 and
-// clears them.
+// Last block, one thread: moves the shard totals into d.acc, d.acc2 and
+// d.acc3 and clears them.
 __device__ __forceinline__ void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
   if (nsh == 1) {
     d.acc = ld_agent(&d.acc);
     d.acc2 = ld_agent(&d.acc2);
+    d.acc3 = ld_agent(&d.acc3);
     return;
   }
-  uint64_t v = 0, v2 = 0;
+  uint64_t v = 0, v2 = 0, v3 = 0;
   for (uint32_t s = 0; s < nsh; ++s) {
     v += atomicExch((unsigned long long*)&b.accs[s * kLineU64], 0ull);
     v2 += atomicExch((unsigned long long*)&b.accs[(kAccShards + s) * kLineU64], 0ull);
+    v3 += atomicExch((unsigned long long*)&b.accs[(2 * kAccShards + s) * kLineU64], 0ull);
   }
   d.acc += v;
   d.acc2 += v2;
+  d.acc3 += v3;
 }
 
 // live = low half, anticommuting count = high half; clears the accumulator.
@@ -775,13 +779,14 @@ struct Smem {
   uint64_t wfx[kWaves][3];
   // counts and expectation partial sum of this block's tiles of one
   // instance, kept by thread 0 and added to the instance once (flush);
-  // plive2 / pcnt2: a two-gate op's counts between its gates
-  uint32_t plive, pcnt, plive2, pcnt2;
+  // plive2 / pcnt2: a two-gate op's counts between its gates; prw: the
+  // entering terms whose coefficient it rewrites
+  uint32_t plive, pcnt, plive2, pcnt2, prw;
   uint64_t pfx[3];
 };
 
 __device__ __forceinline__ void pend_reset(Smem& sm) {
-  sm.plive = sm.pcnt = sm.plive2 = sm.pcnt2 = 0;
+  sm.plive = sm.pcnt = sm.plive2 = sm.pcnt2 = sm.prw = 0;
   sm.pfx[0] = sm.pfx[1] = sm.pfx[2] = 0;
 }
 
@@ -789,6 +794,7 @@ __device__ __forceinline__ void pend_reset(Smem& sm) {
 __device__ __forceinline__ void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh) {
   add_acc(b, d, nsh, sm.plive, sm.pcnt);
   add_acc(b, d, nsh, sm.plive2, sm.pcnt2, 1);
+  add_acc(b, d, nsh, sm.prw, 0, 2);
   if (sm.pfx[0] | sm.pfx[1] | sm.pfx[2]) fx_atomic_add_wait(d.expect_fx, Fx{sm.pfx[0], sm.pfx[1], sm.pfx[2]});
   pend_reset(sm);
 }
@@ -941,7 +947,7 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
     const Op& nx = b.prog[op.next_gate];
     PP_FOR_W(w, 0, W, kMaxW) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
   }
-  uint32_t my_live = 0, my_cnt = 0, my_live1 = 0, my_anti2 = 0;
+  uint32_t my_live = 0, my_cnt = 0, my_live1 = 0, my_anti2 = 0, my_rw = 0;
 
   auto heavy = [&](const uint64_t* x, const uint64_t* z) {
     return wmax >= 0 && weight(x, z, W) > wmax;
@@ -1011,7 +1017,10 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
     }
     if (lead) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) pres[m] = was[m];
+      for (int m = 0; m < 4; ++m) {
+        pres[m] = was[m];
+        if (was[m]) ++my_rw;
+      }
       // gate g acts on the pairs (A, A + step): step 1 for P, 2 for P2
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
@@ -1097,11 +1106,13 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
   const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
   const uint32_t bl1 = block_sum_u32(my_live1, s_tmp);
   const uint32_t ba2 = block_sum_u32(my_anti2, s_tmp);
+  const uint32_t brw = block_sum_u32(my_rw, s_tmp);
   if (threadIdx.x == 0) {
     sm.plive += bl;
     sm.pcnt += bc;
     sm.plive2 += bl1;
     sm.pcnt2 += ba2;
+    sm.prw += brw;
   }
 }
 
@@ -1178,12 +1189,17 @@ struct GateKindT {
     d.propagated += d.live;
     d.merged += (uint64_t)d.live + d.count;
     d.anti_total += d.count;
+    d.key_reads += d.live;
     if (op.type == OP_GATE2) {            // the second rotation's work units
       const uint64_t live1 = (uint32_t)d.acc2, anti2 = d.acc2 >> 32;
       d.propagated += live1;
       d.merged += live1 + anti2;
       d.anti_total += anti2;
+      d.coef_rw += (uint32_t)d.acc3;
       d.acc2 = 0;
+      d.acc3 = 0;
+    } else {
+      d.coef_rw += d.count;
     }
     d.appended += ld_agent(&d.Mnext) - d.M;
     d.M = ld_agent(&d.Mnext);

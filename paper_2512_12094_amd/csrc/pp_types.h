@@ -62,7 +62,7 @@ constexpr int kSyncShards = 16;
 constexpr int kLineU64 = 16;
 constexpr int kLineU32 = 32;
 constexpr size_t kSyncBytes = (1 + kSyncShards) * kLineU32 * sizeof(uint32_t);
-constexpr size_t kAccBytes = 2 * kAccShards * kLineU64 * sizeof(uint64_t);   // acc, acc2
+constexpr size_t kAccBytes = 3 * kAccShards * kLineU64 * sizeof(uint64_t);   // acc, acc2, acc3
 
 // Partitioned merge: used for narrow-key merges of at least kPartMin
 // records; tiles of kPartTile records, kParts partitions, LDS tables of
@@ -105,7 +105,7 @@ struct InstBuf {
   uint32_t* mown;
   uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
   uint32_t* wslot;
-  uint64_t* accs;        // 2 x kAccShards count accumulators (acc, then acc2)
+  uint64_t* accs;        // 3 x kAccShards count accumulators (acc, acc2, acc3)
   // partitioned merge (narrow keys, large sets): records staged per tile of
   // kPartTile, sorted by partition, with each tile's partition offsets
   uint64_t* pkey;        // [tiles * kPartTile] representative keys
@@ -136,6 +136,9 @@ struct InstDyn {
   uint64_t merge_out;    // representatives leaving them
   uint64_t acc;          // counts folded from the shards by the last block
   uint64_t acc2;         // GATE2: live | anticommuting << 32 between its gates
+  uint64_t acc3;         // GATE2: entering terms whose coefficient the launch rewrites
+  uint64_t key_reads;    // sum over gate launches of the live terms entering them
+  uint64_t coef_rw;      // sum over gate launches of the entering terms they rotate
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64
   uint64_t expect_fx[3];    // exact expectation accumulator
  double expect;

@@ -156,3 +156,36 @@ def test_fusion_switch_validates():
     with pytest.raises(L.PPError):
         L.pp_set_gate_fusion(2)
     L.pp_set_gate_fusion(1)
+
+
+def test_gate_unit_counters_and_program_info(gpu):
+    """Without fusion every launch reads the keys of the live terms entering
+    it and rewrites the anticommuting ones: the byte-model counters equal
+    the per-gate counters.  With fusion a launch reads each key once for two
+    rotations: fewer reads, the same work units (propagated, merged)."""
+    from paper_2512_12094_amd import _lib as L, driver
+    prog = prefix(W.config2(), 6)
+    wcs = []
+    for fuse in (0, 1):
+        L.pp_set_gate_fusion(fuse)
+        prog.meta.pop("_dprog", None)
+        dp = driver.device_program(prog)
+        info = L.pp_program_info(dp.h)
+        assert info["gates"] == prog.n_gates
+        assert info["gate_launches"] == prog.n_gates // (1 + fuse)   # ring sub-layers pair up
+        ps = driver.PauliSet.from_program(prog, None, gpu["handle"], gpu["alloc"])
+        L.pp_batch_run([ps.h], [dp.h], gpu["handle"])
+        wcs.append(L.pp_work_counters(ps.h))
+        ps.close()
+        prog.meta.pop("_dprog", None)
+    off, on = wcs
+    assert off["gate_key_reads"] == off["propagated"]
+    assert off["gate_coef_rw"] == off["anticommuting"]
+    for k in ("propagated", "merged", "anticommuting", "merge_in", "merge_out"):
+        assert on[k] == off[k], k
+    # a string that the first rotation creates and the second truncates is
+    # never stored, and one that dies and returns keeps its slot
+    assert on["appended"] <= off["appended"]
+    assert on["gate_key_reads"] < off["gate_key_reads"]
+    assert on["gate_coef_rw"] <= off["gate_coef_rw"]
+    L.pp_set_gate_fusion(1)

@@ -340,18 +340,21 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
 int pp_get_tuning(int out[5]);
 
 /*
- * Gate fusion (process-wide, default on): when a sub-layer has two
- * consecutive rotations whose Pauli strings commute and differ, one launch
- * applies both (each with its own exact merge and truncation, in circuit
- * order, as Algorithm 2 prescribes per gate).  Results, counters and
- * expectations are identical with fusion off; only the launch count
- * changes.  A fused pair needs store room for 2 (live + anticommuting)
+ * Gate fusion (process-wide).  Consecutive rotations of a sub-layer whose
+ * Pauli strings commute pairwise and are independent (no product of a
+ * nonempty subset of them is the identity) are applied by one launch, up to
+ * max_rotations of them (2 or 3; 0 or 1 switches fusion off; default 3).
+ * Each rotation keeps its own exact merge and truncation in circuit order,
+ * as Algorithm 2 prescribes per gate, so results, expectations and the
+ * propagated / merged counters are identical with fusion off; the launch
+ * count, the keys read and the stored-but-dead strings change.  An op of r
+ * fused rotations needs store room for 2^(r-1) (live + anticommuting)
  * terms where a single gate needs live + anticommuting, so near
- * pp_set_max_terms a fused run can report PP_ECAPACITY one gate earlier.
- * Applies to pp_apply_layer and pp_program_create calls made afterwards.
- * enable: 0 or 1, else PP_EINVAL.
+ * pp_set_max_terms a fused run can report PP_ECAPACITY where an unfused
+ * one would not.  Applies to pp_apply_layer and pp_program_create calls
+ * made afterwards.  max_rotations outside 0..3: PP_EINVAL.
  */
-int pp_set_gate_fusion(int enable);
+int pp_set_gate_fusion(int max_rotations);
 
 #ifdef __cplusplus
 }

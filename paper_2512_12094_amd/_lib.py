@@ -324,8 +324,9 @@ def pp_set_tuning(gate_items=0, stream_items=0, max_blocks=0, graph_steps=0, gat
                                gates_per_step))
 
 
-def pp_set_gate_fusion(enable):
-    _check(lib().pp_set_gate_fusion(int(enable)))
+def pp_set_gate_fusion(max_rotations):
+    """Rotations one gate launch may apply (0 or 1: no fusion; 2 or 3)."""
+    _check(lib().pp_set_gate_fusion(int(max_rotations)))
 
 
 def pp_get_tuning():

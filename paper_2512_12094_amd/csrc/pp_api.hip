@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -41,7 +42,7 @@ struct Tuning {
   int gates_per_step = 4; // gate launches per batched step
 };
 Tuning g_tune;
-int g_fuse = 1;           // pp_set_gate_fusion: pair commuting gates of a sub-layer
+int g_fuse = kMaxFuse;    // pp_set_gate_fusion: rotations per gate launch (<= 1: off)
 int g_prof_default = 0;   // pp_profile(NULL, every): new handles start timed
 
 #define HIP_TRY(expr)                                                            \
@@ -81,6 +82,7 @@ struct pp_state {
   InstDyn** d_dynp = nullptr;
   int* d_ninst = nullptr;
   uint32_t* d_sync = nullptr;
+  uint64_t* d_stats = nullptr;        // kStatBytes of statistics lines
   Op* d_ops = nullptr;
   size_t ops_cap = 0;
   double* d_tab = nullptr;
@@ -209,6 +211,28 @@ int read_dyn(pp_state* s) {
   return PP_OK;
 }
 
+// The work counters: the instance's own plus its statistics lines (the
+// later rotations of multi-rotation ops).
+int read_counters(pp_state* s, uint64_t out[8]) {
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  std::vector<uint64_t> st(kStatBytes / sizeof(uint64_t));
+  HIP_TRY(hipMemcpy(st.data(), s->d_stats, kStatBytes, hipMemcpyDeviceToHost));
+  uint64_t sum[kStatKinds] = {0, 0, 0};
+  for (int k = 0; k < kStatKinds; ++k)
+    for (int h = 0; h < kAccShards; ++h) sum[k] += st[(size_t)(k * kAccShards + h) * kLineU64];
+  const InstDyn& d = *s->h_dyn;
+  out[0] = d.propagated + sum[STAT_LIVE];
+  out[1] = d.merged + sum[STAT_LIVE] + sum[STAT_ANTI];
+  out[2] = d.anti_total + sum[STAT_ANTI];
+  out[3] = d.appended;
+  out[4] = d.merge_in;
+  out[5] = d.merge_out;
+  out[6] = d.key_reads;
+  out[7] = d.coef_rw + sum[STAT_RW];
+  return PP_OK;
+}
+
 // Allocates a store of capacity `cap` (both halves and all tables).
 int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* allocs) {
   const int W = s->W;
@@ -318,10 +342,13 @@ int stream_items(bool big) {
   return big ? std::max(g_tune.stream_items, kBigItems) : g_tune.stream_items;
 }
 
-SoloFn solo_of(int kind, bool big, bool two_gate = false) {
+SoloFn solo_of(int kind, bool big, uint32_t nrot = 1) {
   const int gi = gate_items(big), si = stream_items(big);
   switch (kind) {
-    case PP_K_GATE: return two_gate ? PP_PICK(k_gate2_solo, gi) : PP_PICK(k_gate_solo, gi);
+    case PP_K_GATE:
+      return nrot == 3 ? PP_PICK(k_gate3_solo, gi)
+             : nrot == 2 ? PP_PICK(k_gate2_solo, gi)
+                         : PP_PICK(k_gate_solo, gi);
     case PP_K_MERGE_NARROW: return PP_PICK(k_merge_narrow_solo, si);
     case PP_K_MERGE_WIDE1: return PP_PICK(k_merge_wide1_solo, si);
     case PP_K_MERGE_WIDE2: return PP_PICK(k_merge_wide2_solo, si);
@@ -338,13 +365,16 @@ int items_of(int kind, bool big = false) {
 }
 
 // Grows (or just compacts) the store so that the op that stopped fits:
-// live + count entries for a gate, 2 (live + count) for a two-gate op (its
-// second rotation may append one string per term live after the first).
+// live + count entries for a gate, 2^(r-1) (live + count) for an op of r
+// rotations (each later rotation may append one string per term live
+// before it).
 int grow(pp_state* s) {
   const InstDyn& d = *s->h_dyn;
   const std::vector<Op>* ops = s->batch_prog ? &s->batch_prog->ops : s->run_ops_list;
-  const bool two = ops && d.pc < ops->size() && (*ops)[d.pc].type == OP_GATE2;
-  const uint64_t need = ((uint64_t)d.live + d.count) * (two ? 2 : 1);
+  const uint32_t nrot =
+      ops && d.pc < ops->size() && (*ops)[d.pc].type == OP_GATES ? (*ops)[d.pc].nrot : 1u;
+  // after compaction M = live: live + appends <= 2^(nrot-1) (live + count)
+  const uint64_t need = (uint64_t)d.live + gate_append_bound(nrot, d.live, d.count);
   // same capacity (a compaction) when the live terms leave enough room;
   // the headroom shrinks from 4x to 1.5x for very large sets
   const uint64_t head = need < (1ull << 24) ? 4 * need : need < (1ull << 27) ? 2 * need
@@ -396,7 +426,7 @@ int ensure_ops(pp_state* s, size_t nops, size_t ntab) {
 void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
   switch (op.type) {
     case OP_GATE:
-    case OP_GATE2:
+    case OP_GATES:
       out->push_back(PP_K_GATE);
       break;
     case OP_MERGE:
@@ -451,8 +481,8 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      hipLaunchKernelGGL(solo_of(kind, big, ops[k].type == OP_GATE2), dim3(grid), dim3(kBlock), 0,
-                         s->stream, S);
+      const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
+      hipLaunchKernelGGL(solo_of(kind, big, nrot), dim3(grid), dim3(kBlock), 0, s->stream, S);
       ++run_len;
     }
   }
@@ -512,7 +542,7 @@ int run_ops(pp_state* s, std::vector<Op> ops, const std::vector<double>& tab,
   hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, s->stream, s->d_dyn, 0u);
   if ((rc = launch_ops(s, ops, 0))) return rc;
   bool can_overflow = false;
-  for (const auto& op : ops) can_overflow |= op.type == OP_GATE || op.type == OP_GATE2 || op.type == OP_MERGE;
+  for (const auto& op : ops) can_overflow |= op.type == OP_GATE || op.type == OP_GATES || op.type == OP_MERGE;
   if (nosync && !can_overflow) return PP_OK;
   for (int guard = 0; guard < 1000; ++guard) {
     if ((rc = read_dyn(s))) return rc;
@@ -546,6 +576,7 @@ Op make_op(uint32_t type) {
   Op op;
   std::memset(&op, 0, sizeof(op));
   op.type = type;
+  op.nrot = type == OP_GATE ? 1u : 0u;
   op.next_gate = kNone32;
   op.wmax = -1;
   return op;
@@ -555,47 +586,83 @@ void set_next_gates(std::vector<Op>& ops) {
   uint32_t next = kNone32;
   for (size_t k = ops.size(); k-- > 0;) {
     ops[k].next_gate = next;
-    if (ops[k].type == OP_GATE || ops[k].type == OP_GATE2) next = (uint32_t)k;
+    for (int w = 0; w < kMaxW; ++w) {
+      ops[k].nx[w] = next == kNone32 ? 0 : ops[next].px[w];
+      ops[k].nz[w] = next == kNone32 ? 0 : ops[next].pz[w];
+    }
+    if (ops[k].type == OP_GATE || ops[k].type == OP_GATES) next = (uint32_t)k;
   }
 }
 
-// Gate ops ops[from..] (consecutive gates of one sub-layer) become two-gate
-// ops where neighbours commute and differ: gate k+1 then rides with gate k.
-// Only the first gate of a sub-layer carries the full re-check, so the
-// second of a pair never does.
+// Gate ops ops[from..] (consecutive gates of one sub-layer) are grouped into
+// multi-rotation ops of up to g_fuse rotations: a gate joins the group
+// before it when it commutes with every member, has the same truncation
+// parameters, and its string is independent of theirs over GF(2) (no
+// product of a nonempty subset of the group's strings is the identity), so
+// the 2^r strings Q * P^s of a group are distinct.  Only the first gate of
+// a sub-layer carries the full re-check, and it always starts a group.
 void fuse_gates(std::vector<Op>& ops, size_t from, int W) {
-  if (!g_fuse) return;
+  if (g_fuse < 2) return;
   std::vector<Op> out;
   size_t k = from;
   while (k < ops.size()) {
-    const Op& a = ops[k];
-    bool pair = k + 1 < ops.size();
-    if (pair) {
-      const Op& b = ops[k + 1];
-      int odd = 0;
-      bool same = true;
-      for (int w = 0; w < W; ++w) {
-        odd += __builtin_popcountll((a.px[w] & b.pz[w]) ^ (a.pz[w] & b.px[w]));
-        same = same && a.px[w] == b.px[w] && a.pz[w] == b.pz[w];
-      }
-      pair = a.type == OP_GATE && b.type == OP_GATE && !b.full_check && !(odd & 1) && !same &&
-             a.eps == b.eps && a.wmax == b.wmax;
-    }
-    if (!pair) {
-      out.push_back(a);
-      ++k;
+    Op f = ops[k];
+    ++k;
+    if (f.type != OP_GATE) {
+      out.push_back(f);
       continue;
     }
-    Op f = a;
-    f.type = OP_GATE2;
-    for (int w = 0; w < W; ++w) {
-      f.px2[w] = ops[k + 1].px[w];
-      f.pz2[w] = ops[k + 1].pz[w];
+    // span of the group's strings (x words then z words), 2^r entries
+    std::vector<std::array<uint64_t, 2 * kMaxW>> span(1);
+    span[0].fill(0);
+    auto key_of = [&](const Op& o) {
+      std::array<uint64_t, 2 * kMaxW> v;
+      v.fill(0);
+      for (int w = 0; w < W; ++w) {
+        v[w] = o.px[w];
+        v[kMaxW + w] = o.pz[w];
+      }
+      return v;
+    };
+    auto extend = [&](const std::array<uint64_t, 2 * kMaxW>& p) {
+      const size_t n = span.size();
+      for (size_t j = 0; j < n; ++j) {
+        auto q = span[j];
+        for (int w = 0; w < 2 * kMaxW; ++w) q[w] ^= p[w];
+        span.push_back(q);
+      }
+    };
+    extend(key_of(f));
+    std::vector<const Op*> members{&ops[k - 1]};
+    uint32_t nrot = 1;
+    while (nrot < (uint32_t)g_fuse && k < ops.size()) {
+      const Op& b = ops[k];
+      bool ok = b.type == OP_GATE && !b.full_check && b.eps == f.eps && b.wmax == f.wmax;
+      for (const Op* m : members) {
+        int odd = 0;
+        for (int w = 0; w < W; ++w)
+          odd += __builtin_popcountll((m->px[w] & b.pz[w]) ^ (m->pz[w] & b.px[w]));
+        ok = ok && !(odd & 1);
+      }
+      const auto kb = key_of(b);
+      for (const auto& q : span) ok = ok && q != kb;
+      if (!ok) break;
+      extend(kb);
+      members.push_back(&b);
+      for (int w = 0; w < kMaxW; ++w) {
+        f.qx[nrot - 1][w] = b.px[w];
+        f.qz[nrot - 1][w] = b.pz[w];
+      }
+      f.qcs[nrot - 1] = b.cs;
+      f.qsn[nrot - 1] = b.sn;
+      ++nrot;
+      ++k;
     }
-    f.cs2 = ops[k + 1].cs;
-    f.sn2 = ops[k + 1].sn;
+    if (nrot > 1) {
+      f.type = OP_GATES;
+      f.nrot = nrot;
+    }
     out.push_back(f);
-    k += 2;
   }
   ops.resize(from);
   ops.insert(ops.end(), out.begin(), out.end());
@@ -740,9 +807,10 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
   return PP_OK;
 }
 
-int pp_set_gate_fusion(int enable) {
-  if (enable != 0 && enable != 1) return fail(PP_EINVAL, "enable must be 0 or 1");
-  g_fuse = enable;
+int pp_set_gate_fusion(int max_rotations) {
+  if (max_rotations < 0 || max_rotations > kMaxFuse)
+    return fail(PP_EINVAL, "max_rotations must be 0.." + std::to_string(kMaxFuse));
+  g_fuse = max_rotations;
   return PP_OK;
 }
 
@@ -768,6 +836,7 @@ void pp_destroy(pp_state* s) {
   dev_free(s, s->d_dynp);
   dev_free(s, s->d_ninst);
   dev_free(s, s->d_sync);
+  dev_free(s, s->d_stats);
   dev_free(s, s->d_gperm);
   if (s->h_dyn) (void)hipHostFree(s->h_dyn);
   for (auto& st : s->ring) {
@@ -827,7 +896,10 @@ int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
   s->d_dynp = (InstDyn**)dev_alloc(s.get(), sizeof(void*));
   s->d_ninst = (int*)dev_alloc(s.get(), sizeof(int));
   s->d_sync = (uint32_t*)dev_alloc(s.get(), kSyncBytes);
-  if (!s->d_buf || !s->d_dyn || !s->d_bufp || !s->d_dynp || !s->d_ninst || !s->d_sync) {
+  s->d_stats = (uint64_t*)dev_alloc(s.get(), kStatBytes);
+  s->buf.stats = s->d_stats;
+  if (!s->d_buf || !s->d_dyn || !s->d_bufp || !s->d_dynp || !s->d_ninst || !s->d_sync ||
+      !s->d_stats) {
     pp_destroy(s.release());
     return fail(PP_ENOMEM, "handle allocation failed");
   }
@@ -850,7 +922,8 @@ int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
   if (hipMemcpyAsync(s->d_bufp, &s->d_buf, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
       hipMemcpyAsync(s->d_dynp, &s->d_dyn, sizeof(void*), hipMemcpyHostToDevice, s->stream) ||
       hipMemcpyAsync(s->d_ninst, &one, sizeof(int), hipMemcpyHostToDevice, s->stream) ||
-      hipMemsetAsync(s->d_sync, 0, kSyncBytes, s->stream))
+      hipMemsetAsync(s->d_sync, 0, kSyncBytes, s->stream) ||
+      hipMemsetAsync(s->d_stats, 0, kStatBytes, s->stream))
     return bail(fail(PP_EDEVICE, "handle initialisation failed"));
 
   const uint32_t cap = (uint32_t)std::max<uint64_t>(4096, 2 * n_obs);
@@ -950,18 +1023,7 @@ int pp_create_torus(pp_state** out, int lx, int ly, int dtype, const uint64_t* o
 
 int pp_work_counters(pp_state* s, uint64_t out[8]) {
   if (!s || !out) return fail(PP_EINVAL, "NULL argument");
-  int rc = read_dyn(s);
-  if (rc) return rc;
-  const InstDyn& d = *s->h_dyn;
-  out[0] = d.propagated;
-  out[1] = d.merged;
-  out[2] = d.anti_total;
-  out[3] = d.appended;
-  out[4] = d.merge_in;
-  out[5] = d.merge_out;
-  out[6] = d.key_reads;
-  out[7] = d.coef_rw;
-  return PP_OK;
+  return read_counters(s, out);
 }
 
 int pp_profile(pp_state* s, int every) {
@@ -1090,10 +1152,11 @@ int pp_num_terms(pp_state* s, size_t* out) {
 
 int pp_counters(pp_state* s, uint64_t out[2]) {
   if (!s || !out) return fail(PP_EINVAL, "NULL argument");
-  int rc = read_dyn(s);
+  uint64_t all[8];
+  int rc = read_counters(s, all);
   if (rc) return rc;
-  out[0] = s->h_dyn->propagated;
-  out[1] = s->h_dyn->merged;
+  out[0] = all[0];
+  out[1] = all[1];
   return PP_OK;
 }
 
@@ -1235,7 +1298,7 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
 int pp_program_info(const pp_program* p, uint64_t out[3]) {
   if (!p || !out) return fail(PP_EINVAL, "NULL argument");
   uint64_t gates = 0;
-  for (const auto& op : p->ops) gates += op.type == OP_GATE || op.type == OP_GATE2;
+  for (const auto& op : p->ops) gates += op.type == OP_GATE || op.type == OP_GATES;
   out[0] = p->ops.size();
   out[1] = gates;
   out[2] = p->n_gates;

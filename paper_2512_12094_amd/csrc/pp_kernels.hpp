@@ -371,42 +371,24 @@ __device__ __forceinline__ uint32_t acc_shards(uint32_t workers) {
   return workers > kTreeMin ? (uint32_t)kAccShards : 1u;
 }
 
-// Adds a block's counts (live | anticommuting << 32) to accumulator shard
-// blockIdx % nsh (called by thread 0 once per block and instance; the
-// returned value is consumed so that the add has completed before the block
-// reports itself done).
-// With one shard the counts go to d.acc, d.acc2 or d.acc3 (which = 0, 1, 2)
-// itself; otherwise to the shards of accumulator `which`.
-__device__ __forceinline__ void add_acc(const InstBuf& b, InstDyn& d, uint32_t nsh, uint32_t live,
-                                        uint32_t cnt, int which = 0) {
-  const uint64_t v = (uint64_t)live | ((uint64_t)cnt << 32);
-  if (v) {
-    uint64_t* one = which == 0 ? &d.acc : which == 1 ? &d.acc2 : &d.acc3;
-    unsigned long long* a =
-        nsh == 1 ? (unsigned long long*)one
-                 : (unsigned long long*)&b.accs[(which * kAccShards + blockIdx.x % nsh) * kLineU64];
-    consume(atomicAdd(a, (unsigned long long)v));
-  }
-}
-
-// Last block, one thread: moves the shard totals into d.acc, d.acc2 and
-// d.acc3 and clears them.
+// Last block, one thread: moves the shard totals into d.acc and clears the
+// shards (with one shard the blocks added to d.acc itself).
 __device__ __forceinline__ void fold_acc(const InstBuf& b, InstDyn& d, uint32_t nsh) {
   if (nsh == 1) {
     d.acc = ld_agent(&d.acc);
-    d.acc2 = ld_agent(&d.acc2);
-    d.acc3 = ld_agent(&d.acc3);
     return;
   }
-  uint64_t v = 0, v2 = 0, v3 = 0;
-  for (uint32_t s = 0; s < nsh; ++s) {
+  uint64_t v = 0;
+  for (uint32_t s = 0; s < nsh; ++s)
     v += atomicExch((unsigned long long*)&b.accs[s * kLineU64], 0ull);
-    v2 += atomicExch((unsigned long long*)&b.accs[(kAccShards + s) * kLineU64], 0ull);
-    v3 += atomicExch((unsigned long long*)&b.accs[(2 * kAccShards + s) * kLineU64], 0ull);
-  }
   d.acc += v;
-  d.acc2 += v2;
-  d.acc3 += v3;
+}
+
+// Thread 0: adds the statistic v of kind k to this block's shard line; the
+// result is not waited for (no kernel reads the statistics back).
+__device__ __forceinline__ void add_stat(const InstBuf& b, int k, uint64_t v) {
+  if (v) atomicAdd((unsigned long long*)&b.stats[(k * kAccShards + blockIdx.x % kAccShards) * kLineU64],
+                   (unsigned long long)v);
 }
 
 // live = low half, anticommuting count = high half; clears the accumulator.
@@ -457,6 +439,52 @@ __device__ __forceinline__ bool last_block(uint32_t* sync, uint32_t* s_flag, uin
   const bool r = *s_flag != 0;
   if (r && fence) __threadfence();
   return r;
+}
+
+// last_block for thread 0 alone (the block's other threads have left), with
+// no fence: for kinds whose last block reads only the accumulators.
+__device__ __forceinline__ bool last_block_one(uint32_t* sync, uint32_t workers) {
+  if (workers <= 1) return true;
+  if (workers <= kTreeMin) {
+    const uint32_t t = atomicAdd(sync, 1u);
+    if (t != workers - 1) return false;
+    atomicExch(sync, 0u);
+    return true;
+  }
+  const uint32_t sh = blockIdx.x % kSyncShards;
+  const uint32_t members = (workers - sh + kSyncShards - 1) / kSyncShards;
+  const uint32_t roots = workers < (uint32_t)kSyncShards ? workers : kSyncShards;
+  uint32_t* cs = sync + (1 + sh) * kLineU32;
+  if (atomicAdd(cs, 1u) != members - 1) return false;
+  atomicExch(cs, 0u);
+  if (atomicAdd(sync, 1u) != roots - 1) return false;
+  atomicExch(sync, 0u);
+  return true;
+}
+
+// Thread 0 of each working block of a launch of at most kTreeMin blocks over
+// a store below 2^26 entries: counts the block done and adds its live and
+// anticommuting counts (each below 2^26) in the same 64-bit atomic, so the
+// last block learns the launch's totals from the atomic's result, with no
+// separate accumulator round trip.  Returns true in the last block, with
+// the totals as live | count << 32 in *acc.
+constexpr uint32_t kPackedCap = 1u << 26;
+__device__ __forceinline__ bool last_block_packed(uint32_t* sync, uint32_t workers, uint32_t live,
+                                                  uint32_t cnt, bool fence, uint64_t* acc) {
+  const uint64_t mask = (1ull << 26) - 1;
+  const uint64_t v = (1ull << 52) | ((uint64_t)cnt << 26) | live;
+  uint64_t tot = v;
+  if (workers > 1) {
+    if (fence) __threadfence();
+    unsigned long long* w = (unsigned long long*)(sync + kPackedLine * kLineU32);
+    const uint64_t old = atomicAdd(w, (unsigned long long)v);
+    if ((old >> 52) != workers - 1) return false;
+    atomicExch(w, 0ull);                 // every other block has added its share
+    tot = old + v;
+    if (fence) __threadfence();
+  }
+  *acc = (tot & mask) | (((tot >> 26) & mask) << 32);
+  return true;
 }
 
 // Blocks beyond the tile count leave at once; block 0 always stays so that
@@ -518,15 +546,16 @@ __device__ __forceinline__ const Op* cur_op(const InstBuf& b, const InstDyn& d) 
 // (a slot of the current generation always holds an index below cap), so a
 // probe costs one dependent round trip after the slot itself; *c receives
 // the found entry's coefficient.
+// Probing from slot s, `done` probes already made.
 template <class V>
-__device__ __forceinline__ int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mstart,
-                                             const V& view, const uint64_t* rx,
-                                             const uint64_t* rz, double* c) {
+__device__ __forceinline__ int64_t gt_lookup_from(const InstBuf& b, uint32_t gen, uint32_t Mstart,
+                                                  const V& view, const uint64_t* rx,
+                                                  const uint64_t* rz, uint64_t s, uint64_t done,
+                                                  double* c) {
   const int W = b.W;
   const uint32_t cap = b.cap;
   const uint64_t mask = (1ull << b.hg_bits) - 1;
-  uint64_t s = hash_key(rx, rz, W, 0) >> (64 - b.hg_bits);
-  for (uint64_t probe = 0; probe <= mask; ++probe) {
+  for (uint64_t probe = done; probe <= mask; ++probe) {
     const uint64_t v = b.gtab[s];
     if ((uint32_t)(v >> 32) != gen) return -1;
     const uint32_t idx = (uint32_t)v;
@@ -548,6 +577,64 @@ __device__ __forceinline__ int64_t gt_lookup(const InstBuf& b, uint32_t gen, uin
     s = (s + 1) & mask;
   }
   return -1;
+}
+
+template <class V>
+__device__ __forceinline__ int64_t gt_lookup(const InstBuf& b, uint32_t gen, uint32_t Mstart,
+                                             const V& view, const uint64_t* rx,
+                                             const uint64_t* rz, double* c) {
+  return gt_lookup_from(b, gen, Mstart, view, rx, rz, hash_key(rx, rz, b.W, 0) >> (64 - b.hg_bits),
+                        0, c);
+}
+
+// gt_lookup for N keys at once: the first probe of every key is issued
+// together (slot loads, then the candidates' liveness, keys and
+// coefficients), so N lookups cost the round trips of one; a key whose first
+// slot holds another live key continues with gt_lookup from the next slot.
+// want[m] false skips key m (idx[m] = -1).
+template <int N, class V>
+__device__ __forceinline__ void gt_lookup_n(const InstBuf& b, uint32_t gen, uint32_t Mstart,
+                                            const V& view, const bool* want,
+                                            const uint64_t (*rx)[kMaxW],
+                                            const uint64_t (*rz)[kMaxW], int64_t* idx, double* c) {
+  const int W = b.W;
+  const uint32_t cap = b.cap;
+  const uint64_t mask = (1ull << b.hg_bits) - 1;
+  uint64_t s[N], v[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    s[m] = hash_key(rx[m], rz[m], W, 0) >> (64 - b.hg_bits);
+    v[m] = want[m] ? b.gtab[s[m]] : 0ull;
+  }
+  uint8_t a[N];
+  uint64_t kx[N][kMaxW], kz[N][kMaxW];
+  double cj[N];
+  bool hit[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    hit[m] = want[m] && (uint32_t)(v[m] >> 32) == gen;
+    const uint32_t k = hit[m] ? (uint32_t)v[m] : 0u;   // slot of this generation: k < cap
+    a[m] = view.al[k];
+    PP_FOR_W(w, 0, W, kMaxW) {
+      kx[m][w] = view.X[(size_t)w * cap + k];
+      kz[m][w] = view.Z[(size_t)w * cap + k];
+    }
+    cj[m] = view.getc(k);
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    idx[m] = -1;
+    if (!hit[m]) continue;                   // skipped, or an empty slot: absent
+    const uint32_t k = (uint32_t)v[m];
+    bool eq = k < Mstart && a[m];
+    PP_FOR_W(w, 0, W, kMaxW) eq = eq && kx[m][w] == rx[m][w] && kz[m][w] == rz[m][w];
+    if (eq) {
+      idx[m] = k;
+      c[m] = cj[m];
+    } else {
+      idx[m] = gt_lookup_from(b, gen, Mstart, view, rx[m], rz[m], (s[m] + 1) & mask, 1, &c[m]);
+    }
+  }
 }
 
 // Inserts index `idx` (insert-only: the caller guarantees that no live entry
@@ -759,17 +846,72 @@ __device__ __forceinline__ void load_key(const View& v, uint32_t i, uint64_t* x,
 // ---------------------------------------------------------------------------
 // GATE: one Pauli rotation (Prop. 1) + exact merge + truncation
 // ---------------------------------------------------------------------------
-// 0 = not served, 1 = run, 2 = would overflow (appends <= count)
+// What a gate launch needs of its op, read once into registers.
+struct GateArgs {
+  uint64_t px[kMaxFuse][kMaxW], pz[kMaxFuse][kMaxW];   // rotations 1..nrot
+  uint64_t nx[kMaxW], nz[kMaxW];                       // the next gate's rotation
+  double cs[kMaxFuse], sn[kMaxFuse], eps;
+  int wmax;
+  uint32_t type, nrot;
+  bool full, has_next;
+};
+
+__device__ __forceinline__ GateArgs gate_args(const Op& op) {
+  GateArgs g;
+#pragma unroll
+  for (int w = 0; w < kMaxW; ++w) {
+    g.px[0][w] = op.px[w];
+    g.pz[0][w] = op.pz[w];
+#pragma unroll
+    for (int r = 1; r < kMaxFuse; ++r) {
+      g.px[r][w] = op.qx[r - 1][w];
+      g.pz[r][w] = op.qz[r - 1][w];
+    }
+    g.nx[w] = op.nx[w];
+    g.nz[w] = op.nz[w];
+  }
+  g.cs[0] = op.cs;
+  g.sn[0] = op.sn;
+#pragma unroll
+  for (int r = 1; r < kMaxFuse; ++r) {
+    g.cs[r] = op.qcs[r - 1];
+    g.sn[r] = op.qsn[r - 1];
+  }
+  g.eps = op.eps;
+  g.wmax = op.wmax;
+  g.type = op.type;
+  g.nrot = op.type == OP_GATES ? op.nrot : 1u;
+  g.full = op.full_check != 0;
+  g.has_next = op.next_gate != kNone32;
+  return g;
+}
+
+// Appends of a launch of r rotations over `live` terms, `count` of them
+// anticommuting with the first: the first appends at most `count`, each
+// later one at most the terms live before it, and the live terms at most
+// double per rotation: count + (2^(r-1) - 1)(live + count).
+__device__ __host__ __forceinline__ uint64_t gate_append_bound(uint32_t nrot, uint64_t live,
+                                                               uint64_t count) {
+  return count + (((uint64_t)1 << (nrot - 1)) - 1) * (live + count);
+}
+
+// 0 = not served, 1 = run, 2 = would overflow, from the op type and the
+// instance's status, count tag, entries, live and anticommuting counts
+__device__ __forceinline__ int gate_state_of(uint32_t type, uint32_t nrot, uint32_t pc,
+                                             uint32_t status, uint32_t count_for, uint32_t M,
+                                             uint32_t live, uint32_t count, uint32_t cap) {
+  const uint64_t bound = gate_append_bound(type == OP_GATES ? nrot : 1u, live, count);
+  const bool gate = type == OP_GATE || type == OP_GATES;
+  const int fits = (count_for != pc || (uint64_t)M + bound > cap) ? 2 : 1;
+  return ((status & ST_OVERFLOW) || !gate) ? 0 : fits;
+}
+
+// 0 = not served, 1 = run, 2 = would overflow (multi-instance form)
 __device__ __forceinline__ int gate_state(const InstBuf& b, const InstDyn& d) {
-  if (d.status & ST_OVERFLOW) return 0;
   const Op* op = cur_op(b, d);
-  if (!op || (op->type != OP_GATE && op->type != OP_GATE2)) return 0;
-  if (d.count_for != d.pc) return 2;
-  // appends: at most the live terms anticommuting with the (first) rotation;
-  // a second rotation appends at most the terms live after the first
-  const uint64_t bound = op->type == OP_GATE ? d.count : (uint64_t)d.live + 2ull * d.count;
-  if ((uint64_t)d.M + bound > b.cap) return 2;
-  return 1;
+  if (!op) return 0;
+  return gate_state_of(op->type, op->nrot, d.pc, d.status, d.count_for, d.M, d.live, d.count,
+                       b.cap);
 }
 
 struct Smem {
@@ -779,44 +921,50 @@ struct Smem {
   uint64_t wfx[kWaves][3];
   // counts and expectation partial sum of this block's tiles of one
   // instance, kept by thread 0 and added to the instance once (flush);
-  // plive2 / pcnt2: a two-gate op's counts between its gates; prw: the
-  // entering terms whose coefficient it rewrites
-  uint32_t plive, pcnt, plive2, pcnt2, prw;
+  // pstat: a multi-rotation op's statistics (STAT_*)
+  uint32_t plive, pcnt, pstat[kStatKinds];
   uint64_t pfx[3];
 };
 
 __device__ __forceinline__ void pend_reset(Smem& sm) {
-  sm.plive = sm.pcnt = sm.plive2 = sm.pcnt2 = sm.prw = 0;
+  sm.plive = sm.pcnt = 0;
+#pragma unroll
+  for (int k = 0; k < kStatKinds; ++k) sm.pstat[k] = 0;
   sm.pfx[0] = sm.pfx[1] = sm.pfx[2] = 0;
 }
 
-// Thread 0: adds the pending counts / sum to the instance and resets them.
-__device__ __forceinline__ void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh) {
-  add_acc(b, d, nsh, sm.plive, sm.pcnt);
-  add_acc(b, d, nsh, sm.plive2, sm.pcnt2, 1);
-  add_acc(b, d, nsh, sm.prw, 0, 2);
+// Thread 0: adds the pending statistics and expectation sum to the instance
+// and, unless the counts travel with the done count (`packed`), the pending
+// live / anticommuting counts; resets them.
+__device__ __forceinline__ void flush(const InstBuf& b, InstDyn& d, Smem& sm, uint32_t nsh,
+                                      bool packed = false) {
+#pragma unroll
+  for (int k = 0; k < kStatKinds; ++k) add_stat(b, k, sm.pstat[k]);
+  const uint64_t v = (uint64_t)sm.plive | ((uint64_t)sm.pcnt << 32);
+  if (!packed && v) {
+    unsigned long long* a = nsh == 1 ? (unsigned long long*)&d.acc
+                                     : (unsigned long long*)&b.accs[(blockIdx.x % nsh) * kLineU64];
+    consume(atomicAdd(a, (unsigned long long)v));
+  }
   if (sm.pfx[0] | sm.pfx[1] | sm.pfx[2]) fx_atomic_add_wait(d.expect_fx, Fx{sm.pfx[0], sm.pfx[1], sm.pfx[2]});
   pend_reset(sm);
 }
 
 template <int IT>
-__device__ __forceinline__ void gate_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Smem& sm) {
+__device__ __forceinline__ void gate_tile(const InstBuf& b, InstDyn& d, const GateArgs& g,
+                                          const View& v, uint32_t M, uint32_t gen, uint32_t tile,
+                                          Smem& sm) {
   uint32_t* s_tmp = sm.tmp;
   uint32_t* s_base = &sm.base;
-  const View v = view_of(b, d);
-  const Op& op = b.prog[d.pc];
   const int W = v.W;
-  const uint32_t M = d.M, gen = d.gen;
-  const double cs = op.cs, sn = op.sn, eps = op.eps;
-  const int wmax = op.wmax;
-  const bool full = op.full_check != 0;
-  uint64_t px[kMaxW], pz[kMaxW], nxm[kMaxW], nzm[kMaxW];
-  PP_FOR_W(w, 0, W, kMaxW) { px[w] = op.px[w]; pz[w] = op.pz[w]; }
-  const bool has_next = op.next_gate != kNone32;
-  if (has_next) {
-    const Op& nx = b.prog[op.next_gate];
-    PP_FOR_W(w, 0, W, kMaxW) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
-  }
+  const double cs = g.cs[0], sn = g.sn[0], eps = g.eps;
+  const int wmax = g.wmax;
+  const bool full = g.full;
+  const uint64_t* px = g.px[0];
+  const uint64_t* pz = g.pz[0];
+  const uint64_t* nxm = g.nx;
+  const uint64_t* nzm = g.nz;
+  const bool has_next = g.has_next;
   uint32_t my_live = 0, my_cnt = 0;
   uint64_t chx[IT][kMaxW], chz[IT][kMaxW];
   double chc[IT];
@@ -912,42 +1060,36 @@ __device__ __forceinline__ void gate_tile(const InstBuf& b, InstDyn& d, uint32_t
   }
 }
 
-// Two commuting rotations, P then P2, in one pass (OP_GATE2).  The strings
-// Q, PQ, P2Q and PP2Q of a group only mix among themselves under the two
-// gates, and since P and P2 commute all four share Q's anticommutation with
-// each.  So the group's lowest-index live member applies the first gate,
-// its exact merge and its truncation, then the second gate, its merge and
-// its truncation, to the whole group in registers: the same arithmetic in
-// the same order as two one-gate passes, with one lookup round and one
-// launch.  Members m = b1 + 2 b2 (b1: times P, b2: times P2) exist for
-// b1 <= a1 and b2 <= a2 (a1, a2: Q anticommutes with P, P2).  New strings
-// are appended after each row of the tile (at most three per thread), which
-// keeps them out of registers across rows.
-template <int IT>
-__device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_t tile, Smem& sm) {
+// K mutually commuting rotations P_1..P_K of a sub-layer in one pass
+// (OP_GATES).  For a live Q, the strings Q * P^s (s a subset of the rotations
+// that anticommute with Q; P^s their product) only mix among themselves
+// under the K gates, and since the P_g commute every member shares Q's
+// anticommutation with each P_g.  So the group's lowest-index live member
+// applies gate 1, its exact merge and its truncation, then gate 2 and so on,
+// to the whole group in registers: the same arithmetic in the same order as
+// K one-gate passes, with one lookup round and one launch.  Member m (a bit
+// mask over the rotations) exists when its bits are all anticommuting ones;
+// gate g pairs members m and m | 2^g.  The host fuses only rotations whose
+// strings are independent (no product of a nonempty subset is the
+// identity), so the 2^K members are distinct.  New strings are appended
+// after each row of the tile.
+template <int IT, int K>
+__device__ __forceinline__ void gates_tile(const InstBuf& b, InstDyn& d, const GateArgs& ga,
+                                           const View& v, uint32_t M, uint32_t gen, uint32_t tile,
+                                           Smem& sm) {
+  constexpr int NM = 1 << K;
   uint32_t* s_tmp = sm.tmp;
   uint32_t* s_base = &sm.base;
-  const View v = view_of(b, d);
-  const Op& op = b.prog[d.pc];
   const int W = v.W;
-  const uint32_t M = d.M, gen = d.gen;
-  const double eps = op.eps;
-  const int wmax = op.wmax;
-  const bool full = op.full_check != 0;
-  uint64_t px[2][kMaxW], pz[2][kMaxW], nxm[kMaxW], nzm[kMaxW];
-  PP_FOR_W(w, 0, W, kMaxW) {
-    px[0][w] = op.px[w];
-    pz[0][w] = op.pz[w];
-    px[1][w] = op.px2[w];
-    pz[1][w] = op.pz2[w];
-  }
-  const double cs[2] = {op.cs, op.cs2}, sn[2] = {op.sn, op.sn2};
-  const bool has_next = op.next_gate != kNone32;
-  if (has_next) {
-    const Op& nx = b.prog[op.next_gate];
-    PP_FOR_W(w, 0, W, kMaxW) { nxm[w] = nx.px[w]; nzm[w] = nx.pz[w]; }
-  }
-  uint32_t my_live = 0, my_cnt = 0, my_live1 = 0, my_anti2 = 0, my_rw = 0;
+  const double eps = ga.eps;
+  const int wmax = ga.wmax;
+  const bool full = ga.full;
+  const uint64_t* nxm = ga.nx;
+  const uint64_t* nzm = ga.nz;
+  const bool has_next = ga.has_next;
+  // my_lv / my_an: live terms after each rotation but the last, and those of
+  // them anticommuting with the next rotation (summed over the rotations)
+  uint32_t my_live = 0, my_cnt = 0, my_rw = 0, my_lv = 0, my_an = 0;
 
   auto heavy = [&](const uint64_t* x, const uint64_t* z) {
     return wmax >= 0 && weight(x, z, W) > wmax;
@@ -959,19 +1101,20 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
 
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    uint64_t mx[4][kMaxW], mz[4][kMaxW];
-    double c[4];
-    bool ex[4], was[4], pres[4];
-    int64_t idx[4];
+    uint64_t mx[NM][kMaxW], mz[NM][kMaxW];
+    double c[NM];
+    bool ex[NM], was[NM], pres[NM];
+    int64_t idx[NM];
+    bool an[K];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < NM; ++m) {
       ex[m] = was[m] = pres[m] = false;
       idx[m] = -1;
       c[m] = 0.0;
     }
+#pragma unroll
+    for (int g = 0; g < K; ++g) an[g] = false;
     const uint32_t i = tile * (kBlock * IT) + k * kBlock + threadIdx.x;
-    // does this thread lead a group of members to update? (untouched live
-    // terms are finished at once)
     bool lead = false;
     if (i < M) {
       const uint8_t alive_i = v.al[i];
@@ -980,35 +1123,42 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
       if (!alive_i) {
         v.aln[i] = 0;
       } else {
-        const bool a1 = anticommutes(mx[0], mz[0], px[0], pz[0], W);
-        const bool a2 = anticommutes(mx[0], mz[0], px[1], pz[1], W);
-        if (!a1 && !a2) {
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < K; ++g) {
+          an[g] = anticommutes(mx[0], mz[0], ga.px[g], ga.pz[g], W);
+          any = any || an[g];
+        }
+        if (!any) {                        // untouched by every rotation
           bool keep = true;
           if (full) keep = fabs(c[0]) >= eps && !heavy(mx[0], mz[0]);
           v.aln[i] = keep ? 1 : 0;
           if (keep) {
-            ++my_live1;
+            my_lv += K - 1;
             tally(mx[0], mz[0]);
           }
         } else {
-          ex[0] = true;
-          ex[1] = a1;
-          ex[2] = a2;
-          ex[3] = a1 && a2;
-          PP_FOR_W(w, 0, W, kMaxW) {
-            mx[1][w] = mx[0][w] ^ px[0][w];
-            mz[1][w] = mz[0][w] ^ pz[0][w];
-            mx[2][w] = mx[0][w] ^ px[1][w];
-            mz[2][w] = mz[0][w] ^ pz[1][w];
-            mx[3][w] = mx[1][w] ^ px[1][w];
-            mz[3][w] = mz[1][w] ^ pz[1][w];
+#pragma unroll
+          for (int m = 1; m < NM; ++m) {
+            bool e = true;
+#pragma unroll
+            for (int g = 0; g < K; ++g)
+              if ((m >> g) & 1) e = e && an[g];
+            ex[m] = e;
+            const int g0 = 31 - __clz(m);          // highest rotation in m
+            const int rest = m & ~(1 << g0);       // m = rest | 2^g0, rest < m
+            PP_FOR_W(w, 0, W, kMaxW) {
+              mx[m][w] = mx[rest][w] ^ ga.px[g0][w];
+              mz[m][w] = mz[rest][w] ^ ga.pz[g0][w];
+            }
           }
+          ex[0] = true;
+          gt_lookup_n<NM - 1>(b, gen, M, v, &ex[1], &mx[1], &mz[1], &idx[1], &c[1]);
           idx[0] = i;
           was[0] = true;
           lead = true;
 #pragma unroll
-          for (int m = 1; m < 4; ++m) {
-            if (ex[m]) idx[m] = gt_lookup(b, gen, M, v, mx[m], mz[m], &c[m]);
+          for (int m = 1; m < NM; ++m) {
             was[m] = idx[m] >= 0;
             if (was[m] && (uint32_t)idx[m] < i) lead = false;   // a lower member leads
           }
@@ -1017,39 +1167,37 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
     }
     if (lead) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < NM; ++m) {
         pres[m] = was[m];
         if (was[m]) ++my_rw;
       }
-      // gate g acts on the pairs (A, A + step): step 1 for P, 2 for P2
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        const bool acts = g == 0 ? ex[1] : ex[2];
+      for (int g = 0; g < K; ++g) {
         const bool chk = g == 0 && full;   // the sub-layer's first gate re-checks all
-        if (!acts) {
+        if (!an[g]) {
           if (chk)
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < NM; ++m)
               if (pres[m]) pres[m] = fabs(c[m]) >= eps && !heavy(mx[m], mz[m]);
         } else {
-          const int step = g == 0 ? 1 : 2;
+          const int step = 1 << g;
 #pragma unroll
-          for (int A = 0; A < 4; ++A) {
+          for (int A = 0; A < NM; ++A) {
             if ((A & step) || !ex[A] || !ex[A + step]) continue;
             const int B = A + step;
-            const int sig = product_sign(px[g], pz[g], mx[A], mz[A], mx[B], mz[B], W);  // i P A = sig B
+            // i P_g A = sig B, and i P_g B = -sig A
+            const int sig = product_sign(ga.px[g], ga.pz[g], mx[A], mz[A], mx[B], mz[B], W);
             if (pres[A] && pres[B]) {
               double nA, nB;
-              rotate_pair(v.f32, cs[g], sn[g], sig, c[A], c[B], &nA, &nB);
+              rotate_pair(v.f32, ga.cs[g], ga.sn[g], sig, c[A], c[B], &nA, &nB);
               c[A] = nA;
               c[B] = nB;
               pres[A] = fabs(nA) >= eps && !(chk && heavy(mx[A], mz[A]));
               pres[B] = fabs(nB) >= eps && !(chk && heavy(mx[B], mz[B]));
             } else if (pres[A] || pres[B]) {
-              // i P B = -sig A: the source's sign is sig from A, -sig from B
-              const int S = pres[A] ? A : B, T = pres[A] ? B : A;
+              const int S = pres[A] ? A : B, T = pres[A] ? B : A;   // source, new string
               double nS, child;
-              rotate_single(v.f32, cs[g], sn[g], pres[A] ? sig : -sig, c[S], &nS, &child);
+              rotate_single(v.f32, ga.cs[g], ga.sn[g], pres[A] ? sig : -sig, c[S], &nS, &child);
               c[S] = nS;
               pres[S] = fabs(nS) >= eps && !(chk && heavy(mx[S], mz[S]));
               if (fabs(child) >= eps && !heavy(mx[T], mz[T])) {
@@ -1059,17 +1207,17 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
             }
           }
         }
-        if (g == 0)
+        if (g < K - 1)
 #pragma unroll
-          for (int m = 0; m < 4; ++m)
+          for (int m = 0; m < NM; ++m)
             if (pres[m]) {
-              ++my_live1;
-              if (ex[2]) ++my_anti2;   // every member anticommutes with P2 iff Q does
+              ++my_lv;
+              if (an[g + 1 < K ? g + 1 : 0]) ++my_an;
             }
       }
       // members that were live keep their slot; tally the survivors
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < NM; ++m) {
         if (was[m]) {
           v.setc((uint32_t)idx[m], c[m]);
           v.aln[idx[m]] = pres[m] ? 1 : 0;
@@ -1080,7 +1228,7 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
     // append the new members of this row: one atomic per block and row
     uint32_t mine = 0;
 #pragma unroll
-    for (int m = 1; m < 4; ++m) mine += (lead && pres[m] && !was[m]) ? 1u : 0u;
+    for (int m = 1; m < NM; ++m) mine += (lead && pres[m] && !was[m]) ? 1u : 0u;
     uint32_t total;
     uint32_t off = block_scan(mine, s_tmp, &total);
     if (total) {
@@ -1088,7 +1236,7 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
       __syncthreads();
       const uint32_t base = *s_base;
 #pragma unroll
-      for (int m = 1; m < 4; ++m) {
+      for (int m = 1; m < NM; ++m) {
         if (!(lead && pres[m] && !was[m])) continue;
         const uint32_t pos = base + off++;
         if (pos >= v.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }   // guard
@@ -1104,15 +1252,15 @@ __device__ __forceinline__ void gate2_tile(const InstBuf& b, InstDyn& d, uint32_
   }
   const uint32_t bl = block_sum_u32(my_live, s_tmp);
   const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
-  const uint32_t bl1 = block_sum_u32(my_live1, s_tmp);
-  const uint32_t ba2 = block_sum_u32(my_anti2, s_tmp);
   const uint32_t brw = block_sum_u32(my_rw, s_tmp);
+  const uint32_t blv = block_sum_u32(my_lv, s_tmp);
+  const uint32_t ban = block_sum_u32(my_an, s_tmp);
   if (threadIdx.x == 0) {
     sm.plive += bl;
     sm.pcnt += bc;
-    sm.plive2 += bl1;
-    sm.pcnt2 += ba2;
-    sm.prw += brw;
+    sm.pstat[STAT_LIVE] += blv;
+    sm.pstat[STAT_ANTI] += ban;
+    sm.pstat[STAT_RW] += brw;
   }
 }
 
@@ -1145,10 +1293,7 @@ struct NextGate {
   uint64_t x[kMaxW], z[kMaxW];
   __device__ NextGate(const InstBuf& b, const Op& op) {
     has = op.next_gate != kNone32;
-    if (has) {
-      const Op& nx = b.prog[op.next_gate];
-      PP_FOR_W(w, 0, b.W, kMaxW) { x[w] = nx.px[w]; z[w] = nx.pz[w]; }
-    }
+    PP_FOR_W(w, 0, b.W, kMaxW) { x[w] = op.nx[w]; z[w] = op.nz[w]; }
   }
   __device__ __forceinline__ bool anti(const uint64_t* qx, const uint64_t* qz, int W) const {
     return has && anticommutes(qx, qz, x, z, W);
@@ -1164,25 +1309,39 @@ __device__ __forceinline__ void add_counts(InstDyn&, uint32_t live, uint32_t cnt
   }
 }
 
-// Mode 0 runs either gate op (the multi-instance kernel, whose instances may
-// stand at either); the one-instance kernels are built per op type (1: one
-// gate, 2: two gates), so the one-gate kernel keeps its smaller register
-// footprint.
+// Mode 0 runs any gate op (the multi-instance kernel, whose instances may
+// stand at any); the one-instance kernels are built per rotation count
+// (Mode = 1, 2 or 3), so each keeps only the registers it needs.
+__device__ __forceinline__ uint32_t rotations_of(const Op& op) {
+  return op.type == OP_GATES ? op.nrot : 1u;
+}
+
+template <int Mode, int IT>
+__device__ __forceinline__ void gate_tile_any(const InstBuf& b, InstDyn& d, const GateArgs& g,
+                                              const View& v, uint32_t M, uint32_t gen, uint32_t t,
+                                              Smem& sm) {
+  if (Mode == 1 || (Mode == 0 && g.nrot == 1))
+    gate_tile<IT>(b, d, g, v, M, gen, t, sm);
+  else if (Mode == 2 || (Mode == 0 && g.nrot == 2))
+    gates_tile<IT, 2>(b, d, g, v, M, gen, t, sm);
+  else
+    gates_tile<IT, 3>(b, d, g, v, M, gen, t, sm);
+}
+
 template <int Mode>
 struct GateKindT {
   __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
   __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     const int st = gate_state(b, d);
-    if (Mode && st && (b.prog[d.pc].type == OP_GATE2) != (Mode == 2)) return 0;
+    if (Mode && st && rotations_of(b.prog[d.pc]) != (uint32_t)Mode) return 0;
     return st;
   }
   __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
   template <int IT>
   __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
-    if (Mode == 2 || (Mode == 0 && b.prog[d.pc].type == OP_GATE2))
-      gate2_tile<IT>(b, d, t, sm);
-    else
-      gate_tile<IT>(b, d, t, sm);
+    const GateArgs g = gate_args(b.prog[d.pc]);
+    const View v = view_of(b, d);
+    gate_tile_any<Mode, IT>(b, d, g, v, d.M, d.gen, t, sm);
   }
   __device__ __forceinline__ static void finish(const InstBuf& b, InstDyn& d, uint32_t, Smem&) {
     const Op& op = b.prog[d.pc];
@@ -1190,17 +1349,9 @@ struct GateKindT {
     d.merged += (uint64_t)d.live + d.count;
     d.anti_total += d.count;
     d.key_reads += d.live;
-    if (op.type == OP_GATE2) {            // the second rotation's work units
-      const uint64_t live1 = (uint32_t)d.acc2, anti2 = d.acc2 >> 32;
-      d.propagated += live1;
-      d.merged += live1 + anti2;
-      d.anti_total += anti2;
-      d.coef_rw += (uint32_t)d.acc3;
-      d.acc2 = 0;
-      d.acc3 = 0;
-    } else {
-      d.coef_rw += d.count;
-    }
+    // a multi-rotation op's later rotations and rewritten coefficients
+    // went to the statistics lines
+    if (rotations_of(op) == 1) d.coef_rw += d.count;
     d.appended += ld_agent(&d.Mnext) - d.M;
     d.M = ld_agent(&d.Mnext);
     d.Mnext = d.M;
@@ -1935,14 +2086,80 @@ __device__ __forceinline__ void run_solo(const Solo& S, Smem& sm) {
   const uint32_t workers = worker_count(tiles);
   if (blockIdx.x >= workers) return;
   const uint32_t nsh = acc_shards(workers);
+  const bool packed = workers <= kTreeMin && b.cap < kPackedCap;
+  const bool fence = K::needs_fence(b, d);
   if (threadIdx.x == 0) pend_reset(sm);
   for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) K::template tile<IT>(b, d, t, sm);
+  if (packed) {
+    if (fence) __syncthreads();            // the block's stores precede its count
+    if (threadIdx.x != 0) return;
+    const uint32_t live = sm.plive, cnt = sm.pcnt;
+    flush(b, d, sm, nsh, true);
+    uint64_t acc;
+    if (!last_block_packed(S.sync, workers, live, cnt, fence, &acc)) return;
+    d.acc += acc;                          // onto what earlier launches of the op left
+    K::finish(b, d, tiles, sm);
+    return;
+  }
   if (threadIdx.x == 0) flush(b, d, sm, nsh);
-  if (!last_block(S.sync, &sm.flag, workers, K::needs_fence(b, d))) return;
+  if (!last_block(S.sync, &sm.flag, workers, fence)) return;
   if (threadIdx.x == 0) {
     fold_acc(b, d, nsh);
     K::finish(b, d, tiles, sm);
   }
+}
+
+// One-instance gate launch of a Mode-rotation op.  Everything that decides
+// whether and how the launch works (the op, which the launch argument names,
+// and the instance's state) is read up front, so the op's loads do not wait
+// for the program counter; the term loads then wait for one round trip.
+template <int Mode, int IT>
+__device__ __forceinline__ void run_gate_solo(const Solo& S, Smem& sm) {
+  const InstBuf& b = S.b;
+  InstDyn& d = *S.d;
+  const GateArgs g = gate_args(b.prog[S.k]);    // S.k < prog_len
+  const uint32_t pc = d.pc, status = d.status, count_for = d.count_for, M = d.M;
+  const uint32_t live = d.live, count = d.count, gen = d.gen;
+  const View v = view_of(b, d);
+  // one decision from all of them (no branch before every load is issued:
+  // the op's fields are waited on here, together with the state);
+  // pc != S.k: an earlier op did not complete
+  uint64_t all = __double_as_longlong(g.cs[0]) ^ __double_as_longlong(g.sn[0]) ^
+                 __double_as_longlong(g.cs[1]) ^ __double_as_longlong(g.sn[1]) ^
+                 __double_as_longlong(g.eps) ^ (uint64_t)g.wmax;
+#pragma unroll
+  for (int w = 0; w < kMaxW; ++w)
+    all ^= g.px[0][w] ^ g.pz[0][w] ^ g.px[1][w] ^ g.pz[1][w] ^ g.nx[w] ^ g.nz[w];
+  consume(all);
+  int st = gate_state_of(g.type, g.nrot, pc, status, count_for, M, live, count, b.cap);
+  st = (pc == S.k && g.nrot == (uint32_t)Mode) ? st : 0;
+  if (st == 2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { d.status |= ST_OVERFLOW; d.failed_pc = pc; }
+    return;
+  }
+  if (st != 1) return;
+  const uint32_t tiles = ceil_tiles<IT>(M);
+  const uint32_t workers = worker_count(tiles);
+  if (blockIdx.x >= workers) return;
+  const uint32_t nsh = acc_shards(workers);
+  const bool packed = workers <= kTreeMin && b.cap < kPackedCap;
+  if (threadIdx.x == 0) pend_reset(sm);
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x)
+    gate_tile_any<Mode, IT>(b, d, g, v, M, gen, t, sm);
+  if (threadIdx.x != 0) return;            // thread 0 holds the block's counts
+  if (packed) {
+    const uint32_t live = sm.plive, cnt = sm.pcnt;
+    flush(b, d, sm, nsh, true);
+    uint64_t acc;
+    if (!last_block_packed(S.sync, workers, live, cnt, false, &acc)) return;
+    d.acc += acc;                          // onto what earlier launches of the op left
+    GateKindT<Mode>::finish(b, d, tiles, sm);
+    return;
+  }
+  flush(b, d, sm, nsh);
+  if (!last_block_one(S.sync, workers)) return;
+  fold_acc(b, d, nsh);
+  GateKindT<Mode>::finish(b, d, tiles, sm);
 }
 
 #define PP_KERNEL_PAIR(name, Kind)                                                    \
@@ -1968,12 +2185,17 @@ __global__ __launch_bounds__(kBlock) void k_gate(Ctx C) {
 template <int IT>
 __global__ __launch_bounds__(kBlock) void k_gate_solo(Solo S) {
   __shared__ Smem sm;
-  run_solo<GateKindT<1>, IT>(S, sm);
+  run_gate_solo<1, IT>(S, sm);
 }
 template <int IT>
 __global__ __launch_bounds__(kBlock) void k_gate2_solo(Solo S) {
   __shared__ Smem sm;
-  run_solo<GateKindT<2>, IT>(S, sm);
+  run_gate_solo<2, IT>(S, sm);
+}
+template <int IT>
+__global__ __launch_bounds__(kBlock) void k_gate3_solo(Solo S) {
+  __shared__ Smem sm;
+  run_gate_solo<3, IT>(S, sm);
 }
 PP_KERNEL_PAIR(k_merge_narrow, MergeNarrowKind)
 PP_KERNEL_PAIR(k_merge_wide1, MergeWide1Kind)

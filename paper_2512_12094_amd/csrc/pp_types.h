@@ -35,6 +35,7 @@
 namespace pp {
 
 constexpr int kMaxW = 2;                   // up to 128 qubits
+constexpr int kMaxFuse = 3;                // rotations one gate launch may apply
 constexpr uint32_t kNone32 = 0xFFFFFFFFu;
 constexpr uint64_t kEmpty64 = ~0ull;
 constexpr int kMaxInst = 1024;             // instances per batched launch
@@ -47,8 +48,9 @@ enum OpType : uint32_t {
   OP_TRUNC = 4,    // drop |c| < eps or weight > wmax
   OP_COUNT = 5,    // only recount (live, anticommuting with next gate)
   OP_EXPECT = 6,   // expectation in a symmetric product state
-  OP_GATE2 = 7,    // two commuting rotations (P, then P2), each followed by
-                   // the exact merge and truncation, in one pass
+  OP_GATES = 7,    // 2..kMaxFuse mutually commuting rotations in circuit
+                   // order, each followed by the exact merge and
+                   // truncation, in one pass
 };
 
 enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u, ST_FAILED = 8u };
@@ -61,8 +63,16 @@ constexpr int kAccShards = 16;
 constexpr int kSyncShards = 16;
 constexpr int kLineU64 = 16;
 constexpr int kLineU32 = 32;
-constexpr size_t kSyncBytes = (1 + kSyncShards) * kLineU32 * sizeof(uint32_t);
-constexpr size_t kAccBytes = 3 * kAccShards * kLineU64 * sizeof(uint64_t);   // acc, acc2, acc3
+// done counters: the root line, kSyncShards shard lines, and one line whose
+// 64-bit word counts done blocks and their packed counts (kPackedLine)
+constexpr int kPackedLine = 1 + kSyncShards;
+constexpr size_t kSyncBytes = (2 + kSyncShards) * kLineU32 * sizeof(uint32_t);
+constexpr size_t kAccBytes = kAccShards * kLineU64 * sizeof(uint64_t);
+// work statistics that no kernel reads back (multi-rotation ops): live terms
+// after each rotation but the last, those anticommuting with the next
+// rotation, coefficients rewritten; summed over launches, per shard line
+enum : int { STAT_LIVE = 0, STAT_ANTI = 1, STAT_RW = 2, kStatKinds = 3 };
+constexpr size_t kStatBytes = kStatKinds * kAccShards * kLineU64 * sizeof(uint64_t);
 
 // Partitioned merge: used for narrow-key merges of at least kPartMin
 // records; tiles of kPartTile records, kParts partitions, LDS tables of
@@ -82,13 +92,15 @@ struct Op {
   uint32_t next_gate;    // index of the next GATE op after this one, or kNone32
   int32_t wmax;          // GATE/TRUNC: weight limit (< 0: off)
   uint32_t force_full;   // MERGE with group NONE: merge duplicates (creation)
-  uint32_t pad;
-  uint64_t px[kMaxW];    // GATE: the rotation's Pauli string
+  uint32_t nrot;         // GATE: 1; GATES: rotations in the op
+  uint64_t px[kMaxW];    // GATE(S): the (first) rotation's Pauli string
   uint64_t pz[kMaxW];
-  double cs, sn;         // GATE: cos(theta), sin(theta)
-  uint64_t px2[kMaxW];   // GATE2: the second rotation (commutes with the first)
-  uint64_t pz2[kMaxW];
-  double cs2, sn2;
+  double cs, sn;         // GATE(S): cos(theta), sin(theta)
+  uint64_t qx[kMaxFuse - 1][kMaxW];   // GATES: rotations 2..nrot
+  uint64_t qz[kMaxFuse - 1][kMaxW];
+  double qcs[kMaxFuse - 1], qsn[kMaxFuse - 1];
+  uint64_t nx[kMaxW];    // the next gate op's (first) rotation, when next_gate
+  uint64_t nz[kMaxW];    // != kNone32 (its anticommutation count is tallied here)
   double eps;            // GATE/TRUNC: coefficient threshold (0: off)
   const double* table;   // DAMP: (1-p)^w for w = 0..n;
                          // EXPECT: bx^k, by^k, bz^k for k = 0..n (3 blocks)
@@ -105,7 +117,8 @@ struct InstBuf {
   uint32_t* mown;
   uint64_t* wrep;        // [2W][cap]: x words then z words of each record's rep
   uint32_t* wslot;
-  uint64_t* accs;        // 3 x kAccShards count accumulators (acc, acc2, acc3)
+  uint64_t* accs;        // kAccShards count accumulators
+  uint64_t* stats;       // kStatKinds x kAccShards statistics lines (cumulative)
   // partitioned merge (narrow keys, large sets): records staged per tile of
   // kPartTile, sorted by partition, with each tile's partition offsets
   uint64_t* pkey;        // [tiles * kPartTile] representative keys
@@ -135,8 +148,6 @@ struct InstDyn {
   uint64_t merge_in;     // records entering symmetry merges / compactions
   uint64_t merge_out;    // representatives leaving them
   uint64_t acc;          // counts folded from the shards by the last block
-  uint64_t acc2;         // GATE2: live | anticommuting << 32 between its gates
-  uint64_t acc3;         // GATE2: entering terms whose coefficient the launch rewrites
   uint64_t key_reads;    // sum over gate launches of the live terms entering them
   uint64_t coef_rw;      // sum over gate launches of the entering terms they rotate
   uint64_t special_fx[3];   // narrow merge: the one key equal to kEmpty64

@@ -1,9 +1,10 @@
-"""Two-gate fusion (pp_set_gate_fusion): a launch that applies two commuting
-rotations of a sub-layer, each with its own exact merge and truncation,
-gives bitwise the results of one launch per gate (same arithmetic in the same
-order), on every path (per-call layers, the one-instance program, the
-batched form, FP32 storage, store growth), and the oracle's results by the
-parity rules of tests/parity.py; the gate launch count halves."""
+"""Gate fusion (pp_set_gate_fusion): a launch that applies two or three
+commuting, independent rotations of a sub-layer, each with its own exact
+merge and truncation, gives bitwise the results of one launch per gate (same
+arithmetic in the same order), on every path (per-call layers, the
+one-instance program, the batched form, FP32 storage, store growth), and the
+oracle's results by the parity rules of tests/parity.py; the gate launch
+count drops by the group size."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,7 @@ def gpu():
     stream = torch.cuda.Stream()
     yield dict(torch=torch, stream=stream, handle=int(stream.cuda_stream),
                alloc=_lib.TorchAllocator(0))
-    _lib.pp_set_gate_fusion(1)
+    _lib.pp_set_gate_fusion(3)
 
 
 def prefix(prog, k):
@@ -79,9 +80,10 @@ def same(a, b, what):
 def test_fused_program_equals_unfused_and_oracle(gpu, which):
     prog = CASES[which]()
     print(f"[case] fusion program {which}", flush=True)
-    fused = run_program(gpu, prog, 1)
-    plain = run_program(gpu, prog, 0)
-    same(fused, plain, which)
+    plain = run_program(gpu, prog, 1)
+    for k in (2, 3):
+        fused = run_program(gpu, prog, k)
+        same(fused, plain, f"{which} fused {k}")
     ref = O.run_program(prog)
     compare_terms(fused.terms, ref.terms, prog.meta.get("eps", 0.0), what=which)
     compare_expectation(fused.expectation, ref.expectation, ref.terms, what=which)
@@ -95,16 +97,19 @@ def test_fused_layers_equal_unfused(gpu, which):
     prog = CASES[which]()
     print(f"[case] fusion layers {which}", flush=True)
     out = []
-    for fuse in (1, 0):
+    for fuse in (3, 2, 1):
         L.pp_set_gate_fusion(fuse)
         out.append(driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"]))
-    same(out[0], out[1], which)
+    same(out[0], out[2], which)
+    same(out[1], out[2], which)
 
 
 def test_fused_f32_equals_unfused_f32(gpu):
     prog = prefix(W.config2(), 12)
     print("[case] fusion f32", flush=True)
-    same(run_program(gpu, prog, 1, "f32"), run_program(gpu, prog, 0, "f32"), "f32")
+    plain = run_program(gpu, prog, 1, "f32")
+    for k in (2, 3):
+        same(run_program(gpu, prog, k, "f32"), plain, f"f32 fused {k}")
 
 
 def test_fused_batch_equals_unfused(gpu):
@@ -120,7 +125,7 @@ def test_fused_batch_equals_unfused(gpu):
     progs.append(W.heisenberg_all_to_all(9, 1, 0.1, eps=1e-5, name="fs9"))
     print("[case] fusion batch", [p.n for p in progs], flush=True)
     results = []
-    for fuse in (1, 0):
+    for fuse in (3, 1, 2):
         L.pp_set_gate_fusion(fuse)
         e, sets, dprogs, _ = driver.batch_propagate(progs, gpu["handle"], gpu["alloc"])
         results.append((list(e), [s.as_dict() for s in sets], [s.counters() for s in sets]))
@@ -129,18 +134,20 @@ def test_fused_batch_equals_unfused(gpu):
         for d in dprogs:
             d.close()
     assert results[0] == results[1]
+    assert results[2] == results[1]
     for p, ei, terms, cnt in zip(progs, *results[0]):
         ref = O.run_program(p)
         compare_expectation(ei, ref.expectation, ref.terms, what=p.name)
         assert cnt == (ref.propagated, ref.merged), p.name
 
 
-def test_fusion_halves_gate_launches(gpu):
-    """All gates of a ring sub-layer commute: n gates take n/2 launches."""
+def test_fusion_divides_gate_launches(gpu):
+    """All gates of a ring sub-layer commute and any three neighbouring bonds
+    are independent: n gates take ceil(n / k) launches."""
     from paper_2512_12094_amd import _lib as L, driver
     prog = W.xxz_ring(16, 1, 0.2, 1.0, eps=1e-6, name="z16")
     counts = []
-    for fuse in (1, 0):
+    for fuse in (3, 2, 1):
         L.pp_set_gate_fusion(fuse)
         ps = driver.PauliSet.from_program(prog, None, gpu["handle"], gpu["alloc"])
         L.pp_profile(ps.h, 1)
@@ -148,14 +155,15 @@ def test_fusion_halves_gate_launches(gpu):
             ps.apply_layer(la)
         counts.append(L.pp_profile_read(ps.h)["gate"][0])
         ps.close()
-    assert counts == [3 * 8, 3 * 16], counts
+    assert counts == [3 * 6, 3 * 8, 3 * 16], counts
 
 
 def test_fusion_switch_validates():
     from paper_2512_12094_amd import _lib as L
-    with pytest.raises(L.PPError):
-        L.pp_set_gate_fusion(2)
-    L.pp_set_gate_fusion(1)
+    for bad in (-1, 4):
+        with pytest.raises(L.PPError):
+            L.pp_set_gate_fusion(bad)
+    L.pp_set_gate_fusion(3)
 
 
 def test_gate_unit_counters_and_program_info(gpu):
@@ -166,13 +174,14 @@ def test_gate_unit_counters_and_program_info(gpu):
     from paper_2512_12094_amd import _lib as L, driver
     prog = prefix(W.config2(), 6)
     wcs = []
-    for fuse in (0, 1):
+    for fuse in (1, 3):
         L.pp_set_gate_fusion(fuse)
         prog.meta.pop("_dprog", None)
         dp = driver.device_program(prog)
         info = L.pp_program_info(dp.h)
         assert info["gates"] == prog.n_gates
-        assert info["gate_launches"] == prog.n_gates // (1 + fuse)   # ring sub-layers pair up
+        per_sub = -(-prog.n // fuse)                 # ring sub-layers group up
+        assert info["gate_launches"] == per_sub * len(prog.sublayers)
         ps = driver.PauliSet.from_program(prog, None, gpu["handle"], gpu["alloc"])
         L.pp_batch_run([ps.h], [dp.h], gpu["handle"])
         wcs.append(L.pp_work_counters(ps.h))
@@ -188,4 +197,19 @@ def test_gate_unit_counters_and_program_info(gpu):
     assert on["appended"] <= off["appended"]
     assert on["gate_key_reads"] < off["gate_key_reads"]
     assert on["gate_coef_rw"] <= off["gate_coef_rw"]
-    L.pp_set_gate_fusion(1)
+    L.pp_set_gate_fusion(3)
+
+
+def test_fusion_needs_independent_strings(gpu):
+    """All pairs of 4 qubits, lexicographic: XX01 XX02 XX03 form one launch;
+    XX12 XX13 commute with XX23 but multiply to it, so XX23 starts a new
+    launch: 3 launches per sub-layer (2 if dependence were ignored)."""
+    from paper_2512_12094_amd import _lib as L, driver
+    prog = W.heisenberg_all_to_all(4, 1, 0.1, eps=1e-6, name="s4")
+    L.pp_set_gate_fusion(3)
+    prog.meta.pop("_dprog", None)
+    info = L.pp_program_info(driver.device_program(prog).h)
+    prog.meta.pop("_dprog", None)
+    assert info["gates"] == 18 and info["gate_launches"] == 9, info
+    res = run_program(gpu, prog, 3)
+    same(res, run_program(gpu, prog, 1), "s4")

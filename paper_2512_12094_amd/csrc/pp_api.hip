@@ -459,6 +459,9 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
 int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
   std::vector<int> kinds;
   const bool big = s->m_hint >= kBigSet;   // last term count seen on the host
+  // a set last seen well below the partitioned merge's threshold merges
+  // unpartitioned (correct at any size): its two kernels are not launched
+  const bool small = (uint64_t)s->m_hint * 4 < kPartMin;
   int run_kind = -1;
   uint32_t run_len = 0;
   hipEvent_t run_ev = nullptr;
@@ -466,6 +469,7 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
     kinds.clear();
     kinds_of(s, ops[k], &kinds);
     for (int kind : kinds) {
+      if (small && (kind == PP_K_PART_SORT || kind == PP_K_PART_AGG)) continue;
       if (kind != run_kind) {
         if (run_kind >= 0) prof_end(s, run_kind, run_ev, run_len);
         run_kind = kind;
@@ -478,6 +482,7 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
                                                 : launch_blocks(elems, items_of(kind, big));
       Solo S;
       S.b = s->buf;
+      if (small) S.b.nopart = 1;
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
@@ -958,6 +963,7 @@ int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
   d.live = (uint32_t)n_obs;
   d.seed = 1;
   d.failed_pc = kNone32;
+  s->m_hint = (uint32_t)n_obs;
   if (hipMemcpyAsync(s->d_dyn, &d, sizeof(InstDyn), hipMemcpyHostToDevice, s->stream))
     return bail(fail(PP_EDEVICE, "state upload failed"));
   // Algorithm 1, step 1: merge the rows by representative (duplicates too)
@@ -1418,11 +1424,16 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation) {
   s->batch_prog = p;
   if ((rc = upload_buf(s))) return rc;
   hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, st, s->d_dyn, 0u);
-  // chunk ends: after a MERGE (and the TRUNC that follows it), or the last op
+  // chunk ends: after every kChunkSubs-th sub-layer (its MERGE and the TRUNC
+  // that follows it), or the last op; the host reads the state once per chunk
+  constexpr int kChunkSubs = 1;
   std::vector<size_t> ends;
+  int subs = 0;
   for (size_t k = 0; k < len; ++k) {
     const bool merge_end = ops[k].type == OP_MERGE && !(k + 1 < len && ops[k + 1].type == OP_TRUNC);
-    if (merge_end || ops[k].type == OP_TRUNC || k + 1 == len) ends.push_back(k + 1);
+    if (merge_end || ops[k].type == OP_TRUNC) ++subs;
+    if (((merge_end || ops[k].type == OP_TRUNC) && subs % kChunkSubs == 0) || k + 1 == len)
+      ends.push_back(k + 1);
   }
   if (!s->solo_slots) {
     HIP_TRY(hipHostMalloc((void**)&s->solo_slots, sizeof(InstDyn) * 2, hipHostMallocDefault));

@@ -352,9 +352,14 @@ int pp_get_tuning(int out[5]);
  * terms where a single gate needs live + anticommuting, so near
  * pp_set_max_terms a fused run can report PP_ECAPACITY where an unfused
  * one would not.  Applies to pp_apply_layer and pp_program_create calls
- * made afterwards.  max_rotations outside 0..3: PP_EINVAL.
+ * made afterwards.  lanes = 1 runs a fused op over a set last seen below
+ * 2^19 terms with one lane per member of each group of 2^r strings instead
+ * of one thread per term (the same values, bitwise; more blocks, so more
+ * contended append atomics); lanes = 0 (default) always uses one thread per
+ * term.  Applies to launches made afterwards.  max_rotations outside 0..3
+ * or lanes outside 0..1: PP_EINVAL.
  */
-int pp_set_gate_fusion(int max_rotations);
+int pp_set_gate_fusion(int max_rotations, int lanes);
 
 #ifdef __cplusplus
 }

@@ -88,7 +88,7 @@ def lib():
     L.pp_batch_step.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_size_t, _vp,
                                 ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p]
     L.pp_set_tuning.argtypes = [ctypes.c_int] * 5
-    L.pp_set_gate_fusion.argtypes = [ctypes.c_int]
+    L.pp_set_gate_fusion.argtypes = [ctypes.c_int, ctypes.c_int]
     L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     _lib = L
     return L
@@ -324,9 +324,10 @@ def pp_set_tuning(gate_items=0, stream_items=0, max_blocks=0, graph_steps=0, gat
                                gates_per_step))
 
 
-def pp_set_gate_fusion(max_rotations):
-    """Rotations one gate launch may apply (0 or 1: no fusion; 2 or 3)."""
-    _check(lib().pp_set_gate_fusion(int(max_rotations)))
+def pp_set_gate_fusion(max_rotations, lanes=0):
+    """Rotations one gate launch may apply (0 or 1: no fusion; 2 or 3), and
+    whether smaller sets run fused ops with one lane per group member."""
+    _check(lib().pp_set_gate_fusion(int(max_rotations), int(lanes)))
 
 
 def pp_get_tuning():

@@ -43,6 +43,7 @@ struct Tuning {
 };
 Tuning g_tune;
 int g_fuse = kMaxFuse;    // pp_set_gate_fusion: rotations per gate launch (<= 1: off)
+int g_lanes = 0;          // pp_set_gate_fusion: lane-per-member form for smaller sets
 int g_prof_default = 0;   // pp_profile(NULL, every): new handles start timed
 
 #define HIP_TRY(expr)                                                            \
@@ -342,10 +343,24 @@ int stream_items(bool big) {
   return big ? std::max(g_tune.stream_items, kBigItems) : g_tune.stream_items;
 }
 
-SoloFn solo_of(int kind, bool big, uint32_t nrot = 1) {
+// Rows per tile of the lane form of an r-rotation op over a set last seen
+// with `hint` terms: the fewest that keep the launch within kTreeMin
+// blocks (one append atomic and one done count per block), or 0 when the
+// set is too large for the lane form.
+int lane_items(uint32_t hint, uint32_t nrot) {
+  if (!g_lanes || nrot < 2) return 0;
+  const uint64_t lanes = (uint64_t)std::max<uint32_t>(hint, 1) << nrot;
+  for (int it = 1; it <= 8; it *= 2)
+    if ((lanes + (uint64_t)kBlock * it - 1) / ((uint64_t)kBlock * it) <= kTreeMin) return it;
+  return 0;
+}
+
+SoloFn solo_of(int kind, bool big, uint32_t nrot = 1, int lane_it = 0) {
   const int gi = gate_items(big), si = stream_items(big);
   switch (kind) {
     case PP_K_GATE:
+      if (lane_it)
+        return nrot == 3 ? PP_PICK(k_gate3_lane_solo, lane_it) : PP_PICK(k_gate2_lane_solo, lane_it);
       return nrot == 3 ? PP_PICK(k_gate3_solo, gi)
              : nrot == 2 ? PP_PICK(k_gate2_solo, gi)
                          : PP_PICK(k_gate_solo, gi);
@@ -477,8 +492,11 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
         run_ev = prof_begin(s, kind);
       }
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
+      const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
+      const int lane_it = kind == PP_K_GATE && !big ? lane_items(s->m_hint, nrot) : 0;
       const int grid = kind == PP_K_PART_AGG    ? kParts
                        : kind == PP_K_PART_SORT ? launch_blocks(elems, kPartTile / kBlock)
+                       : lane_it                ? launch_blocks(elems << nrot, lane_it)
                                                 : launch_blocks(elems, items_of(kind, big));
       Solo S;
       S.b = s->buf;
@@ -486,8 +504,8 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
-      hipLaunchKernelGGL(solo_of(kind, big, nrot), dim3(grid), dim3(kBlock), 0, s->stream, S);
+      hipLaunchKernelGGL(solo_of(kind, big, nrot, lane_it), dim3(grid), dim3(kBlock), 0,
+                         s->stream, S);
       ++run_len;
     }
   }
@@ -812,10 +830,12 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
   return PP_OK;
 }
 
-int pp_set_gate_fusion(int max_rotations) {
+int pp_set_gate_fusion(int max_rotations, int lanes) {
   if (max_rotations < 0 || max_rotations > kMaxFuse)
     return fail(PP_EINVAL, "max_rotations must be 0.." + std::to_string(kMaxFuse));
+  if (lanes != 0 && lanes != 1) return fail(PP_EINVAL, "lanes must be 0 or 1");
   g_fuse = max_rotations;
+  g_lanes = lanes;
   return PP_OK;
 }
 

@@ -916,6 +916,7 @@ __device__ __forceinline__ int gate_state(const InstBuf& b, const InstDyn& d) {
 
 struct Smem {
   uint32_t tmp[kWaves + 1];
+  uint32_t red[kWaves][8];   // block_sums: per-wave partial sums
   uint32_t base;
   uint32_t flag;
   uint64_t wfx[kWaves][3];
@@ -931,6 +932,34 @@ __device__ __forceinline__ void pend_reset(Smem& sm) {
 #pragma unroll
   for (int k = 0; k < kStatKinds; ++k) sm.pstat[k] = 0;
   sm.pfx[0] = sm.pfx[1] = sm.pfx[2] = 0;
+}
+
+// Block totals of N per-thread counters, for thread 0: each wave sums with
+// lane exchanges, one barrier, then thread 0 adds the waves' sums (one
+// barrier where N separate block reductions take 3N).  `trail` adds a
+// barrier after the read, for callers with no barrier before their next
+// call.
+template <int N, bool trail = true>
+__device__ __forceinline__ void block_sums(const uint32_t (&v)[N], Smem& sm, uint32_t (&out)[N]) {
+  static_assert(N <= 8, "block_sums: at most 8 counters");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    uint32_t x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+    if (lane == 0) sm.red[wid][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      uint32_t t = 0;
+      for (int w = 0; w < kWaves; ++w) t += sm.red[w][k];
+      out[k] = t;
+    }
+  }
+  if (trail) __syncthreads();
 }
 
 // Thread 0: adds the pending statistics and expectation sum to the instance
@@ -1052,11 +1081,13 @@ __device__ __forceinline__ void gate_tile(const InstBuf& b, InstDyn& d, const Ga
     v.aln[pos] = 1;
     gt_insert(b.gtab, b.hg_bits, gen, pos, hash_key(chx[k], chz[k], W, 0));
   }
-  const uint32_t bl = block_sum_u32(my_live, s_tmp);
-  const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
+  // (the tile's append scan has its barriers before the next tile's sums)
+  const uint32_t v2[2] = {my_live, my_cnt};
+  uint32_t t2[2];
+  block_sums<2, false>(v2, sm, t2);
   if (threadIdx.x == 0) {
-    sm.plive += bl;
-    sm.pcnt += bc;
+    sm.plive += t2[0];
+    sm.pcnt += t2[1];
   }
 }
 
@@ -1250,17 +1281,194 @@ __device__ __forceinline__ void gates_tile(const InstBuf& b, InstDyn& d, const G
       }
     }
   }
-  const uint32_t bl = block_sum_u32(my_live, s_tmp);
-  const uint32_t bc = block_sum_u32(my_cnt, s_tmp);
-  const uint32_t brw = block_sum_u32(my_rw, s_tmp);
-  const uint32_t blv = block_sum_u32(my_lv, s_tmp);
-  const uint32_t ban = block_sum_u32(my_an, s_tmp);
+  // (every tile runs an append scan, whose barriers precede the next sums)
+  const uint32_t v5[5] = {my_live, my_cnt, my_lv, my_an, my_rw};
+  uint32_t t5[5];
+  block_sums<5, false>(v5, sm, t5);
   if (threadIdx.x == 0) {
-    sm.plive += bl;
-    sm.pcnt += bc;
-    sm.pstat[STAT_LIVE] += blv;
-    sm.pstat[STAT_ANTI] += ban;
-    sm.pstat[STAT_RW] += brw;
+    sm.plive += t5[0];
+    sm.pcnt += t5[1];
+    sm.pstat[STAT_LIVE] += t5[2];
+    sm.pstat[STAT_ANTI] += t5[3];
+    sm.pstat[STAT_RW] += t5[4];
+  }
+}
+
+// The same K-rotation op with one lane per group member: the 2^K lanes of a
+// lane group hold the members Q * P^s of one term Q's group (lane index =
+// s), so the lookups, signs, rotations and checks of a group run side by
+// side and a rotation pairs lane s with lane s ^ 2^g through a lane
+// exchange.  Every lane computes exactly the value the one-thread form
+// computes for its member (the pair rotation from either side gives the same
+// operations on the same operands), so the two forms agree bitwise.  A
+// block covers kBlock / 2^K terms per row; IT rows are loaded before any
+// append, and the new strings of all rows are appended with one atomic.
+template <int IT, int K>
+__device__ __forceinline__ void gates_lane_tile(const InstBuf& b, InstDyn& d, const GateArgs& ga,
+                                                const View& v, uint32_t M, uint32_t gen,
+                                                uint32_t tile, Smem& sm) {
+  constexpr int G = 1 << K;
+  constexpr uint32_t kRow = kBlock / G;      // terms per row of the tile
+  uint32_t* s_tmp = sm.tmp;
+  uint32_t* s_base = &sm.base;
+  const int W = v.W;
+  const double eps = ga.eps;
+  const int wmax = ga.wmax;
+  const bool full = ga.full;
+  const int m = (int)(threadIdx.x & (G - 1));  // this lane's member
+  uint32_t my_live = 0, my_cnt = 0, my_rw = 0, my_lv = 0, my_an = 0;
+  uint64_t chx[IT][kMaxW], chz[IT][kMaxW];
+  double chc[IT];
+  bool chv[IT];
+
+  auto heavy = [&](const uint64_t* x, const uint64_t* z) {
+    return wmax >= 0 && weight(x, z, W) > wmax;
+  };
+  auto tally = [&](const uint64_t* x, const uint64_t* z) {
+    ++my_live;
+    if (ga.has_next && anticommutes(x, z, ga.nx, ga.nz, W)) ++my_cnt;
+  };
+
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    chv[k] = false;
+    const uint32_t i = (tile * IT + k) * kRow + (threadIdx.x >> K);
+    const bool valid = i < M;
+    uint64_t qx[kMaxW], qz[kMaxW], mx[kMaxW], mz[kMaxW];
+    PP_FOR_W(w, 0, W, kMaxW) { qx[w] = qz[w] = 0; }
+    double cq = 0.0;
+    uint8_t alive = 0;
+    if (valid) {
+      alive = v.al[i];
+      load_key(v, i, qx, qz);
+      cq = v.getc(i);
+    }
+    bool an[K], any = false, ex = alive != 0;
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      an[g] = anticommutes(qx, qz, ga.px[g], ga.pz[g], W);
+      any = any || an[g];
+      if ((m >> g) & 1) ex = ex && an[g];
+    }
+    ex = ex && any;
+    PP_FOR_W(w, 0, W, kMaxW) { mx[w] = qx[w]; mz[w] = qz[w]; }
+#pragma unroll
+    for (int g = 0; g < K; ++g)
+      if ((m >> g) & 1) PP_FOR_W(w, 0, W, kMaxW) { mx[w] ^= ga.px[g][w]; mz[w] ^= ga.pz[g][w]; }
+    if (m == 0 && valid) {
+      if (!alive) {
+        v.aln[i] = 0;
+      } else if (!any) {                     // untouched by every rotation
+        bool keep = true;
+        if (full) keep = fabs(cq) >= eps && !heavy(qx, qz);
+        v.aln[i] = keep ? 1 : 0;
+        if (keep) {
+          my_lv += K - 1;
+          tally(qx, qz);
+        }
+      }
+    }
+    int64_t idx = -1;
+    double c = 0.0;
+    if (ex) {
+      if (m == 0) {
+        idx = i;
+        c = cq;
+      } else {
+        idx = gt_lookup(b, gen, M, v, mx, mz, &c);
+      }
+    }
+    const bool was = idx >= 0;
+    // the group's lowest live index leads it
+    uint32_t low = was ? (uint32_t)idx : 0xFFFFFFFFu;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) low = min(low, (uint32_t)__shfl_xor((int)low, o, 64));
+    const bool lead = ex && low == i;
+    bool pres = lead && was;
+    if (pres) ++my_rw;
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const bool chk = g == 0 && full;      // the sub-layer's first gate re-checks all
+      const double cp = __shfl_xor(c, 1 << g, 64);
+      const bool pp = __shfl_xor((int)pres, 1 << g, 64) != 0;
+      if (lead) {
+        if (!an[g]) {
+          if (chk && pres) pres = fabs(c) >= eps && !heavy(mx, mz);
+        } else {
+          uint64_t rx[kMaxW], rz[kMaxW];
+          PP_FOR_W(w, 0, W, kMaxW) { rx[w] = mx[w] ^ ga.px[g][w]; rz[w] = mz[w] ^ ga.pz[g][w]; }
+          const int sig = product_sign(ga.px[g], ga.pz[g], mx, mz, rx, rz, W);  // i P_g me = sig partner
+          if (pres && pp) {
+            double n0, n1;
+            rotate_pair(v.f32, ga.cs[g], ga.sn[g], sig, c, cp, &n0, &n1);
+            c = n0;
+            pres = fabs(n0) >= eps && !(chk && heavy(mx, mz));
+          } else if (pres) {
+            double n0, child;
+            rotate_single(v.f32, ga.cs[g], ga.sn[g], sig, c, &n0, &child);
+            c = n0;
+            pres = fabs(n0) >= eps && !(chk && heavy(mx, mz));
+          } else if (pp) {                    // the partner's new string is me
+            double n0, child;
+            rotate_single(v.f32, ga.cs[g], ga.sn[g], -sig, cp, &n0, &child);
+            if (fabs(child) >= eps && !heavy(mx, mz)) {
+              c = child;
+              pres = true;
+            }
+          }
+        }
+        if (g < K - 1 && pres) {
+          ++my_lv;
+          if (an[g + 1 < K ? g + 1 : 0]) ++my_an;
+        }
+      }
+    }
+    if (lead) {
+      if (was) {
+        v.setc((uint32_t)idx, c);
+        v.aln[idx] = pres ? 1 : 0;
+      } else if (pres) {
+        chv[k] = true;
+        PP_FOR_W(w, 0, W, kMaxW) { chx[k][w] = mx[w]; chz[k][w] = mz[w]; }
+        chc[k] = c;
+      }
+      if (pres) tally(mx, mz);
+    }
+  }
+  // append the new strings of all rows: one atomic per tile
+  uint32_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < IT; ++k) mine += chv[k] ? 1u : 0u;
+  uint32_t total;
+  uint32_t off = block_scan(mine, s_tmp, &total);
+  if (total) {
+    if (threadIdx.x == 0) *s_base = atomicAdd(&d.Mnext, total);
+    __syncthreads();
+    const uint32_t base = *s_base;
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      if (!chv[k]) continue;
+      const uint32_t pos = base + off++;
+      if (pos >= v.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }   // guard
+      PP_FOR_W(w, 0, W, kMaxW) {
+        v.X[(size_t)w * v.cap + pos] = chx[k][w];
+        v.Z[(size_t)w * v.cap + pos] = chz[k][w];
+      }
+      v.setc(pos, chc[k]);
+      v.aln[pos] = 1;
+      gt_insert(b.gtab, b.hg_bits, gen, pos, hash_key(chx[k], chz[k], W, 0));
+    }
+  }
+  // (every tile runs an append scan, whose barriers precede the next sums)
+  const uint32_t v5[5] = {my_live, my_cnt, my_lv, my_an, my_rw};
+  uint32_t t5[5];
+  block_sums<5, false>(v5, sm, t5);
+  if (threadIdx.x == 0) {
+    sm.plive += t5[0];
+    sm.pcnt += t5[1];
+    sm.pstat[STAT_LIVE] += t5[2];
+    sm.pstat[STAT_ANTI] += t5[3];
+    sm.pstat[STAT_RW] += t5[4];
   }
 }
 
@@ -1301,11 +1509,12 @@ struct NextGate {
 };
 
 __device__ __forceinline__ void add_counts(InstDyn&, uint32_t live, uint32_t cnt, Smem& sm) {
-  const uint32_t bl = block_sum_u32(live, sm.tmp);
-  const uint32_t bc = block_sum_u32(cnt, sm.tmp);
+  const uint32_t v2[2] = {live, cnt};
+  uint32_t t2[2];
+  block_sums<2>(v2, sm, t2);
   if (threadIdx.x == 0) {
-    sm.plive += bl;
-    sm.pcnt += bc;
+    sm.plive += t2[0];
+    sm.pcnt += t2[1];
   }
 }
 
@@ -2113,7 +2322,7 @@ __device__ __forceinline__ void run_solo(const Solo& S, Smem& sm) {
 // whether and how the launch works (the op, which the launch argument names,
 // and the instance's state) is read up front, so the op's loads do not wait
 // for the program counter; the term loads then wait for one round trip.
-template <int Mode, int IT>
+template <int Mode, int IT, bool Lane = false>
 __device__ __forceinline__ void run_gate_solo(const Solo& S, Smem& sm) {
   const InstBuf& b = S.b;
   InstDyn& d = *S.d;
@@ -2138,14 +2347,20 @@ __device__ __forceinline__ void run_gate_solo(const Solo& S, Smem& sm) {
     return;
   }
   if (st != 1) return;
-  const uint32_t tiles = ceil_tiles<IT>(M);
+  // lane form: kBlock / 2^Mode terms per row
+  const uint32_t tiles = Lane ? (uint32_t)(((uint64_t)M * (1u << Mode) + kBlock * IT - 1) / (kBlock * IT))
+                              : ceil_tiles<IT>(M);
   const uint32_t workers = worker_count(tiles);
   if (blockIdx.x >= workers) return;
   const uint32_t nsh = acc_shards(workers);
   const bool packed = workers <= kTreeMin && b.cap < kPackedCap;
   if (threadIdx.x == 0) pend_reset(sm);
-  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x)
-    gate_tile_any<Mode, IT>(b, d, g, v, M, gen, t, sm);
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    if constexpr (Lane)
+      gates_lane_tile<IT, (Mode > 1 ? Mode : 2)>(b, d, g, v, M, gen, t, sm);
+    else
+      gate_tile_any<Mode, IT>(b, d, g, v, M, gen, t, sm);
+  }
   if (threadIdx.x != 0) return;            // thread 0 holds the block's counts
   if (packed) {
     const uint32_t live = sm.plive, cnt = sm.pcnt;
@@ -2196,6 +2411,17 @@ template <int IT>
 __global__ __launch_bounds__(kBlock) void k_gate3_solo(Solo S) {
   __shared__ Smem sm;
   run_gate_solo<3, IT>(S, sm);
+}
+// lane forms of the multi-rotation ops (smaller sets)
+template <int IT>
+__global__ __launch_bounds__(kBlock) void k_gate2_lane_solo(Solo S) {
+  __shared__ Smem sm;
+  run_gate_solo<2, IT, true>(S, sm);
+}
+template <int IT>
+__global__ __launch_bounds__(kBlock) void k_gate3_lane_solo(Solo S) {
+  __shared__ Smem sm;
+  run_gate_solo<3, IT, true>(S, sm);
 }
 PP_KERNEL_PAIR(k_merge_narrow, MergeNarrowKind)
 PP_KERNEL_PAIR(k_merge_wide1, MergeWide1Kind)

@@ -26,7 +26,7 @@ def gpu():
     stream = torch.cuda.Stream()
     yield dict(torch=torch, stream=stream, handle=int(stream.cuda_stream),
                alloc=_lib.TorchAllocator(0))
-    _lib.pp_set_gate_fusion(3)
+    _lib.pp_set_gate_fusion(3, 0)
 
 
 def prefix(prog, k):
@@ -60,9 +60,9 @@ CASES = {
 }
 
 
-def run_program(gpu, prog, fuse, dtype="f64"):
+def run_program(gpu, prog, fuse, dtype="f64", lanes=0):
     from paper_2512_12094_amd import _lib as L, driver
-    L.pp_set_gate_fusion(fuse)
+    L.pp_set_gate_fusion(fuse, lanes)
     prog.meta.pop("_dprog", None)          # the program is rebuilt with the setting
     res = driver.propagate_program(prog, stream=gpu["handle"], allocator=gpu["alloc"],
                                    keep_terms=True, dtype=dtype)
@@ -82,8 +82,9 @@ def test_fused_program_equals_unfused_and_oracle(gpu, which):
     print(f"[case] fusion program {which}", flush=True)
     plain = run_program(gpu, prog, 1)
     for k in (2, 3):
-        fused = run_program(gpu, prog, k)
-        same(fused, plain, f"{which} fused {k}")
+        for lanes in (0, 1):                   # one thread per term, one lane per member
+            fused = run_program(gpu, prog, k, lanes=lanes)
+            same(fused, plain, f"{which} fused {k} lanes {lanes}")
     ref = O.run_program(prog)
     compare_terms(fused.terms, ref.terms, prog.meta.get("eps", 0.0), what=which)
     compare_expectation(fused.expectation, ref.expectation, ref.terms, what=which)
@@ -97,11 +98,11 @@ def test_fused_layers_equal_unfused(gpu, which):
     prog = CASES[which]()
     print(f"[case] fusion layers {which}", flush=True)
     out = []
-    for fuse in (3, 2, 1):
-        L.pp_set_gate_fusion(fuse)
+    for fuse, lanes in ((3, 1), (2, 1), (3, 0), (1, 1)):
+        L.pp_set_gate_fusion(fuse, lanes)
         out.append(driver.propagate(prog, stream=gpu["handle"], allocator=gpu["alloc"]))
-    same(out[0], out[2], which)
-    same(out[1], out[2], which)
+    for o in out[:3]:
+        same(o, out[3], which)
 
 
 def test_fused_f32_equals_unfused_f32(gpu):
@@ -109,7 +110,8 @@ def test_fused_f32_equals_unfused_f32(gpu):
     print("[case] fusion f32", flush=True)
     plain = run_program(gpu, prog, 1, "f32")
     for k in (2, 3):
-        same(run_program(gpu, prog, k, "f32"), plain, f"f32 fused {k}")
+        for lanes in (0, 1):
+            same(run_program(gpu, prog, k, "f32", lanes), plain, f"f32 fused {k} lanes {lanes}")
 
 
 def test_fused_batch_equals_unfused(gpu):
@@ -160,10 +162,10 @@ def test_fusion_divides_gate_launches(gpu):
 
 def test_fusion_switch_validates():
     from paper_2512_12094_amd import _lib as L
-    for bad in (-1, 4):
+    for bad in ((-1, 1), (4, 1), (3, 2)):
         with pytest.raises(L.PPError):
-            L.pp_set_gate_fusion(bad)
-    L.pp_set_gate_fusion(3)
+            L.pp_set_gate_fusion(*bad)
+    L.pp_set_gate_fusion(3, 0)
 
 
 def test_gate_unit_counters_and_program_info(gpu):

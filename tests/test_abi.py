@@ -54,6 +54,10 @@ def test_argument_errors_need_no_gpu():
     assert L.pp_set_tuning(3, 0, 0, 0, 0) == -1
     assert L.pp_set_tuning(0, 16, 0, 0, 0) == -1
     assert L.pp_set_tuning(0, 0, 0, 0, 65) == -1
+    for bad in ((4, 0), (-1, 0), (3, 2)):
+        assert L.pp_set_gate_fusion(*bad) == -1
+    assert L.pp_set_gate_fusion(3, 0) == 0
+    assert L.pp_program_info(None, None) == -1
 
 
 def test_explicit_group_list_is_validated_on_the_host():

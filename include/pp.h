@@ -227,7 +227,8 @@ int pp_counters(pp_state* s, uint64_t out[2]);
  * out[2] = sum over gates of the live terms that anticommute with the gate,
  * out[3] = strings appended by gates (children whose partner was absent),
  * out[4] = records entering symmetry merges / compactions,
- * out[5] = representatives leaving them,
+ * out[5] = representatives leaving them (in programs, after the sub-layer's
+ *          truncation, which is applied as the merge emits),
  * out[6] = sum over gate launches of the live terms entering the launch
  *          (keys read; a fused launch of two gates reads each key once),
  * out[7] = sum over gate launches of the entering terms that anticommute

@@ -1285,13 +1285,13 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
       ops.push_back(op);
     }
     fuse_gates(ops, first_gate, W);
-    ops.push_back(make_op(OP_MERGE));
-    if (eps[j] > 0.0 || max_weight[j] >= 0) {
-      Op op = make_op(OP_TRUNC);
-      op.eps = eps[j];
-      op.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
-      ops.push_back(op);
+    Op merge = make_op(OP_MERGE);
+    if (eps[j] > 0.0 || max_weight[j] >= 0) {   // the truncation rides with the merge
+      merge.trunc = 1;
+      merge.eps = eps[j];
+      merge.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
     }
+    ops.push_back(merge);
   }
   {
     refs.push_back({ops.size(), tab.size()});

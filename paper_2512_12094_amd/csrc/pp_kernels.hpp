@@ -1698,6 +1698,16 @@ struct MergeWide2Kind {
   }
 };
 
+// A merge that carries its sub-layer's truncation emits a term only if the
+// coefficient as stored (FP32-rounded in FP32 mode) is at least eps and the
+// weight at most wmax, exactly what a truncation pass after the merge keeps.
+__device__ __forceinline__ bool merge_keeps(const InstBuf& b, const Op& op, const uint64_t* x,
+                                            const uint64_t* z, double c) {
+  if (!op.trunc) return true;
+  const double cs = b.f32 ? (double)(float)c : c;
+  return fabs(cs) >= op.eps && !(op.wmax >= 0 && weight(x, z, b.W) > op.wmax);
+}
+
 // Writes one output term at the cursor position `pos` of the other half.
 __device__ __forceinline__ void emit_term(const InstBuf& b, const InstDyn& d, uint32_t pos,
                                  const uint64_t* x, const uint64_t* z, double c) {
@@ -1750,7 +1760,8 @@ struct CollectKind {
     const bool collided = (d.status & ST_COLLISION) != 0;
     const uint32_t nslots = 1u << merge_bits(b, d);
     const int W = b.W;
-    const NextGate ng(b, b.prog[d.pc]);
+    const Op& mop = b.prog[d.pc];
+    const NextGate ng(b, mop);
     uint64_t ox[IT][kMaxW], oz[IT][kMaxW];
     double oc[IT];
     bool ov[IT];
@@ -1774,9 +1785,11 @@ struct CollectKind {
         }
         const Fx f{b.mfx[3 * (size_t)s], b.mfx[3 * (size_t)s + 1], b.mfx[3 * (size_t)s + 2]};
         oc[k] = fx_to_double(f);
-        ov[k] = true;
-        ++mine;
-        if (ng.anti(ox[k], oz[k], W)) ++my_cnt;
+        ov[k] = merge_keeps(b, mop, ox[k], oz[k], oc[k]);
+        if (ov[k]) {
+          ++mine;
+          if (ng.anti(ox[k], oz[k], W)) ++my_cnt;
+        }
       }
       b.mkey[s] = kEmpty64;
       b.mfx[3 * (size_t)s] = 0;
@@ -1814,9 +1827,12 @@ struct CollectKind {
       uint64_t x[kMaxW], z[kMaxW];
       narrow_decode(b, kEmpty64, x, z);
       const uint32_t pos = d.nuniq;
-      if (pos < b.cap) {
-        const Fx f{d.special_fx[0], d.special_fx[1], d.special_fx[2]};
-        emit_term(b, d, pos, x, z, fx_to_double(f));
+      const Fx f{d.special_fx[0], d.special_fx[1], d.special_fx[2]};
+      const double c = fx_to_double(f);
+      if (!merge_keeps(b, b.prog[d.pc], x, z, c)) {
+        // truncated with the merge
+      } else if (pos < b.cap) {
+        emit_term(b, d, pos, x, z, c);
         d.nuniq = pos + 1;
         const NextGate ng(b, b.prog[d.pc]);
         d.acc += 1ull + (ng.anti(x, z, b.W) ? (1ull << 32) : 0ull);
@@ -2077,23 +2093,34 @@ struct PartAggKind {
       if (threadIdx.x == 0) atomicOr(&d.pglobal, 1u);
       return;
     }
-    // emit one term per key
+    // emit one term per key (that the merge's truncation keeps)
     constexpr int kPer = kPartSlots / kBlock;
-    uint32_t mine = 0;
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) mine += s_tk[q * kBlock + threadIdx.x] != kEmpty64 ? 1u : 0u;
-    uint32_t tot;
-    uint32_t off = block_scan(mine, sm.tmp, &tot);
-    if (threadIdx.x == 0) sm.base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
-    __syncthreads();
-    const uint32_t base = sm.base;
-    const NextGate ng(b, b.prog[d.pc]);
-    uint32_t my_cnt = 0;
+    const Op& mop = b.prog[d.pc];
+    uint32_t keep = 0, mine = 0;           // keep: bit q = slot q's term is emitted
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const uint32_t sl = q * kBlock + threadIdx.x;
       const uint64_t key = s_tk[sl];
       if (key == kEmpty64) continue;
+      uint64_t x[kMaxW], z[kMaxW];
+      narrow_decode(b, key, x, z);
+      if (merge_keeps(b, mop, x, z, fx_to_double(Fx{s_tf[3 * sl], s_tf[3 * sl + 1], s_tf[3 * sl + 2]}))) {
+        keep |= 1u << q;
+        ++mine;
+      }
+    }
+    uint32_t tot;
+    uint32_t off = block_scan(mine, sm.tmp, &tot);
+    if (threadIdx.x == 0) sm.base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
+    __syncthreads();
+    const uint32_t base = sm.base;
+    const NextGate ng(b, mop);
+    uint32_t my_cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (!((keep >> q) & 1u)) continue;
+      const uint32_t sl = q * kBlock + threadIdx.x;
+      const uint64_t key = s_tk[sl];
       const uint32_t pos = base + off++;
       if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
       uint64_t x[kMaxW], z[kMaxW];
@@ -2124,13 +2151,19 @@ struct CompactKind {
   __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const View v = view_of(b, d);
     const int W = b.W;
-    const NextGate ng(b, b.prog[d.pc]);
+    const Op& mop = b.prog[d.pc];
+    const NextGate ng(b, mop);
     bool ov[IT];
     uint32_t mine = 0, my_cnt = 0;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       const uint32_t i = t * (kBlock * IT) + k * kBlock + threadIdx.x;
       ov[k] = i < d.M && v.al[i];
+      if (ov[k] && mop.trunc) {            // the merge's truncation
+        uint64_t x[kMaxW], z[kMaxW];
+        load_key(v, i, x, z);
+        ov[k] = merge_keeps(b, mop, x, z, v.getc(i));
+      }
       mine += ov[k] ? 1u : 0u;
     }
     uint32_t tot;

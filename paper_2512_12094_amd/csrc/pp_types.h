@@ -92,6 +92,9 @@ struct Op {
   uint32_t next_gate;    // index of the next GATE op after this one, or kNone32
   int32_t wmax;          // GATE/TRUNC: weight limit (< 0: off)
   uint32_t force_full;   // MERGE with group NONE: merge duplicates (creation)
+  uint32_t trunc;        // MERGE: emit only terms passing eps / wmax (the
+                         // sub-layer's truncation, folded into the merge)
+  uint32_t pad;
   uint32_t nrot;         // GATE: 1; GATES: rotations in the op
   uint64_t px[kMaxW];    // GATE(S): the (first) rotation's Pauli string
   uint64_t pz[kMaxW];

@@ -58,6 +58,7 @@ def parse():
                     help="also run a plain device copy of known size (for PMC scaling)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the gate-at-scale leg")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-sublayers", type=int, default=12)
     ap.add_argument("--serve-count", type=int, default=200)
@@ -155,6 +156,44 @@ def prefix(prog, k):
     k = min(k, len(prog.sublayers))
     return W.Program(f"{prog.name}[:{k}]", prog.n, prog.group, prog.obs,
                      prog.sublayers[len(prog.sublayers) - k:], prog.bloch, dict(prog.meta))
+
+
+def gate_scale_leg(stream, alloc):
+    """The gate kernel where it is not latency-bound: a Z_32 XXZ ring with
+    theta 0.2 and eps 1e-6, weight <= 12, 5 steps (the set grows to
+    8.4 x 10^6 representatives).  One device program; every gate launch
+    timed (HIP events around each run of back-to-back launches); bytes by
+    the same model as the headline roofline."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from paper_2512_12094_amd import workloads as W
+    import torch
+    prog = W.xxz_ring(32, 5, 0.2, 1.5, eps=1e-6, wmax=12, obs=W.sum_ring_pairs(32, "X"),
+                      name="ring32_scale")
+    dp = driver.device_program(prog)
+    out = None
+    for rep in range(2):                       # the first run warms the allocator
+        L.pp_profile(None, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ps = driver.PauliSet.from_program(prog, None, stream, alloc)
+        L.pp_batch_run([ps.h], [dp.h], stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        L.pp_profile(None, 0)
+        wc = L.pp_work_counters(ps.h)
+        prof = L.pp_profile_read(ps.h)
+        n_final = L.pp_num_terms(ps.h)
+        ps.close()
+        gate_n, gate_ms = prof["gate"]
+        gb = gate_bytes(wc)
+        out = dict(workload="Z_32 XXZ ring, theta 0.2, Delta 1.5, eps 1e-6, weight <= 12, 5 steps",
+                   final_representatives=int(n_final), units=wc["propagated"] + wc["merged"],
+                   wall_s=round(wall, 4), value=(wc["propagated"] + wc["merged"]) / wall,
+                   unit="terms/s", gate_launches=gate_n, gate_ms=round(gate_ms, 3),
+                   gate_algorithmic_GBs=round(gb / (gate_ms * 1e-3) / 1e9, 1),
+                   gate_frac_of_hbm=round(gb / (gate_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    return out
 
 
 def batched_leg(stream, alloc, count, sublayers):
@@ -423,6 +462,10 @@ def main():
                  if k in ("rotations_per_string", "representatives", "ms", "algorithmic_GBs",
                           "frac_of_hbm")} for d in (1, 4)]
             print(f"[bench] merge pass done", file=sys.stderr, flush=True)
+        scale = None
+        if not args.no_scale:
+            scale = gate_scale_leg(stream, alloc)
+            print(f"[bench] gate-at-scale leg done", file=sys.stderr, flush=True)
         batched = served = None
         if not args.no_batched:
             tuned_batch = autotune.apply(autotune.class_key("batch", "Zn"))
@@ -454,6 +497,7 @@ def main():
                    "terms_per_step": units // args.steps, "expectation": e},
         "plain_pp": plain,
         "dihedral_pp": dihedral,
+        "gate_at_scale": scale,
         "roofline": roof,
         "kernels": kernels,
         "variants": variants,

@@ -346,11 +346,6 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* s_tmp, uint
   return r;
 }
 
-__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
-  uint32_t t;
-  block_scan(v, s_tmp, &t);
-  return t;
-}
 
 // Makes the wave wait for a returned value (an atomic's result) before it
 // issues anything after this point; emits no instruction of its own.

@@ -494,7 +494,7 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
       const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
       const int lane_it = kind == PP_K_GATE && !big ? lane_items(s->m_hint, nrot) : 0;
-      const int grid = kind == PP_K_PART_AGG    ? kParts
+      const int grid = kind == PP_K_PART_AGG    ? kParts * kPartSplit
                        : kind == PP_K_PART_SORT ? launch_blocks(elems, kPartTile / kBlock)
                        : lane_it                ? launch_blocks(elems << nrot, lane_it)
                                                 : launch_blocks(elems, items_of(kind, big));

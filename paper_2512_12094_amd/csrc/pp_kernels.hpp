@@ -1972,8 +1972,11 @@ struct PartAggKind {
   __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return (merge_served(b, d, true, 1) && use_part(b, d)) ? 1 : 0;
   }
-  // one tile (of kBlock elements at one item per thread) per partition
-  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn&) { return kParts * kBlock; }
+  // kPartSplit tiles (of kBlock elements at one item per thread) per
+  // partition: tile p + kParts * s is share s of partition p
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn&) {
+    return kParts * kPartSplit * kBlock;
+  }
 
   // Walks partition p: each thread takes p's segment of every kBlock-th tile
   // and loads up to kBatch records of it at a time (in flight together);
@@ -2004,7 +2007,9 @@ struct PartAggKind {
     }
   }
 
-  // Partition p.  First pass: every thread adds its records into the
+  // Partition p (or, for a hot partition, share `share` of it: those go
+  // straight to the write-combining pass below and always end in the global
+  // table).  First pass: every thread adds its records into the
   // block's LDS table, stopping as soon as a key finds no room.  If that
   // happened (more than kPartFill keys), the table is cleared and the
   // partition is summed again with the table as a write-combining cache:
@@ -2014,10 +2019,29 @@ struct PartAggKind {
   // partition ends in the global table, never split.  Otherwise the block
   // emits one term per key.
   template <int IT>
-  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t p, Smem& sm) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t pt, Smem& sm) {
     __shared__ uint64_t s_tk[kPartSlots];
     __shared__ uint64_t s_tf[3 * kPartSlots];
-    __shared__ uint32_t s_fill, s_over;
+    __shared__ uint32_t s_fill, s_over, s_size;
+    const uint32_t p = pt % kParts, share = pt / kParts;
+    const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
+    // the partition's record count, from the staging tiles' offsets
+    {
+      uint32_t n = 0;
+      for (uint32_t t = threadIdx.x; t < T; t += kBlock) {
+        const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
+        n += (uint32_t)pre[p + 1] - pre[p];
+      }
+      const uint32_t v1[1] = {n};
+      uint32_t t1[1];
+      block_sums<1>(v1, sm, t1);
+      if (threadIdx.x == 0) s_size = t1[0];
+      __syncthreads();
+    }
+    // a hot partition is summed by kPartSplit blocks through the global
+    // table; any other by its first block alone
+    const bool hot = (uint64_t)s_size * kParts > (uint64_t)kPartHot * d.M;
+    if (!hot && share != 0) return;         // block-uniform
     auto clear = [&]() {
       for (int q = threadIdx.x; q < kPartSlots; q += kBlock) {
         s_tk[q] = kEmpty64;
@@ -2026,25 +2050,27 @@ struct PartAggKind {
       if (threadIdx.x == 0) s_fill = 0;
       __syncthreads();
     };
-    if (threadIdx.x == 0) s_over = 0;
+    if (threadIdx.x == 0) s_over = hot ? 1u : 0u;
     clear();
     bool range = false;
-    each_record(b, d, p, [&](uint64_t key, double c) {
-      if (!part_try_add(s_tk, s_tf, &s_fill, key, fx_from_double(c, &range))) atomicExch(&s_over, 1u);
-    }, &s_over);
+    if (!hot)
+      each_record(b, d, p, [&](uint64_t key, double c) {
+        if (!part_try_add(s_tk, s_tf, &s_fill, key, fx_from_double(c, &range))) atomicExch(&s_over, 1u);
+      }, &s_over);
     __syncthreads();
     const bool flushed = s_over != 0;
     if (flushed) {                         // block-uniform
-      clear();
-      const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
-      uint32_t t = threadIdx.x, r = 0, hi = 0;
+      if (!hot) clear();
+      // a hot partition's share: every kPartSplit-th group of kBlock tiles
+      const uint32_t stride = hot ? kBlock * kPartSplit : kBlock;
+      uint32_t t = (hot ? share * kBlock : 0u) + threadIdx.x, r = 0, hi = 0;
       auto seek = [&]() {                  // next tile with records of p
         while (t < T) {
           const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
           r = pre[p];
           hi = pre[p + 1];
           if (r < hi) return;
-          t += kBlock;
+          t += stride;
         }
       };
       seek();
@@ -2064,7 +2090,7 @@ struct PartAggKind {
           }
           r += got;
           if (r >= hi) {
-            t += kBlock;
+            t += stride;
             seek();
           }
         }

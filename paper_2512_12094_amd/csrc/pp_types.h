@@ -82,6 +82,11 @@ constexpr int kPartTile = 4096;
 constexpr int kParts = 256;
 constexpr int kPartSlots = 4096;
 constexpr int kPartFill = 3072;
+// A partition holding more than kPartHot times the average share of the
+// records is summed by kPartSplit blocks, each over every kPartSplit-th
+// group of tiles, through the global merge table.
+constexpr int kPartSplit = 16;
+constexpr int kPartHot = 4;
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range

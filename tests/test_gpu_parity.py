@@ -75,6 +75,20 @@ def test_config2_prefix(gpu, group):
     check(res, ref, prog, what=f"c2 {group}")
 
 
+def test_config2_full_program_path(gpu):
+    """The benchmarked workload at its full size (all 60 sub-layers), in the
+    launch configuration bench.py times (one device program, default gate
+    fusion and tuning), against the oracle: sets, coefficients, expectation
+    and work counters."""
+    from paper_2512_12094_amd import driver
+    prog = W.config2()
+    print("[case] config 2 full program", flush=True)
+    res = driver.propagate_program(prog, stream=gpu["handle"], allocator=gpu["alloc"],
+                                   keep_terms=True)
+    ref = O.run_program(prog)
+    check(res, ref, prog, what="c2 full")
+
+
 def test_translation_wide_keys(gpu):
     """n = 48 > 32: merge keys do not fit 64 bits (hash + owner compare)."""
     prog = W.xxz_ring(48, 2, 0.3, 1.4, eps=1e-6, obs=W.sum_ring_pairs(48, "X"),

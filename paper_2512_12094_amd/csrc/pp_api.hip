@@ -268,11 +268,13 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   nb.pkey = nullptr;
   nb.pcoef = nullptr;
   nb.ppre = nullptr;
+  nb.pclaim = nullptr;
   if (nb.narrow && s->group != PP_GROUP_PERMUTATION && cap >= kPartMin) {
     const size_t tiles = (cap + kPartTile - 1) / kPartTile;
     ok = ok && (nb.pkey = (uint64_t*)take(sizeof(uint64_t) * tiles * kPartTile));
     ok = ok && (nb.pcoef = (double*)take(sizeof(double) * tiles * kPartTile));
     ok = ok && (nb.ppre = (uint16_t*)take(sizeof(uint16_t) * tiles * (kParts + 1)));
+    ok = ok && (nb.pclaim = (uint32_t*)take(sizeof(uint32_t) * kClaimWords));
   }
   const bool wide = !nb.narrow;
   nb.mown = nullptr;
@@ -494,7 +496,7 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
       const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
       const int lane_it = kind == PP_K_GATE && !big ? lane_items(s->m_hint, nrot) : 0;
-      const int grid = kind == PP_K_PART_AGG    ? kParts * kPartSplit
+      const int grid = kind == PP_K_PART_AGG    ? kParts
                        : kind == PP_K_PART_SORT ? launch_blocks(elems, kPartTile / kBlock)
                        : lane_it                ? launch_blocks(elems << nrot, lane_it)
                                                 : launch_blocks(elems, items_of(kind, big));

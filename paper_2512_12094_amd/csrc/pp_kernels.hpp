@@ -1869,6 +1869,8 @@ struct PartSortKind {
     __shared__ uint32_t s_cnt[kParts];
     const View v = view_of(b, d);
     s_cnt[threadIdx.x] = 0;
+    if (t == 0)                            // pass 2's share claims start at zero
+      for (int q = threadIdx.x; q < kClaimWords; q += kBlock) b.pclaim[q] = 0;
     __syncthreads();
     uint64_t key[IT];
     double c[IT];
@@ -1972,11 +1974,8 @@ struct PartAggKind {
   __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return (merge_served(b, d, true, 1) && use_part(b, d)) ? 1 : 0;
   }
-  // kPartSplit tiles (of kBlock elements at one item per thread) per
-  // partition: tile p + kParts * s is share s of partition p
-  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn&) {
-    return kParts * kPartSplit * kBlock;
-  }
+  // one tile (of kBlock elements at one item per thread) per partition
+  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn&) { return kParts * kBlock; }
 
   // Walks partition p: each thread takes p's segment of every kBlock-th tile
   // and loads up to kBatch records of it at a time (in flight together);
@@ -2007,24 +2006,28 @@ struct PartAggKind {
     }
   }
 
-  // Partition p (or, for a hot partition, share `share` of it: those go
-  // straight to the write-combining pass below and always end in the global
-  // table).  First pass: every thread adds its records into the
-  // block's LDS table, stopping as soon as a key finds no room.  If that
-  // happened (more than kPartFill keys), the table is cleared and the
-  // partition is summed again with the table as a write-combining cache:
-  // the threads advance in rounds of up to kBatch records; a round that
-  // finds the table full flushes it into the global merge table and retries
-  // its leftovers; the last table is flushed too, so every key of such a
-  // partition ends in the global table, never split.  Otherwise the block
-  // emits one term per key.
+  // Partition p.  A cold partition: first pass, every thread adds its
+  // records into the block's LDS table, stopping as soon as a key finds no
+  // room.  If that happened (more than kPartFill keys), the table is cleared
+  // and the partition is summed again with the table as a write-combining
+  // cache: the threads advance in rounds of up to kBatch records; a round
+  // that finds the table full flushes it into the global merge table and
+  // retries its leftovers; the last table is flushed too, so every key of
+  // such a partition ends in the global table, never split.  Otherwise the
+  // block emits one term per key.  A hot partition (more than kPartHot
+  // times the average share of records) is cut into kPartSplit shares that
+  // blocks claim with an atomic counter and sum by the write-combining pass
+  // into the global table: its own block claims shares until none is left,
+  // and every cold block, once its partition is done, claims shares of the
+  // hot partitions it sees in the mask.  No block waits for another; every
+  // share is claimed exactly once, and the claimer sums all of it.
   template <int IT>
-  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t pt, Smem& sm) {
+  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t p, Smem& sm) {
     __shared__ uint64_t s_tk[kPartSlots];
     __shared__ uint64_t s_tf[3 * kPartSlots];
-    __shared__ uint32_t s_fill, s_over, s_size;
-    const uint32_t p = pt % kParts, share = pt / kParts;
+    __shared__ uint32_t s_fill, s_over, s_size, s_claim;
     const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
+    uint32_t* mask = b.pclaim + kParts;
     // the partition's record count, from the staging tiles' offsets
     {
       uint32_t n = 0;
@@ -2038,10 +2041,8 @@ struct PartAggKind {
       if (threadIdx.x == 0) s_size = t1[0];
       __syncthreads();
     }
-    // a hot partition is summed by kPartSplit blocks through the global
-    // table; any other by its first block alone
     const bool hot = (uint64_t)s_size * kParts > (uint64_t)kPartHot * d.M;
-    if (!hot && share != 0) return;         // block-uniform
+    if (hot && threadIdx.x == 0) atomicOr(&mask[p / 32], 1u << (p % 32));
     auto clear = [&]() {
       for (int q = threadIdx.x; q < kPartSlots; q += kBlock) {
         s_tk[q] = kEmpty64;
@@ -2050,25 +2051,17 @@ struct PartAggKind {
       if (threadIdx.x == 0) s_fill = 0;
       __syncthreads();
     };
-    if (threadIdx.x == 0) s_over = hot ? 1u : 0u;
-    clear();
     bool range = false;
-    if (!hot)
-      each_record(b, d, p, [&](uint64_t key, double c) {
-        if (!part_try_add(s_tk, s_tf, &s_fill, key, fx_from_double(c, &range))) atomicExch(&s_over, 1u);
-      }, &s_over);
-    __syncthreads();
-    const bool flushed = s_over != 0;
-    if (flushed) {                         // block-uniform
-      if (!hot) clear();
-      // a hot partition's share: every kPartSplit-th group of kBlock tiles
-      const uint32_t stride = hot ? kBlock * kPartSplit : kBlock;
-      uint32_t t = (hot ? share * kBlock : 0u) + threadIdx.x, r = 0, hi = 0;
-      auto seek = [&]() {                  // next tile with records of p
+    // The write-combining pass over the tiles first, first + stride, ... of
+    // partition q, ending with the table flushed into the global table.
+    auto combine = [&](uint32_t q, uint32_t first, uint32_t stride) {
+      clear();
+      uint32_t t = first, r = 0, hi = 0;
+      auto seek = [&]() {                  // next tile with records of q
         while (t < T) {
           const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
-          r = pre[p];
-          hi = pre[p + 1];
+          r = pre[q];
+          hi = pre[q + 1];
           if (r < hi) return;
           t += stride;
         }
@@ -2081,11 +2074,11 @@ struct PartAggKind {
         if (t < T) {
           const size_t base = (size_t)t * kPartTile;
 #pragma unroll
-          for (int q = 0; q < kBatch; ++q) {
-            if (r + q < hi) {
-              k[q] = b.pkey[base + r + q];
-              v[q] = fx_from_double(b.pcoef[base + r + q], &range);
-              got = q + 1;
+          for (int j = 0; j < kBatch; ++j) {
+            if (r + j < hi) {
+              k[j] = b.pkey[base + r + j];
+              v[j] = fx_from_double(b.pcoef[base + r + j], &range);
+              got = j + 1;
             }
           }
           r += got;
@@ -2096,24 +2089,64 @@ struct PartAggKind {
         }
         uint32_t fail = 0;
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-          if ((uint32_t)q < got && !part_try_add(s_tk, s_tf, &s_fill, k[q], v[q])) fail |= 1u << q;
+        for (int j = 0; j < kBatch; ++j)
+          if ((uint32_t)j < got && !part_try_add(s_tk, s_tf, &s_fill, k[j], v[j])) fail |= 1u << j;
         if (__syncthreads_or(fail != 0)) {
           part_flush(b, d, s_tk, s_tf, &s_fill);
 #pragma unroll
-          for (int q = 0; q < kBatch; ++q)    // at most kBlock * kBatch <= kPartFill keys
-            if ((fail >> q) & 1u) part_try_add(s_tk, s_tf, &s_fill, k[q], v[q]);
+          for (int j = 0; j < kBatch; ++j)    // at most kBlock * kBatch <= kPartFill keys
+            if ((fail >> j) & 1u) part_try_add(s_tk, s_tf, &s_fill, k[j], v[j]);
         }
         if (!__syncthreads_or(t < T)) break;
       }
+      __syncthreads();
+      part_flush(b, d, s_tk, s_tf, &s_fill);
+      if (threadIdx.x == 0) atomicOr(&d.pglobal, 1u);
+    };
+    // claims and sums shares of hot partition q until none is left
+    auto work_shares = [&](uint32_t q) {
+      while (true) {
+        if (threadIdx.x == 0) s_claim = atomicAdd(&b.pclaim[q], 1u);
+        __syncthreads();
+        const uint32_t share = s_claim;
+        __syncthreads();
+        if (share >= (uint32_t)kPartSplit) break;   // block-uniform
+        combine(q, share + kPartSplit * threadIdx.x, kPartSplit * kBlock);
+      }
+    };
+    // the cold blocks, when done, help with the hot partitions they see
+    auto help = [&]() {
+      for (uint32_t w = 0; w < (uint32_t)kParts / 32; ++w) {
+        if (threadIdx.x == 0) s_claim = ld_agent(&mask[w]);
+        __syncthreads();
+        uint32_t bits = s_claim;            // one value for the whole block
+        __syncthreads();
+        while (bits) {
+          const uint32_t q = w * 32 + (31 - __clz(bits));
+          bits &= ~(1u << (q % 32));
+          work_shares(q);
+        }
+      }
+    };
+    if (hot) {
+      work_shares(p);
+      if (range) atomicOr(&d.status, ST_RANGE);
+      return;
+    }
+    if (threadIdx.x == 0) s_over = 0;
+    clear();
+    each_record(b, d, p, [&](uint64_t key, double c) {
+      if (!part_try_add(s_tk, s_tf, &s_fill, key, fx_from_double(c, &range))) atomicExch(&s_over, 1u);
+    }, &s_over);
+    __syncthreads();
+    if (s_over != 0) {                     // block-uniform
+      combine(p, threadIdx.x, kBlock);
+      help();
+      if (range) atomicOr(&d.status, ST_RANGE);
+      return;
     }
     if (range) atomicOr(&d.status, ST_RANGE);
     __syncthreads();
-    if (flushed) {                         // block-uniform
-      part_flush(b, d, s_tk, s_tf, &s_fill);
-      if (threadIdx.x == 0) atomicOr(&d.pglobal, 1u);
-      return;
-    }
     // emit one term per key (that the merge's truncation keeps)
     constexpr int kPer = kPartSlots / kBlock;
     const Op& mop = b.prog[d.pc];
@@ -2150,6 +2183,8 @@ struct PartAggKind {
       if (ng.anti(x, z, b.W)) ++my_cnt;
     }
     add_counts(d, mine, my_cnt, sm);
+    help();
+    if (range) atomicOr(&d.status, ST_RANGE);
   }
   __device__ __forceinline__ static void finish(const InstBuf&, InstDyn&, uint32_t, Smem&) {}
 };

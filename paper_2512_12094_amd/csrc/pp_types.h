@@ -83,10 +83,12 @@ constexpr int kParts = 256;
 constexpr int kPartSlots = 4096;
 constexpr int kPartFill = 3072;
 // A partition holding more than kPartHot times the average share of the
-// records is summed by kPartSplit blocks, each over every kPartSplit-th
-// group of tiles, through the global merge table.
-constexpr int kPartSplit = 16;
+// records is cut into kPartSplit shares (share s: the staging tiles t with
+// t mod kPartSplit = s), summed through the global merge table by whichever
+// blocks claim them.
+constexpr int kPartSplit = 32;
 constexpr int kPartHot = 4;
+constexpr int kClaimWords = kParts + kParts / 32;
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
@@ -132,6 +134,8 @@ struct InstBuf {
   uint64_t* pkey;        // [tiles * kPartTile] representative keys
   double* pcoef;         // [tiles * kPartTile] coefficients (FP64)
   uint16_t* ppre;        // [tiles][kParts + 1] exclusive offsets per partition
+  uint32_t* pclaim;      // [kParts] next share of each hot partition, then the
+                         // kParts / 32 words of the hot-partition mask
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;

@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import subprocess
@@ -59,6 +60,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the gate-at-scale leg")
+    ap.add_argument("--no-ising", action="store_true", help="skip the Ising layers leg")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-sublayers", type=int, default=12)
     ap.add_argument("--serve-count", type=int, default=200)
@@ -194,6 +196,41 @@ def gate_scale_leg(stream, alloc):
                    gate_algorithmic_GBs=round(gb / (gate_ms * 1e-3) / 1e9, 1),
                    gate_frac_of_hbm=round(gb / (gate_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
     return out
+
+
+def ising_layers_leg(stream, alloc, n=12, layers=(2, 4, 6, 8, 10), dt=0.25):
+    """Sec. IV's tilted-field Ising ring (g_x = 1.4, g_z = 0.9045, O = Z at the
+    middle site), untruncated: final set size and time per propagation
+    against the number of Trotter layers, merged after every sub-layer,
+    merged after every full layer (the paper's schedule), and plain PP."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from paper_2512_12094_amd import workloads as W
+    import torch
+    rows = []
+    for nl in layers:
+        row = dict(layers=nl)
+        for mode in ("sublayer", "layer", "plain"):
+            prog = W.tilted_ising_ring(n, nl, dt, merge="layer" if mode == "layer" else "sublayer")
+            group = "none" if mode == "plain" else None
+            dp = driver.device_program(prog)
+            best = None
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ps = driver.PauliSet.from_program(prog, group, stream, alloc)
+                L.pp_batch_run([ps.h], [dp.h], stream)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                terms = L.pp_num_terms(ps.h)
+                ps.close()
+                best = wall if best is None else min(best, wall)
+            dp.close()
+            row[mode] = dict(terms=int(terms), ms=round(best * 1e3, 3))
+        rows.append(row)
+    neck = sum(4 ** math.gcd(j, n) for j in range(1, n + 1)) // n
+    return dict(workload=f"tilted-field Ising ring n={n}, dt={dt}, untruncated",
+                necklaces=neck, rows=rows)
 
 
 def batched_leg(stream, alloc, count, sublayers):
@@ -462,6 +499,10 @@ def main():
                  if k in ("rotations_per_string", "representatives", "ms", "algorithmic_GBs",
                           "frac_of_hbm")} for d in (1, 4)]
             print(f"[bench] merge pass done", file=sys.stderr, flush=True)
+        ising = None
+        if not args.no_ising:
+            ising = ising_layers_leg(stream, alloc)
+            print(f"[bench] Ising layers leg done", file=sys.stderr, flush=True)
         scale = None
         if not args.no_scale:
             scale = gate_scale_leg(stream, alloc)
@@ -498,6 +539,7 @@ def main():
         "plain_pp": plain,
         "dihedral_pp": dihedral,
         "gate_at_scale": scale,
+        "ising_layers": ising,
         "roofline": roof,
         "kernels": kernels,
         "variants": variants,

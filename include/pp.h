@@ -287,12 +287,19 @@ const char* pp_last_error(void);
  * final Bloch vector.  The library uploads it once.  Every sub-layer runs
  * damp -> gates (exact merge + truncation after each) -> symmetry merge ->
  * truncation, and the program ends with the expectation value.
+ * merge_after: NULL (merge after every sub-layer) or n_sub flags; a 0 skips
+ * sub-layer j's symmetry merge (Algorithm 1 step 2b) and keeps only its
+ * truncation, as when merging after a full Trotter layer of several
+ * symmetric sub-layers (Sec. IV, Ising example): the set then holds
+ * non-representative strings until the next merge, and the expectation is
+ * the same (Theorem 1 needs only a symmetric state).
  */
 int pp_program_create(pp_program** out, int n_qubits, size_t n_sub,
                       const size_t* sub_start, const uint64_t* gate_x,
                       const uint64_t* gate_z, const double* theta,
                       const double* eps, const int* max_weight,
-                      const double* depol_p, const double bloch_xyz[3]);
+                      const double* depol_p, const double bloch_xyz[3],
+                      const int* merge_after);
 void pp_program_destroy(pp_program* p);
 
 /*

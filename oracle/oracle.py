@@ -231,7 +231,8 @@ def run_program(prog, group: str | None = None, max_sublayers: int | None = None
         for g in reversed(sub.gates):
             o.apply_gate(g.x, g.z, g.theta, sub.eps, sub.wmax)
             peak = max(peak, o.size())
-        o.merge()                               # step 2b
+        if getattr(sub, "merge", True):         # step 2b (deferred: Sec. IV's
+            o.merge()                           # merge after a full Trotter layer)
         o.truncate(sub.eps, sub.wmax)
         sizes.append(o.size())
         done += 1

@@ -79,7 +79,8 @@ def lib():
     L.pp_destroy.restype = None
     L.pp_program_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_size_t,
                                     ctypes.POINTER(ctypes.c_size_t), _u64p, _u64p, _f64p,
-                                    _f64p, ctypes.POINTER(ctypes.c_int), _f64p, _f64p]
+                                    _f64p, ctypes.POINTER(ctypes.c_int), _f64p, _f64p,
+                                    ctypes.POINTER(ctypes.c_int)]
     L.pp_program_destroy.argtypes = [_vp]
     L.pp_program_destroy.restype = None
     L.pp_program_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -268,7 +269,8 @@ def pp_destroy(h):
         lib().pp_destroy(h)
 
 
-def pp_program_create(n, sub_start, gate_x, gate_z, theta, eps, max_weight, depol_p, bloch):
+def pp_program_create(n, sub_start, gate_x, gate_z, theta, eps, max_weight, depol_p, bloch,
+                      merge_after=None):
     W = (n + 63) // 64
     ss = np.ascontiguousarray(sub_start, dtype=np.uint64)
     x, xp = _u64(np.asarray(gate_x, dtype=np.uint64).reshape(-1, W))
@@ -278,10 +280,14 @@ def pp_program_create(n, sub_start, gate_x, gate_z, theta, eps, max_weight, depo
     w = np.ascontiguousarray(max_weight, dtype=np.int32)
     p, pq = _f64(depol_p)
     b, bp = _f64(np.asarray(bloch, dtype=np.float64))
+    mp = None
+    if merge_after is not None:
+        m = np.ascontiguousarray(merge_after, dtype=np.int32)
+        mp = m.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     h = _vp()
     _check(lib().pp_program_create(
         ctypes.byref(h), n, len(ss) - 1, ss.ctypes.data_as(ctypes.POINTER(ctypes.c_size_t)),
-        xp, zp, tp, ep, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), pq, bp))
+        xp, zp, tp, ep, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), pq, bp, mp))
     return h
 
 

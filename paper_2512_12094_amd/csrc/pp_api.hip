@@ -1242,7 +1242,7 @@ int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef, size_t 
 int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t* sub_start,
                       const uint64_t* gate_x, const uint64_t* gate_z, const double* theta,
                       const double* eps, const int* max_weight, const double* depol_p,
-                      const double bloch_xyz[3]) {
+                      const double bloch_xyz[3], const int* merge_after) {
   if (!out) return fail(PP_EINVAL, "out is NULL");
   *out = nullptr;
   if (n_qubits < 1 || n_qubits > 128) return fail(PP_EINVAL, "n_qubits out of range");
@@ -1287,13 +1287,21 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
       ops.push_back(op);
     }
     fuse_gates(ops, first_gate, W);
-    Op merge = make_op(OP_MERGE);
-    if (eps[j] > 0.0 || max_weight[j] >= 0) {   // the truncation rides with the merge
-      merge.trunc = 1;
-      merge.eps = eps[j];
-      merge.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
+    const bool trunc = eps[j] > 0.0 || max_weight[j] >= 0;
+    if (!merge_after || merge_after[j]) {
+      Op merge = make_op(OP_MERGE);
+      if (trunc) {                          // the truncation rides with the merge
+        merge.trunc = 1;
+        merge.eps = eps[j];
+        merge.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
+      }
+      ops.push_back(merge);
+    } else if (trunc) {                     // merge deferred: truncation alone
+      Op op = make_op(OP_TRUNC);
+      op.eps = eps[j];
+      op.wmax = max_weight[j] < 0 ? -1 : max_weight[j];
+      ops.push_back(op);
     }
-    ops.push_back(merge);
   }
   {
     refs.push_back({ops.size(), tab.size()});

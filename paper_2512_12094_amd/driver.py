@@ -38,6 +38,7 @@ class LayerArrays:
     eps: float
     wmax: int
     p: float
+    merge: bool = True
 
 
 def heisenberg_layers(prog: Program):
@@ -54,7 +55,8 @@ def heisenberg_layers(prog: Program):
         gates = list(reversed(sub.gates))
         out.append(LayerArrays(_rows([g.x for g in gates], W), _rows([g.z for g in gates], W),
                                np.array([g.theta for g in gates], dtype=np.float64),
-                               float(sub.eps), int(sub.wmax), float(sub.p)))
+                               float(sub.eps), int(sub.wmax), float(sub.p),
+                               bool(getattr(sub, "merge", True))))
     prog.meta["_heis"] = out
     return out
 
@@ -146,7 +148,8 @@ def run_layers(ps: PauliSet, layers, record_sizes=False):
         if la.p > 0:
             ps.truncate(0.0, -1, la.p)
         ps.apply_layer(la)
-        ps.merge()
+        if la.merge:
+            ps.merge()
         if la.eps > 0 or la.wmax >= 0:
             ps.truncate(la.eps, la.wmax, 0.0)
         if record_sizes:
@@ -188,7 +191,8 @@ def program_arrays(prog: Program):
     eps = np.array([la.eps for la in layers], dtype=np.float64)
     wmax = np.array([la.wmax for la in layers], dtype=np.int32)
     p = np.array([la.p for la in layers], dtype=np.float64)
-    return starts, gx, gz, th, eps, wmax, p
+    merge = np.array([1 if la.merge else 0 for la in layers], dtype=np.int32)
+    return starts, gx, gz, th, eps, wmax, p, merge
 
 
 class DeviceProgram:
@@ -196,8 +200,9 @@ class DeviceProgram:
 
     def __init__(self, prog: Program):
         self.prog = prog
-        starts, gx, gz, th, eps, wmax, p = program_arrays(prog)
-        self.h = L.pp_program_create(prog.n, starts, gx, gz, th, eps, wmax, p, prog.bloch)
+        starts, gx, gz, th, eps, wmax, p, merge = program_arrays(prog)
+        self.h = L.pp_program_create(prog.n, starts, gx, gz, th, eps, wmax, p, prog.bloch,
+                                     merge_after=merge)
 
     def close(self):
         if self.h:

@@ -51,6 +51,9 @@ class SubLayer:
     wmax: int = -1          # drop Pauli weight > wmax (<0 = off)
     p: float = 0.0          # depolarising strength per qubit for this sub-layer
     m: int = 1              # exact merge (and truncation) after every m gates
+    merge: bool = True      # symmetry merge after this sub-layer (Alg. 1 step 2b);
+                            # False defers it to a later sub-layer (Sec. IV merges
+                            # only after a full Trotter layer)
 
 
 @dataclass
@@ -191,18 +194,25 @@ def heisenberg_all_to_all(n: int, steps: int, theta: float, *, eps=0.0, wmax=-1,
 
 
 def tilted_ising_ring(n: int, steps: int, dt: float, gx: float = 1.4,
-                      gz: float = 0.9045, **kw) -> Program:
+                      gz: float = 0.9045, merge: str = "sublayer", **kw) -> Program:
     """Trotterised tilted-field Ising ring (Sec. IV): per step the ZZ bonds,
     then the Z field, then the X field, as three Z_n-symmetric sub-layers.
-    exp(-i dt Z_iZ_j) = R_ZZ(2dt); exp(-i h dt P) = R_P(2 h dt)."""
+    exp(-i dt Z_iZ_j) = R_ZZ(2dt); exp(-i h dt P) = R_P(2 h dt).
+    merge="sublayer" merges after every sub-layer; merge="layer" only after
+    a full Trotter step, as the paper's Ising example does (Sec. IV): in
+    Heisenberg order a step ends with its first sub-layer in time, ZZ.
+    kw (eps, wmax, p) sets every sub-layer's truncation and noise."""
+    if merge not in ("sublayer", "layer"):
+        raise ValueError("merge is 'sublayer' or 'layer'")
     subs = []
     for _ in range(steps):
-        subs.append(ring_sublayer(n, "Z", 2.0 * dt))
-        subs.append(field_sublayer(n, "Z", 2.0 * gz * dt))
-        subs.append(field_sublayer(n, "X", 2.0 * gx * dt))
+        subs.append(ring_sublayer(n, "Z", 2.0 * dt, **kw))
+        subs.append(field_sublayer(n, "Z", 2.0 * gz * dt, merge=merge == "sublayer", **kw))
+        subs.append(field_sublayer(n, "X", 2.0 * gx * dt, merge=merge == "sublayer", **kw))
     mid = (n + 1) // 2 - 1   # qubit ceil(n/2) in 1-based numbering
     return Program("ising", n, GROUP_ZN, [(*one_site("Z", mid), 1.0)], subs,
-                   ZERO_STATE, dict(steps=steps, dt=dt, gx=gx, gz=gz))
+                   ZERO_STATE, dict(steps=steps, dt=dt, gx=gx, gz=gz, merge=merge,
+                                    eps=kw.get("eps", 0.0)))
 
 
 def torus_distance(i: int, j: int, lx: int, ly: int) -> float:

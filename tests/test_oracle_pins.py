@@ -359,6 +359,32 @@ def test_saturation_below_necklace_count():
     assert (0, 0) not in res.terms
 
 
+def test_merge_after_full_trotter_layer_matches_dense():
+    """Sec. IV's Ising example merges only after a full Trotter layer (three
+    symmetric sub-layers).  The layer is symmetric as a whole, so after its
+    merge the representatives carry the dense orbit sums, exactly as with a
+    merge after every sub-layer; in between, the set holds
+    non-representative strings (more terms than the merged schedule)."""
+    n = 5
+    layer = W.tilted_ising_ring(n, 3, 0.3, merge="layer")
+    sub = W.tilted_ising_ring(n, 3, 0.3, merge="sublayer")
+    a = O.run_program(layer)
+    b = O.run_program(sub)
+    Od = dense.heisenberg(layer)
+    coeffs = {k: v.real for k, v in dense.pauli_coefficients(Od, n).items()}
+    want = orbit_sums(coeffs, n, "Zn")
+    assert_terms_match(a.terms, {k: v for k, v in want.items() if abs(v) > 1e-13})
+    assert_terms_match(a.terms, b.terms)
+    e = dense.expectation(Od, layer.bloch, n)
+    assert abs(a.expectation - e) < 1e-12 and abs(b.expectation - e) < 1e-12
+    # merges happen at sub-layers 3, 6, 9 (Heisenberg order), where both
+    # schedules hold the same representatives; before them the deferred
+    # schedule holds at least as many strings
+    assert a.sizes[2::3] == b.sizes[2::3]
+    assert all(x >= y for x, y in zip(a.sizes, b.sizes))
+    assert any(x > y for x, y in zip(a.sizes, b.sizes))
+
+
 def test_total_spin_is_invariant_under_isotropic_layers():
     """S^2 commutes with every exp(-i theta sum_{i<j} P_i P_j): at p = 0 and
     without truncation the merged set returns to {I, XX, YY, ZZ} with the

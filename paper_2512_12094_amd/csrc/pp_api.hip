@@ -290,13 +290,13 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
     return fail(PP_ENOMEM, "allocation of a term store of capacity " + std::to_string(cap) +
                                " failed");
   }
-  HIP_TRY(hipMemsetAsync(nb.gtab, 0, sizeof(uint64_t) * ng, s->stream));
-  HIP_TRY(hipMemsetAsync(nb.mkey, 0xFF, sizeof(uint64_t) * nm, s->stream));
-  HIP_TRY(hipMemsetAsync(nb.mfx, 0, 3 * sizeof(uint64_t) * nm, s->stream));
-  HIP_TRY(hipMemsetAsync(nb.accs, 0, kAccBytes, s->stream));
-  if (wide) HIP_TRY(hipMemsetAsync(nb.mown, 0xFF, sizeof(uint32_t) * nm, s->stream));
-  for (int h = 0; h < 2; ++h)
-    for (int p = 0; p < 2; ++p) HIP_TRY(hipMemsetAsync(nb.alive[h][p], 0, cap, s->stream));
+  // the tables' initial state in one launch (instead of a fill per array)
+  const uint64_t init_elems = std::max<uint64_t>({ng, nm, cap / 8});
+  const int init_grid = (int)std::min<uint64_t>(
+      std::max<uint64_t>(1, (init_elems + 4 * kBlock - 1) / (4 * kBlock)), 2048);
+  hipLaunchKernelGGL(k_init_store, dim3(init_grid), dim3(kBlock), 0, s->stream, nb, (uint64_t)ng,
+                     (uint64_t)nm, wide ? 1u : 0u);
+  HIP_TRY(hipGetLastError());
   *b = nb;
   *allocs = std::move(got);
   return PP_OK;

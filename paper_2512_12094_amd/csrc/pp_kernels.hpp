@@ -2530,6 +2530,32 @@ __global__ __launch_bounds__(kBlock) void k_part_agg_solo(Solo S) {
 }
 
 // ---------------------------------------------------------------------------
+// Initial state of a new store's tables, in one launch (grid-stride): gate
+// table slots free (generation 0), merge keys empty, merge sums, count
+// accumulators and (wide keys) slot owners cleared, the four alive arrays
+// zero (written as 64-bit words; the allocations are 8-byte aligned).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_init_store(InstBuf nb, uint64_t ng, uint64_t nm,
+                                                       uint32_t wide) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (uint64_t i = first; i < ng; i += stride) nb.gtab[i] = 0;
+  for (uint64_t i = first; i < nm; i += stride) {
+    nb.mkey[i] = kEmpty64;
+    nb.mfx[3 * i] = nb.mfx[3 * i + 1] = nb.mfx[3 * i + 2] = 0;
+    if (wide) nb.mown[i] = kNone32;
+  }
+  for (uint64_t i = first; i < kAccBytes / sizeof(uint64_t); i += stride) nb.accs[i] = 0;
+  const uint64_t words = nb.cap / 8;
+  for (uint64_t i = first; i < words; i += stride)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) reinterpret_cast<uint64_t*>(nb.alive[a >> 1][a & 1])[i] = 0;
+  for (uint64_t i = 8 * words + first; i < nb.cap; i += stride)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) nb.alive[a >> 1][a & 1][i] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Host-driven growth / compaction of one instance into a new store.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_grow(InstBuf src, InstBuf dst, InstDyn* dp,

@@ -230,7 +230,7 @@ int pp_counters(pp_state* s, uint64_t out[2]);
  * out[5] = representatives leaving them (in programs, after the sub-layer's
  *          truncation, which is applied as the merge emits),
  * out[6] = sum over gate launches of the live terms entering the launch
- *          (keys read; a fused launch of two gates reads each key once),
+ *          (keys read; a fused launch of several rotations reads each key once),
  * out[7] = sum over gate launches of the entering terms that anticommute
  *          with one of its rotations (coefficients read and written once).
  * Without fusion out[6] = out[0] and out[7] = out[2].  These are the unit

@@ -218,7 +218,8 @@ int read_counters(pp_state* s, uint64_t out[8]) {
   int rc = read_dyn(s);
   if (rc) return rc;
   std::vector<uint64_t> st(kStatBytes / sizeof(uint64_t));
-  HIP_TRY(hipMemcpy(st.data(), s->d_stats, kStatBytes, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpyAsync(st.data(), s->d_stats, kStatBytes, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
   uint64_t sum[kStatKinds] = {0, 0, 0};
   for (int k = 0; k < kStatKinds; ++k)
     for (int h = 0; h < kAccShards; ++h) sum[k] += st[(size_t)(k * kAccShards + h) * kLineU64];

@@ -122,7 +122,8 @@ def run_steps(prog, group, steps, stream, alloc, profile, mode="program"):
     return wall, totals, kern, e
 
 
-MERGE_KINDS = ("merge_narrow", "merge_wide1", "merge_wide2", "part_sort", "part_agg",
+MERGE_KINDS = ("merge_narrow", "merge_wide1", "merge_wide2", "part_hist", "part_scan",
+               "part_scatter", "part_agg",
                "merge_collect")
 
 

@@ -238,6 +238,18 @@ int pp_counters(pp_state* s, uint64_t out[2]);
  */
 int pp_work_counters(pp_state* s, uint64_t out[8]);
 
+/*
+ * Statistics of the partitioned merge (the path large merges of 64-bit keys
+ * take, except S_n), cumulative since creation: out[0] = partitioned merges
+ * run, out[1] = buckets split over several blocks because a few
+ * representatives hold more than twice a bucket's average share of the
+ * records, out[2] = buckets with more distinct representatives than one LDS
+ * table holds (summed in several selector passes), out[3] = representatives
+ * whose sums went through the global merge table (split buckets and
+ * overfull passes).  Synchronises.  NULL arguments: PP_EINVAL.
+ */
+int pp_merge_stats(pp_state* s, uint64_t out[4]);
+
 /* Kernel kinds for per-kernel timing. */
 enum {
   PP_K_GATE = 0,          /* one rotation + exact merge + truncation     */
@@ -248,9 +260,11 @@ enum {
   PP_K_COMPACT = 5,       /* plain-PP layer end: drop dead entries       */
   PP_K_SCAN = 6,          /* damping / truncation / recount / expectation */
   PP_K_GROW = 7,          /* store growth                                */
-  PP_K_PART_SORT = 8,     /* partitioned merge, pass 1: sort tiles       */
-  PP_K_PART_AGG = 9,      /* partitioned merge, pass 2: LDS exact sums   */
-  PP_KERNEL_KINDS = 10
+  PP_K_PART_HIST = 8,     /* partitioned merge 1: bucket counts per tile   */
+  PP_K_PART_SCAN = 9,     /* partitioned merge 2: offsets, bucket bases    */
+  PP_K_PART_SCATTER = 10, /* partitioned merge 3: bucket-contiguous stage  */
+  PP_K_PART_AGG = 11,     /* partitioned merge 4: LDS exact sums per bucket */
+  PP_KERNEL_KINDS = 12
 };
 
 /*

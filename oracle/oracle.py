@@ -78,6 +78,9 @@ def lib():
         L.orc_create_torus.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_multiply.restype = ctypes.c_int
         L.orc_multiply.argtypes = [ctypes.c_int] + [_u64p] * 6
+        L.orc_merge_records.restype = ctypes.c_size_t
+        L.orc_merge_records.argtypes = [ctypes.c_int, ctypes.c_int, _u64p, _u64p, _f64p,
+                                        ctypes.c_size_t, _u64p, _u64p, _f64p]
         L.orc_exact_sum.restype = ctypes.c_double
         L.orc_exact_sum.argtypes = [_f64p, ctypes.c_size_t]
         L.orc_int_less.restype = ctypes.c_int
@@ -126,6 +129,25 @@ def multiply(n: int, a, b):
 def exact_sum(values) -> float:
     v = np.ascontiguousarray(values, dtype=np.float64)
     return lib().orc_exact_sum(v.ctypes.data_as(_f64p), len(v))
+
+
+def merge_records(n: int, group: str, x, z, c) -> dict:
+    """Algorithm 1 step 1 on raw rows: {representative: exact sum of every
+    row of its orbit, repeated rows counted as separate addends}.  x, z:
+    arrays of shape (m,) or (m, W) of uint64; c: m doubles."""
+    W = (n + 63) // 64
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint64).reshape(-1, W))
+    za = np.ascontiguousarray(np.asarray(z, dtype=np.uint64).reshape(-1, W))
+    ca = np.ascontiguousarray(c, dtype=np.float64)
+    m = len(ca)
+    ox = np.zeros((max(m, 1), W), dtype=np.uint64)
+    oz = np.zeros((max(m, 1), W), dtype=np.uint64)
+    oc = np.zeros(max(m, 1), dtype=np.float64)
+    k = lib().orc_merge_records(n, GROUP_CODE[group], xa.ctypes.data_as(_u64p),
+                                za.ctypes.data_as(_u64p), ca.ctypes.data_as(_f64p), m,
+                                ox.ctypes.data_as(_u64p), oz.ctypes.data_as(_u64p),
+                                oc.ctypes.data_as(_f64p))
+    return {(_join(ox[i]), _join(oz[i])): float(oc[i]) for i in range(k)}
 
 
 def int_less(n: int, a, b) -> bool:

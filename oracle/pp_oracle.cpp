@@ -481,6 +481,29 @@ int orc_multiply(int n, const uint64_t* ax, const uint64_t* az,
   return k;
 }
 
+// Algorithm 1 step 1 on a stream of raw rows (x, z, c): every row is one
+// addend of its orbit's sum (repeated rows included, not added together
+// first); per representative the exact sum of its addends, rounded once.
+// Writes the representatives in container order to ox/oz (m rows of W
+// words, caller-allocated) and oc; returns how many.
+size_t orc_merge_records(int n, int group, const uint64_t* x, const uint64_t* z,
+                         const double* c, size_t m, uint64_t* ox, uint64_t* oz, double* oc) {
+  const int W = (n + 63) / 64;
+  std::map<Pauli, std::vector<double>> addends;
+  for (size_t r = 0; r < m; ++r)
+    addends[canon(load(x + r * W, z + r * W, n), n, group)].push_back(c[r]);
+  size_t k = 0;
+  for (const auto& [rep, v] : addends) {
+    for (int w = 0; w < W; ++w) {
+      ox[k * W + w] = rep.x[w];
+      oz[k * W + w] = rep.z[w];
+    }
+    oc[k] = exact_sum(v);
+    ++k;
+  }
+  return k;
+}
+
 double orc_exact_sum(const double* v, size_t n) {
   return exact_sum(std::vector<double>(v, v + n));
 }

@@ -73,6 +73,7 @@ def lib():
     L.pp_counters.argtypes = [_vp, _u64p]
     L.pp_set_max_terms.argtypes = [_vp, ctypes.c_size_t]
     L.pp_work_counters.argtypes = [_vp, _u64p]
+    L.pp_merge_stats.argtypes = [_vp, _u64p]
     L.pp_profile.argtypes = [_vp, ctypes.c_int]
     L.pp_profile_read.argtypes = [_vp, _u64p, _f64p]
     L.pp_destroy.argtypes = [_vp]
@@ -237,7 +238,7 @@ def pp_counters(h):
 
 
 KERNELS = ["gate", "merge_narrow", "merge_wide1", "merge_wide2", "merge_collect", "compact",
-           "scan", "grow", "part_sort", "part_agg"]
+           "scan", "grow", "part_hist", "part_scan", "part_scatter", "part_agg"]
 
 
 def pp_work_counters(h):
@@ -245,6 +246,13 @@ def pp_work_counters(h):
     _check(lib().pp_work_counters(h, out))
     keys = ["propagated", "merged", "anticommuting", "appended", "merge_in", "merge_out",
             "gate_key_reads", "gate_coef_rw"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def pp_merge_stats(h):
+    out = (ctypes.c_uint64 * 4)()
+    _check(lib().pp_merge_stats(h, out))
+    keys = ["partitioned_merges", "split_buckets", "selector_buckets", "global_keys"]
     return {k: int(v) for k, v in zip(keys, out)}
 
 

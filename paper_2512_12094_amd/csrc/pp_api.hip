@@ -21,6 +21,7 @@
 
 #include "pp.h"
 #include "pp_kernels.hpp"
+#include "pp_merge.hpp"
 #include "pp_types.h"
 
 using namespace pp;
@@ -266,16 +267,25 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   ok = ok && (nb.mfx = (uint64_t*)take(3 * sizeof(uint64_t) * nm));
   ok = ok && (nb.accs = (uint64_t*)take(kAccBytes));
   // staging of the partitioned merge (narrow keys, not S_n, large stores)
-  nb.pkey = nullptr;
-  nb.pcoef = nullptr;
-  nb.ppre = nullptr;
-  nb.pclaim = nullptr;
+  nb.phash = nullptr;
+  nb.pstage = nullptr;
+  nb.phist = nullptr;
+  nb.ptot = nullptr;
+  nb.pbase = nullptr;
+  nb.pwork = nullptr;
+  nb.plist = nullptr;
+  nb.pmaxbits = 0;
   if (nb.narrow && s->group != PP_GROUP_PERMUTATION && cap >= kPartMin) {
-    const size_t tiles = (cap + kPartTile - 1) / kPartTile;
-    ok = ok && (nb.pkey = (uint64_t*)take(sizeof(uint64_t) * tiles * kPartTile));
-    ok = ok && (nb.pcoef = (double*)take(sizeof(double) * tiles * kPartTile));
-    ok = ok && (nb.ppre = (uint16_t*)take(sizeof(uint16_t) * tiles * (kParts + 1)));
-    ok = ok && (nb.pclaim = (uint32_t*)take(sizeof(uint32_t) * kClaimWords));
+    nb.pmaxbits = part_bits(cap, kPartMaxBits);
+    const size_t P = size_t(1) << nb.pmaxbits;
+    const size_t tiles = (cap + kPartTileRec - 1) / kPartTileRec;
+    ok = ok && (nb.phash = (uint64_t*)take(sizeof(uint64_t) * cap));
+    ok = ok && (nb.pstage = (uint64_t*)take(2 * sizeof(uint64_t) * cap));
+    ok = ok && (nb.phist = (uint32_t*)take(sizeof(uint32_t) * tiles * P));
+    ok = ok && (nb.ptot = (uint32_t*)take(sizeof(uint32_t) * P));
+    ok = ok && (nb.pbase = (uint32_t*)take(sizeof(uint32_t) * (P + 1)));
+    ok = ok && (nb.pwork = (uint32_t*)take(sizeof(uint32_t) * 2 * P));
+    ok = ok && (nb.plist = (uint32_t*)take(sizeof(uint32_t) * nm));
   }
   const bool wide = !nb.narrow;
   nb.mown = nullptr;
@@ -358,7 +368,18 @@ int lane_items(uint32_t hint, uint32_t nrot) {
   return 0;
 }
 
-SoloFn solo_of(int kind, bool big, uint32_t nrot = 1, int lane_it = 0) {
+// The histogram pass canonicalises, so it is built per group.
+SoloFn part_hist_of(int group) {
+  switch (group) {
+    case PP_GROUP_TRANSLATION: return &k_part_hist<1>;
+    case PP_GROUP_DIHEDRAL: return &k_part_hist<3>;
+    case PP_GROUP_TORUS: return &k_part_hist<4>;
+    case PP_GROUP_EXPLICIT: return &k_part_hist<5>;
+    default: return &k_part_hist<0>;
+  }
+}
+
+SoloFn solo_of(int kind, bool big, uint32_t nrot = 1, int lane_it = 0, int group = 0) {
   const int gi = gate_items(big), si = stream_items(big);
   switch (kind) {
     case PP_K_GATE:
@@ -372,8 +393,10 @@ SoloFn solo_of(int kind, bool big, uint32_t nrot = 1, int lane_it = 0) {
     case PP_K_MERGE_WIDE2: return PP_PICK(k_merge_wide2_solo, si);
     case PP_K_MERGE_COLLECT: return PP_PICK(k_merge_collect_solo, si);
     case PP_K_COMPACT: return PP_PICK(k_compact_solo, si);
-    case PP_K_PART_SORT: return &k_part_sort_solo;
-    case PP_K_PART_AGG: return &k_part_agg_solo;
+    case PP_K_PART_HIST: return part_hist_of(group);
+    case PP_K_PART_SCAN: return &k_part_scan;
+    case PP_K_PART_SCATTER: return &k_part_scatter;
+    case PP_K_PART_AGG: return &k_part_agg;
     default: return PP_PICK(k_scan_op_solo, si);
   }
 }
@@ -439,6 +462,42 @@ int ensure_ops(pp_state* s, size_t nops, size_t ntab) {
   return PP_OK;
 }
 
+bool is_part_kind(int kind) {
+  return kind == PP_K_PART_HIST || kind == PP_K_PART_SCAN || kind == PP_K_PART_SCATTER ||
+         kind == PP_K_PART_AGG;
+}
+
+// Grids of the partitioned merge's kernels, sized for the store's capacity
+// (the device takes its sizes from the live record count and idles the
+// surplus blocks): tiles of kPartTileRec records, one column band of 64
+// buckets per scan block, one aggregation item per block up to 3P/2.
+int part_grid(const InstBuf& b, int kind) {
+  const uint64_t P = uint64_t(1) << std::max<uint32_t>(b.pmaxbits, kPartMinBits);
+  const uint64_t tiles = (b.cap + kPartTileRec - 1) / kPartTileRec;
+  uint64_t g = kind == PP_K_PART_SCAN ? P / 64 : kind == PP_K_PART_AGG ? 3 * P / 2 : tiles;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 4096));
+}
+
+// Dynamic LDS of the partitioned merge's kernels: the histogram's P
+// counters, the scatter's three arrays of P (P = 2^pmaxbits, the most the
+// device may pick for this store).
+size_t part_lds(const InstBuf& b, int kind) {
+  static std::once_flag once;
+  std::call_once(once, [] {   // the most any store may ask for
+    const int most = 3 * (1 << kPartMaxBits) * (int)sizeof(uint32_t);
+    (void)hipFuncSetAttribute((const void*)&k_part_scatter,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    for (const void* f : {(const void*)&k_part_hist<0>, (const void*)&k_part_hist<1>,
+                          (const void*)&k_part_hist<3>, (const void*)&k_part_hist<4>,
+                          (const void*)&k_part_hist<5>})
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, most / 3);
+  });
+  const size_t P = size_t(1) << std::max<uint32_t>(b.pmaxbits, kPartMinBits);
+  if (kind == PP_K_PART_HIST) return P * sizeof(uint32_t);
+  if (kind == PP_K_PART_SCATTER) return 3 * P * sizeof(uint32_t);
+  return 0;
+}
+
 // Launches the kernels that execute ops[from..] assuming none overflows.
 // Kernel kinds that execute one op of this handle.
 void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
@@ -452,8 +511,10 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
         out->push_back(PP_K_COMPACT);
       } else if (s->buf.narrow) {
         out->push_back(PP_K_MERGE_NARROW);
-        if (s->buf.pkey && !s->buf.nopart) {   // large merges: partitioned
-          out->push_back(PP_K_PART_SORT);
+        if (s->buf.pstage && !s->buf.nopart) {   // large merges: partitioned
+          out->push_back(PP_K_PART_HIST);
+          out->push_back(PP_K_PART_SCAN);
+          out->push_back(PP_K_PART_SCATTER);
           out->push_back(PP_K_PART_AGG);
         }
         out->push_back(PP_K_MERGE_COLLECT);
@@ -487,7 +548,7 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
     kinds.clear();
     kinds_of(s, ops[k], &kinds);
     for (int kind : kinds) {
-      if (small && (kind == PP_K_PART_SORT || kind == PP_K_PART_AGG)) continue;
+      if (small && is_part_kind(kind)) continue;
       if (kind != run_kind) {
         if (run_kind >= 0) prof_end(s, run_kind, run_ev, run_len);
         run_kind = kind;
@@ -497,18 +558,21 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
       const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
       const int lane_it = kind == PP_K_GATE && !big ? lane_items(s->m_hint, nrot) : 0;
-      const int grid = kind == PP_K_PART_AGG    ? kParts
-                       : kind == PP_K_PART_SORT ? launch_blocks(elems, kPartTile / kBlock)
-                       : lane_it                ? launch_blocks(elems << nrot, lane_it)
-                                                : launch_blocks(elems, items_of(kind, big));
+      const int grid = is_part_kind(kind) ? part_grid(s->buf, kind)
+                       : lane_it            ? launch_blocks(elems << nrot, lane_it)
+                                            : launch_blocks(elems, items_of(kind, big));
+      const int block = kind == PP_K_PART_SCAN ? kPCBlock
+                        : kind == PP_K_PART_AGG ? kPABlock
+                        : is_part_kind(kind)    ? kPHBlock
+                                                : kBlock;
       Solo S;
       S.b = s->buf;
       if (small) S.b.nopart = 1;
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      hipLaunchKernelGGL(solo_of(kind, big, nrot, lane_it), dim3(grid), dim3(kBlock), 0,
-                         s->stream, S);
+      hipLaunchKernelGGL(solo_of(kind, big, nrot, lane_it, s->group), dim3(grid), dim3(block),
+                         part_lds(s->buf, kind), s->stream, S);
       ++run_len;
     }
   }
@@ -1053,6 +1117,18 @@ int pp_create_torus(pp_state** out, int lx, int ly, int dtype, const uint64_t* o
 int pp_work_counters(pp_state* s, uint64_t out[8]) {
   if (!s || !out) return fail(PP_EINVAL, "NULL argument");
   return read_counters(s, out);
+}
+
+int pp_merge_stats(pp_state* s, uint64_t out[4]) {
+  if (!s || !out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  const InstDyn& d = *s->h_dyn;
+  out[0] = d.pruns;
+  out[1] = d.phot;
+  out[2] = d.pover;
+  out[3] = d.pglob;
+  return PP_OK;
 }
 
 int pp_profile(pp_state* s, int every) {

@@ -40,7 +40,7 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 // splitmix64 finalizer (Steele, Lea, Flood, "Fast splittable pseudorandom
 // number generators", OOPSLA 2014): a bijective 64-bit mixer.
-__host__ __device__ __forceinline__ uint64_t mix64(uint64_t v) {
+__host__ __device__ __forceinline__ constexpr uint64_t mix64(uint64_t v) {
   v ^= v >> 30;
   v *= 0xbf58476d1ce4e5b9ull;
   v ^= v >> 27;
@@ -48,6 +48,23 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t v) {
   v ^= v >> 31;
   return v;
 }
+
+// Inverse of mix64: each xor-shift undone by folding the shifted copies back
+// in, each odd multiplier by its inverse modulo 2^64 (Newton iteration).
+__host__ __device__ constexpr uint64_t inv_mod64(uint64_t a) {
+  uint64_t x = a;
+  for (int i = 0; i < 6; ++i) x *= 2 - a * x;
+  return x;
+}
+__host__ __device__ __forceinline__ constexpr uint64_t unmix64(uint64_t v) {
+  v ^= (v >> 31) ^ (v >> 62);
+  v *= inv_mod64(0x94d049bb133111ebull);
+  v ^= (v >> 27) ^ (v >> 54);
+  v *= inv_mod64(0xbf58476d1ce4e5b9ull);
+  v ^= (v >> 30) ^ (v >> 60);
+  return v;
+}
+static_assert(unmix64(mix64(0x0123456789abcdefull)) == 0x0123456789abcdefull, "unmix64");
 
 __device__ __forceinline__ uint64_t hash_key(const uint64_t* x, const uint64_t* z, int W,
                                     uint64_t seed) {
@@ -132,7 +149,7 @@ __device__ __forceinline__ void canon_translation(uint64_t x, uint64_t z, int n,
     for (int k = 1; k < 7; ++k) {
       pw[k] = 0;
       if ((1 << k) <= n) {
-        pw[k] = pw[k - 1] & rotr_n(pw[k - 1], (1 << (k - 1)) % n, n, mask);
+        pw[k] = pw[k - 1] & rotr_n(pw[k - 1], 1 << (k - 1), n, mask);
         nb = k + 1;
       }
     }
@@ -154,6 +171,78 @@ __device__ __forceinline__ void canon_translation(uint64_t x, uint64_t z, int n,
       if (j >= n) j -= n;
       const uint64_t tx = rotr_n(x, j, n, mask), tz = rotr_n(z, j, n, mask);
       if (first || int_less1(tx, tz, bx, bz)) { bx = tx; bz = tz; first = false; }
+    }
+  }
+  *rx = bx;
+  *rz = bz;
+}
+
+// The same representative for n <= 32 in 32-bit words: a rotation within
+// n = 32 bits is one funnel shift (v_alignbit_b32), and every step of the
+// search above is a 32-bit operation instead of a 64-bit pair.
+__device__ __forceinline__ uint32_t rotr32(uint32_t v, int j, int n, uint32_t mask) {
+  if (n == 32) return __builtin_amdgcn_alignbit(v, v, (uint32_t)j);
+  if (j == 0) return v;
+  return ((v >> j) | (v << (n - j))) & mask;
+}
+
+__device__ __forceinline__ bool int_less32(uint32_t xa, uint32_t za, uint32_t xb, uint32_t zb) {
+  const uint32_t d = (xa ^ xb) | (za ^ zb);
+  if (d == 0) return false;
+  const int t = 31 - __clz(d);
+  const uint32_t ca = (((xa ^ za) >> t) & 1u) | (((za >> t) & 1u) << 1);
+  const uint32_t cb = (((xb ^ zb) >> t) & 1u) | (((zb >> t) & 1u) << 1);
+  return ca < cb;
+}
+
+__device__ __forceinline__ void canon_translation32(uint32_t x, uint32_t z, int n, uint32_t* rx,
+                                                    uint32_t* rz) {
+  const uint32_t mask = (n == 32) ? ~0u : ((1u << n) - 1);
+  const uint32_t idm = ~(x | z) & mask;
+  uint32_t bx = x, bz = z;
+  if (__builtin_expect(idm == 0, 0)) {      // no identity: compare all n translations
+    for (int j = 1; j < n; ++j) {
+      const uint32_t tx = rotr32(x, j, n, mask), tz = rotr32(z, j, n, mask);
+      if (int_less32(tx, tz, bx, bz)) { bx = tx; bz = tz; }
+    }
+    *rx = bx;
+    *rz = bz;
+    return;
+  }
+  // pw[k] bit a: qubits a .. a + 2^k - 1 (cyclic) are all identities
+  uint32_t pw[6];
+  pw[0] = idm;
+#pragma unroll
+  for (int k = 1; k < 6; ++k)
+    pw[k] = (1 << k) <= n ? pw[k - 1] & rotr32(pw[k - 1], 1 << (k - 1), n, mask) : 0u;
+  // longest run length and its starts, by selects (no divergent branch):
+  // the all-identity string has a run of n starting everywhere, which puts
+  // it on itself below
+  uint32_t cur = mask;
+  int len = 0;
+#pragma unroll
+  for (int b = 5; b >= 0; --b) {
+    if ((1 << b) > n) continue;               // uniform: n is the same for every lane
+    const uint32_t cand = cur & rotr32(pw[b], len < n ? len : 0, n, mask);
+    const bool take = cand != 0 && len + (1 << b) <= n;
+    cur = take ? cand : cur;
+    len = take ? len + (1 << b) : len;
+  }
+  // translation j = (a + len) mod n puts the run starting at a on the top
+  // qubits; the first start unconditionally, the others in a loop (rare)
+  int j0 = __ffs(cur) - 1 + len;
+  if (j0 >= n) j0 -= n;
+  bx = rotr32(x, j0, n, mask);
+  bz = rotr32(z, j0, n, mask);
+  cur &= cur - 1;
+  if (__builtin_expect(cur != 0, 0) && len < n) {
+    while (cur) {
+      const int a = __ffs(cur) - 1;
+      cur &= cur - 1;
+      int j = a + len;
+      if (j >= n) j -= n;
+      const uint32_t tx = rotr32(x, j, n, mask), tz = rotr32(z, j, n, mask);
+      if (int_less32(tx, tz, bx, bz)) { bx = tx; bz = tz; }
     }
   }
   *rx = bx;
@@ -263,6 +352,35 @@ __device__ __forceinline__ void perm_rep(uint32_t nx, uint32_t ny, uint32_t nz, 
   }
 }
 
+// Narrow merge key of a one-word string for a group known at compile time
+// (0 none, 1 Z_n, 3 D_n, 4 torus, 5 explicit; n <= 32): the representative
+// packed as x | z << 32.
+template <int G>
+__device__ __forceinline__ uint64_t narrow_key_t(const InstBuf& b, uint64_t x, uint64_t z) {
+  if constexpr (G == 1) {
+    uint32_t ax, az;
+    canon_translation32((uint32_t)x, (uint32_t)z, b.n, &ax, &az);
+    return (uint64_t)ax | ((uint64_t)az << 32);
+  } else if constexpr (G == 3) {
+    uint32_t ax, az, bx, bz;
+    canon_translation32((uint32_t)x, (uint32_t)z, b.n, &ax, &az);
+    const uint32_t xr = __brev((uint32_t)x) >> (32 - b.n), zr = __brev((uint32_t)z) >> (32 - b.n);
+    canon_translation32(xr, zr, b.n, &bx, &bz);
+    if (int_less32(bx, bz, ax, az)) { ax = bx; az = bz; }
+    return (uint64_t)ax | ((uint64_t)az << 32);
+  } else if constexpr (G == 4) {
+    uint64_t rx, rz;
+    canon_torus(x, z, b.n, b.lx, &rx, &rz);
+    return rx | (rz << 32);
+  } else if constexpr (G == 5) {
+    uint64_t rx, rz;
+    canon_explicit(x, z, b.n, b.gperm, b.gsize, &rx, &rz);
+    return rx | (rz << 32);
+  } else {
+    return x | (z << 32);
+  }
+}
+
 // Narrow merge key: the representative itself, packed into 64 bits.
 __device__ __forceinline__ uint64_t narrow_key(const InstBuf& b, const uint64_t* x,
                                       const uint64_t* z) {
@@ -272,8 +390,19 @@ __device__ __forceinline__ uint64_t narrow_key(const InstBuf& b, const uint64_t*
     return (uint64_t)nx | ((uint64_t)ny << 8) | ((uint64_t)nz << 16);
   }
   uint64_t rx = x[0], rz = z[0];
-  if (b.group == 1) canon_translation(x[0], z[0], b.n, &rx, &rz);
-  if (b.group == 3) canon_dihedral(x[0], z[0], b.n, &rx, &rz);
+  if (b.group == 1) {                       // n <= 32 here
+    uint32_t ax, az;
+    canon_translation32((uint32_t)x[0], (uint32_t)z[0], b.n, &ax, &az);
+    return (uint64_t)ax | ((uint64_t)az << 32);
+  }
+  if (b.group == 3) {
+    uint32_t ax, az, bx, bz;
+    canon_translation32((uint32_t)x[0], (uint32_t)z[0], b.n, &ax, &az);
+    const uint32_t xr = __brev((uint32_t)x[0]) >> (32 - b.n), zr = __brev((uint32_t)z[0]) >> (32 - b.n);
+    canon_translation32(xr, zr, b.n, &bx, &bz);
+    if (int_less32(bx, bz, ax, az)) { ax = bx; az = bz; }
+    return (uint64_t)ax | ((uint64_t)az << 32);
+  }
   if (b.group == 4) canon_torus(x[0], z[0], b.n, b.lx, &rx, &rz);
   if (b.group == 5) canon_explicit(x[0], z[0], b.n, b.gperm, b.gsize, &rx, &rz);
   return rx | (rz << 32);   // n <= 32
@@ -1576,14 +1705,9 @@ __device__ __forceinline__ bool merge_served(const InstBuf& b, const InstDyn& d,
   return (b.narrow != 0) == narrow && d.mphase == phase;
 }
 
+// The partitioned merge (pp_merge.hpp) takes large narrow-key merges (not S_n).
 __device__ __forceinline__ bool use_part(const InstBuf& b, const InstDyn& d) {
-  return b.pkey != nullptr && !b.nopart && b.narrow && b.group != 2 && d.M >= kPartMin;
-}
-
-__device__ __forceinline__ uint32_t part_of(uint64_t key) { return (uint32_t)(mix64(key) >> 56); }
-
-__device__ __forceinline__ uint32_t part_slot(uint64_t key) {
-  return (uint32_t)(mix64(key) >> 20) & (uint32_t)(kPartSlots - 1);
+  return b.pstage != nullptr && !b.nopart && b.narrow && b.group != 2 && d.M >= kPartMin;
 }
 
 
@@ -1736,6 +1860,7 @@ __device__ __forceinline__ void finish_rebuild(const InstBuf& b, InstDyn& d) {
   d.nuniq = 0;
   d.mphase = 0;
   d.pglobal = 0;
+  d.plist_n = 0;
   d.pc += 1;
 }
 
@@ -1746,14 +1871,20 @@ struct CollectKind {
   __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
     return (merge_served(b, d, true, 1) || merge_served(b, d, false, 2)) ? 1 : 0;
   }
+  // after a partitioned merge only the listed slots (keys of split or
+  // overfull buckets) are occupied
+  __device__ __forceinline__ static bool listed(const InstBuf& b, const InstDyn& d) {
+    return b.narrow && use_part(b, d);
+  }
   __device__ __forceinline__ static uint32_t elems(const InstBuf& b, const InstDyn& d) {
-    if (b.narrow && use_part(b, d) && !d.pglobal) return 0u;   // all emitted by pass 2
+    if (listed(b, d)) return d.pglobal ? d.plist_n : 0u;
     return 1u << merge_bits(b, d);
   }
   template <int IT>
   __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
     const bool collided = (d.status & ST_COLLISION) != 0;
-    const uint32_t nslots = 1u << merge_bits(b, d);
+    const bool lst = listed(b, d);
+    const uint32_t nslots = lst ? d.plist_n : 1u << merge_bits(b, d);
     const int W = b.W;
     const Op& mop = b.prog[d.pc];
     const NextGate ng(b, mop);
@@ -1764,8 +1895,9 @@ struct CollectKind {
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       ov[k] = false;
-      const uint32_t s = t * (kBlock * IT) + k * kBlock + threadIdx.x;
-      if (s >= nslots) continue;
+      const uint32_t e = t * (kBlock * IT) + k * kBlock + threadIdx.x;
+      if (e >= nslots) continue;
+      const uint32_t s = lst ? b.plist[e] : e;
       const uint64_t key = b.mkey[s];
       if (key == kEmpty64) continue;
       if (!collided) {
@@ -1839,354 +1971,6 @@ struct CollectKind {
     }
     finish_rebuild(b, d);
   }
-};
-
-// ---------------------------------------------------------------------------
-// Partitioned exact merge (narrow keys, at least kPartMin records, one
-// instance).  Pass 1 takes tiles of kPartTile records, computes each live
-// record's representative key and its partition (top 8 bits of a mix of
-// the key), counting-sorts the tile by partition in LDS and writes it back
-// to the staging buffer at the tile's own place, with the tile's partition
-// offsets: no global atomics.  Pass 2 gives each partition to one block,
-// which gathers the partition's records from every tile and adds them into
-// an LDS table of exact fixed-point sums, then emits one term per key.  A
-// partition with more than kPartFill distinct keys discards its table (the
-// decision is taken after a barrier, so no key is split between the two
-// paths) and adds its records to the global merge table instead; the
-// collect pass then emits those.
-// ---------------------------------------------------------------------------
-struct PartSortKind {
-  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
-    return (merge_served(b, d, true, 0) && use_part(b, d)) ? 1 : 0;
-  }
-  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn& d) { return d.M; }
-  template <int IT>
-  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t t, Smem& sm) {
-    static_assert(IT * kBlock == kPartTile && kBlock == kParts, "tile and partition shape");
-    __shared__ uint64_t s_key[kPartTile];
-    __shared__ double s_c[kPartTile];
-    __shared__ uint32_t s_cnt[kParts];
-    const View v = view_of(b, d);
-    s_cnt[threadIdx.x] = 0;
-    if (t == 0)                            // pass 2's share claims start at zero
-      for (int q = threadIdx.x; q < kClaimWords; q += kBlock) b.pclaim[q] = 0;
-    __syncthreads();
-    uint64_t key[IT];
-    double c[IT];
-    uint32_t at[IT];                       // partition << 16 | rank, or kNone32
-    bool range = false;
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      at[k] = kNone32;
-      const uint32_t i = t * kPartTile + k * kBlock + threadIdx.x;
-      if (i >= d.M || !v.al[i]) continue;
-      uint64_t qx[kMaxW], qz[kMaxW];
-      load_key(v, i, qx, qz);
-      key[k] = narrow_key(b, qx, qz);
-      c[k] = v.getc(i);
-      if (key[k] == kEmpty64) {            // the one key equal to the empty marker
-        fx_atomic_add(d.special_fx, fx_from_double(c[k], &range));
-        atomicOr(&d.special, 1u);
-        continue;
-      }
-      const uint32_t p = part_of(key[k]);
-      at[k] = (p << 16) | atomicAdd(&s_cnt[p], 1u);
-    }
-    if (range) atomicOr(&d.status, ST_RANGE);
-    __syncthreads();
-    uint32_t total;
-    const uint32_t off = block_scan(s_cnt[threadIdx.x], sm.tmp, &total);
-    uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
-    pre[threadIdx.x] = (uint16_t)off;
-    if (threadIdx.x == 0) pre[kParts] = (uint16_t)total;
-    __syncthreads();
-    s_cnt[threadIdx.x] = off;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      if (at[k] == kNone32) continue;
-      const uint32_t pos = s_cnt[at[k] >> 16] + (at[k] & 0xffffu);
-      s_key[pos] = key[k];
-      s_c[pos] = c[k];
-    }
-    __syncthreads();
-    const size_t base = (size_t)t * kPartTile;
-    for (uint32_t j = threadIdx.x; j < total; j += kBlock) {
-      b.pkey[base + j] = s_key[j];
-      b.pcoef[base + j] = s_c[j];
-    }
-    __syncthreads();                       // LDS is reused by the next tile
-  }
-  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn& d, uint32_t, Smem&) {
-    d.merged += d.live;
-    d.pglobal = 0;
-    d.mphase = 1;
-  }
-};
-
-// Adds (key, v) to a partition's LDS table; false when v's key is new and
-// the table already holds kPartFill keys (the caller flushes and retries).
-// At most kPartFill + kBlock keys are ever inserted, so a probe always ends.
-__device__ __forceinline__ bool part_try_add(uint64_t* tk, uint64_t* tf, uint32_t* fill,
-                                             uint64_t key, Fx v) {
-  uint32_t s = part_slot(key);
-  for (int probe = 0; probe < kPartSlots; ++probe) {
-    uint64_t k = tk[s];
-    if (k == kEmpty64) {
-      if (*(volatile uint32_t*)fill >= (uint32_t)kPartFill) return false;
-      k = atomicCAS((unsigned long long*)&tk[s], (unsigned long long)kEmpty64,
-                    (unsigned long long)key);
-      if (k == kEmpty64) {
-        atomicAdd(fill, 1u);
-        k = key;
-      }
-    }
-    if (k == key) {
-      fx_atomic_add(&tf[3 * s], v);
-      return true;
-    }
-    s = (s + 1) & (uint32_t)(kPartSlots - 1);
-  }
-  return false;
-}
-
-// All threads: moves every key of the LDS table into the global merge table
-// and empties the LDS table.
-__device__ __forceinline__ void part_flush(const InstBuf& b, InstDyn& d, uint64_t* tk, uint64_t* tf,
-                                           uint32_t* fill) {
-  for (int q = threadIdx.x; q < kPartSlots; q += kBlock) {
-    const uint64_t key = tk[q];
-    if (key != kEmpty64) {
-      mt_add(b, d, key, Fx{tf[3 * q], tf[3 * q + 1], tf[3 * q + 2]});
-      tk[q] = kEmpty64;
-      tf[3 * q] = tf[3 * q + 1] = tf[3 * q + 2] = 0;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) *fill = 0;
-  __syncthreads();
-}
-
-struct PartAggKind {
-  static constexpr int kBatch = 8;         // records loaded before they are added
-  __device__ __forceinline__ static bool needs_fence(const InstBuf&, const InstDyn&) { return false; }
-  __device__ __forceinline__ static int state(const InstBuf& b, const InstDyn& d) {
-    return (merge_served(b, d, true, 1) && use_part(b, d)) ? 1 : 0;
-  }
-  // one tile (of kBlock elements at one item per thread) per partition
-  __device__ __forceinline__ static uint32_t elems(const InstBuf&, const InstDyn&) { return kParts * kBlock; }
-
-  // Walks partition p: each thread takes p's segment of every kBlock-th tile
-  // and loads up to kBatch records of it at a time (in flight together);
-  // a non-null `stop` (an LDS flag) ends the walk once it is set.
-  template <class F>
-  __device__ __forceinline__ static void each_record(const InstBuf& b, const InstDyn& d, uint32_t p,
-                                                     F f, const uint32_t* stop) {
-    const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
-    for (uint32_t t = threadIdx.x; t < T; t += kBlock) {
-      const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
-      const uint32_t lo = pre[p], hi = pre[p + 1];
-      const size_t base = (size_t)t * kPartTile;
-      for (uint32_t r = lo; r < hi; r += kBatch) {
-        if (stop && *(const volatile uint32_t*)stop) return;
-        uint64_t k[kBatch];
-        double c[kBatch];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-          if (r + q < hi) {
-            k[q] = b.pkey[base + r + q];
-            c[q] = b.pcoef[base + r + q];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-          if (r + q < hi) f(k[q], c[q]);
-      }
-    }
-  }
-
-  // Partition p.  A cold partition: first pass, every thread adds its
-  // records into the block's LDS table, stopping as soon as a key finds no
-  // room.  If that happened (more than kPartFill keys), the table is cleared
-  // and the partition is summed again with the table as a write-combining
-  // cache: the threads advance in rounds of up to kBatch records; a round
-  // that finds the table full flushes it into the global merge table and
-  // retries its leftovers; the last table is flushed too, so every key of
-  // such a partition ends in the global table, never split.  Otherwise the
-  // block emits one term per key.  A hot partition (more than kPartHot
-  // times the average share of records) is cut into kPartSplit shares that
-  // blocks claim with an atomic counter and sum by the write-combining pass
-  // into the global table: its own block claims shares until none is left,
-  // and every cold block, once its partition is done, claims shares of the
-  // hot partitions it sees in the mask.  No block waits for another; every
-  // share is claimed exactly once, and the claimer sums all of it.
-  template <int IT>
-  __device__ __forceinline__ static void tile(const InstBuf& b, InstDyn& d, uint32_t p, Smem& sm) {
-    __shared__ uint64_t s_tk[kPartSlots];
-    __shared__ uint64_t s_tf[3 * kPartSlots];
-    __shared__ uint32_t s_fill, s_over, s_size, s_claim;
-    const uint32_t T = (d.M + kPartTile - 1) / kPartTile;
-    uint32_t* mask = b.pclaim + kParts;
-    // the partition's record count, from the staging tiles' offsets
-    {
-      uint32_t n = 0;
-      for (uint32_t t = threadIdx.x; t < T; t += kBlock) {
-        const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
-        n += (uint32_t)pre[p + 1] - pre[p];
-      }
-      const uint32_t v1[1] = {n};
-      uint32_t t1[1];
-      block_sums<1>(v1, sm, t1);
-      if (threadIdx.x == 0) s_size = t1[0];
-      __syncthreads();
-    }
-    const bool hot = (uint64_t)s_size * kParts > (uint64_t)kPartHot * d.M;
-    if (hot && threadIdx.x == 0) atomicOr(&mask[p / 32], 1u << (p % 32));
-    auto clear = [&]() {
-      for (int q = threadIdx.x; q < kPartSlots; q += kBlock) {
-        s_tk[q] = kEmpty64;
-        s_tf[3 * q] = s_tf[3 * q + 1] = s_tf[3 * q + 2] = 0;
-      }
-      if (threadIdx.x == 0) s_fill = 0;
-      __syncthreads();
-    };
-    bool range = false;
-    // The write-combining pass over the tiles first, first + stride, ... of
-    // partition q, ending with the table flushed into the global table.
-    auto combine = [&](uint32_t q, uint32_t first, uint32_t stride) {
-      clear();
-      uint32_t t = first, r = 0, hi = 0;
-      auto seek = [&]() {                  // next tile with records of q
-        while (t < T) {
-          const uint16_t* pre = b.ppre + (size_t)t * (kParts + 1);
-          r = pre[q];
-          hi = pre[q + 1];
-          if (r < hi) return;
-          t += stride;
-        }
-      };
-      seek();
-      while (true) {
-        uint64_t k[kBatch];
-        Fx v[kBatch];
-        uint32_t got = 0;
-        if (t < T) {
-          const size_t base = (size_t)t * kPartTile;
-#pragma unroll
-          for (int j = 0; j < kBatch; ++j) {
-            if (r + j < hi) {
-              k[j] = b.pkey[base + r + j];
-              v[j] = fx_from_double(b.pcoef[base + r + j], &range);
-              got = j + 1;
-            }
-          }
-          r += got;
-          if (r >= hi) {
-            t += stride;
-            seek();
-          }
-        }
-        uint32_t fail = 0;
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j)
-          if ((uint32_t)j < got && !part_try_add(s_tk, s_tf, &s_fill, k[j], v[j])) fail |= 1u << j;
-        if (__syncthreads_or(fail != 0)) {
-          part_flush(b, d, s_tk, s_tf, &s_fill);
-#pragma unroll
-          for (int j = 0; j < kBatch; ++j)    // at most kBlock * kBatch <= kPartFill keys
-            if ((fail >> j) & 1u) part_try_add(s_tk, s_tf, &s_fill, k[j], v[j]);
-        }
-        if (!__syncthreads_or(t < T)) break;
-      }
-      __syncthreads();
-      part_flush(b, d, s_tk, s_tf, &s_fill);
-      if (threadIdx.x == 0) atomicOr(&d.pglobal, 1u);
-    };
-    // claims and sums shares of hot partition q until none is left
-    auto work_shares = [&](uint32_t q) {
-      while (true) {
-        if (threadIdx.x == 0) s_claim = atomicAdd(&b.pclaim[q], 1u);
-        __syncthreads();
-        const uint32_t share = s_claim;
-        __syncthreads();
-        if (share >= (uint32_t)kPartSplit) break;   // block-uniform
-        combine(q, share + kPartSplit * threadIdx.x, kPartSplit * kBlock);
-      }
-    };
-    // the cold blocks, when done, help with the hot partitions they see
-    auto help = [&]() {
-      for (uint32_t w = 0; w < (uint32_t)kParts / 32; ++w) {
-        if (threadIdx.x == 0) s_claim = ld_agent(&mask[w]);
-        __syncthreads();
-        uint32_t bits = s_claim;            // one value for the whole block
-        __syncthreads();
-        while (bits) {
-          const uint32_t q = w * 32 + (31 - __clz(bits));
-          bits &= ~(1u << (q % 32));
-          work_shares(q);
-        }
-      }
-    };
-    if (hot) {
-      work_shares(p);
-      if (range) atomicOr(&d.status, ST_RANGE);
-      return;
-    }
-    if (threadIdx.x == 0) s_over = 0;
-    clear();
-    each_record(b, d, p, [&](uint64_t key, double c) {
-      if (!part_try_add(s_tk, s_tf, &s_fill, key, fx_from_double(c, &range))) atomicExch(&s_over, 1u);
-    }, &s_over);
-    __syncthreads();
-    if (s_over != 0) {                     // block-uniform
-      combine(p, threadIdx.x, kBlock);
-      help();
-      if (range) atomicOr(&d.status, ST_RANGE);
-      return;
-    }
-    if (range) atomicOr(&d.status, ST_RANGE);
-    __syncthreads();
-    // emit one term per key (that the merge's truncation keeps)
-    constexpr int kPer = kPartSlots / kBlock;
-    const Op& mop = b.prog[d.pc];
-    uint32_t keep = 0, mine = 0;           // keep: bit q = slot q's term is emitted
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const uint32_t sl = q * kBlock + threadIdx.x;
-      const uint64_t key = s_tk[sl];
-      if (key == kEmpty64) continue;
-      uint64_t x[kMaxW], z[kMaxW];
-      narrow_decode(b, key, x, z);
-      if (merge_keeps(b, mop, x, z, fx_to_double(Fx{s_tf[3 * sl], s_tf[3 * sl + 1], s_tf[3 * sl + 2]}))) {
-        keep |= 1u << q;
-        ++mine;
-      }
-    }
-    uint32_t tot;
-    uint32_t off = block_scan(mine, sm.tmp, &tot);
-    if (threadIdx.x == 0) sm.base = tot ? atomicAdd(&d.nuniq, tot) : 0u;
-    __syncthreads();
-    const uint32_t base = sm.base;
-    const NextGate ng(b, mop);
-    uint32_t my_cnt = 0;
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      if (!((keep >> q) & 1u)) continue;
-      const uint32_t sl = q * kBlock + threadIdx.x;
-      const uint64_t key = s_tk[sl];
-      const uint32_t pos = base + off++;
-      if (pos >= b.cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
-      uint64_t x[kMaxW], z[kMaxW];
-      narrow_decode(b, key, x, z);
-      emit_term(b, d, pos, x, z, fx_to_double(Fx{s_tf[3 * sl], s_tf[3 * sl + 1], s_tf[3 * sl + 2]}));
-      if (ng.anti(x, z, b.W)) ++my_cnt;
-    }
-    add_counts(d, mine, my_cnt, sm);
-    help();
-    if (range) atomicOr(&d.status, ST_RANGE);
-  }
-  __device__ __forceinline__ static void finish(const InstBuf&, InstDyn&, uint32_t, Smem&) {}
 };
 
 // MERGE for plain PP: the set is already free of duplicates, so the merge
@@ -2518,16 +2302,6 @@ PP_KERNEL_PAIR(k_merge_wide2, MergeWide2Kind)
 PP_KERNEL_PAIR(k_merge_collect, CollectKind)
 PP_KERNEL_PAIR(k_compact, CompactKind)
 PP_KERNEL_PAIR(k_scan_op, ScanKind)
-
-// the partitioned merge runs on the one-instance path only
-__global__ __launch_bounds__(kBlock) void k_part_sort_solo(Solo S) {
-  __shared__ Smem sm;
-  run_solo<PartSortKind, kPartTile / kBlock>(S, sm);
-}
-__global__ __launch_bounds__(kBlock) void k_part_agg_solo(Solo S) {
-  __shared__ Smem sm;
-  run_solo<PartAggKind, 1>(S, sm);
-}
 
 // ---------------------------------------------------------------------------
 // Initial state of a new store's tables, in one launch (grid-stride): gate

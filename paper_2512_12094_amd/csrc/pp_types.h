@@ -74,21 +74,30 @@ constexpr size_t kAccBytes = kAccShards * kLineU64 * sizeof(uint64_t);
 enum : int { STAT_LIVE = 0, STAT_ANTI = 1, STAT_RW = 2, kStatKinds = 3 };
 constexpr size_t kStatBytes = kStatKinds * kAccShards * kLineU64 * sizeof(uint64_t);
 
-// Partitioned merge: used for narrow-key merges of at least kPartMin
-// records; tiles of kPartTile records, kParts partitions, LDS tables of
-// kPartSlots slots of which at most kPartFill may be filled.
+// Partitioned merge (narrow keys except S_n, at least kPartMin records):
+//   1. histogram: tiles of kPartTileRec records; each live record's key goes
+//      to bucket mix64(key) >> (64 - pbits); per-tile bucket counts;
+//   2. column scan: per bucket, the tiles' exclusive offsets and the total;
+//      the last block turns the totals into bucket bases and the list of
+//      aggregation work items;
+//   3. scatter: every record (key, coefficient) to its exact place in the
+//      bucket-contiguous staging array, through an LDS counting sort of
+//      kPartSub records at a time;
+//   4. aggregation: one block per bucket (or per chunk of a bucket holding
+//      more than twice the average), LDS table of kPartSlots keys with exact
+//      carry-free sums; emits one term per key (chunks of a split bucket add
+//      into the global merge table instead, emitted by the collect pass).
+// P = 2^pbits buckets, pbits = clamp(ceil(log2(M / 2^kPartShift)), 6, 12).
 constexpr uint32_t kPartMin = 1u << 18;
-constexpr int kPartTile = 4096;
-constexpr int kParts = 256;
-constexpr int kPartSlots = 4096;
-constexpr int kPartFill = 3072;
-// A partition holding more than kPartHot times the average share of the
-// records is cut into kPartSplit shares (share s: the staging tiles t with
-// t mod kPartSplit = s), summed through the global merge table by whichever
-// blocks claim them.
-constexpr int kPartSplit = 32;
-constexpr int kPartHot = 4;
-constexpr int kClaimWords = kParts + kParts / 32;
+constexpr int kPartTileRec = 32768;
+constexpr int kPartSub = 4096;
+constexpr int kPartShift = 14;
+constexpr int kPartMinBits = 6;
+constexpr int kPartMaxBits = 12;
+constexpr int kPartSlots = 2048;
+constexpr int kPartFill = 1536;
+constexpr int kPartChunks = 5;       // 32-bit chunks of a fixed-point sum (160 bits)
+constexpr int kPartMaxPasses = 64;   // selector passes over an overfull bucket
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
@@ -129,13 +138,16 @@ struct InstBuf {
   uint32_t* wslot;
   uint64_t* accs;        // kAccShards count accumulators
   uint64_t* stats;       // kStatKinds x kAccShards statistics lines (cumulative)
-  // partitioned merge (narrow keys, large sets): records staged per tile of
-  // kPartTile, sorted by partition, with each tile's partition offsets
-  uint64_t* pkey;        // [tiles * kPartTile] representative keys
-  double* pcoef;         // [tiles * kPartTile] coefficients (FP64)
-  uint16_t* ppre;        // [tiles][kParts + 1] exclusive offsets per partition
-  uint32_t* pclaim;      // [kParts] next share of each hot partition, then the
-                         // kParts / 32 words of the hot-partition mask
+  // partitioned merge (narrow keys, large sets)
+  uint64_t* phash;       // [cap] mix64 of each record's representative key
+                         // (mix64(kEmpty64): no record to merge)
+  uint64_t* pstage;      // [cap][2]: (mixed key, coefficient bits), bucket-contiguous
+  uint32_t* phist;       // [tiles][P]: per-tile counts, then exclusive offsets
+  uint32_t* ptot;        // [P] bucket totals
+  uint32_t* pbase;       // [P + 1] bucket bases
+  uint32_t* pwork;       // aggregation items: bucket | chunk << 16
+  uint32_t* plist;       // [2^hm_bits] global merge-table slots in use
+  uint32_t pmaxbits;     // largest pbits the staging tables were sized for
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;
@@ -180,7 +192,16 @@ struct InstDyn {
   uint32_t seed;         // wide-merge hash seed (bumped on a collision)
   uint32_t special;
   uint32_t failed_pc;
-  uint32_t pglobal;      // partitioned merge: some partition used the table
+  uint32_t pglobal;      // partitioned merge: some bucket used the global table
+  uint32_t pbits;        // partitioned merge: log2 of the bucket count
+  uint32_t pnwork;       // partitioned merge: aggregation items
+  uint32_t plist_n;      // partitioned merge: global-table slots listed
+  uint32_t pchunk;       // partitioned merge: records per item of a split bucket
+  // cumulative partitioned-merge statistics (pp_merge_stats)
+  uint32_t pruns;        // partitioned merges run
+  uint32_t phot;         // buckets split over several blocks (hot representatives)
+  uint32_t pover;        // buckets summed in several selector passes
+  uint32_t pglob;        // keys that went through the global merge table
 };
 
 }  // namespace pp

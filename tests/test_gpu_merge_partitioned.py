@@ -1,9 +1,19 @@
-"""The partitioned exact merge (large narrow-key merges): pp_create on
-record streams of 2^19 and 2^20 Z_32 records (distinct strings) against
-the oracle's exact orbit sums, bitwise.  With 8 rotations per string the partitions are summed in LDS;
-with no duplicates each partition holds more keys than its LDS table and
-is summed through the global merge table.  Both streams carry the one key
-equal to the table's empty marker (Y on all 32 qubits)."""
+"""The partitioned exact merge (large merges of 64-bit keys): pp_create on
+record streams of 2^19..2^21 Z_32 records against the oracle's exact orbit
+sums, bitwise (both sides add every record exactly and round each orbit sum
+once).
+
+The streams are built so that every branch of the partitioned path runs and
+is counted by pp_merge_stats:
+* buckets summed in one LDS table and emitted by their block;
+* buckets split over several blocks because a few representatives hold far
+  more than a bucket's share of the records (weight-1 strings: three
+  representatives hold 1/8 of the stress stream; a stream where half the
+  rows are five strings), summed through the global merge table;
+* buckets with more distinct representatives than one table holds (every
+  string once), summed in selector passes;
+* the one key equal to the merge table's empty marker (Y on all 32 qubits).
+Algorithm 1 step 1; Algorithms 2 and 3."""
 import numpy as np
 import pytest
 
@@ -26,38 +36,86 @@ def gpu():
                 alloc=_lib.TorchAllocator(0))
 
 
-@pytest.mark.parametrize("log2n,dup", [(19, 8), (20, 1)])
-def test_partitioned_merge_matches_oracle(gpu, log2n, dup):
+def merge_on_gpu(gpu, x, z, c, group="Zn", n=32):
     from paper_2512_12094_amd import _lib as L
-    x, z, c = W.merge_stress_records(log2n, dup, seed=11)
-    x[0] = z[0] = np.uint64(0xFFFFFFFF)
-    # distinct strings only: the oracle adds repeated rows in FP64 before its
-    # exact orbit sum, so with each string once both sides round each orbit
-    # sum exactly once and must agree bitwise
-    _, first = np.unique(x | (z << np.uint64(32)), return_index=True)
-    first.sort()
-    x, z, c = x[first], z[first], c[first]
-    assert len(c) >= 1 << 18                    # large enough for the partitioned path
-    print(f"[case] partitioned merge 2^{log2n} records, {dup} rotations", flush=True)
     L.pp_profile(None, 1)
-    h = L.pp_create(32, "Zn", x.reshape(-1, 1), z.reshape(-1, 1), c, gpu["handle"],
-                    gpu["alloc"])
+    h = L.pp_create(n, group, x.reshape(-1, 1), z.reshape(-1, 1), c, gpu["handle"], gpu["alloc"])
     L.pp_profile(None, 0)
     prof = L.pp_profile_read(h)
-    # the partitioned kernels are issued (the device takes them for >= 2^18 records)
-    assert prof["part_sort"][0] == 1 and prof["part_agg"][0] == 1, prof
     wc = L.pp_work_counters(h)
+    st = L.pp_merge_stats(h)
     gx, gz, gc = L.pp_export_terms(h, 1)
     L.pp_destroy(h)
-    gpu_terms = {(int(a), int(b)): float(v) for a, b, v in zip(gx[:, 0], gz[:, 0], gc)}
+    terms = {(int(a), int(b)): float(v) for a, b, v in zip(gx[:, 0], gz[:, 0], gc)}
+    return terms, wc, st, prof
 
-    ref = O.Oracle(32, "Zn")
-    for a, b, v in zip(x.tolist(), z.tolist(), c.tolist()):
-        ref.add(a, b, v)
-    ref.merge()
-    want = ref.as_dict()
-    assert wc["merge_in"] == len(c) and wc["merge_out"] == len(want)
-    assert set(gpu_terms) == set(want)
+
+def check_bitwise(terms, want, wc, nrec):
+    assert wc["merge_in"] == nrec and wc["merge_out"] == len(want)
+    assert set(terms) == set(want)
+    bad = [k for k in want if terms[k] != want[k]]   # exact sums, rounded once
+    assert not bad, [(k, terms[k], want[k]) for k in bad[:5]]
+
+
+@pytest.mark.parametrize("log2n,dup", [(19, 8), (20, 1), (20, 32), (21, 4)])
+def test_partitioned_merge_matches_oracle(gpu, log2n, dup):
+    """The stress stream as generated (repeated strings stay separate rows)."""
+    x, z, c = W.merge_stress_records(log2n, dup, seed=11)
+    x[0] = z[0] = np.uint64(0xFFFFFFFF)          # the empty-marker key
+    print(f"[case] partitioned merge 2^{log2n} records, {dup} rotations", flush=True)
+    terms, wc, st, prof = merge_on_gpu(gpu, x, z, c)
+    assert prof["part_hist"][0] == 1 and prof["part_agg"][0] == 1, prof
+    assert st["partitioned_merges"] == 1, st
+    want = O.merge_records(32, "Zn", x, z, c)
     assert (0xFFFFFFFF, 0xFFFFFFFF) in want
-    bad = [k for k in want if gpu_terms[k] != want[k]]   # exact sums, rounded once
-    assert not bad, [(k, gpu_terms[k], want[k]) for k in bad[:5]]
+    check_bitwise(terms, want, wc, len(c))
+    # three weight-1 representatives hold ~1/8 of the records: split buckets
+    assert st["split_buckets"] > 0, st
+    assert st["global_keys"] > 0, st
+    if dup == 1:                                 # ~every record its own key
+        assert st["selector_buckets"] > 0, st
+
+
+def test_partitioned_merge_hot_rows(gpu):
+    """Half of 2^19 rows are five strings (and their rotations): their buckets
+    are split over many blocks; the rest are distinct strings."""
+    rng = np.random.default_rng(5)
+    x, z, c = W.merge_stress_records(19, 2, seed=13)
+    hot_x = np.array([0x3, 0x5, 0x101, 0xF0, 0x1], dtype=np.uint64)
+    hot_z = np.array([0x1, 0x4, 0x100, 0x30, 0x1], dtype=np.uint64)
+    idx = rng.choice(len(c), size=len(c) // 2, replace=False)
+    pick = rng.integers(0, 5, size=len(idx))
+    sh = rng.integers(0, 32, size=len(idx)).astype(np.uint64)
+    m32 = np.uint64(0xFFFFFFFF)
+    rot = lambda v: np.where(sh == 0, v, ((v << sh) | (v >> (np.uint64(32) - sh))) & m32)
+    x[idx] = rot(hot_x[pick])
+    z[idx] = rot(hot_z[pick])
+    print("[case] partitioned merge 2^19 rows, half of them five strings", flush=True)
+    terms, wc, st, _ = merge_on_gpu(gpu, x, z, c)
+    want = O.merge_records(32, "Zn", x, z, c)
+    check_bitwise(terms, want, wc, len(c))
+    assert st["split_buckets"] > 0 and st["global_keys"] > 0, st
+
+
+def test_partitioned_merge_dihedral_and_plain(gpu):
+    """The same path under D_32 (duplicates of one orbit across reflections)
+    and with no group (identical rows only)."""
+    x, z, c = W.merge_stress_records(19, 4, seed=17)
+    for group in ("Dn", "none"):
+        print(f"[case] partitioned merge 2^19 records, group {group}", flush=True)
+        terms, wc, st, _ = merge_on_gpu(gpu, x, z, c, group=group)
+        want = O.merge_records(32, group, x, z, c)
+        check_bitwise(terms, want, wc, len(c))
+        assert st["partitioned_merges"] == 1, st
+
+
+def test_partitioned_merge_ragged_sizes(gpu):
+    """Sizes around the partitioned path's threshold and tile edges."""
+    for m in ((1 << 18), (1 << 18) + 1, 9 * 32768 + 4095, 300001):
+        x, z, c = W.merge_stress_records(19, 16, seed=m)
+        x, z, c = x[:m], z[:m], c[:m]
+        print(f"[case] partitioned merge {m} records", flush=True)
+        terms, wc, st, _ = merge_on_gpu(gpu, x, z, c)
+        want = O.merge_records(32, "Zn", x, z, c)
+        check_bitwise(terms, want, wc, len(c))
+        assert st["partitioned_merges"] == 1, st

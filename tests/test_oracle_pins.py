@@ -465,6 +465,46 @@ def test_orbit_sum_is_exactly_rounded():
     assert o.as_dict() == {W.from_letters("XIII"): 1.0}
 
 
+@pytest.mark.parametrize("n,group", [(5, "Zn"), (6, "Zn"), (5, "Sn"), (6, "Dn"), (4, "none")])
+def test_merge_of_raw_records_against_brute_force(n, group):
+    """Algorithm 1 step 1 on raw rows with many repeats: each representative
+    is the orbit's lowest integer (brute force over the group with the
+    independent encoding) and its coefficient the correctly rounded sum of
+    every row of the orbit (math.fsum), repeated rows as separate addends."""
+    rng = random.Random(23 + n)
+    base = [random_string(rng, n) for _ in range(12)]
+    rows = []
+    for _ in range(400):
+        s = rng.choice(base)
+        if group in ("Zn", "Dn"):
+            s = rotate_letters(s, rng.randrange(n))
+            if group == "Dn" and rng.random() < 0.5:
+                s = s[::-1]
+        elif group == "Sn":
+            s = "".join(rng.sample(s, n))
+        rows.append((s, rng.gauss(0, 1) * 10.0 ** rng.uniform(-8, 8)))
+    rows += [(rows[0][0], -rows[0][1]), (rows[1][0], 1e16), (rows[1][0], -1e16)]
+
+    def images(s):
+        if group == "Zn":
+            return [rotate_letters(s, j) for j in range(n)]
+        if group == "Dn":
+            return [rotate_letters(t, j) for t in (s, s[::-1]) for j in range(n)]
+        if group == "Sn":
+            return ["".join(p) for p in itertools.permutations(s)]
+        return [s]
+
+    want = {}
+    for s, c in rows:
+        rep = min(images(s), key=lambda t: sum(DIGIT[ch] * 4 ** q for q, ch in enumerate(t)))
+        want.setdefault(W.from_letters(rep), []).append(c)
+    want = {k: math.fsum(v) for k, v in want.items()}
+    x = np.array([W.from_letters(s)[0] for s, _ in rows], dtype=np.uint64)
+    z = np.array([W.from_letters(s)[1] for s, _ in rows], dtype=np.uint64)
+    got = O.merge_records(n, group, x, z, [c for _, c in rows])
+    assert got == want
+
+
 # ----------------------------------------------------------------------------
 # Dihedral group D_n (translations and the reflection of the ring)
 # ----------------------------------------------------------------------------

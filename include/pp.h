@@ -202,6 +202,23 @@ int pp_truncate(pp_state* s, double eps, int max_weight, double depol_p);
  */
 int pp_expectation(pp_state* s, const double bloch_xyz[3], double* out);
 
+/*
+ * pp_expectation_noalloc -- pp_expectation for callers that cannot allocate
+ * device or pinned memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, same result
+ * (bitwise: the same products summed exactly and rounded once).  Its
+ * working memory is a fixed device array inside the library (about 1.6 MB
+ * per GPU, held until the process ends): the powers table, one exact
+ * partial sum per 2048 store entries, a done counter and the result.  The
+ * first call on a device looks the array up for that device (the handle's
+ * device must be current); later calls allocate nothing.  Stores of more
+ * than 2^27 entries (live and not yet compacted): PP_EINVAL with a message.
+ * Every call on one GPU shares that array, so calls that overlap on one GPU
+ * (other threads, other streams) race; calls on one stream are ordered.
+ * Synchronises the handle's stream.
+ */
+int pp_expectation_noalloc(pp_state* s, const double bloch_xyz[3], double* out);
+
 /* Number of live terms. */
 int pp_num_terms(pp_state* s, size_t* out);
 

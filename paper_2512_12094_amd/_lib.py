@@ -67,6 +67,7 @@ def lib():
     L.pp_merge_canonicalize.argtypes = [_vp]
     L.pp_truncate.argtypes = [_vp, ctypes.c_double, ctypes.c_int, ctypes.c_double]
     L.pp_expectation.argtypes = [_vp, _f64p, _f64p]
+    L.pp_expectation_noalloc.argtypes = [_vp, _f64p, _f64p]
     L.pp_num_terms.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
     L.pp_export_terms.argtypes = [_vp, _u64p, _u64p, _f64p, ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_size_t)]
@@ -210,6 +211,13 @@ def pp_expectation(h, bloch) -> float:
     b, bp = _f64(np.asarray(bloch, dtype=np.float64))
     out = ctypes.c_double()
     _check(lib().pp_expectation(h, bp, ctypes.byref(out)))
+    return out.value
+
+
+def pp_expectation_noalloc(h, bloch) -> float:
+    b, bp = _f64(np.asarray(bloch, dtype=np.float64))
+    out = ctypes.c_double()
+    _check(lib().pp_expectation_noalloc(h, bp, ctypes.byref(out)))
     return out.value
 
 

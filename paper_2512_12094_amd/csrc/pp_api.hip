@@ -90,6 +90,7 @@ struct pp_state {
   double* d_tab = nullptr;
   size_t tab_cap = 0;
   InstDyn* h_dyn = nullptr;            // pinned
+  double* h_na = nullptr;              // pinned: result and flag of pp_expectation_noalloc
   const pp_program* batch_prog = nullptr;
   const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
@@ -931,6 +932,7 @@ void pp_destroy(pp_state* s) {
   dev_free(s, s->d_stats);
   dev_free(s, s->d_gperm);
   if (s->h_dyn) (void)hipHostFree(s->h_dyn);
+  if (s->h_na) (void)hipHostFree(s->h_na);
   for (auto& st : s->ring) {
     if (st.h) (void)hipHostFree(st.h);
     if (st.ev) (void)hipEventDestroy(st.ev);
@@ -982,6 +984,7 @@ int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
   s->lx = lx;
 
   HIP_TRY(hipHostMalloc((void**)&s->h_dyn, sizeof(InstDyn), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&s->h_na, 2 * sizeof(double), hipHostMallocDefault));
   s->d_buf = (InstBuf*)dev_alloc(s.get(), sizeof(InstBuf));
   s->d_dyn = (InstDyn*)dev_alloc(s.get(), sizeof(InstDyn));
   s->d_bufp = (const InstBuf**)dev_alloc(s.get(), sizeof(void*));
@@ -1244,6 +1247,161 @@ int pp_expectation(pp_state* s, const double bloch_xyz[3], double* out) {
   int rc = run_ops(s, ops, tab, {{0, 0}}, false);
   if (rc) return rc;
   *out = s->h_dyn->expect;
+  return PP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free expectation.  Its working memory (the powers table, one
+// exact partial sum per tile of kNaTile entries, the done counter, the
+// result) is the file-scope device array `scratch`, of a fixed size; every
+// GPU holds its own copy.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (na_scratch_ptr).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNaTile = 2048;                  // entries per tile (256 threads x 8)
+constexpr uint32_t kNaMaxTiles = 65536;        // entries at most 2^27
+constexpr int kNaTab = 3 * (64 * kMaxW + 1);   // bx^k, by^k, bz^k for k = 0..n
+
+struct NaScratch {
+  double tab[kNaTab];
+  double result;
+  uint32_t range;                              // a term out of the fixed-point range
+  uint32_t done;                               // blocks done
+  uint64_t part[kNaMaxTiles][3];               // exact partial sum of each tile
+};
+
+static __device__ __align__(256) unsigned char scratch[sizeof(NaScratch)];
+
+// Powers table (the same products, in the same order, as pp_expectation's
+// host table), and the counters cleared by a kernel rather than a memset.
+__global__ void k_na_init(NaScratch* sc, double bx, double by, double bz, int n) {
+  const int a = threadIdx.x;
+  if (a < 3) {
+    const double b = a == 0 ? bx : a == 1 ? by : bz;
+    double p = 1.0;
+    for (int k = 0; k <= n; ++k) {
+      sc->tab[a * (n + 1) + k] = p;
+      p *= b;
+    }
+  }
+  if (a == 0) {
+    sc->range = 0;
+    sc->done = 0;
+    sc->result = 0.0;
+  }
+}
+
+// One exact partial sum per tile of live terms (the expectation's terms as
+// the scan kernel forms them), then the last block adds the partials and
+// rounds once.
+__global__ __launch_bounds__(kBlock) void k_na_expect(InstBuf b, const InstDyn* dp, NaScratch* sc,
+                                                      uint32_t tiles) {
+  __shared__ uint64_t s_w[kWaves][3];
+  __shared__ uint32_t s_last;
+  const InstDyn& d = *dp;
+  const View v = view_of(b, d);
+  const uint32_t M = d.M;
+  const int W = b.W, n = b.n;
+  bool range = false;
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    Fx acc{0, 0, 0};
+    for (int k = 0; k < kNaTile / kBlock; ++k) {
+      const uint32_t i = t * kNaTile + k * kBlock + threadIdx.x;
+      if (i >= M || !v.al[i]) continue;
+      uint64_t x[kMaxW], z[kMaxW];
+      load_key(v, i, x, z);
+      uint32_t nx, ny, nz;
+      perm_counts(x, z, W, &nx, &ny, &nz);
+      const double term = v.getc(i) * sc->tab[nx] * sc->tab[(n + 1) + ny] * sc->tab[2 * (n + 1) + nz];
+      acc = fx_add(acc, fx_from_double(term, &range));
+    }
+    const Fx w = wave_sum_fx(acc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { s_w[wid][0] = w.l0; s_w[wid][1] = w.l1; s_w[wid][2] = w.l2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Fx s{0, 0, 0};
+      for (int q = 0; q < kWaves; ++q) s = fx_add(s, Fx{s_w[q][0], s_w[q][1], s_w[q][2]});
+      sc->part[t][0] = s.l0;
+      sc->part[t][1] = s.l1;
+      sc->part[t][2] = s.l2;
+    }
+    __syncthreads();
+  }
+  if (range) atomicOr(&sc->range, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&sc->done, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  Fx acc{0, 0, 0};
+  for (uint32_t t = threadIdx.x; t < tiles; t += kBlock)
+    acc = fx_add(acc, Fx{ld_agent(&sc->part[t][0]), ld_agent(&sc->part[t][1]),
+                         ld_agent(&sc->part[t][2])});
+  const Fx w = wave_sum_fx(acc);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { s_w[wid][0] = w.l0; s_w[wid][1] = w.l1; s_w[wid][2] = w.l2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Fx s{0, 0, 0};
+    for (int q = 0; q < kWaves; ++q) s = fx_add(s, Fx{s_w[q][0], s_w[q][1], s_w[q][2]});
+    sc->result = fx_to_double(s);
+    sc->done = 0;
+  }
+}
+
+std::mutex g_na_mu;
+void* g_na_ptr[256] = {};                      // scratch's address, per device
+
+// The device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+int na_scratch_ptr(NaScratch** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) return fail(PP_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_na_ptr[dev] = p;
+  }
+  *out = static_cast<NaScratch*>(g_na_ptr[dev]);
+  return PP_OK;
+}
+
+}  // namespace
+
+int pp_expectation_noalloc(pp_state* s, const double bloch_xyz[3], double* out) {
+  if (!s || !bloch_xyz || !out) return fail(PP_EINVAL, "NULL argument");
+  NaScratch* sc = nullptr;
+  int rc = na_scratch_ptr(&sc);
+  if (rc) return rc;
+  if ((rc = read_dyn(s))) return rc;            // the entry count, into pinned memory
+  const uint32_t M = s->h_dyn->M;
+  const uint64_t tiles = ((uint64_t)M + kNaTile - 1) / kNaTile;
+  if (tiles > kNaMaxTiles)
+    return fail(PP_EINVAL, "pp_expectation_noalloc takes stores of at most " +
+                               std::to_string((uint64_t)kNaMaxTiles * kNaTile) +
+                               " entries (this one holds " + std::to_string(M) + ")");
+  hipLaunchKernelGGL(k_na_init, dim3(1), dim3(64), 0, s->stream, sc, bloch_xyz[0], bloch_xyz[1],
+                     bloch_xyz[2], s->n);
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 2048));
+  hipLaunchKernelGGL(k_na_expect, dim3(grid), dim3(kBlock), 0, s->stream, s->buf,
+                     (const InstDyn*)s->d_dyn, sc, (uint32_t)tiles);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(s->h_na, &sc->result, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  uint32_t range = 0;
+  std::memcpy(&range, s->h_na + 1, sizeof(range));
+  if (range) return fail(PP_EINVAL, "a coefficient is not finite or exceeds 2^54 in magnitude");
+  *out = s->h_na[0];
   return PP_OK;
 }
 

@@ -55,6 +55,8 @@ def parse():
                     help="time every N-th run of back-to-back launches of one kernel "
                          "kind with HIP events")
     ap.add_argument("--merge-log2n", type=int, default=24)
+    ap.add_argument("--merge-more", type=int, nargs="*", default=[26],
+                    help="more merge-pass sizes (log2 of the records), 32 rotations each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
     ap.add_argument("--no-batched", action="store_true")
@@ -71,11 +73,18 @@ def parse():
 
 
 def gate_bytes(wc, W=1):
-    """Algorithmic bytes of the gate kernel: every live term entering a launch
-    has its key read (16W B; a launch of two fused rotations reads it once);
-    every entering term that a rotation of the launch touches has its
-    coefficient read and written (16 B); every appended string is written
-    (16W + 8 B)."""
+    """Algorithmic bytes of the apply step, priced per term-gate (Prop. 1's
+    propagation unit): every live term tested against a rotation has its key
+    read (16W B); every anticommuting one has its coefficient read and
+    written (16 B); every appended child is written (16W + 8 B)."""
+    return (16 * W * wc["propagated"] + 16 * wc["anticommuting"] +
+            (16 * W + 8) * wc["appended"])
+
+
+def gate_bytes_launch(wc, W=1):
+    """The same bytes as a fused launch moves them: each key read once per
+    launch (one launch applies up to three commuting rotations), each
+    touched coefficient read and written once per launch."""
     return (16 * W * wc["gate_key_reads"] + 16 * wc["gate_coef_rw"] +
             (16 * W + 8) * wc["appended"])
 
@@ -130,7 +139,10 @@ MERGE_KINDS = ("merge_narrow", "merge_wide1", "merge_wide2", "part_hist", "part_
 def merge_pass(stream, alloc, log2n, dup=32):
     """Exact merge of 2^log2n records: random weight <= 8 Z_32 strings, each
     emitted in `dup` random rotations (Algorithm 1 step 1 on that stream).
-    The duration is the sum of the merge kernels' HIP-event intervals."""
+    The duration is the sum of the merge kernels' HIP-event intervals (each
+    kernel timed on the library's stream, the launch gaps between them
+    excluded); `span_ms` is the interval from the first merge kernel's start
+    to the last one's end, gaps included."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import workloads as W
     import torch
@@ -142,14 +154,18 @@ def merge_pass(stream, alloc, log2n, dup=32):
     wc = L.pp_work_counters(h)
     L.pp_destroy(h)
     L.pp_profile(None, False)
+    st = L.pp_merge_stats(h)
     ms = sum(prof[k][1] for k in MERGE_KINDS)
     nbytes = merge_bytes(wc)
     return dict(records=int(wc["merge_in"]), representatives=int(wc["merge_out"]),
                 rotations_per_string=dup, ms=round(ms, 4),
                 kernels_ms={k: round(prof[k][1], 4) for k in MERGE_KINDS if prof[k][0]},
                 records_per_s=wc["merge_in"] / (ms * 1e-3),
+                sort_keys_per_s=wc["merge_in"] / (ms * 1e-3),
+                algorithmic_bytes=int(nbytes),
                 algorithmic_GBs=round(nbytes / (ms * 1e-3) / 1e9, 1),
-                frac_of_hbm=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                frac_of_hbm=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                partitioned=st)
 
 
 def prefix(prog, k):
@@ -369,11 +385,12 @@ def served_leg(stream, alloc, count, sublayers, cap_terms, seed=5):
     return summ
 
 
-def pmc_traffic(bytes_launches):
-    """HBM bytes per gate launch from the committed rocprofv3 counter
-    summary, when it was taken on the kernel sources as they are now."""
+def pmc_traffic(bytes_launches, name="k_gate_c2_z32_pmc.json"):
+    """HBM bytes per launch (per pass, for the merge summary) from a
+    committed rocprofv3 counter summary, when it was taken on the kernel
+    sources as they are now."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_gate_c2_z32_pmc.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None, "no counter summary"
     with open(path) as f:
@@ -456,11 +473,18 @@ def main():
         gb = gate_bytes(tot)
         avg_s = gate_ms * 1e-3 / max(gate_n, 1)
         bpl = gb / gates_run
+        bpl_launch = gate_bytes_launch(tot) / gates_run
         roof = dict(bound="hbm", kernel="k_gate", achieved=round(bpl / avg_s / 1e9, 2),
                     peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 5), traffic=None,
+                    byte_model="per term-gate: 16W key per live term and rotation, 16 B "
+                               "coefficient read+write per anticommuting term, 16W+8 B per "
+                               "appended child",
                     avg_launch_us=round(avg_s * 1e6, 3), timed_launches=gate_n,
                     launches=gates_run, bytes_per_launch=round(bpl, 1),
+                    launch_model=dict(bytes_per_launch=round(bpl_launch, 1),
+                                      achieved=round(bpl_launch / avg_s / 1e9, 2),
+                                      frac=round(bpl_launch / avg_s / 1e9 / HBM_PEAK_GBS, 5)),
                     rotations_per_launch=round(prog.n_gates / per_step, 3),
                     est_kernel_ms_per_step=round(avg_s * 1e3 * per_step, 3))
         kernels = {k: dict(launches=n, ms=round(ms, 3)) for k, (n, ms) in kern.items() if n}
@@ -491,14 +515,31 @@ def main():
         roof["traffic"] = round(traffic, 1) if traffic is not None else None
         roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
         roof["traffic_source"] = traffic_src
-        mp = None
+        mp = roof_merge = None
         if not args.no_merge_pass:
             merge_pass(stream, alloc, args.merge_log2n)            # warm
             mp = merge_pass(stream, alloc, args.merge_log2n)
+            keep = ("records", "rotations_per_string", "representatives", "ms",
+                    "records_per_s", "algorithmic_GBs", "frac_of_hbm")
             mp["other_duplicate_factors"] = [
                 {k: v for k, v in merge_pass(stream, alloc, args.merge_log2n, d).items()
-                 if k in ("rotations_per_string", "representatives", "ms", "algorithmic_GBs",
-                          "frac_of_hbm")} for d in (1, 4)]
+                 if k in keep} for d in (1, 4)]
+            mp["other_sizes"] = []
+            for lg in args.merge_more:
+                merge_pass(stream, alloc, lg)                      # warm the allocator
+                mp["other_sizes"].append({k: v for k, v in merge_pass(stream, alloc, lg).items()
+                                          if k in keep})
+            mtraffic, msrc = pmc_traffic(None, "k_merge_stress_2p24_pmc.json")
+            roof_merge = dict(bound="hbm", kernel="merge pass (k_part_hist, k_part_scan, "
+                              "k_part_scatter, k_part_agg, k_merge_collect)",
+                              achieved=mp["algorithmic_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=mp["frac_of_hbm"],
+                              traffic=round(mtraffic, 1) if mtraffic is not None else None,
+                              traffic_unit="HBM bytes per pass of 2^24 records (rocprofv3 "
+                                           "FETCH_SIZE + WRITE_SIZE, scaled)",
+                              traffic_source=msrc, algorithmic_bytes=mp["algorithmic_bytes"],
+                              byte_model="(16W + 8) B per record read + (16W + 8) B per "
+                                         "representative written")
             print(f"[bench] merge pass done", file=sys.stderr, flush=True)
         ising = None
         if not args.no_ising:
@@ -542,6 +583,7 @@ def main():
         "gate_at_scale": scale,
         "ising_layers": ising,
         "roofline": roof,
+        "roofline_merge": roof_merge,
         "kernels": kernels,
         "variants": variants,
         "tuning": {"single": tuned_single, "source": autotune.cache_path()},

@@ -50,19 +50,26 @@
  *   passed in are copied before the call returns; the caller keeps them.
  *   Output arrays are owned by the caller.
  * - Calls that synchronise the stream: pp_create, pp_apply_layer (once, to
- *   learn whether the term store had to grow), pp_merge_canonicalize,
- *   pp_expectation, pp_num_terms, pp_export_terms, pp_counters,
- *   pp_batch_run.  pp_truncate does not synchronise.
+ *   learn whether the term store had to grow: the growth of a layer is not
+ *   known before its gates run, and the store is grown by the host),
+ *   pp_merge_canonicalize (to learn whether every sum stayed in range, so
+ *   that a failure can be rolled back), pp_expectation, pp_num_terms,
+ *   pp_export_terms, pp_counters, pp_batch_run.  pp_truncate does not
+ *   synchronise.  A whole propagation that must not wait on the host runs
+ *   as a program (pp_program_create + pp_batch_run): its steps run on the
+ *   device and the host only reads the state after each chunk of them.
  * - A handle is not thread-safe; distinct handles are independent.
  *
  * Errors
  * ------
  * Every int-returning function returns PP_OK (0) or a negative code; nothing
  * throws across the ABI.  pp_last_error() returns a thread-local message for
- * the most recent failure.  After PP_EINVAL / PP_ENOTSYM the handle is
- * unchanged.  After PP_ECAPACITY / PP_ENOMEM inside pp_apply_layer the handle
- * stays valid and holds the result of the gates that were applied before
- * the one that did not fit (pp_last_error names how many).
+ * the most recent failure.  pp_apply_layer and pp_merge_canonicalize are
+ * transactional: after any error (PP_EINVAL, PP_ENOTSYM, PP_ECAPACITY when
+ * the store would exceed pp_set_max_terms, PP_ENOMEM, a coefficient out of
+ * range) the handle holds exactly its state from before the call (terms,
+ * coefficients, counters).  pp_truncate validates its arguments before it
+ * changes anything.
  */
 #ifndef PP_H
 #define PP_H
@@ -186,11 +193,15 @@ int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
 int pp_merge_canonicalize(pp_state* s);
 
 /*
- * pp_truncate -- damping and truncation.
+ * pp_truncate -- damping and truncation (Sec. IV: coefficient truncation of
+ * the numerical examples; Fig. 3 caption: depolarising noise damping each
+ * Pauli string by its weight after every Trotter step).
  * First multiplies every coefficient by (1 - depol_p)^{weight} (depolarising
  * noise on every qubit, Heisenberg picture; depol_p = 0: no damping), then
  * drops terms with |c| < eps or weight > max_weight (eps = 0 and
- * max_weight < 0: off).  Does not synchronise.
+ * max_weight < 0: off; weight truncation is not in the paper, its truncated
+ * workloads name it).  Does not synchronise.  PP_EINVAL for eps < 0 or
+ * depol_p outside [0, 1], before anything changes.
  */
 int pp_truncate(pp_state* s, double eps, int max_weight, double depol_p);
 

@@ -91,6 +91,14 @@ struct pp_state {
   size_t tab_cap = 0;
   InstDyn* h_dyn = nullptr;            // pinned
   double* h_na = nullptr;              // pinned: result and flag of pp_expectation_noalloc
+  // transaction of a pp_apply_layer / pp_merge_canonicalize call: the store
+  // at the call's start (kept, not freed, if the store grows meanwhile) and
+  // a device copy of what the call may change in it
+  bool txn = false;
+  InstBuf txn_buf{};
+  std::vector<std::vector<void*>> retired;   // stores replaced during the call
+  void* txn_backup = nullptr;
+  uint32_t txn_m = 0, txn_half = 0, txn_parity = 0;
   const pp_program* batch_prog = nullptr;
   const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
@@ -439,7 +447,10 @@ int grow(pp_state* s) {
   prof_end(s, PP_K_GROW, ev);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s->stream));
-  free_store(s, s->store);
+  if (s->txn)
+    s->retired.push_back(std::move(s->store));   // the call may still roll back to it
+  else
+    free_store(s, s->store);
   s->store = std::move(allocs);
   s->buf = nb;
   int r = upload_buf(s);
@@ -1169,6 +1180,100 @@ int pp_set_max_terms(pp_state* s, size_t max_terms) {
   return PP_OK;
 }
 
+// Transactions.  A gate rotates coefficients in place and flips the alive
+// parity; it never changes a key below the entry count M (children go past
+// M), and a merge writes only the other half.  So the state of a call's
+// start is restored from: the instance's dynamic state, the statistics
+// lines, and the first M coefficients and current-parity alive flags of the
+// current half; plus the store itself when the call grew it (the old one is
+// kept until the call ends).  The copies are stream-ordered (no
+// synchronisation); M, half and parity come from the host mirror, which
+// every call that can change them refreshes.
+size_t txn_bytes(const pp_state* s, uint32_t M) {
+  const size_t cs = s->buf.f32 ? sizeof(float) : sizeof(double);
+  return sizeof(InstDyn) + kStatBytes + (size_t)M * (cs + 1) + 64;
+}
+
+int txn_begin(pp_state* s) {
+  const InstDyn& h = *s->h_dyn;
+  const uint32_t M = h.M;
+  void* b = dev_alloc(s, txn_bytes(s, M));
+  if (!b) return fail(PP_ENOMEM, "transaction backup allocation failed");
+  char* p = static_cast<char*>(b);
+  const size_t cs = s->buf.f32 ? sizeof(float) : sizeof(double);
+  HIP_TRY(hipMemcpyAsync(p, s->d_dyn, sizeof(InstDyn), hipMemcpyDeviceToDevice, s->stream));
+  p += sizeof(InstDyn);
+  HIP_TRY(hipMemcpyAsync(p, s->d_stats, kStatBytes, hipMemcpyDeviceToDevice, s->stream));
+  p += kStatBytes;
+  if (M) {
+    HIP_TRY(hipMemcpyAsync(p, s->buf.c[h.half], (size_t)M * cs, hipMemcpyDeviceToDevice,
+                           s->stream));
+    p += (size_t)M * cs;
+    HIP_TRY(hipMemcpyAsync(p, s->buf.alive[h.half][h.parity], M, hipMemcpyDeviceToDevice,
+                           s->stream));
+  }
+  s->txn = true;
+  s->txn_buf = s->buf;
+  s->txn_backup = b;
+  s->txn_m = M;
+  s->txn_half = h.half;
+  s->txn_parity = h.parity;
+  return PP_OK;
+}
+
+void txn_end(pp_state* s) {
+  dev_free(s, s->txn_backup);
+  s->txn_backup = nullptr;
+  for (auto& st : s->retired) free_store(s, st);
+  s->retired.clear();
+  s->txn = false;
+}
+
+// Restores the state of the call's start; returns `rc` (the call's error).
+int txn_rollback(pp_state* s, int rc) {
+  const std::string msg = g_err;
+  if (s->buf.x[0] != s->txn_buf.x[0] && !s->retired.empty()) {
+    free_store(s, s->store);                     // the grown store
+    s->store = std::move(s->retired.front());
+    s->retired.erase(s->retired.begin());
+  }
+  s->buf = s->txn_buf;
+  char* p = static_cast<char*>(s->txn_backup);
+  const size_t cs = s->buf.f32 ? sizeof(float) : sizeof(double);
+  const uint32_t M = s->txn_m;
+  bool ok = hipMemcpyAsync(s->d_buf, &s->buf, sizeof(InstBuf), hipMemcpyHostToDevice,
+                           s->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(s->d_dyn, p, sizeof(InstDyn), hipMemcpyDeviceToDevice,
+                            s->stream) == hipSuccess;
+  p += sizeof(InstDyn);
+  ok = ok && hipMemcpyAsync(s->d_stats, p, kStatBytes, hipMemcpyDeviceToDevice,
+                            s->stream) == hipSuccess;
+  p += kStatBytes;
+  if (M) {
+    ok = ok && hipMemcpyAsync(s->buf.c[s->txn_half], p, (size_t)M * cs,
+                              hipMemcpyDeviceToDevice, s->stream) == hipSuccess;
+    p += (size_t)M * cs;
+    ok = ok && hipMemcpyAsync(s->buf.alive[s->txn_half][s->txn_parity], p, M,
+                              hipMemcpyDeviceToDevice, s->stream) == hipSuccess;
+  }
+  ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+  txn_end(s);
+  if (ok) (void)read_dyn(s);
+  g_err = ok ? msg + " (the handle is as before the call)"
+             : msg + " (restoring the handle's state also failed)";
+  return ok ? rc : PP_EDEVICE;
+}
+
+// Runs ops as one transaction: on any error the handle is restored.
+int run_ops_txn(pp_state* s, const std::vector<Op>& ops) {
+  int rc = txn_begin(s);
+  if (rc) return rc;
+  rc = run_ops(s, ops, {}, {}, false);
+  if (rc) return txn_rollback(s, rc);
+  txn_end(s);
+  return PP_OK;
+}
+
 int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
                    const double* theta, size_t n_gates, int merge_every, double inner_eps,
                    int inner_max_weight) {
@@ -1203,13 +1308,13 @@ int pp_apply_layer(pp_state* s, const uint64_t* gate_x, const uint64_t* gate_z,
   }
   fuse_gates(ops, 1, W);
   set_next_gates(ops);
-  return run_ops(s, ops, {}, {}, false);
+  return run_ops_txn(s, ops);
 }
 
 int pp_merge_canonicalize(pp_state* s) {
   if (!s) return fail(PP_EINVAL, "state is NULL");
   std::vector<Op> ops(1, make_op(OP_MERGE));
-  return run_ops(s, ops, {}, {}, false);
+  return run_ops_txn(s, ops);
 }
 
 int pp_truncate(pp_state* s, double eps, int max_weight, double depol_p) {

@@ -9,11 +9,12 @@
 
 FP32 coefficient mode against the FP64 oracle:
 
-* coefficients: |a - b| <= 1e-5 max(|a|, |b|) + 2^-19 max_r |c_r|.  The
-  relative part is the stated FP32 accuracy; the floor allows 32 FP32
+* coefficients: |a - b| <= 1e-5 max(|a|, |b|) + 2^-21 max_r |c_r|.  The
+  relative part is the stated FP32 accuracy; the floor allows 8 FP32
   roundings (unit 2^-24) of terms as large as the largest coefficient,
   which covers cancellations (measured: at most 4.6 such roundings on the
-  ring, all-to-all and batched workloads).
+  ring, all-to-all and batched workloads).  `f32_error_report` gives the
+  achieved relative error per decade of coefficient magnitude.
 * Pauli sets: strings whose |c| lies within that floor of eps (absolute) on
   either side are left out, since FP32 rounding may move them across it.
 * Expectations: |a - b| <= 1e-5 sum_r |c_r|.
@@ -23,7 +24,7 @@ from __future__ import annotations
 REL = 1e-12
 BAND = 1e-9
 REL32 = 1e-5
-FLOOR32 = 2.0 ** -19
+FLOOR32 = 2.0 ** -21
 
 
 def near_threshold(c: float, eps: float, band_abs: float = 0.0) -> bool:
@@ -64,3 +65,21 @@ def compare_terms_f32(gpu: dict, ref: dict, eps: float = 0.0, what: str = ""):
 def compare_expectation(a: float, b: float, terms: dict, rel: float = REL, what: str = ""):
     scale = max(1.0, sum(abs(v) for v in terms.values()))
     assert abs(a - b) <= rel * scale, f"{what}: expectation gpu {a!r} oracle {b!r}"
+
+
+def f32_error_report(gpu: dict, ref: dict) -> dict:
+    """Largest relative error |a - b| / |b| of the FP32 coefficients per
+    decade of |b| (keys: floor(log10 |b|)), over the strings both sides
+    hold; and the largest error in units of 2^-24 max_r |c_r|."""
+    import math
+    scale = max([abs(v) for v in ref.values()] + [0.0])
+    out, worst_units = {}, 0.0
+    for k, b in ref.items():
+        if k not in gpu or b == 0.0:
+            continue
+        e = abs(gpu[k] - b)
+        dec = int(math.floor(math.log10(abs(b))))
+        out[dec] = max(out.get(dec, 0.0), e / abs(b))
+        if scale:
+            worst_units = max(worst_units, e / (scale * 2.0 ** -24))
+    return {"rel_by_decade": dict(sorted(out.items())), "worst_roundings": worst_units}

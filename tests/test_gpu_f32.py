@@ -6,7 +6,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2512_12094_amd import workloads as W
-from tests.parity import REL32, compare_expectation, compare_terms_f32
+from tests.parity import REL32, compare_expectation, compare_terms_f32, f32_error_report
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +31,10 @@ def prefix(prog, k):
 
 def check(res, ref, prog, what):
     n, skipped = compare_terms_f32(res.terms, ref.terms, prog.meta.get("eps", 0.0), what=what)
+    rep = f32_error_report(res.terms, ref.terms)
+    print(f"[f32] {what}: relative error by decade {rep['rel_by_decade']}, worst "
+          f"{rep['worst_roundings']:.2f} roundings of max|c|, {skipped} near eps skipped",
+          flush=True)
     compare_expectation(res.expectation, ref.expectation, ref.terms, rel=REL32, what=what)
     assert (res.propagated, res.merged) == (ref.propagated, ref.merged), what
     return n

@@ -228,15 +228,21 @@ def test_capacity_limit(gpu):
     ps = driver.PauliSet.from_program(prog, stream=gpu["handle"], allocator=gpu["alloc"])
     L.pp_set_max_terms(ps.h, 5000)
     layers = driver.heisenberg_layers(prog)
+    before = after = None
     with pytest.raises(L.PPError) as e:
         for la in layers:
+            before = (ps.as_dict(), L.pp_work_counters(ps.h))
             ps.apply_layer(la)
     assert e.value.code == -4
-    # the handle stays usable and consistent
-    n = ps.num_terms()
-    assert 0 < n <= 5000
-    x, z, c = ps.export()
-    assert len(c) == n
+    assert "as before the call" in str(e.value)
+    # the failed call left the handle exactly as it was before it
+    after = (ps.as_dict(), L.pp_work_counters(ps.h))
+    assert after[1] == before[1]
+    assert after[0] == before[0]
+    # and the handle keeps working: the same layer under a larger limit
+    L.pp_set_max_terms(ps.h, 0)
+    ps.apply_layer(la)
+    assert ps.num_terms() > 0
     ps.close()
 
 

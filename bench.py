@@ -152,9 +152,9 @@ def merge_pass(stream, alloc, log2n, dup=32):
     h = L.pp_create(32, "Zn", x.reshape(-1, 1), z.reshape(-1, 1), c, stream, alloc)
     prof = L.pp_profile_read(h)
     wc = L.pp_work_counters(h)
+    st = L.pp_merge_stats(h)
     L.pp_destroy(h)
     L.pp_profile(None, False)
-    st = L.pp_merge_stats(h)
     ms = sum(prof[k][1] for k in MERGE_KINDS)
     nbytes = merge_bytes(wc)
     return dict(records=int(wc["merge_in"]), representatives=int(wc["merge_out"]),

@@ -390,6 +390,18 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
 int pp_get_tuning(int out[5]);
 
 /*
+ * Merge tuning (process-wide; the autotuner picks it): the partitioned
+ * merge of large sets aims at 2^bucket_log2 records per bucket (10..18;
+ * default 14; 0 keeps the current value; applies to term stores allocated
+ * afterwards), and its aggregation pass runs on agg_blocks blocks that
+ * take the buckets in turn (0: one block per bucket or chunk, the default;
+ * at most 4096).  Results do not depend on either (exact sums).
+ * pp_get_merge_tuning returns the two current values.
+ */
+int pp_set_merge_tuning(int bucket_log2, int agg_blocks);
+int pp_get_merge_tuning(int out[2]);
+
+/*
  * Gate fusion (process-wide).  Consecutive rotations of a sub-layer whose
  * Pauli strings commute pairwise and are independent (no product of a
  * nonempty subset of them is the identity) are applied by one launch, up to

@@ -93,6 +93,8 @@ def lib():
     L.pp_set_tuning.argtypes = [ctypes.c_int] * 5
     L.pp_set_gate_fusion.argtypes = [ctypes.c_int, ctypes.c_int]
     L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    L.pp_set_merge_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.pp_get_merge_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     _lib = L
     return L
 
@@ -356,3 +358,13 @@ def pp_get_tuning():
     out = (ctypes.c_int * 5)()
     _check(lib().pp_get_tuning(out))
     return dict(zip(TUNING_KEYS, list(out)))
+
+
+def pp_set_merge_tuning(bucket_log2=0, agg_blocks=0):
+    _check(lib().pp_set_merge_tuning(int(bucket_log2), int(agg_blocks)))
+
+
+def pp_get_merge_tuning():
+    out = (ctypes.c_int * 2)()
+    _check(lib().pp_get_merge_tuning(out))
+    return dict(bucket_log2=int(out[0]), agg_blocks=int(out[1]))

@@ -41,6 +41,8 @@ struct Tuning {
   int max_blocks = 2048;  // persistent grid cap
   int graph_steps = 32;   // batched steps per captured graph
   int gates_per_step = 4; // gate launches per batched step
+  int part_shift = kPartShift;    // log2 records per bucket of the partitioned merge
+  int part_agg_blocks = 0;        // aggregation blocks (0: one per item, up to 3P/2)
 };
 Tuning g_tune;
 int g_fuse = kMaxFuse;    // pp_set_gate_fusion: rotations per gate launch (<= 1: off)
@@ -285,7 +287,8 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   nb.plist = nullptr;
   nb.pmaxbits = 0;
   if (nb.narrow && s->group != PP_GROUP_PERMUTATION && cap >= kPartMin) {
-    nb.pmaxbits = part_bits(cap, kPartMaxBits);
+    nb.pshift = (uint32_t)g_tune.part_shift;
+    nb.pmaxbits = part_bits(cap, kPartMaxBits, nb.pshift);
     const size_t P = size_t(1) << nb.pmaxbits;
     const size_t tiles = (cap + kPartTileRec - 1) / kPartTileRec;
     ok = ok && (nb.phash = (uint64_t*)take(sizeof(uint64_t) * cap));
@@ -487,6 +490,8 @@ int part_grid(const InstBuf& b, int kind) {
   const uint64_t P = uint64_t(1) << std::max<uint32_t>(b.pmaxbits, kPartMinBits);
   const uint64_t tiles = (b.cap + kPartTileRec - 1) / kPartTileRec;
   uint64_t g = kind == PP_K_PART_SCAN ? P / 64 : kind == PP_K_PART_AGG ? 3 * P / 2 : tiles;
+  if (kind == PP_K_PART_AGG && g_tune.part_agg_blocks)   // blocks walk the items grid-stride
+    g = std::min<uint64_t>(g, (uint64_t)g_tune.part_agg_blocks);
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 4096));
 }
 
@@ -906,6 +911,23 @@ int pp_set_tuning(int gate_items, int stream_items, int max_blocks, int graph_st
   if (max_blocks) g_tune.max_blocks = max_blocks;
   if (graph_steps) g_tune.graph_steps = graph_steps;
   if (gates_per_step) g_tune.gates_per_step = gates_per_step;
+  return PP_OK;
+}
+
+int pp_set_merge_tuning(int bucket_log2, int agg_blocks) {
+  if (bucket_log2 != 0 && (bucket_log2 < 10 || bucket_log2 > 18))
+    return fail(PP_EINVAL, "bucket_log2 must be 0 (keep) or 10..18");
+  if (agg_blocks < 0 || agg_blocks > 4096)
+    return fail(PP_EINVAL, "agg_blocks must be 0 (one per item) .. 4096");
+  if (bucket_log2) g_tune.part_shift = bucket_log2;
+  g_tune.part_agg_blocks = agg_blocks;
+  return PP_OK;
+}
+
+int pp_get_merge_tuning(int out[2]) {
+  if (!out) return fail(PP_EINVAL, "NULL argument");
+  out[0] = g_tune.part_shift;
+  out[1] = g_tune.part_agg_blocks;
   return PP_OK;
 }
 

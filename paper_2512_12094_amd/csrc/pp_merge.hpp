@@ -47,8 +47,9 @@ constexpr int kPASub = 2;        // records per thread per aggregation round
 // the aggregation table: the mix of kEmpty64, the one key summed apart.
 constexpr uint64_t kMixEmpty = mix64(kEmpty64);
 
-__host__ __device__ __forceinline__ uint32_t part_bits(uint32_t M, uint32_t maxbits) {
-  const uint32_t need = (M >> kPartShift) + ((M & ((1u << kPartShift) - 1)) ? 1u : 0u);
+__host__ __device__ __forceinline__ uint32_t part_bits(uint32_t M, uint32_t maxbits,
+                                                       uint32_t shift) {
+  const uint32_t need = (M >> shift) + ((M & ((1u << shift) - 1)) ? 1u : 0u);
   uint32_t bits = 0;
   while ((1u << bits) < need && bits < 31) ++bits;
   if (bits < (uint32_t)kPartMinBits) bits = kPartMinBits;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kPHBlock) void k_part_hist(Solo S) {
   InstDyn& d = *S.d;
   if (d.pc != S.k || !part_served(b, d, 0)) return;
   const uint32_t M = d.M;
-  const uint32_t pbits = part_bits(M, b.pmaxbits), P = 1u << pbits;
+  const uint32_t pbits = part_bits(M, b.pmaxbits, b.pshift), P = 1u << pbits;
   const uint32_t T = (M + kPartTileRec - 1) / kPartTileRec;
   const uint32_t workers = worker_count(T);
   if (blockIdx.x >= workers) return;
@@ -304,15 +305,23 @@ __global__ __launch_bounds__(kPHBlock) void k_part_scatter(Solo S) {
       s_cur[q] = b.pbase[q] + b.phist[(size_t)t * P + q];
     const uint32_t lo = t * kPartTileRec;
     const uint32_t hi = M - lo < (uint32_t)kPartTileRec ? M : lo + kPartTileRec;
+    // the next sub-round's records are loaded while this one is sorted
+    uint64_t nhk[R], ncb[R];
+    auto load = [&](uint32_t r0) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const uint32_t i = r0 + k * kPHBlock + threadIdx.x;
+        nhk[k] = i < hi ? b.phash[i] : kMixEmpty;
+        ncb[k] = __double_as_longlong(i < hi ? v.getc(i) : 0.0);
+      }
+    };
+    load(lo);
     for (uint32_t r0 = lo; r0 < hi; r0 += kPartSub) {
       for (uint32_t q = threadIdx.x; q < P; q += kPHBlock) s_cnt[q] = 0;
       uint64_t hk[R], cb[R];
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const uint32_t i = r0 + k * kPHBlock + threadIdx.x;
-        hk[k] = i < hi ? b.phash[i] : kMixEmpty;
-        cb[k] = __double_as_longlong(i < hi ? v.getc(i) : 0.0);
-      }
+      for (int k = 0; k < R; ++k) { hk[k] = nhk[k]; cb[k] = ncb[k]; }
+      if (r0 + kPartSub < hi) load(r0 + kPartSub);
       __syncthreads();
       uint32_t at[R];                            // bucket << 16 | rank, or kNone32
 #pragma unroll
@@ -429,8 +438,10 @@ struct PartTable {
 
 // Adds (mixed key h, pieces) to the LDS table; false when h is new and the
 // table is full (a new key is refused once kPartFill keys are in; at most
-// blockDim more can race past that check, and a probe gives up after every
-// slot, so a full table only refuses).
+// blockDim more can race past that check), or when kPartProbe probes did not
+// reach h or an empty slot (a crowded table: the key is refused, whether or
+// not it is further on, and the pass is redone another way).  `k` is the key
+// already read from the home slot part_slot(h).
 __device__ __forceinline__ void pa_put(const PartTable& tb, uint32_t s, const Pieces& pc) {
   const uint32_t q1 = pc.q0 + 1, q2 = pc.q0 + 2 < (uint32_t)kPartChunks ? pc.q0 + 2 : pc.q0 + 1;
   atomicAdd(&tb.sum[pc.q0][s], (unsigned long long)pc.a0);
@@ -438,14 +449,10 @@ __device__ __forceinline__ void pa_put(const PartTable& tb, uint32_t s, const Pi
   atomicAdd(&tb.sum[q2][s], (unsigned long long)pc.a2);
 }
 
-__device__ __forceinline__ bool pa_add(const PartTable& tb, uint64_t h, const Pieces& pc) {
+__device__ __forceinline__ bool pa_add_from(const PartTable& tb, uint64_t h, uint64_t k,
+                                            const Pieces& pc) {
   uint32_t s = part_slot(h);
-  uint64_t k = tb.key[s];
-  if (k == h) {                                  // the usual case: first probe, present
-    pa_put(tb, s, pc);
-    return true;
-  }
-  for (int probe = 0; probe < kPartSlots; ++probe) {
+  for (int probe = 0; probe < kPartProbe; ++probe) {
     if (k == kMixEmpty) {
       if (*(volatile uint32_t*)tb.fill >= (uint32_t)kPartFill) return false;
       k = atomicCAS((unsigned long long*)&tb.key[s], (unsigned long long)kMixEmpty,
@@ -463,6 +470,10 @@ __device__ __forceinline__ bool pa_add(const PartTable& tb, uint64_t h, const Pi
     k = tb.key[s];
   }
   return false;
+}
+
+__device__ __forceinline__ bool pa_add(const PartTable& tb, uint64_t h, const Pieces& pc) {
+  return pa_add_from(tb, h, tb.key[part_slot(h)], pc);
 }
 
 __device__ __forceinline__ Fx pa_value(const PartTable& tb, uint32_t s) {
@@ -527,7 +538,7 @@ __device__ __forceinline__ uint32_t pa_flush(const InstBuf& b, InstDyn& d, const
 __global__ __launch_bounds__(kPABlock) void k_part_agg(Solo S) {
   __shared__ uint64_t s_key[kPartSlots];
   __shared__ unsigned long long s_sum[kPartChunks][kPartSlots];
-  __shared__ uint32_t s_fill, s_flag, s_base;
+  __shared__ uint32_t s_fill, s_flag, s_base, s_stop;
   __shared__ uint32_t s_tmp[2 * (kPABlock / 64) + 2];
   const InstBuf& b = S.b;
   InstDyn& d = *S.d;
@@ -548,12 +559,15 @@ __global__ __launch_bounds__(kPABlock) void k_part_agg(Solo S) {
   // selector q of K; the next round's records are loaded while this round's
   // are added.  Global mode (`glob`): a round that finds the table full
   // flushes it into the global table and retries; returns false.  Otherwise
-  // the pass stops at the first round that finds the table full and returns
-  // true, with *added = records added before it stopped (block total).
+  // the rounds run without barriers; the first record the table refuses
+  // stops the pass, which returns true (it is then redone another way) with
+  // *est = the bucket's distinct keys estimated from what it saw (thread 0).
   auto pass = [&](uint32_t lo, uint32_t hi, uint32_t K, uint32_t q, bool glob,
-                  uint32_t* added) -> bool {
+                  uint32_t* est) -> bool {
+    if (threadIdx.x == 0) s_stop = 0;
     pa_clear(tb);
-    uint32_t ok = 0;
+    uint32_t proc = 0, refused = 0;
+    bool over_any = false;
     uint64_t nh[kPASub], nc[kPASub];
     auto load = [&](uint32_t r0) {
 #pragma unroll
@@ -571,23 +585,38 @@ __global__ __launch_bounds__(kPABlock) void k_part_agg(Solo S) {
     };
     if (lo < hi) load(lo);
     for (uint32_t r0 = lo; r0 < hi; r0 += kRound) {
+      // without global mode, the first refusal anywhere in the block stops
+      // the pass (read without a barrier: a round or two may still run)
+      if (!glob && *(volatile uint32_t*)&s_stop) break;
       uint64_t h[kPASub], cbv[kPASub];
 #pragma unroll
       for (int k = 0; k < kPASub; ++k) { h[k] = nh[k]; cbv[k] = nc[k]; }
       if (r0 + kRound < hi) load(r0 + kRound);
       uint32_t fail = 0;
+      // the home slots of all the round's records are read together; a
+      // record whose key sits there (the usual case) adds at once
+      uint64_t home[kPASub];
 #pragma unroll
       for (int k = 0; k < kPASub; ++k) {
-        if (h[k] == kMixEmpty || part_sel(h[k], K) != q) continue;
-        if (pa_add(tb, h[k], pieces_of(__longlong_as_double(cbv[k]), &range))) ++ok;
-        else fail |= 1u << k;
+        if (h[k] != kMixEmpty && part_sel(h[k], K) != q) h[k] = kMixEmpty;
+        home[k] = h[k] == kMixEmpty ? kMixEmpty : tb.key[part_slot(h[k])];
       }
-      if (!glob) {
-        if (__syncthreads_or(fail != 0)) {
-          uint32_t tot, tz;
-          bsum2<kPABlock>(ok, 0u, s_tmp, &tot, &tz);
-          *added = tot;                          // thread 0
-          return true;
+#pragma unroll
+      for (int k = 0; k < kPASub; ++k) {
+        if (h[k] == kMixEmpty) continue;
+        const Pieces pc = pieces_of(__longlong_as_double(cbv[k]), &range);
+        ++proc;
+        if (home[k] == h[k]) {
+          pa_put(tb, part_slot(h[k]), pc);
+        } else if (!pa_add_from(tb, h[k], home[k], pc)) {
+          fail |= 1u << k;
+          ++refused;
+        }
+      }
+      if (!glob) {                                 // a refused record spoils the pass
+        if (fail) {
+          over_any = true;
+          s_stop = 1;
         }
         continue;
       }
@@ -602,6 +631,18 @@ __global__ __launch_bounds__(kPABlock) void k_part_agg(Solo S) {
           }
         fail = again;
       }
+    }
+    if (!glob && __syncthreads_or(over_any)) {
+      // distinct keys of the bucket, estimated from the records processed:
+      // the keys the table holds plus every refused record, scaled up
+      uint32_t tp, tr;
+      bsum2<kPABlock>(proc, refused, s_tmp, &tp, &tr);
+      if (threadIdx.x == 0) {
+        const uint64_t seen = (uint64_t)s_fill + tr, n = hi - lo;
+        *est = (uint32_t)std::min<uint64_t>((seen * n + (tp ? tp : 1) - 1) / (tp ? tp : 1),
+                                            0xFFFFFFFFull);
+      }
+      return true;
     }
     __syncthreads();
     return false;
@@ -666,20 +707,17 @@ __global__ __launch_bounds__(kPABlock) void k_part_agg(Solo S) {
     uint32_t K = 1, q = 0;
     bool glob = split;
     while (q < K) {
-      uint32_t added = 0;
-      const bool over = pass(lo, hi, K, q, glob, &added);
+      uint32_t est = 0;
+      const bool over = pass(lo, hi, K, q, glob, &est);
       if (glob) {
         my_glob += pa_flush(b, d, tb);
       } else if (!over) {
         emit();
       } else if (K == 1) {
-        // more keys than the table takes: 2^k selector passes, sized from
-        // the keys the table took per record added before it filled
+        // more keys than the table takes: 2^k selector passes, each aimed
+        // at three quarters of the table
         if (threadIdx.x == 0) {
-          const uint64_t n = hi - lo, got = added ? added : 1;
-          const uint64_t keys = s_fill;            // >= kPartFill
-          const uint64_t est = (keys * n + got - 1) / got;
-          const uint64_t want = (4 * est + 3 * kPartFill - 1) / (3 * kPartFill);
+          const uint64_t want = (4 * (uint64_t)est + 3 * kPartFill - 1) / (3 * kPartFill);
           uint32_t k2 = 2;
           while (k2 < want && k2 < (uint32_t)kPartMaxPasses) k2 <<= 1;
           s_flag = k2;

@@ -87,7 +87,8 @@ constexpr size_t kStatBytes = kStatKinds * kAccShards * kLineU64 * sizeof(uint64
 //      more than twice the average), LDS table of kPartSlots keys with exact
 //      carry-free sums; emits one term per key (chunks of a split bucket add
 //      into the global merge table instead, emitted by the collect pass).
-// P = 2^pbits buckets, pbits = clamp(ceil(log2(M / 2^kPartShift)), 6, 12).
+// P = 2^pbits buckets, pbits = clamp(ceil(log2(M / 2^pshift)), 6, 12), where
+// pshift (records per bucket aimed at, default kPartShift) is a tuning knob.
 constexpr uint32_t kPartMin = 1u << 18;
 constexpr int kPartTileRec = 32768;
 constexpr int kPartSub = 4096;
@@ -98,6 +99,7 @@ constexpr int kPartSlots = 2048;
 constexpr int kPartFill = 1536;
 constexpr int kPartChunks = 5;       // 32-bit chunks of a fixed-point sum (160 bits)
 constexpr int kPartMaxPasses = 64;   // selector passes over an overfull bucket
+constexpr int kPartProbe = 64;       // probes before the LDS table refuses a key
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
@@ -148,6 +150,7 @@ struct InstBuf {
   uint32_t* pwork;       // aggregation items: bucket | chunk << 16
   uint32_t* plist;       // [2^hm_bits] global merge-table slots in use
   uint32_t pmaxbits;     // largest pbits the staging tables were sized for
+  uint32_t pshift;       // log2 of the records per bucket aimed at (tuning)
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;

@@ -230,6 +230,24 @@ int pp_expectation(pp_state* s, const double bloch_xyz[3], double* out);
  */
 int pp_expectation_noalloc(pp_state* s, const double bloch_xyz[3], double* out);
 
+/*
+ * Largest number of entries (live terms plus those truncated but not yet
+ * compacted) the handle's term store has held since creation: the store
+ * size a propagation needed, which the served form's admission learns from.
+ * Synchronises.  NULL arguments: PP_EINVAL.
+ */
+int pp_peak_terms(pp_state* s, size_t* out);
+
+/*
+ * Device bytes of a term store of `cap` entries for a handle of n_qubits,
+ * group and dtype (both halves, tables and the merge staging, as the
+ * library would allocate them now; no allocation happens).  A handle's
+ * store grows to hold its largest set with headroom (4x below 2^24
+ * entries, 2x below 2^27, 1.5x above), and the old store is freed only
+ * after the new one is filled.  PP_EINVAL for a bad group or size.
+ */
+int pp_store_bytes(int n_qubits, int group, int dtype, size_t cap, size_t* out);
+
 /* Number of live terms. */
 int pp_num_terms(pp_state* s, size_t* out);
 

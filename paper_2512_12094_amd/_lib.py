@@ -69,6 +69,9 @@ def lib():
     L.pp_expectation.argtypes = [_vp, _f64p, _f64p]
     L.pp_expectation_noalloc.argtypes = [_vp, _f64p, _f64p]
     L.pp_num_terms.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.pp_peak_terms.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.pp_store_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_size_t)]
     L.pp_export_terms.argtypes = [_vp, _u64p, _u64p, _f64p, ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_size_t)]
     L.pp_counters.argtypes = [_vp, _u64p]
@@ -221,6 +224,20 @@ def pp_expectation_noalloc(h, bloch) -> float:
     out = ctypes.c_double()
     _check(lib().pp_expectation_noalloc(h, bp, ctypes.byref(out)))
     return out.value
+
+
+def pp_store_bytes(n, group, cap, dtype="f64") -> int:
+    out = ctypes.c_size_t()
+    _check(lib().pp_store_bytes(int(n), PP_GROUP[group] if isinstance(group, str) else int(group),
+                                DTYPES[dtype] if isinstance(dtype, str) else int(dtype),
+                                int(cap), ctypes.byref(out)))
+    return int(out.value)
+
+
+def pp_peak_terms(h) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().pp_peak_terms(h, ctypes.byref(out)))
+    return int(out.value)
 
 
 def pp_num_terms(h) -> int:

@@ -101,6 +101,7 @@ struct pp_state {
   std::vector<std::vector<void*>> retired;   // stores replaced during the call
   void* txn_backup = nullptr;
   uint32_t txn_m = 0, txn_half = 0, txn_parity = 0;
+  bool shrunk = false;                 // a finished batched instance's store was compacted
   const pp_program* batch_prog = nullptr;
   const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
@@ -248,7 +249,10 @@ int read_counters(pp_state* s, uint64_t out[8]) {
 }
 
 // Allocates a store of capacity `cap` (both halves and all tables).
-int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* allocs) {
+// With `dry` set, nothing is allocated or launched: *dry receives the bytes
+// the store would take.
+int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* allocs,
+                size_t* dry = nullptr) {
   const int W = s->W;
   InstBuf nb = s->buf;
   nb.cap = cap;
@@ -262,6 +266,10 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   const size_t ng = size_t(1) << nb.hg_bits, nm = size_t(1) << nb.hm_bits;
   std::vector<void*> got;
   auto take = [&](size_t bytes) -> void* {
+    if (dry) {
+      *dry += (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+      return reinterpret_cast<void*>(uintptr_t(256));
+    }
     void* p = dev_alloc(s, bytes);
     if (p) got.push_back(p);
     return p;
@@ -313,6 +321,7 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
     return fail(PP_ENOMEM, "allocation of a term store of capacity " + std::to_string(cap) +
                                " failed");
   }
+  if (dry) return PP_OK;
   // the tables' initial state in one launch (instead of a fill per array)
   const uint64_t init_elems = std::max<uint64_t>({ng, nm, cap / 8});
   const int init_grid = (int)std::min<uint64_t>(
@@ -1081,6 +1090,7 @@ int create_handle(pp_state** out, int n_qubits, int group, int lx, int dtype,
   InstDyn& d = *s->h_dyn;
   std::memset(&d, 0, sizeof(InstDyn));
   d.M = d.Mnext = (uint32_t)n_obs;
+  d.peak = (uint32_t)n_obs;
   d.gen = 1;
   d.count_for = kNone32;
   d.live = (uint32_t)n_obs;
@@ -1153,6 +1163,38 @@ int pp_create_torus(pp_state** out, int lx, int ly, int dtype, const uint64_t* o
 int pp_work_counters(pp_state* s, uint64_t out[8]) {
   if (!s || !out) return fail(PP_EINVAL, "NULL argument");
   return read_counters(s, out);
+}
+
+int pp_store_bytes(int n_qubits, int group, int dtype, size_t cap, size_t* out) {
+  if (!out) return fail(PP_EINVAL, "NULL argument");
+  if (!valid_group_n(group, n_qubits) && group != PP_GROUP_EXPLICIT)
+    return fail(PP_EINVAL, "unsupported (group, n_qubits)");
+  if (cap == 0 || cap > 0xFFFFFFF0ull) return fail(PP_EINVAL, "cap out of range");
+  pp_state st;
+  st.n = n_qubits;
+  st.W = (n_qubits + 63) / 64;
+  st.group = group;
+  std::memset(&st.buf, 0, sizeof(InstBuf));
+  st.buf.n = n_qubits;
+  st.buf.W = st.W;
+  st.buf.group = group;
+  st.buf.narrow = (group == PP_GROUP_PERMUTATION || n_qubits <= 32) ? 1u : 0u;
+  st.buf.f32 = dtype == PP_F32_COMPENSATED ? 1u : 0u;
+  InstBuf b;
+  std::vector<void*> none;
+  size_t bytes = 0;
+  int rc = alloc_store(&st, (uint32_t)cap, &b, &none, &bytes);
+  if (rc) return rc;
+  *out = bytes;
+  return PP_OK;
+}
+
+int pp_peak_terms(pp_state* s, size_t* out) {
+  if (!s || !out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  *out = s->h_dyn->peak;
+  return PP_OK;
 }
 
 int pp_merge_stats(pp_state* s, uint64_t out[4]) {
@@ -1805,7 +1847,9 @@ int ensure_graph(BatchCtx* b) {
 // dynamic state is copied to pinned memory behind an event, so the host
 // learns of an overflow (or a merge retry) without draining the stream, and
 // only then synchronises, grows and relaunches from the op that stopped.
-int solo_program(pp_state* s, const pp_program* p, double* expectation) {
+// `resume`: continue from the op the device state names (an instance that
+// leaves a batch at a step boundary) instead of starting the program.
+int solo_program(pp_state* s, const pp_program* p, double* expectation, bool resume = false) {
   int rc;
   const hipStream_t st = s->stream;
   const Op* ops = p->ops.data();
@@ -1815,7 +1859,7 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation) {
   s->buf.nopart = 0;
   s->batch_prog = p;
   if ((rc = upload_buf(s))) return rc;
-  hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, st, s->d_dyn, 0u);
+  if (!resume) hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, st, s->d_dyn, 0u);
   // chunk ends: after every kChunkSubs-th sub-layer (its MERGE and the TRUNC
   // that follows it), or the last op; the host reads the state once per chunk
   constexpr int kChunkSubs = 1;
@@ -1831,7 +1875,12 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation) {
     HIP_TRY(hipHostMalloc((void**)&s->solo_slots, sizeof(InstDyn) * 2, hipHostMallocDefault));
     for (auto& e : s->solo_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
-  size_t next_chunk = 0, launched_to = 0;
+  size_t next_chunk = 0, launched_to = resume ? s->h_dyn->pc : 0;
+  while (next_chunk < ends.size() && ends[next_chunk] <= launched_to) ++next_chunk;
+  if (resume && launched_to >= len) {
+    if (expectation) *expectation = s->h_dyn->expect;
+    return PP_OK;
+  }
   std::vector<size_t> inflight;            // chunk indices, oldest first
   for (int guard = 0; guard < 1 << 30; ++guard) {
     while (inflight.size() < 2 && next_chunk < ends.size()) {
@@ -1902,6 +1951,36 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation) {
   return fail(PP_EDEVICE, "program did not complete");
 }
 
+// A finished instance's store holding far more room than its final set
+// is compacted into a store just large enough (the batch's finished
+// instances keep their sets, not their peaks).
+int shrink_finished(pp_state* s) {
+  const InstDyn& d = *s->h_dyn;
+  const uint64_t want = std::max<uint64_t>(4096, 2ull * d.live);
+  if ((uint64_t)s->buf.cap <= 4 * want || s->buf.cap <= (1u << 20)) return PP_OK;
+  InstBuf nb;
+  std::vector<void*> allocs;
+  int rc = alloc_store(s, (uint32_t)want, &nb, &allocs);
+  if (rc) return PP_OK;                    // keeping the larger store is correct too
+  nb.prog = s->buf.prog;
+  nb.prog_len = s->buf.prog_len;
+  nb.nopart = s->buf.nopart;
+  hipLaunchKernelGGL(k_grow, dim3(launch_blocks(d.M)), dim3(kBlock), 0, s->stream, s->buf, nb,
+                     s->d_dyn, s->d_sync);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  free_store(s, s->store);
+  s->store = std::move(allocs);
+  s->buf = nb;
+  if ((rc = upload_buf(s))) return rc;
+  return read_dyn(s);
+}
+
+// Instances whose store has held this many entries leave the batch at the
+// next step boundary and finish on the one-instance path (partitioned
+// merges, the whole GPU), while the rest of the batch waits.
+constexpr uint32_t kPromote = kPartMin;
+
 int batch_common(pp_state* const* states, const pp_program* const* programs, size_t n,
                  void* hip_stream, int max_replays, int* done, double* expectations) {
   if (!states || !programs) return fail(PP_EINVAL, "NULL argument");
@@ -1922,6 +2001,7 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
     pp_state* s = states[i];
     if (s->batch_prog != programs[i]) {
       if (s->h_dyn->status & ST_FAILED) return fail(PP_EINVAL, "state failed in an earlier batch");
+      s->shrunk = false;
       s->buf.prog = programs[i]->d_ops;
       s->buf.prog_len = (uint32_t)programs[i]->ops.size();
       s->batch_prog = programs[i];
@@ -1970,6 +2050,31 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
         HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
                                hipMemcpyHostToDevice, stream));
         continue;
+      }
+      if (s->h_dyn->pc < s->buf.prog_len && s->h_dyn->peak >= kPromote && max_replays < 0) {
+        // a large instance: finish it alone, then put it back (finished)
+        const pp_program* prog = s->batch_prog;
+        double e = 0.0;
+        s->m_hint = s->h_dyn->M;
+        const int g = solo_program(s, prog, &e, true);
+        s->buf.prog = prog->d_ops;
+        s->buf.prog_len = (uint32_t)prog->ops.size();
+        s->buf.nopart = 1;
+        s->batch_prog = prog;
+        if (g) {
+          s->h_dyn->status |= ST_FAILED | ST_OVERFLOW;
+          s->fail_code = g;
+          HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, stream));
+          if ((rc = upload_buf(s))) return rc;
+          continue;
+        }
+        if ((rc = upload_buf(s))) return rc;
+        b->h_gather[i] = *s->h_dyn;
+      }
+      if (s->h_dyn->pc >= s->buf.prog_len && !s->shrunk) {
+        if ((rc = shrink_finished(s))) return rc;
+        s->shrunk = true;
       }
       all_done = all_done && s->h_dyn->pc >= s->buf.prog_len;
     }

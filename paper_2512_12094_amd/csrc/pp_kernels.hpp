@@ -1688,6 +1688,7 @@ struct GateKindT {
     d.appended += ld_agent(&d.Mnext) - d.M;
     d.M = ld_agent(&d.Mnext);
     d.Mnext = d.M;
+    if (d.M > d.peak) d.peak = d.M;
     d.parity ^= 1u;
     take_acc(d);
     d.count_for = op.next_gate;

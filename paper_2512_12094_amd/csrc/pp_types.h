@@ -205,6 +205,7 @@ struct InstDyn {
   uint32_t phot;         // buckets split over several blocks (hot representatives)
   uint32_t pover;        // buckets summed in several selector passes
   uint32_t pglob;        // keys that went through the global merge table
+  uint32_t peak;         // most entries (live and not yet compacted) the store held
 };
 
 }  // namespace pp

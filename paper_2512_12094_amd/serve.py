@@ -11,12 +11,17 @@ Every iteration of the event loop
 3. advances every admitted job together by a few batched steps
    (pp_batch_step: one persistent launch per kernel kind serves all jobs);
 4. retires finished jobs (expectation, latency = finish - arrival) and frees
-   their memory; a job whose store outgrew its estimate is re-queued with
-   four times the estimate (it restarts from its observable, nothing is
-   reused), and rejected once it has failed at the largest estimate the
-   store limit allows, or would not fit the whole budget (its result then
-   says so).  A failure also raises the starting estimate of later jobs of
-   the same class.
+   their memory; the estimator learns the job's peak store size as the
+   device tracked it (pp_peak_terms); a job whose store outgrew its estimate
+   is re-queued with four times the estimate (it restarts from its
+   observable, nothing is reused), and rejected once it has failed at the
+   largest estimate the store limit or the whole budget allows (its result
+   then says so).  A failure also raises the starting estimate of later
+   jobs of the same class.
+
+Memory is accounted by the bytes the library would allocate for the job's
+store at its limit (pp_store_bytes), and an estimate is lowered to what the
+whole budget holds, so a job alone never exceeds it either.
 
 Jobs that arrive while others run join at the next iteration.  The GPU work
 goes through an engine object so the policy can be exercised on the CPU with
@@ -55,6 +60,7 @@ class JobResult:
     retries: int = 0
     est_terms: int = 0
     rejected: bool = False
+    unfinished: bool = False      # stopped by the server's time budget
 
     @property
     def latency(self) -> float:
@@ -111,12 +117,22 @@ class GpuEngine:
         return done, e
 
     def finish(self, handle):
+        """Work units and the largest store (entries) the job needed, as the
+        device tracked it."""
         ps, _ = handle
         wc = self.L.pp_work_counters(ps.h)
         units = wc["propagated"] + wc["merged"]
-        peak = max(wc["merge_in"], 1)
+        peak = max(self.L.pp_peak_terms(ps.h), 1)
         ps.close()
         return units, peak
+
+    def job_bytes(self, prog: Program, est: int) -> int:
+        """Device bytes of a job allowed `est` terms: its store at the limit
+        it is started with (4 est entries), plus half that for the copy while
+        the store last grew."""
+        cap = max(4096, 4 * int(est))
+        b = self.L.pp_store_bytes(prog.n, prog.group, cap)
+        return b + b // 2
 
     def abort(self, handle):
         handle[0].close()
@@ -133,9 +149,23 @@ class Server:
     max_retries: int = 8
     growth: int = 4                        # estimate factor after a failure
 
-    def run(self, jobs, on_event=None):
+    def job_bytes(self, prog: Program, est: int) -> float:
+        fn = getattr(self.engine, "job_bytes", None)
+        return fn(prog, est) if fn else est * bytes_per_term(prog.n)
+
+    def fit_estimate(self, prog: Program, est: int) -> int:
+        """The estimate, lowered if needed until the job fits the whole
+        budget (a job alone may use all of it); 0 if not even the smallest
+        store fits."""
+        est = max(1, int(est))
+        while est > 1024 and self.job_bytes(prog, est) > self.hbm_budget:
+            est //= 2
+        return est if self.job_bytes(prog, est) <= self.hbm_budget else 0
+
+    def run(self, jobs, on_event=None, time_budget=None):
         """Serves `jobs` (objects with .arrival and .program); returns
-        JobResult per job in input order."""
+        JobResult per job in input order.  With `time_budget` (seconds),
+        jobs not finished by then are stopped and marked unfinished."""
         order = sorted(range(len(jobs)), key=lambda i: jobs[i].arrival)
         pending = deque(order)
         waiting = deque()
@@ -147,15 +177,29 @@ class Server:
         t0 = self.clock()
         while pending or waiting or active:
             now = self.clock() - t0
+            if time_budget is not None and now > time_budget:
+                for i, handle, need, est in active:
+                    self.engine.abort(handle)
+                    results[i].unfinished = True
+                for i in list(waiting) + list(pending):
+                    results[i].unfinished = True
+                break
             while pending and jobs[pending[0]].arrival <= now:
                 waiting.append(pending.popleft())
             # admission, in arrival order
             while waiting and len(active) < self.max_active:
                 i = waiting[0]
                 prog = jobs[i].program
-                est = max(results[i].est_terms, self.estimator.estimate(prog))
-                need = est * bytes_per_term(prog.n)
-                if active and used + need > self.hbm_budget:
+                est = self.fit_estimate(prog, max(results[i].est_terms,
+                                                  self.estimator.estimate(prog)))
+                if est == 0:                       # no store fits the budget
+                    waiting.popleft()
+                    results[i].rejected, results[i].finished = True, now
+                    if on_event:
+                        on_event("reject", i, used)
+                    continue
+                need = self.job_bytes(prog, est)
+                if used + need > self.hbm_budget:
                     break
                 waiting.popleft()
                 results[i].est_terms = est
@@ -191,8 +235,8 @@ class Server:
                     prog = jobs[i].program
                     self.estimator.failed(prog, 4 * est)
                     if (r.retries > self.max_retries or est >= self.estimator.cap_terms or
-                            min(new_est, self.estimator.cap_terms) * bytes_per_term(prog.n) >
-                            self.hbm_budget):
+                            self.fit_estimate(prog, min(new_est, self.estimator.cap_terms))
+                            <= est):
                         r.rejected, r.finished = True, now
                         if on_event:
                             on_event("reject", i, used)
@@ -209,11 +253,13 @@ class Server:
 
 def summarize(results, wall: float) -> dict:
     """Latency percentiles over the completed jobs, throughput over all
-    completed work, counts of retries and rejections."""
-    done = [r for r in results if not r.rejected]
+    completed work, counts of retries, rejections and unfinished jobs."""
+    done = [r for r in results if not r.rejected and not r.unfinished]
     lat = np.array([r.latency for r in done]) if done else np.array([math.nan])
     units = sum(r.units for r in done)
-    return dict(jobs=len(results), completed=len(done), rejected=len(results) - len(done),
+    return dict(jobs=len(results), completed=len(done),
+                rejected=sum(r.rejected for r in results),
+                unfinished=sum(r.unfinished for r in results),
                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 mean_s=float(lat.mean()),
                 terms_per_s=units / wall if wall > 0 else float("nan"), wall_s=wall,

@@ -100,3 +100,43 @@ def test_batch_instance_failure_is_isolated(gpu):
     compare_expectation(e[0], ref.expectation, ref.terms, what="good")
     for s in sets:
         s.close()
+
+
+def test_batch_promotes_a_large_instance(gpu):
+    """A batch holding one instance that grows past 2^18 stored entries (the
+    at-scale Z_32 ring over 12 sub-layers) beside small ones: the large one
+    leaves the batch and finishes on the one-instance path (partitioned
+    merges), the others stay batched.  Every instance equals its solo run
+    bitwise (set, coefficients, expectation, counters); the small ones also
+    match the oracle."""
+    from paper_2512_12094_amd import driver, _lib as L
+    big = W.xxz_ring(32, 5, 0.2, 1.5, eps=1e-6, wmax=12, obs=W.sum_ring_pairs(32, "X"),
+                     name="ring32_scale")
+    progs = [prefix(big, 12)] + [prefix(p, 2) for p in W.config4()[:5]]
+    print("[case] batch with a large instance", [(p.n, len(p.sublayers)) for p in progs],
+          flush=True)
+    old = L.pp_get_tuning()
+    L.pp_set_tuning(graph_steps=8)                 # step boundaries inside the program
+    try:
+        e, sets, dprogs, wall = driver.batch_propagate(progs, gpu["handle"], gpu["alloc"])
+    finally:
+        L.pp_set_tuning(graph_steps=old["graph_steps"])
+    assert L.pp_peak_terms(sets[0].h) >= 1 << 18
+    assert L.pp_merge_stats(sets[0].h)["partitioned_merges"] >= 1
+    for k, (p, ei, s) in enumerate(zip(progs, e, sets)):
+        got = s.as_dict()
+        cnt = s.counters()
+        solo_ps = driver.PauliSet.from_program(p, None, gpu["handle"], gpu["alloc"])
+        dp = driver.device_program(p)
+        es = float(L.pp_batch_run([solo_ps.h], [dp.h], gpu["handle"])[0])
+        assert ei == es, (p.name, ei, es)
+        assert got == solo_ps.as_dict(), p.name
+        assert cnt == solo_ps.counters(), p.name
+        solo_ps.close()
+        dp.close()
+        if k:
+            ref = O.run_program(p)
+            compare_terms(got, ref.terms, p.meta["eps"], what=p.name)
+        s.close()
+    for d in dprogs:
+        d.close()

@@ -119,3 +119,35 @@ def test_partitioned_merge_ragged_sizes(gpu):
         want = O.merge_records(32, "Zn", x, z, c)
         check_bitwise(terms, want, wc, len(c))
         assert st["partitioned_merges"] == 1, st
+
+
+def test_program_path_merges_above_partition_threshold(gpu):
+    """The device program of a Z_32 XXZ ring (theta 0.2, eps 1e-6, weight
+    <= 12; the benchmark's at-scale workload) over its first 8 sub-layers:
+    the last symmetry merges take ~3x10^5 records, above the partitioned
+    path's threshold, between gates with exact merges and truncation.
+    Against the oracle by the FP64 rules (sets, coefficients, expectation,
+    work counters)."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from tests.parity import compare_expectation, compare_terms
+    full = W.xxz_ring(32, 5, 0.2, 1.5, eps=1e-6, wmax=12, obs=W.sum_ring_pairs(32, "X"),
+                      name="ring32_scale")
+    k = 8
+    prog = W.Program(f"{full.name}[:{k}]", full.n, full.group, full.obs,
+                     full.sublayers[len(full.sublayers) - k:], full.bloch, dict(full.meta))
+    print(f"[case] program path {prog.name}", flush=True)
+    dp = driver.device_program(prog)
+    ps = driver.PauliSet.from_program(prog, None, gpu["handle"], gpu["alloc"])
+    e = float(L.pp_batch_run([ps.h], [dp.h], gpu["handle"])[0])
+    st = L.pp_merge_stats(ps.h)
+    prop, merged = ps.counters()
+    terms = ps.as_dict()
+    ps.close()
+    dp.close()
+    assert st["partitioned_merges"] >= 1, st
+    ref = O.run_program(prog)
+    n, skipped = compare_terms(terms, ref.terms, 1e-6, what=prog.name)
+    assert n > 200000
+    compare_expectation(e, ref.expectation, ref.terms, what=prog.name)
+    assert (prop, merged) == (ref.propagated, ref.merged)

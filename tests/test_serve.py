@@ -142,3 +142,47 @@ def test_summary():
     s = serve.summarize(rs, 4.0)
     assert s["terms_per_s"] == 10.0 and s["jobs"] == 2
     assert 1.0 <= s["p50_s"] <= 3.0
+
+
+def test_a_job_alone_never_exceeds_the_budget():
+    """An estimate larger than the whole budget is lowered to what the budget
+    holds (the job then runs alone within it); a job whose smallest store
+    does not fit is rejected without running."""
+    clock = FakeClock()
+    jobs = make_jobs(3)
+    eng = FakeEngine(clock, {j.program.name: 3 for j in jobs},
+                     {j.program.name: 500 for j in jobs})
+    per_term = serve.bytes_per_term(16)
+    budget = 4000 * per_term
+    est = serve.Estimator(prior=1 << 20)                 # far above the budget
+    srv = serve.Server(eng, budget, estimator=est, clock=clock, sleep=clock.sleep)
+    res = srv.run(jobs)
+    assert srv.peak_used <= budget
+    assert all(not r.rejected for r in res)
+    assert all(max_terms <= 4 * 4000 for _, max_terms in eng.started)
+    tiny = serve.Server(FakeEngine(clock, {j.program.name: 1 for j in jobs},
+                                   {j.program.name: 1 for j in jobs}),
+                        10 * per_term, clock=clock, sleep=clock.sleep)
+    assert all(r.rejected for r in tiny.run(jobs))
+
+
+def test_time_budget_stops_unfinished_jobs():
+    clock = FakeClock()
+    jobs = make_jobs(10, gap=0.0)
+    eng = FakeEngine(clock, {j.program.name: 1000 for j in jobs},
+                     {j.program.name: 10 for j in jobs})
+    srv = serve.Server(eng, 1e12, clock=clock, sleep=clock.sleep)
+    res = srv.run(jobs, time_budget=0.5)
+    assert all(r.unfinished for r in res)
+    s = serve.summarize(res, 0.5)
+    assert s["completed"] == 0 and s["unfinished"] == 10
+
+
+def test_estimator_learns_the_peak_the_engine_reports():
+    clock = FakeClock()
+    jobs = make_jobs(2)
+    eng = FakeEngine(clock, {j.program.name: 2 for j in jobs},
+                     {j.program.name: 777 for j in jobs})
+    est = serve.Estimator(prior=1 << 12)
+    serve.Server(eng, 1e12, estimator=est, clock=clock, sleep=clock.sleep).run(jobs)
+    assert est.estimate(jobs[0].program) == 2 * 777

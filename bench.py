@@ -64,11 +64,14 @@ def parse():
     ap.add_argument("--no-scale", action="store_true", help="skip the gate-at-scale leg")
     ap.add_argument("--no-ising", action="store_true", help="skip the Ising layers leg")
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--batch-sublayers", type=int, default=12)
-    ap.add_argument("--serve-count", type=int, default=200)
-    ap.add_argument("--serve-sublayers", type=int, default=3)
-    ap.add_argument("--serve-cap-terms", type=int, default=1 << 24,
+    ap.add_argument("--batch-cap-terms", type=int, default=1 << 26,
+                    help="store limit (entries) of a batched instance at full depth")
+    ap.add_argument("--serve-count", type=int, default=600)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-cap-terms", type=int, default=1 << 25,
                     help="largest estimate a served job may reach (store = 4x)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the all-to-all leg")
+    ap.add_argument("--cpu-pool-seconds", type=float, default=15.0)
     return ap.parse_args()
 
 
@@ -250,23 +253,38 @@ def ising_layers_leg(stream, alloc, n=12, layers=(2, 4, 6, 8, 10), dt=0.25):
                 necklaces=neck, rows=rows)
 
 
-def batched_leg(stream, alloc, count, sublayers):
-    """Batched ring instances (uneven n, depth, angles, thresholds; each cut
-    to its first `sublayers` sub-layers): one batched run against a loop of
-    single-instance runs over the same instances, and the batched run with
-    FP32 coefficients (largest relative deviation of its expectations from
-    the FP64 ones).  All include creating each instance's set from its
-    observable."""
+def batched_leg(stream, alloc, count, cap_terms):
+    """The batched ring workload at full depth (every instance's whole
+    program).  A first pass runs every instance alone with a store limit of
+    `cap_terms` entries and keeps the instances that finish within it (the
+    others, listed, would need more); on those: one batched run (FP64), the
+    same batched with FP32 coefficients (largest relative deviation of its
+    expectations from FP64), and a loop of single-instance runs, all timed
+    from creating each set from its observable."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
     from paper_2512_12094_amd import workloads as W
     import torch
-    progs = [prefix(p, sublayers) for p in W.config4()[:count]]
-    dps = [driver.device_program(p) for p in progs]
+    allp = W.config4()[:count]
+    keep, excluded = [], []
+    for p in allp:
+        dp = driver.device_program(p)
+        ps = driver.PauliSet.from_program(p, None, stream, alloc)
+        L.pp_set_max_terms(ps.h, cap_terms)
+        try:
+            L.pp_batch_run([ps.h], [dp.h], stream)
+            keep.append(p)
+        except L.PPError:
+            excluded.append(dict(name=p.name, n=p.n, sublayers=len(p.sublayers)))
+        ps.close()
+        dp.close()
+    print(f"[bench] batched: {len(keep)} of {len(allp)} instances fit {cap_terms} entries",
+          file=sys.stderr, flush=True)
+    dps = [driver.device_program(p) for p in keep]
 
     def solo_loop():
         es, units = [], 0
-        for p, dp in zip(progs, dps):
+        for p, dp in zip(keep, dps):
             ps = driver.PauliSet.from_program(p, None, stream, alloc)
             es.append(float(L.pp_batch_run([ps.h], [dp.h], stream)[0]))
             wc = L.pp_work_counters(ps.h)
@@ -275,7 +293,7 @@ def batched_leg(stream, alloc, count, sublayers):
         return es, units
 
     def batch(dtype="f64"):
-        sets = [driver.PauliSet.from_program(p, None, stream, alloc, dtype) for p in progs]
+        sets = [driver.PauliSet.from_program(p, None, stream, alloc, dtype) for p in keep]
         e = L.pp_batch_run([s.h for s in sets], [d.h for d in dps], stream)
         units = 0
         for s in sets:
@@ -285,9 +303,10 @@ def batched_leg(stream, alloc, count, sublayers):
         return [float(v) for v in e], units
 
     out = {}
-    for name, fn in (("per_instance", solo_loop), ("batched", batch),
-                     ("batched_f32", lambda: batch("f32"))):
-        fn()                                   # warm (graph capture, allocator)
+    for name, fn in (("batched", batch), ("batched_f32", lambda: batch("f32")),
+                     ("per_instance", solo_loop)):
+        if name != "per_instance":
+            fn()                               # warm (graph capture, allocator)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         es, units = fn()
@@ -297,92 +316,273 @@ def batched_leg(stream, alloc, count, sublayers):
         out[name + "_e"] = es
     e32 = out.pop("batched_f32_e")
     same = sum(a == b for a, b in zip(out.pop("per_instance_e"), out["batched_e"]))
+    e64 = out.pop("batched_e")
     out["batched_f32"]["max_rel_dev_from_f64"] = max(
-        abs(a - b) / max(abs(b), 1e-300) for a, b in zip(e32, out.pop("batched_e")))
-    out.update(instances=len(progs), sublayers_each=sublayers,
-               gates=sum(p.n_gates for p in progs),
+        abs(a - b) / max(abs(b), 1e-300) for a, b in zip(e32, e64))
+    out["batched_f32"]["max_abs_dev_over_n"] = max(
+        abs(a - b) / p.n for a, b, p in zip(e32, e64, keep))
+    out.update(instances=len(allp), full_depth_completed=len(keep),
+               excluded_over_store_limit=len(excluded), store_limit_entries=cap_terms,
+               excluded_n=sorted({e["n"] for e in excluded}),
+               gates=sum(p.n_gates for p in keep),
                speedup=round(out["batched"]["value"] / out["per_instance"]["value"], 3),
-               bitwise_equal_expectations=f"{same}/{len(progs)}",
+               bitwise_equal_expectations=f"{same}/{len(keep)}",
                knobs=L.pp_get_tuning())
-    return out
+    for d in dps:
+        d.close()
+    return out, keep
 
 
-def served_leg(stream, alloc, count, sublayers, cap_terms, seed=5):
-    """Continuous batching of a mixed job stream (rings and all-to-all
-    Heisenberg jobs, each cut to its first `sublayers` sub-layers).  A first,
-    untimed pass serves every job once (the estimator learns peak sizes per
-    job class; a job whose store would exceed 4 x cap_terms entries is
-    rejected and listed).  On the jobs that completed, the leg then times:
-    a loop of single-instance runs; serving them all arriving at once (the
-    capacity); serving them with Poisson arrivals at 0.8 x that rate (p50 /
-    p99 latency)."""
+def served_leg(stream, alloc, count, cap_terms, seconds, seed=5):
+    """Continuous batching of the mixed job stream at full depth (config 5:
+    rings and all-to-all Heisenberg jobs), on its first `count` jobs.
+    1. Per-instance pass: every job alone (one-instance program path) with a
+       store limit of 4 x cap_terms entries; the jobs that finish within it
+       are served below (the others, listed by kind, need more), their
+       device-tracked peak store sizes seed the estimator, and their summed
+       wall time is the per-instance loop's.
+    2. Burst: those jobs all arriving at once (the capacity).
+    3. Poisson arrivals at 0.8 x that rate, for at most `seconds`.
+    p50 / p99 latency over the jobs served."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
     from paper_2512_12094_amd import serve
     from paper_2512_12094_amd import workloads as W
     import numpy as np
     import torch
-    jobs = [W.Job(0.0, prefix(j.program, sublayers)) for j in W.config5(count=count)]
+    jobs = W.config5(count=count)              # the same first jobs as the full stream
+    torch.cuda.empty_cache()                   # what earlier legs left cached
     free, _ = torch.cuda.mem_get_info()
     budget = 0.8 * free
     est = serve.Estimator(cap_terms=cap_terms)
+    ok, over = [], []
+    wall_solo, units_solo = 0.0, 0
+    for j in jobs:
+        dp = driver.device_program(j.program)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ps = driver.PauliSet.from_program(j.program, None, stream, alloc)
+        L.pp_set_max_terms(ps.h, 4 * cap_terms)
+        try:
+            L.pp_batch_run([ps.h], [dp.h], stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            wc = L.pp_work_counters(ps.h)
+            wall_solo += dt
+            units_solo += wc["propagated"] + wc["merged"]
+            est.observe(j.program, L.pp_peak_terms(ps.h))
+            ok.append(j)
+        except L.PPError:
+            over.append(j)
+        ps.close()
+        dp.close()
+    print(f"[bench] served: {len(ok)} of {len(jobs)} jobs fit {4 * cap_terms} entries",
+          file=sys.stderr, flush=True)
     eng = serve.GpuEngine(stream, alloc, steps_per_iter=16)
 
-    def run(js, label):
+    def run(js, label, budget_s=None):
         srv = serve.Server(eng, budget, estimator=est)
         ended = [0]
 
         def progress(kind, i, used):
             if kind in ("finish", "reject"):
                 ended[0] += 1
-                if ended[0] % 25 == 0:
+                if ended[0] % 100 == 0:
                     print(f"[bench] served ({label}): {ended[0]}/{len(js)} jobs ended",
                           file=sys.stderr, flush=True)
 
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = srv.run(js, on_event=progress)
+        res = srv.run(js, on_event=progress, time_budget=budget_s)
         torch.cuda.synchronize()
         return res, time.perf_counter() - t0
 
-    first, _ = run(jobs, "learning")
-    done = [j for j, r in zip(jobs, first) if not r.rejected]
-    rejected = sorted({f"{j.program.group} n={j.program.n}"
-                       for j, r in zip(jobs, first) if r.rejected})
-
-    # single-instance loop over the same jobs
-    dps = [driver.device_program(j.program) for j in done]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    units_solo = 0
-    for j, dp in zip(done, dps):
-        ps = driver.PauliSet.from_program(j.program, None, stream, alloc)
-        L.pp_set_max_terms(ps.h, 4 * cap_terms)
-        L.pp_batch_run([ps.h], [dp.h], stream)
-        wc = L.pp_work_counters(ps.h)
-        units_solo += wc["propagated"] + wc["merged"]
-        ps.close()
-    torch.cuda.synchronize()
-    wall_solo = time.perf_counter() - t0
-
-    burst, wall_b = run(done, "burst")
-    rate = 0.8 * len(done) / wall_b
-    rng = np.random.default_rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=len(done)))
-    timed = [W.Job(float(a), j.program) for a, j in zip(t, done)]
-    res, wall = run(timed, "Poisson")
-    summ = serve.summarize(res, wall)
+    run([W.Job(0.0, j.program) for j in ok[:32]], "warm")
+    burst, wall_b = run([W.Job(0.0, j.program) for j in ok], "burst")
     burst_s = serve.summarize(burst, wall_b)
-    summ.update(sampled_jobs=len(jobs), sublayers_each=sublayers,
-                store_limit_terms=4 * cap_terms, rejected_in_learning_pass=len(jobs) - len(done),
-                rejected_kinds=rejected, ring_jobs=sum(j.program.group == "Zn" for j in done),
+    rate = 0.8 * len(ok) / wall_b
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=len(ok)))
+    timed = [W.Job(float(a), j.program) for a, j in zip(t, ok)]
+    res, wall = run(timed, "Poisson", seconds)
+    summ = serve.summarize(res, wall)
+    per = units_solo / wall_solo if wall_solo else None
+    summ.update(workload=f"config 5 at full depth, the first {count} of its 2000 jobs (Poisson "
+                         "arrivals of 70% Z_n rings and 30% S_n all-to-all jobs)",
+                jobs_fitting_store_limit=len(ok), store_limit_entries=4 * cap_terms,
+                over_limit_kinds=sorted({f"{j.program.group} n={j.program.n}" for j in over}),
+                over_limit_jobs=len(over), time_budget_s=seconds,
                 arrival_rate_per_s=round(rate, 2),
-                burst=dict(terms_per_s=burst_s["terms_per_s"], wall_s=round(wall_b, 4),
-                           jobs_per_s=round(len(done) / wall_b, 2), p99_s=burst_s["p99_s"]),
-                per_instance=dict(terms_per_s=units_solo / wall_solo, wall_s=round(wall_solo, 4)),
-                burst_vs_per_instance=round(burst_s["terms_per_s"] / (units_solo / wall_solo), 3),
+                burst=dict(jobs=len(ok), completed=burst_s["completed"],
+                           terms_per_s=burst_s["terms_per_s"], wall_s=round(wall_b, 4),
+                           p99_s=burst_s["p99_s"]),
+                per_instance=dict(terms_per_s=per, wall_s=round(wall_solo, 4)),
+                burst_vs_per_instance=round(burst_s["terms_per_s"] / per, 3) if per else None,
                 hbm_budget_GB=round(budget / 1e9, 1))
-    return summ
+    return summ, timed
+
+
+def c3_leg(stream, alloc, k=2):
+    """Config 3 (S_64 all-to-all Heisenberg, 2016 pair rotations per
+    sub-layer, damping p = 1e-3, eps = 1e-5) over its first k sub-layers in
+    Heisenberg order, FP64 and FP32 coefficients: terms/s, the expectation,
+    and the FP32 coefficients' deviation from FP64 per decade.  Then the
+    first k + 1 sub-layers once more with the store allowed 2^31 - 1
+    entries, which reports how many entries the next sub-layer needs."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from paper_2512_12094_amd import workloads as W
+    import torch
+    c3 = W.config3()
+    prog = prefix(c3, k)
+    dp = driver.device_program(prog)
+    res = {}
+    for dtype in ("f64", "f32"):
+        best = None
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ps = driver.PauliSet.from_program(prog, None, stream, alloc, dtype)
+            e = float(L.pp_batch_run([ps.h], [dp.h], stream)[0])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            wc = L.pp_work_counters(ps.h)
+            peak = L.pp_peak_terms(ps.h)
+            terms = ps.as_dict()
+            ps.close()
+            best = wall if best is None else min(best, wall)
+        units = wc["propagated"] + wc["merged"]
+        res[dtype] = dict(value=units / best, unit="terms/s", wall_s=round(best, 4), units=units,
+                          expectation=e, peak_entries=peak, representatives=len(terms))
+        res[dtype + "_terms"] = terms
+    t64, t32 = res.pop("f64_terms"), res.pop("f32_terms")
+    scale = max(abs(v) for v in t64.values())
+    by_dec = {}
+    for key, b in t64.items():
+        if key in t32 and b != 0.0:
+            dec = int(math.floor(math.log10(abs(b))))
+            by_dec[dec] = max(by_dec.get(dec, 0.0), abs(t32[key] - b) / abs(b))
+    res["f32_vs_f64"] = dict(expectation_rel=abs(res["f32"]["expectation"] - res["f64"]["expectation"])
+                             / max(abs(res["f64"]["expectation"]), 1e-300),
+                             coef_rel_by_decade={str(k2): v for k2, v in sorted(by_dec.items())},
+                             max_abs_over_max_coef=max(abs(t32.get(k2, 0.0) - v)
+                                                       for k2, v in t64.items()) / scale)
+    dp.close()
+    nxt = prefix(c3, k + 1)
+    dpn = driver.device_program(nxt)
+    ps = driver.PauliSet.from_program(nxt, None, stream, alloc)
+    L.pp_set_max_terms(ps.h, (1 << 31) - 1)
+    try:
+        L.pp_batch_run([ps.h], [dpn.h], stream)
+        res["next_sublayer"] = dict(fits=True, peak_entries=L.pp_peak_terms(ps.h))
+    except L.PPError as ex:
+        res["next_sublayer"] = dict(fits=False, peak_entries=L.pp_peak_terms(ps.h),
+                                    message=str(ex)[:160])
+    ps.close()
+    dpn.close()
+    res.update(workload=f"config 3, first {k} of {len(c3.sublayers)} sub-layers (Heisenberg "
+                        "order); the full depth needs more entries inside sub-layer "
+                        f"{k + 1} than a store indexes (2^31)" if not res["next_sublayer"]["fits"]
+               else f"config 3, first {k} sub-layers")
+    return res
+
+
+# ---------------------------------------------------------------------------
+# CPU baselines of the batched and served forms (oracle, host cores)
+# ---------------------------------------------------------------------------
+def _oracle_job(args):
+    """Worker: Algorithm 1 for one program on the oracle, stopping after the
+    gate at which the wall clock passes `deadline` (time.time()).  Returns
+    (work units done, seconds, finished)."""
+    prog, deadline = args
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    o = O.Oracle(prog.n, prog.group, prog.meta.get("lx", 0), prog.meta.get("perms"))
+    for (x, z, c) in prog.obs:
+        o.add(x, z, c)
+    o.merge()
+    finished = True
+    for sub in reversed(prog.sublayers):
+        if sub.p > 0:
+            o.damp(sub.p)
+        for g in reversed(sub.gates):
+            if time.time() > deadline:
+                finished = False
+                break
+            o.apply_gate(g.x, g.z, g.theta, sub.eps, sub.wmax)
+        if not finished:
+            break
+        if getattr(sub, "merge", True):
+            o.merge()
+        o.truncate(sub.eps, sub.wmax)
+    if finished:
+        o.expectation(prog.bloch)
+    prop, merged = o.counters()
+    return prop + merged, time.perf_counter() - t0, finished
+
+
+def _host_program(prog):
+    """The program without the device objects cached on it (they do not
+    cross a process boundary)."""
+    import dataclasses
+    return dataclasses.replace(prog, meta={k: v for k, v in prog.meta.items()
+                                           if not k.startswith("_")})
+
+
+def cpu_pool_baseline(progs, seconds, workers):
+    """The oracle over the batched instances on `workers` host processes,
+    each instance until `seconds` have passed (a bounded sample)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))          # workers started before the clock
+        deadline = time.time() + seconds
+        t0 = time.perf_counter()
+        out = pool.map(_oracle_job, [(_host_program(p), deadline) for p in progs[:workers]])
+    wall = time.perf_counter() - t0
+    units = sum(u for u, _, _ in out)
+    return dict(value=units / wall, unit="terms/s", cores=workers, kind="oracle",
+                sample=f"the first {len(out)} batched instances, one per process, each for at "
+                       f"most {seconds:.0f} s ({sum(d for _, _, d in out)} finished; {units} "
+                       f"terms in {wall:.1f} s)")
+
+
+def cpu_served_baseline(timed_jobs, seconds, workers):
+    """The served job stream on the oracle: `workers` host processes take
+    the jobs FIFO at their arrival times, each job allowed what is left of
+    `seconds`; latency = (time its result was ready) - arrival, over the jobs
+    that finished."""
+    import multiprocessing as mp
+    import numpy as np
+    ctx = mp.get_context("spawn")
+    ready, handles, errors = [], [], []
+    progs = [_host_program(j.program) for j in timed_jobs]
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))          # workers started before the clock
+        deadline = time.time() + seconds
+        t0 = time.perf_counter()
+        for j, prog in zip(timed_jobs, progs):
+            now = time.perf_counter() - t0
+            if j.arrival > seconds or now > seconds:
+                break
+            if j.arrival > now:
+                time.sleep(j.arrival - now)
+            cb = (lambda r, a=j.arrival: ready.append((a, time.perf_counter() - t0, r)))
+            handles.append(pool.apply_async(_oracle_job, ((prog, deadline),), callback=cb,
+                                            error_callback=errors.append))
+        for h in handles:
+            h.wait()
+    if errors:
+        raise RuntimeError(f"oracle worker failed: {errors[0]!r}")
+    wall = time.perf_counter() - t0
+    units = sum(r[0] for _, _, r in ready)
+    lat = np.array([f - a for a, f, r in ready if r[2]])
+    return dict(value=units / wall, unit="terms/s", cores=workers, kind="oracle",
+                jobs_submitted=len(handles), jobs_finished=int(lat.size),
+                p50_s=float(np.percentile(lat, 50)) if lat.size else None,
+                p99_s=float(np.percentile(lat, 99)) if lat.size else None,
+                sample=f"the served job stream's first {len(handles)} arrivals on {workers} "
+                       f"oracle processes (FIFO) for {seconds:.0f} s")
 
 
 def pmc_traffic(bytes_launches, name="k_gate_c2_z32_pmc.json"):
@@ -549,15 +749,21 @@ def main():
         if not args.no_scale:
             scale = gate_scale_leg(stream, alloc)
             print(f"[bench] gate-at-scale leg done", file=sys.stderr, flush=True)
+        c3 = None
+        if not args.no_c3:
+            c3 = c3_leg(stream, alloc)
+            print(f"[bench] all-to-all leg done", file=sys.stderr, flush=True)
         batched = served = None
+        batch_progs = served_jobs = None
         if not args.no_batched:
             tuned_batch = autotune.apply(autotune.class_key("batch", "Zn"))
-            batched = batched_leg(stream, alloc, args.batch_count, args.batch_sublayers)
+            batched, batch_progs = batched_leg(stream, alloc, args.batch_count,
+                                               args.batch_cap_terms)
             batched["tuned"] = tuned_batch is not None
             print(f"[bench] batched leg done", file=sys.stderr, flush=True)
         if not args.no_served:
-            served = served_leg(stream, alloc, args.serve_count, args.serve_sublayers,
-                                args.serve_cap_terms)
+            served, served_jobs = served_leg(stream, alloc, args.serve_count,
+                                             args.serve_cap_terms, args.serve_seconds)
             print(f"[bench] served leg done", file=sys.stderr, flush=True)
 
     out = {
@@ -588,6 +794,7 @@ def main():
         "variants": variants,
         "tuning": {"single": tuned_single, "source": autotune.cache_path()},
         "merge_pass": mp,
+        "all_to_all_c3": c3,
         "batched": batched,
         "served": served,
         "host": host_info(),
@@ -595,6 +802,13 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prog, args.cpu_seconds)
+        workers = max(1, min(16, os.cpu_count() or 1))
+        if batch_progs:
+            batched["cpu_baseline"] = cpu_pool_baseline(batch_progs, args.cpu_pool_seconds,
+                                                        workers)
+        if served_jobs:
+            served["cpu_baseline"] = cpu_served_baseline(served_jobs, args.cpu_pool_seconds,
+                                                         workers)
     print(json.dumps(out), flush=True)
 
 

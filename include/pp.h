@@ -373,8 +373,12 @@ int pp_program_info(const pp_program* p, uint64_t out[3]);
  * Runs programs[i] on states[i] for i < n (n <= 1024), all instances
  * advancing together: every step is one pass of a fixed sequence of
  * persistent kernels that serve all instances at once, and steps are
- * replayed from a captured HIP graph.  Each state must have been created on
- * `hip_stream` with the program's n_qubits.  On return
+ * replayed from a captured HIP graph.  An instance whose store has held
+ * 2^18 entries leaves the batch at the next step boundary and finishes
+ * alone (the one-instance path, whose large merges are partitioned) while
+ * the others wait; results do not depend on it (exact sums).  Each state
+ * must have been created on `hip_stream` with the program's n_qubits.  On
+ * return
  * expectations[i] (host array, may be NULL) holds Tr[rho O] of instance i.
  */
 int pp_batch_run(pp_state* const* states, const pp_program* const* programs,
@@ -387,7 +391,8 @@ int pp_batch_run(pp_state* const* states, const pp_program* const* programs,
  * 0 for running ones and -1 for one whose term store could not grow
  * (allocator failure or pp_set_max_terms); a failed instance stops, the
  * others continue, and the call still returns PP_OK.  Instances may join or
- * leave between calls.  A state starts its program at the first
+ * leave between calls.  An instance promoted as in pp_batch_run finishes
+ * within the call that promotes it.  A state starts its program at the first
  * pp_batch_step/pp_batch_run call that lists it with that program.
  * pp_batch_run returns the first failure's code instead.
  */

@@ -2051,7 +2051,7 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
                                hipMemcpyHostToDevice, stream));
         continue;
       }
-      if (s->h_dyn->pc < s->buf.prog_len && s->h_dyn->peak >= kPromote && max_replays < 0) {
+      if (s->h_dyn->pc < s->buf.prog_len && s->h_dyn->peak >= kPromote) {
         // a large instance: finish it alone, then put it back (finished)
         const pp_program* prog = s->batch_prog;
         double e = 0.0;

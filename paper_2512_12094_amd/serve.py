@@ -75,6 +75,7 @@ class Estimator:
     def __init__(self, prior: int = 1 << 16, cap_terms: int = 1 << 28):
         self.prior, self.cap_terms = prior, cap_terms
         self.seen: dict = {}
+        self.hopeless: set = set()   # classes that failed at the largest estimate
 
     @staticmethod
     def key(prog: Program):
@@ -93,6 +94,14 @@ class Estimator:
         """A job of this class outgrew a store of `store_terms` entries: jobs
         of the class start from twice that (capped) from now on."""
         self.observe(prog, store_terms)
+
+    def give_up(self, prog: Program):
+        """A job of this class failed at the largest estimate allowed: later
+        jobs of the class are rejected without running."""
+        self.hopeless.add(self.key(prog))
+
+    def is_hopeless(self, prog: Program) -> bool:
+        return self.key(prog) in self.hopeless
 
 
 class GpuEngine:
@@ -148,6 +157,8 @@ class Server:
     sleep: object = time.sleep
     max_retries: int = 8
     growth: int = 4                        # estimate factor after a failure
+    give_up_classes: bool = False          # reject later jobs of a class that failed
+                                           # at the largest estimate, without running
 
     def job_bytes(self, prog: Program, est: int) -> float:
         fn = getattr(self.engine, "job_bytes", None)
@@ -192,7 +203,7 @@ class Server:
                 prog = jobs[i].program
                 est = self.fit_estimate(prog, max(results[i].est_terms,
                                                   self.estimator.estimate(prog)))
-                if est == 0:                       # no store fits the budget
+                if est == 0 or (self.give_up_classes and self.estimator.is_hopeless(prog)):
                     waiting.popleft()
                     results[i].rejected, results[i].finished = True, now
                     if on_event:
@@ -238,6 +249,7 @@ class Server:
                             self.fit_estimate(prog, min(new_est, self.estimator.cap_terms))
                             <= est):
                         r.rejected, r.finished = True, now
+                        self.estimator.give_up(prog)
                         if on_event:
                             on_event("reject", i, used)
                     else:                 # the last try is at the limit itself

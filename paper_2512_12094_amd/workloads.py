@@ -22,6 +22,8 @@ Conventions (restated from the paper, arXiv:2512.12094):
 """
 from __future__ import annotations
 
+import dataclasses
+
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
@@ -182,11 +184,14 @@ def heisenberg_all_to_all(n: int, steps: int, theta: float, *, eps=0.0, wmax=-1,
                           name="heis_a2a") -> Program:
     """Each step: exp(-i theta sum_{i<j} P_i P_j) for P = X, Y, Z, each
     applied as C(n,2) pair rotations exp(-i theta P_i P_j) = R_PP(2 theta)."""
+    # the three sub-layers repeat every step: their (read-only) gate lists
+    # are built once and shared
+    once = {kind: all_pairs_sublayer(n, kind, 2.0 * theta, eps=eps, wmax=wmax, p=p)
+            for kind in "XYZ"}
     subs = []
     for _ in range(steps):
         for kind in "XYZ":
-            subs.append(all_pairs_sublayer(n, kind, 2.0 * theta, eps=eps,
-                                           wmax=wmax, p=p))
+            subs.append(dataclasses.replace(once[kind]))
     if obs is None:
         obs = sum_single(n, "Z")
     return Program(name, n, group, obs, subs, bloch,

@@ -186,3 +186,18 @@ def test_estimator_learns_the_peak_the_engine_reports():
     est = serve.Estimator(prior=1 << 12)
     serve.Server(eng, 1e12, estimator=est, clock=clock, sleep=clock.sleep).run(jobs)
     assert est.estimate(jobs[0].program) == 2 * 777
+
+
+def test_give_up_on_a_class_that_failed_at_the_limit():
+    """With give_up_classes, a later job of a class that failed at the
+    largest estimate is rejected without being started."""
+    clock = FakeClock()
+    jobs = [FakeJob(5.0 * i, W.xxz_ring(24, 1, 0.1, 1.0, eps=1e-4, name=f"h{i}")) for i in range(3)]
+    eng = FakeEngine(clock, {j.program.name: 3 for j in jobs},
+                     {j.program.name: 1 << 40 for j in jobs})
+    srv = serve.Server(eng, 1e15, estimator=serve.Estimator(cap_terms=1 << 20), clock=clock,
+                       sleep=clock.sleep, give_up_classes=True)
+    res = srv.run(jobs)
+    assert all(r.rejected for r in res)
+    started = {name for name, _ in eng.started}
+    assert started == {"h0"}

@@ -310,7 +310,9 @@ enum {
   PP_K_PART_SCAN = 9,     /* partitioned merge 2: offsets, bucket bases    */
   PP_K_PART_SCATTER = 10, /* partitioned merge 3: bucket-contiguous stage  */
   PP_K_PART_AGG = 11,     /* partitioned merge 4: LDS exact sums per bucket */
-  PP_KERNEL_KINDS = 12
+  PP_K_LAYER_SCATTER = 12,/* layer op 1: strings to closed buckets        */
+  PP_K_LAYER_APPLY = 13,  /* layer op 2: a bucket's rotations in LDS      */
+  PP_KERNEL_KINDS = 14
 };
 
 /*
@@ -445,6 +447,29 @@ int pp_get_merge_tuning(int out[2]);
  * or lanes outside 0..1: PP_EINVAL.
  */
 int pp_set_gate_fusion(int max_rotations, int lanes);
+
+/*
+ * Layer ops (process-wide; programs created afterwards).  A sub-layer of
+ * 4 to 64 pairwise commuting rotations (Algorithm 1 step 2a: each rotation
+ * of Prop. 1 followed by the exact merge of identical strings and the
+ * truncation) is applied by two launches instead of one per group of fused
+ * rotations: every live string goes to a bucket keyed by what the
+ * sub-layer's rotations cannot change (which rotations it anticommutes
+ * with, and its letters outside those rotations' support), so a bucket holds
+ * everything its strings can become, and one block applies all the
+ * rotations to its bucket in LDS, in circuit order, with the same arithmetic
+ * as the gate launches.  Results, expectations and the propagated / merged
+ * counters equal those with layer ops off, bitwise.  A bucket that does not
+ * fit its staging slots or the block's LDS makes the op run again with
+ * twice the buckets, then as its fused gate launches; after eight such
+ * fallbacks a handle runs the gate launches throughout.  One-instance
+ * programs only (pp_batch_run / pp_batch_step with one instance, and
+ * promoted instances); the batched steps run the gate launches.  The store
+ * then also carries (16W + 8) bytes of staging per entry.  mode 0: off,
+ * 1: on (default), 2: on, but every layer op reports a failure (tests of the
+ * fallback path).  Other modes: PP_EINVAL.
+ */
+int pp_set_layer_ops(int mode);
 
 #ifdef __cplusplus
 }

@@ -95,6 +95,7 @@ def lib():
                                 ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p]
     L.pp_set_tuning.argtypes = [ctypes.c_int] * 5
     L.pp_set_gate_fusion.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.pp_set_layer_ops.argtypes = [ctypes.c_int]
     L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     L.pp_set_merge_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
     L.pp_get_merge_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
@@ -265,7 +266,8 @@ def pp_counters(h):
 
 
 KERNELS = ["gate", "merge_narrow", "merge_wide1", "merge_wide2", "merge_collect", "compact",
-           "scan", "grow", "part_hist", "part_scan", "part_scatter", "part_agg"]
+           "scan", "grow", "part_hist", "part_scan", "part_scatter", "part_agg",
+           "layer_scatter", "layer_apply"]
 
 
 def pp_work_counters(h):
@@ -369,6 +371,12 @@ def pp_set_gate_fusion(max_rotations, lanes=0):
     """Rotations one gate launch may apply (0 or 1: no fusion; 2 or 3), and
     whether smaller sets run fused ops with one lane per group member."""
     _check(lib().pp_set_gate_fusion(int(max_rotations), int(lanes)))
+
+
+def pp_set_layer_ops(mode):
+    """Layer ops for programs created afterwards: 0 off, 1 on, 2 on with
+    every layer op falling back to its gate launches."""
+    _check(lib().pp_set_layer_ops(int(mode)))
 
 
 def pp_get_tuning():

@@ -22,6 +22,7 @@
 #include "pp.h"
 #include "pp_kernels.hpp"
 #include "pp_merge.hpp"
+#include "pp_layer.hpp"
 #include "pp_types.h"
 
 using namespace pp;
@@ -47,6 +48,7 @@ struct Tuning {
 Tuning g_tune;
 int g_fuse = kMaxFuse;    // pp_set_gate_fusion: rotations per gate launch (<= 1: off)
 int g_lanes = 0;          // pp_set_gate_fusion: lane-per-member form for smaller sets
+int g_layer = 1;          // pp_set_layer_ops: 0 off, 1 on, 2 on but every op falls back
 int g_prof_default = 0;   // pp_profile(NULL, every): new handles start timed
 
 #define HIP_TRY(expr)                                                            \
@@ -102,6 +104,10 @@ struct pp_state {
   void* txn_backup = nullptr;
   uint32_t txn_m = 0, txn_half = 0, txn_parity = 0;
   bool shrunk = false;                 // a finished batched instance's store was compacted
+  bool layer_used = false;             // layer ops ran: stores carry their staging
+  bool layer_off = false;              // layer ops failed too often: their fallbacks run
+  int layer_fallbacks = 0;             // layer ops that fell back (this handle)
+  size_t fb_lo = 0, fb_hi = 0;         // fallback ops [fb_lo, fb_hi) that launch_range runs
   const pp_program* batch_prog = nullptr;
   const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
@@ -251,6 +257,14 @@ int read_counters(pp_state* s, uint64_t out[8]) {
 // Allocates a store of capacity `cap` (both halves and all tables).
 // With `dry` set, nothing is allocated or launched: *dry receives the bytes
 // the store would take.
+// Bucket bits a layer op may use over `slots` staging slots: every bucket
+// keeps at least kLayerMinSlots of them.
+uint32_t layer_max_bits(uint32_t slots) {
+  uint32_t bits = 0;
+  while (bits < (uint32_t)kLayerMaxBits && (slots >> (bits + 1)) >= (uint32_t)kLayerMinSlots) ++bits;
+  return bits;
+}
+
 int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* allocs,
                 size_t* dry = nullptr) {
   const int W = s->W;
@@ -307,6 +321,20 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
     ok = ok && (nb.pwork = (uint32_t*)take(sizeof(uint32_t) * 2 * P));
     ok = ok && (nb.plist = (uint32_t*)take(sizeof(uint32_t) * nm));
   }
+  // staging of the layer op (once a layer op has run on this handle)
+  nb.lstx = nb.lstz = nullptr;
+  nb.lstc = nullptr;
+  nb.lcount = nullptr;
+  nb.lslots = 0;
+  nb.lmaxbits = 0;
+  if (s->layer_used) {
+    nb.lslots = 1u << ceil_log2(cap);
+    nb.lmaxbits = layer_max_bits(nb.lslots);
+    ok = ok && (nb.lstx = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots));
+    ok = ok && (nb.lstz = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots));
+    ok = ok && (nb.lstc = (double*)take(sizeof(double) * nb.lslots));
+    ok = ok && (nb.lcount = (uint32_t*)take(sizeof(uint32_t) << nb.lmaxbits));
+  }
   const bool wide = !nb.narrow;
   nb.mown = nullptr;
   nb.wrep = nullptr;
@@ -329,6 +357,8 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   hipLaunchKernelGGL(k_init_store, dim3(init_grid), dim3(kBlock), 0, s->stream, nb, (uint64_t)ng,
                      (uint64_t)nm, wide ? 1u : 0u);
   HIP_TRY(hipGetLastError());
+  if (nb.lcount)
+    HIP_TRY(hipMemsetAsync(nb.lcount, 0, sizeof(uint32_t) << nb.lmaxbits, s->stream));
   *b = nb;
   *allocs = std::move(got);
   return PP_OK;
@@ -422,6 +452,43 @@ SoloFn solo_of(int kind, bool big, uint32_t nrot = 1, int lane_it = 0, int group
   }
 }
 
+SoloFn layer_of(int kind, int W) {
+  if (kind == PP_K_LAYER_SCATTER) return W == 1 ? &k_layer_scatter<1> : &k_layer_scatter<2>;
+  return W == 1 ? &k_layer_apply<1> : &k_layer_apply<2>;
+}
+
+// The layer op's staging, allocated when a handle first runs one (and
+// then with every store it grows into).
+int ensure_layer(pp_state* s) {
+  if (s->buf.lcount) return PP_OK;
+  s->layer_used = true;
+  InstBuf& nb = s->buf;
+  const int W = s->W;
+  nb.lslots = 1u << ceil_log2(nb.cap);
+  nb.lmaxbits = layer_max_bits(nb.lslots);
+  std::vector<void*> got;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = dev_alloc(s, bytes);
+    if (p) got.push_back(p);
+    return p;
+  };
+  bool ok = (nb.lstx = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots)) != nullptr;
+  ok = ok && (nb.lstz = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots));
+  ok = ok && (nb.lstc = (double*)take(sizeof(double) * nb.lslots));
+  ok = ok && (nb.lcount = (uint32_t*)take(sizeof(uint32_t) << nb.lmaxbits));
+  if (!ok) {
+    for (void* p : got) dev_free(s, p);
+    nb.lstx = nb.lstz = nullptr;
+    nb.lstc = nullptr;
+    nb.lcount = nullptr;
+    nb.lslots = nb.lmaxbits = 0;
+    return fail(PP_ENOMEM, "allocation of the layer staging failed");
+  }
+  HIP_TRY(hipMemsetAsync(nb.lcount, 0, sizeof(uint32_t) << nb.lmaxbits, s->stream));
+  for (void* p : got) s->store.push_back(p);
+  return upload_buf(s);
+}
+
 int items_of(int kind, bool big = false) {
   return kind == PP_K_GATE ? gate_items(big) : stream_items(big);
 }
@@ -435,8 +502,11 @@ int grow(pp_state* s) {
   const std::vector<Op>* ops = s->batch_prog ? &s->batch_prog->ops : s->run_ops_list;
   const uint32_t nrot =
       ops && d.pc < ops->size() && (*ops)[d.pc].type == OP_GATES ? (*ops)[d.pc].nrot : 1u;
-  // after compaction M = live: live + appends <= 2^(nrot-1) (live + count)
-  const uint64_t need = (uint64_t)d.live + gate_append_bound(nrot, d.live, d.count);
+  // after compaction M = live: live + appends <= 2^(nrot-1) (live + count);
+  // a layer op whose survivors did not fit says how many there were
+  const bool layer = ops && d.pc < ops->size() && (*ops)[d.pc].type == OP_LAYER;
+  const uint64_t need = layer ? std::max<uint64_t>((uint64_t)d.lneed, (uint64_t)d.live + d.count)
+                              : (uint64_t)d.live + gate_append_bound(nrot, d.live, d.count);
   // same capacity (a compaction) when the live terms leave enough room;
   // the headroom shrinks from 4x to 1.5x for very large sets
   const uint64_t head = need < (1ull << 24) ? 4 * need : need < (1ull << 27) ? 2 * need
@@ -532,6 +602,10 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
     case OP_GATES:
       out->push_back(PP_K_GATE);
       break;
+    case OP_LAYER:
+      out->push_back(PP_K_LAYER_SCATTER);
+      out->push_back(PP_K_LAYER_APPLY);
+      break;
     case OP_MERGE:
       if (s->group == PP_GROUP_NONE && !op.force_full) {
         out->push_back(PP_K_COMPACT);
@@ -571,10 +645,19 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
   uint32_t run_len = 0;
   hipEvent_t run_ev = nullptr;
   for (size_t k = from; k < to; ++k) {
+    // a layer op's fallback copies run only after it failed (or with layer
+    // ops off for this handle, in place of it)
+    if (ops[k].type == OP_LAYER && s->buf.nolayer) continue;
+    if (ops[k].fallback && !s->buf.nolayer && !(k >= s->fb_lo && k < s->fb_hi)) continue;
     kinds.clear();
     kinds_of(s, ops[k], &kinds);
     for (int kind : kinds) {
       if (small && is_part_kind(kind)) continue;
+      const bool layer = kind == PP_K_LAYER_SCATTER || kind == PP_K_LAYER_APPLY;
+      if (layer) {
+        int rc = ensure_layer(s);
+        if (rc) return rc;
+      }
       if (kind != run_kind) {
         if (run_kind >= 0) prof_end(s, run_kind, run_ev, run_len);
         run_kind = kind;
@@ -584,11 +667,17 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       const uint64_t elems = kind == PP_K_MERGE_COLLECT ? (1ull << s->buf.hm_bits) : s->buf.cap;
       const uint32_t nrot = ops[k].type == OP_GATES ? ops[k].nrot : 1u;
       const int lane_it = kind == PP_K_GATE && !big ? lane_items(s->m_hint, nrot) : 0;
-      const int grid = is_part_kind(kind) ? part_grid(s->buf, kind)
-                       : lane_it            ? launch_blocks(elems << nrot, lane_it)
-                                            : launch_blocks(elems, items_of(kind, big));
+      int grid = is_part_kind(kind) ? part_grid(s->buf, kind)
+                 : lane_it            ? launch_blocks(elems << nrot, lane_it)
+                                      : launch_blocks(elems, items_of(kind, big));
+      if (kind == PP_K_LAYER_APPLY) {       // about two blocks per bucket of the last size seen
+        const uint32_t bits = layer_bits(std::max<uint32_t>(s->m_hint, 1), s->h_dyn->lboost,
+                                         s->buf.lmaxbits);
+        grid = (int)std::min<uint32_t>(2u << bits, 8192u);
+      }
       const int block = kind == PP_K_PART_SCAN ? kPCBlock
                         : kind == PP_K_PART_AGG ? kPABlock
+                        : kind == PP_K_LAYER_APPLY ? kLBlock
                         : is_part_kind(kind)    ? kPHBlock
                                                 : kBlock;
       Solo S;
@@ -597,8 +686,11 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
       S.d = s->d_dyn;
       S.sync = s->d_sync;
       S.k = (uint32_t)k;
-      hipLaunchKernelGGL(solo_of(kind, big, nrot, lane_it, s->group), dim3(grid), dim3(block),
-                         part_lds(s->buf, kind), s->stream, S);
+      if (layer)
+        hipLaunchKernelGGL(layer_of(kind, s->W), dim3(grid), dim3(block), 0, s->stream, S);
+      else
+        hipLaunchKernelGGL(solo_of(kind, big, nrot, lane_it, s->group), dim3(grid), dim3(block),
+                           part_lds(s->buf, kind), s->stream, S);
       ++run_len;
     }
   }
@@ -698,16 +790,70 @@ Op make_op(uint32_t type) {
   return op;
 }
 
+// next_gate of every op: the first GATE(S) op after it (after a LAYER op's
+// own fallback copies for the LAYER op; LAYER ops themselves count no
+// anticommuting terms ahead, so they are not in the chain).
 void set_next_gates(std::vector<Op>& ops) {
-  uint32_t next = kNone32;
-  for (size_t k = ops.size(); k-- > 0;) {
+  std::vector<uint32_t> first(ops.size() + 1, kNone32);
+  for (size_t k = ops.size(); k-- > 0;)
+    first[k] = (ops[k].type == OP_GATE || ops[k].type == OP_GATES) ? (uint32_t)k : first[k + 1];
+  for (size_t k = 0; k < ops.size(); ++k) {
+    const size_t after = ops[k].type == OP_LAYER ? k + 1 + ops[k].skip : k + 1;
+    const uint32_t next = first[std::min(after, ops.size())];
     ops[k].next_gate = next;
     for (int w = 0; w < kMaxW; ++w) {
       ops[k].nx[w] = next == kNone32 ? 0 : ops[next].px[w];
       ops[k].nz[w] = next == kNone32 ? 0 : ops[next].pz[w];
     }
-    if (ops[k].type == OP_GATE || ops[k].type == OP_GATES) next = (uint32_t)k;
   }
+}
+
+void fuse_gates(std::vector<Op>& ops, size_t from, int W);
+
+// Gate ops ops[from..] of one sub-layer: when they are kLayerMinRot to
+// kLayerMaxRot pairwise commuting rotations, a LAYER op carrying them (its
+// rotation table appended to `tab`) is put in front of them and they become
+// its fallback copies.
+void add_layer_op(std::vector<Op>& ops, size_t from, size_t to_gate_end, int W,
+                  std::vector<double>& tab, TabRefs& refs, bool merge_follows) {
+  if (!g_layer) return;
+  const size_t r = to_gate_end - from;
+  if (r < (size_t)kLayerMinRot || r > (size_t)kLayerMaxRot) return;
+  for (size_t a = from; a < to_gate_end; ++a) {
+    if (ops[a].type != OP_GATE) return;
+    for (size_t c = a + 1; c < to_gate_end; ++c) {
+      int odd = 0;
+      for (int w = 0; w < W; ++w)
+        odd += __builtin_popcountll((ops[a].px[w] & ops[c].pz[w]) ^ (ops[a].pz[w] & ops[c].px[w]));
+      if (odd & 1) return;
+    }
+  }
+  Op layer = make_op(OP_LAYER);
+  layer.nrot = (uint32_t)r;
+  layer.eps = ops[from].eps;
+  layer.wmax = ops[from].wmax;
+  layer.full_check = ops[from].full_check;
+  layer.gtab = merge_follows ? 0u : 1u;
+  layer.fail_test = g_layer == 2 ? 1u : 0u;
+  for (int w = 0; w < kMaxW; ++w) {       // the first rotation (for the op's own record)
+    layer.px[w] = ops[from].px[w];
+    layer.pz[w] = ops[from].pz[w];
+  }
+  refs.push_back({from, tab.size()});
+  for (size_t a = from; a < to_gate_end; ++a) {
+    double rec[kLayerRec] = {};
+    for (int w = 0; w < kMaxW; ++w) {
+      std::memcpy(&rec[w], &ops[a].px[w], sizeof(double));
+      std::memcpy(&rec[kMaxW + w], &ops[a].pz[w], sizeof(double));
+    }
+    rec[2 * kMaxW] = ops[a].cs;
+    rec[2 * kMaxW + 1] = ops[a].sn;
+    tab.insert(tab.end(), rec, rec + kLayerRec);
+  }
+  fuse_gates(ops, from, W);
+  for (size_t a = from; a < ops.size(); ++a) ops[a].fallback = 1;
+  layer.skip = (uint32_t)(ops.size() - from);
+  ops.insert(ops.begin() + from, layer);
 }
 
 // Gate ops ops[from..] (consecutive gates of one sub-layer) are grouped into
@@ -949,6 +1095,12 @@ int pp_set_gate_fusion(int max_rotations, int lanes) {
   return PP_OK;
 }
 
+int pp_set_layer_ops(int mode) {
+  if (mode < 0 || mode > 2) return fail(PP_EINVAL, "mode must be 0, 1 or 2");
+  g_layer = mode;
+  return PP_OK;
+}
+
 int pp_get_tuning(int out[5]) {
   if (!out) return fail(PP_EINVAL, "NULL argument");
   out[0] = g_tune.gate_items;
@@ -1180,6 +1332,7 @@ int pp_store_bytes(int n_qubits, int group, int dtype, size_t cap, size_t* out) 
   st.buf.group = group;
   st.buf.narrow = (group == PP_GROUP_PERMUTATION || n_qubits <= 32) ? 1u : 0u;
   st.buf.f32 = dtype == PP_F32_COMPENSATED ? 1u : 0u;
+  st.layer_used = g_layer != 0;          // programs may run layer ops
   InstBuf b;
   std::vector<void*> none;
   size_t bytes = 0;
@@ -1677,6 +1830,7 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
       ops.push_back(make_op(OP_DAMP));
     }
     const size_t first_gate = ops.size();
+    const bool merge_follows = !merge_after || merge_after[j];
     for (size_t k = sub_start[j]; k < sub_start[j + 1]; ++k) {
       Op op = make_op(OP_GATE);
       for (int w = 0; w < W; ++w) {
@@ -1690,7 +1844,9 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
       op.full_check = k == sub_start[j];
       ops.push_back(op);
     }
-    fuse_gates(ops, first_gate, W);
+    const size_t before = ops.size();
+    add_layer_op(ops, first_gate, ops.size(), W, tab, refs, merge_follows);
+    if (ops.size() == before) fuse_gates(ops, first_gate, W);
     const bool trunc = eps[j] > 0.0 || max_weight[j] >= 0;
     if (!merge_after || merge_after[j]) {
       Op merge = make_op(OP_MERGE);
@@ -1737,8 +1893,9 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
 
 int pp_program_info(const pp_program* p, uint64_t out[3]) {
   if (!p || !out) return fail(PP_EINVAL, "NULL argument");
-  uint64_t gates = 0;
-  for (const auto& op : p->ops) gates += op.type == OP_GATE || op.type == OP_GATES;
+  uint64_t gates = 0;              // apply ops the one-instance path runs
+  for (const auto& op : p->ops)
+    gates += op.type == OP_LAYER || ((op.type == OP_GATE || op.type == OP_GATES) && !op.fallback);
   out[0] = p->ops.size();
   out[1] = gates;
   out[2] = p->n_gates;
@@ -1849,6 +2006,56 @@ int ensure_graph(BatchCtx* b) {
 // only then synchronises, grows and relaunches from the op that stopped.
 // `resume`: continue from the op the device state names (an instance that
 // leaves a batch at a step boundary) instead of starting the program.
+// A layer op at pc reported a bucket that did not fit (ST_LAYER; h_dyn is
+// fresh and the device idles behind it): grow a crowded store, else run it
+// again with twice the buckets, else run its GATE(S) copies instead.  After
+// kLayerGiveUp fallbacks the handle runs the copies in place of every layer
+// op.
+constexpr int kLayerGiveUp = 8;
+
+int layer_failed(pp_state* s, const Op* ops, size_t len) {
+  InstDyn& h = *s->h_dyn;
+  h.status &= ~ST_LAYER;
+  const uint32_t k = h.pc;
+  int rc;
+  if (k < len && ops[k].type == OP_LAYER) {
+    if (!ops[k].fail_test && (uint64_t)h.M * 3 > s->buf.cap) {
+      if ((rc = grow(s))) return rc;           // more staging slots per bucket
+    } else if (!ops[k].fail_test && h.lboost < (uint32_t)kLayerMaxBoost) {
+      h.lboost += 1;
+      HIP_TRY(hipMemcpyAsync(&s->d_dyn->lboost, &h.lboost, sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s->stream));
+    } else {
+      s->fb_lo = k + 1;
+      s->fb_hi = k + 1 + ops[k].skip;
+      h.pc = k + 1;
+      HIP_TRY(hipMemcpyAsync(&s->d_dyn->pc, &h.pc, sizeof(uint32_t), hipMemcpyHostToDevice,
+                             s->stream));
+      if (++s->layer_fallbacks >= kLayerGiveUp && !ops[k].fail_test && !s->buf.nolayer) {
+        s->layer_off = true;
+        s->buf.nolayer = 1;
+        if ((rc = upload_buf(s))) return rc;
+      }
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &h.status, sizeof(uint32_t), hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return PP_OK;
+}
+
+// The fallback copies around pc when a program resumes inside them.
+void resume_window(pp_state* s, const Op* ops, size_t len, size_t pc) {
+  s->fb_lo = s->fb_hi = 0;
+  if (pc >= len || !ops[pc].fallback) return;
+  size_t k = pc;
+  while (k > 0 && ops[k].type != OP_LAYER) --k;
+  if (ops[k].type == OP_LAYER) {
+    s->fb_lo = k + 1;
+    s->fb_hi = k + 1 + ops[k].skip;
+  }
+}
+
 int solo_program(pp_state* s, const pp_program* p, double* expectation, bool resume = false) {
   int rc;
   const hipStream_t st = s->stream;
@@ -1857,9 +2064,11 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
   s->buf.prog = p->d_ops;
   s->buf.prog_len = (uint32_t)len;
   s->buf.nopart = 0;
+  s->buf.nolayer = s->layer_off ? 1u : 0u;
   s->batch_prog = p;
   if ((rc = upload_buf(s))) return rc;
   if (!resume) hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, st, s->d_dyn, 0u);
+  resume_window(s, ops, len, resume ? s->h_dyn->pc : 0);
   // chunk ends: after every kChunkSubs-th sub-layer (its MERGE and the TRUNC
   // that follows it), or the last op; the host reads the state once per chunk
   constexpr int kChunkSubs = 1;
@@ -1924,6 +2133,9 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
           HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
                                  hipMemcpyHostToDevice, st));
         }
+        if (s->h_dyn->status & ST_LAYER) {
+          if ((rc = layer_failed(s, ops, len))) return rc;
+        }
         launched_to = s->h_dyn->pc;
         next_chunk = 0;
         while (next_chunk < ends.size() && ends[next_chunk] <= launched_to) ++next_chunk;
@@ -1942,6 +2154,9 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
       s->h_dyn->status &= ~ST_OVERFLOW;
       HIP_TRY(hipMemcpyAsync(&s->d_dyn->status, &s->h_dyn->status, sizeof(uint32_t),
                              hipMemcpyHostToDevice, st));
+    }
+    if (s->h_dyn->status & ST_LAYER) {
+      if ((rc = layer_failed(s, ops, len))) return rc;
     }
     inflight.clear();
     launched_to = s->h_dyn->pc;
@@ -2006,10 +2221,12 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
       s->buf.prog_len = (uint32_t)programs[i]->ops.size();
       s->batch_prog = programs[i];
       s->buf.nopart = 1;                   // the batched steps have no partitioned merge
+      s->buf.nolayer = 1;                  // nor layer ops (their GATE(S) copies run)
       if ((rc = upload_buf(s))) return rc;
       hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, stream, s->d_dyn, 0u);
-    } else if (!s->buf.nopart) {
+    } else if (!s->buf.nopart || !s->buf.nolayer) {
       s->buf.nopart = 1;
+      s->buf.nolayer = 1;
       if ((rc = upload_buf(s))) return rc;
     }
     b->h_bufp[i] = s->d_buf;
@@ -2060,6 +2277,7 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
         s->buf.prog = prog->d_ops;
         s->buf.prog_len = (uint32_t)prog->ops.size();
         s->buf.nopart = 1;
+        s->buf.nolayer = 1;
         s->batch_prog = prog;
         if (g) {
           s->h_dyn->status |= ST_FAILED | ST_OVERFLOW;

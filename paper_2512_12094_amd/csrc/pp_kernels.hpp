@@ -659,6 +659,14 @@ __device__ __forceinline__ const Op* cur_op(const InstBuf& b, const InstDyn& d) 
   return d.pc < b.prog_len ? &b.prog[d.pc] : nullptr;
 }
 
+// Past the current op; where LAYER ops are off (the batched form), past
+// every LAYER op too: the GATE(S) copies of its rotations follow it.
+__device__ __forceinline__ void next_op(const InstBuf& b, InstDyn& d) {
+  uint32_t pc = d.pc + 1;
+  while (b.nolayer && pc < b.prog_len && b.prog[pc].type == OP_LAYER) ++pc;
+  d.pc = pc;
+}
+
 // ---------------------------------------------------------------------------
 // gate table
 // ---------------------------------------------------------------------------
@@ -1692,7 +1700,7 @@ struct GateKindT {
     d.parity ^= 1u;
     take_acc(d);
     d.count_for = op.next_gate;
-    d.pc += 1;
+    next_op(b, d);
   }
 };
 
@@ -1862,7 +1870,7 @@ __device__ __forceinline__ void finish_rebuild(const InstBuf& b, InstDyn& d) {
   d.mphase = 0;
   d.pglobal = 0;
   d.plist_n = 0;
-  d.pc += 1;
+  next_op(b, d);
 }
 
 // Collect: every occupied merge slot becomes one representative of the new
@@ -2108,7 +2116,7 @@ struct ScanKind {
     }
     take_acc(d);
     d.count_for = op.next_gate;
-    d.pc += 1;
+    next_op(b, d);
   }
 };
 

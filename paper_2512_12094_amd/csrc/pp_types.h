@@ -51,9 +51,15 @@ enum OpType : uint32_t {
   OP_GATES = 7,    // 2..kMaxFuse mutually commuting rotations in circuit
                    // order, each followed by the exact merge and
                    // truncation, in one pass
+  OP_LAYER = 8,    // 4..kLayerMaxRot mutually commuting rotations in circuit
+                   // order, each followed by the exact merge and truncation,
+                   // applied to buckets of strings closed under all of them
+                   // (two launches); its `skip` following ops are the same
+                   // rotations as GATE(S) ops, run only if it fails
 };
 
-enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u, ST_FAILED = 8u };
+enum : uint32_t { ST_OVERFLOW = 1u, ST_COLLISION = 2u, ST_RANGE = 4u, ST_FAILED = 8u,
+                  ST_LAYER = 16u };   // a LAYER op did not fit its buckets
 
 // Contended device-scope atomics on one address serialise (about 12 ns each
 // on gfx950), so per-launch counts go to kAccShards accumulators and the
@@ -101,6 +107,29 @@ constexpr int kPartChunks = 5;       // 32-bit chunks of a fixed-point sum (160 
 constexpr int kPartMaxPasses = 64;   // selector passes over an overfull bucket
 constexpr int kPartProbe = 64;       // probes before the LDS table refuses a key
 
+// Layer op (OP_LAYER): a commuting run of r rotations P_1..P_r maps a string
+// Q only within the set Q * <P_g : P_g anticommutes with Q>, and every
+// member of that set anticommutes with the same P_g.  So the key
+//   (anticommutation pattern a, x bits outside the x-support of the
+//    anticommuting rotations, z bits outside their z-support)
+// is the same for all members, and strings bucketed by a hash of it can be
+// rotated bucket by bucket, each bucket in one block's LDS:
+//   1. scatter: each live string to its bucket (2^lbits buckets of
+//      lslots >> lbits staging slots; a global counter per bucket);
+//   2. apply: one block per bucket runs the r rotations with the exact
+//      merge and truncation after each, then writes the survivors to the
+//      other half of the store.
+// A bucket that does not fit its staging slots or the LDS fails the op; the
+// host then retries it with twice the buckets, then falls back to the
+// op's GATE(S) copies.
+constexpr int kLayerMaxRot = 64;
+constexpr int kLayerMinRot = 4;
+constexpr int kLayerShift = 7;        // strings per bucket aimed at: 2^7
+constexpr int kLayerMaxBits = 20;
+constexpr int kLayerMinSlots = 64;    // staging slots per bucket, at least
+constexpr int kLayerMaxBoost = 1;     // extra bucket bits after a failure
+constexpr int kLayerAcc = 8;          // per-shard layer sums (accs line entries 1..8)
+
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
 constexpr int kFxMaxShift = 105;   // |c| < 2^54 keeps 2^32 addends in range
 
@@ -112,8 +141,14 @@ struct Op {
   uint32_t force_full;   // MERGE with group NONE: merge duplicates (creation)
   uint32_t trunc;        // MERGE: emit only terms passing eps / wmax (the
                          // sub-layer's truncation, folded into the merge)
-  uint32_t pad;
-  uint32_t nrot;         // GATE: 1; GATES: rotations in the op
+  uint32_t fallback;     // GATE(S): copy of a LAYER op's rotations, run only
+                         // after that op failed
+  uint32_t nrot;         // GATE: 1; GATES, LAYER: rotations in the op
+  uint32_t skip;         // LAYER: number of fallback ops that follow it
+  uint32_t gtab;         // LAYER: its output gets gate-table entries (no
+                         // merge follows before the next gate)
+  uint32_t fail_test;    // LAYER: always reports a failure (tests of the
+                         // fallback path)
   uint64_t px[kMaxW];    // GATE(S): the (first) rotation's Pauli string
   uint64_t pz[kMaxW];
   double cs, sn;         // GATE(S): cos(theta), sin(theta)
@@ -124,8 +159,12 @@ struct Op {
   uint64_t nz[kMaxW];    // != kNone32 (its anticommutation count is tallied here)
   double eps;            // GATE/TRUNC: coefficient threshold (0: off)
   const double* table;   // DAMP: (1-p)^w for w = 0..n;
-                         // EXPECT: bx^k, by^k, bz^k for k = 0..n (3 blocks)
+                         // EXPECT: bx^k, by^k, bz^k for k = 0..n (3 blocks);
+                         // LAYER: per rotation kLayerRec doubles: x words,
+                         // z words (bit patterns), cos, sin
 };
+
+constexpr int kLayerRec = 2 * kMaxW + 2;
 
 struct InstBuf {
   uint64_t* x[2];
@@ -151,6 +190,14 @@ struct InstBuf {
   uint32_t* plist;       // [2^hm_bits] global merge-table slots in use
   uint32_t pmaxbits;     // largest pbits the staging tables were sized for
   uint32_t pshift;       // log2 of the records per bucket aimed at (tuning)
+  // layer op (allocated on first use)
+  uint64_t* lstx;        // [W][lslots] staged x words
+  uint64_t* lstz;        // [W][lslots] staged z words
+  double* lstc;          // [lslots] staged coefficients (exact in FP64)
+  uint32_t* lcount;      // [2^lmaxbits] strings per bucket (zero between ops)
+  uint32_t lslots;       // staging slots (a power of two)
+  uint32_t lmaxbits;     // largest bucket bits (lslots >> lmaxbits >= kLayerMinSlots)
+  uint32_t nolayer;      // LAYER ops are skipped (their fallback ops run)
   const Op* prog;
   uint32_t prog_len;
   uint32_t cap;
@@ -206,6 +253,9 @@ struct InstDyn {
   uint32_t pover;        // buckets summed in several selector passes
   uint32_t pglob;        // keys that went through the global merge table
   uint32_t peak;         // most entries (live and not yet compacted) the store held
+  uint32_t lboost;       // layer ops: extra bucket bits after a failed op
+  uint32_t lfail;        // layer op: a bucket overflowed its slots or the LDS
+  uint32_t lneed;        // layer op: survivors of an op whose output did not fit
 };
 
 }  // namespace pp

@@ -4,7 +4,8 @@ merge and truncation, gives bitwise the results of one launch per gate (same
 arithmetic in the same order), on every path (per-call layers, the
 one-instance program, the batched form, FP32 storage, store growth), and the
 oracle's results by the parity rules of tests/parity.py; the gate launch
-count drops by the group size."""
+count drops by the group size.  Programs here are built with layer ops off
+(tests/test_gpu_layer.py covers those)."""
 import numpy as np
 import pytest
 
@@ -24,9 +25,11 @@ def gpu():
     _lib.lib()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    _lib.pp_set_layer_ops(0)             # programs run their gate launches here
     yield dict(torch=torch, stream=stream, handle=int(stream.cuda_stream),
                alloc=_lib.TorchAllocator(0))
     _lib.pp_set_gate_fusion(3, 0)
+    _lib.pp_set_layer_ops(1)
 
 
 def prefix(prog, k):

@@ -98,14 +98,21 @@ def merge_bytes(wc, W=1):
     return (16 * W + 8) * (wc["merge_in"] + wc["merge_out"])
 
 
-def run_steps(prog, group, steps, stream, alloc, profile, mode="program"):
+def run_steps(prog, group, steps, stream, alloc, profile, mode="program", layer_ops=1):
     """`steps` propagations; mode "program" = one device program per step
-    (pp_batch_run with one instance), "calls" = one C call per operation."""
+    (pp_batch_run with one instance), "calls" = one C call per operation;
+    layer_ops 0 builds the program with every sub-layer as gate launches."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
     import torch
     layers = driver.heisenberg_layers(prog)
-    dp = driver.device_program(prog) if mode == "program" else None
+    dp = None
+    if mode == "program":
+        L.pp_set_layer_ops(layer_ops)
+        try:
+            dp = driver.DeviceProgram(prog) if layer_ops != 1 else driver.device_program(prog)
+        finally:
+            L.pp_set_layer_ops(1)
     totals = dict(propagated=0, merged=0, anticommuting=0, appended=0, merge_in=0,
                   merge_out=0, gate_key_reads=0, gate_coef_rw=0)
     kern = {k: [0, 0.0] for k in L.KERNELS}
@@ -131,6 +138,8 @@ def run_steps(prog, group, steps, stream, alloc, profile, mode="program"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     L.pp_profile(None, 0)
+    if dp is not None and layer_ops != 1:
+        dp.close()
     return wall, totals, kern, e
 
 
@@ -585,7 +594,7 @@ def cpu_served_baseline(timed_jobs, seconds, workers):
                        f"oracle processes (FIFO) for {seconds:.0f} s")
 
 
-def pmc_traffic(bytes_launches, name="k_gate_c2_z32_pmc.json"):
+def pmc_traffic(bytes_launches, name="k_layer_c2_z32_pmc.json"):
     """HBM bytes per launch (per pass, for the merge summary) from a
     committed rocprofv3 counter summary, when it was taken on the kernel
     sources as they are now."""
@@ -666,30 +675,49 @@ def main():
                                         mode="calls")
         units = tot["propagated"] + tot["merged"]
         value = units / wall
-        gate_n, gate_ms = kern["gate"]             # sampled launches and their time
+        # the apply step (Algorithm 1 step 2a): one layer op per sub-layer
+        # (k_layer_scatter + k_layer_apply), gate launches where a sub-layer
+        # has no layer op; each kind's average launch from the sampled events
         from paper_2512_12094_amd import driver
-        per_step = L.pp_program_info(driver.device_program(prog).h)["gate_launches"]
-        gates_run = per_step * args.steps           # every gate op runs once per step
-        gb = gate_bytes(tot)
-        avg_s = gate_ms * 1e-3 / max(gate_n, 1)
-        bpl = gb / gates_run
-        bpl_launch = gate_bytes_launch(tot) / gates_run
-        roof = dict(bound="hbm", kernel="k_gate", achieved=round(bpl / avg_s / 1e9, 2),
+        info = L.pp_program_info(driver.device_program(prog).h)
+        layer_ops = info["layer_ops"]
+        gate_ops = info["gate_launches"] - layer_ops
+        avg = {k: (kern[k][1] * 1e-3 / kern[k][0] if kern[k][0] else 0.0)
+               for k in ("gate", "layer_scatter", "layer_apply")}
+        op_s = avg["layer_scatter"] + avg["layer_apply"]          # one layer op
+        step_apply_s = layer_ops * op_s + gate_ops * avg["gate"]
+        gb = gate_bytes(tot) / args.steps                          # per propagation
+        apply_ops = layer_ops + gate_ops
+        bpl = gb / max(apply_ops, 1)
+        avg_s = step_apply_s / max(apply_ops, 1)
+        roof = dict(bound="hbm",
+                    kernel="apply step: k_layer_scatter + k_layer_apply, one launch pair per "
+                           "sub-layer (its 32 rotations)" if layer_ops else "k_gate",
+                    achieved=round(bpl / avg_s / 1e9, 2) if avg_s else None,
                     peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 5), traffic=None,
+                    frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 5) if avg_s else None,
+                    traffic=None,
                     byte_model="per term-gate: 16W key per live term and rotation, 16 B "
                                "coefficient read+write per anticommuting term, 16W+8 B per "
                                "appended child",
-                    avg_launch_us=round(avg_s * 1e6, 3), timed_launches=gate_n,
-                    launches=gates_run, bytes_per_launch=round(bpl, 1),
-                    launch_model=dict(bytes_per_launch=round(bpl_launch, 1),
-                                      achieved=round(bpl_launch / avg_s / 1e9, 2),
-                                      frac=round(bpl_launch / avg_s / 1e9 / HBM_PEAK_GBS, 5)),
-                    rotations_per_launch=round(prog.n_gates / per_step, 3),
-                    est_kernel_ms_per_step=round(avg_s * 1e3 * per_step, 3))
+                    avg_launch_us=round(avg_s * 1e6, 3),
+                    avg_us={k: round(v * 1e6, 3) for k, v in avg.items() if v},
+                    timed_launches={k: kern[k][0] for k in avg if kern[k][0]},
+                    launches_per_step=dict(layer_ops=layer_ops, gate_launches=gate_ops),
+                    bytes_per_launch=round(bpl, 1),
+                    rotations_per_launch=round(prog.n_gates / max(apply_ops, 1), 3),
+                    est_kernel_ms_per_step=round(step_apply_s * 1e3, 3))
         kernels = {k: dict(launches=n, ms=round(ms, 3)) for k, (n, ms) in kern.items() if n}
+        # the same propagation with every sub-layer as fused gate launches
+        L.pp_set_layer_ops(0)
+        prog_g = W.config2()
+        L.pp_set_layer_ops(1)
+        wall_gates, _, kern_g, e_g = run_steps(prog_g, "Zn", args.steps, stream, alloc, 0,
+                                               layer_ops=0)
         variants = dict(ms_per_step_without_events=round(wall_np / args.steps * 1e3, 3),
-                        ms_per_step_one_call_per_op=round(wall_calls / args.steps * 1e3, 3))
+                        ms_per_step_one_call_per_op=round(wall_calls / args.steps * 1e3, 3),
+                        ms_per_step_gate_launches=round(wall_gates / args.steps * 1e3, 3),
+                        gate_launches_same_expectation=e_g == e)
         plain = None
         if not args.no_plain:
             run_steps(prog, "none", 1, stream, alloc, False)
@@ -711,9 +739,10 @@ def main():
                             terms_per_step=(dtot["propagated"] + dtot["merged"]) // dsteps,
                             expectation=de)
             print(f"[bench] dihedral done", file=sys.stderr, flush=True)
-        traffic, traffic_src = pmc_traffic(None)
+        traffic, traffic_src = pmc_traffic(None, "k_layer_c2_z32_pmc.json")
         roof["traffic"] = round(traffic, 1) if traffic is not None else None
-        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
+        roof["traffic_unit"] = ("HBM bytes per layer op, k_layer_scatter + k_layer_apply "
+                                "(rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)")
         roof["traffic_source"] = traffic_src
         mp = roof_merge = None
         if not args.no_merge_pass:

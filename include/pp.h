@@ -239,6 +239,16 @@ int pp_expectation_noalloc(pp_state* s, const double bloch_xyz[3], double* out);
 int pp_peak_terms(pp_state* s, size_t* out);
 
 /*
+ * Layer-op statistics of a handle (see pp_set_layer_ops): out[0] layer ops
+ * completed, out[1] layer-op runs that reported a bucket that did not fit
+ * (each was run again with more buckets or replaced by its gate launches),
+ * out[2] layer ops replaced by their gate launches, out[3] 1 when the
+ * handle runs the gate launches throughout.  Synchronises the handle's
+ * stream.
+ */
+int pp_layer_stats(pp_state* s, uint64_t out[4]);
+
+/*
  * Device bytes of a term store of `cap` entries for a handle of n_qubits,
  * group and dtype (both halves, tables and the merge staging, as the
  * library would allocate them now; no allocation happens).  A handle's
@@ -365,11 +375,13 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub,
 void pp_program_destroy(pp_program* p);
 
 /*
- * Shape of a created program: out[0] = device operations, out[1] = gate
- * launches per run (a fused pair of rotations is one launch), out[2] =
- * rotations.  NULL arguments: PP_EINVAL.
+ * Shape of a created program: out[0] = device operations, out[1] = apply
+ * operations a one-instance run launches (a layer op, or a gate launch of
+ * up to three fused rotations outside the fallback copies of layer ops),
+ * out[2] = rotations, out[3] = layer ops (see pp_set_layer_ops).  NULL
+ * arguments: PP_EINVAL.
  */
-int pp_program_info(const pp_program* p, uint64_t out[3]);
+int pp_program_info(const pp_program* p, uint64_t out[4]);
 
 /*
  * Runs programs[i] on states[i] for i < n (n <= 1024), all instances
@@ -470,6 +482,16 @@ int pp_set_gate_fusion(int max_rotations, int lanes);
  * fallback path).  Other modes: PP_EINVAL.
  */
 int pp_set_layer_ops(int mode);
+
+/*
+ * Layer-op tuning knobs (process-wide, launches made afterwards):
+ * bucket_log2 = log2 of the strings per bucket aimed at (4..10, default 7;
+ * 0 keeps the current value), block = threads per bucket block (256 or 512,
+ * default 512; 0 keeps).  Results do not depend on them.  Out of range:
+ * PP_EINVAL.  pp_get_layer_tuning returns the two current values.
+ */
+int pp_set_layer_tuning(int bucket_log2, int block);
+int pp_get_layer_tuning(int out[2]);
 
 #ifdef __cplusplus
 }

@@ -96,6 +96,9 @@ def lib():
     L.pp_set_tuning.argtypes = [ctypes.c_int] * 5
     L.pp_set_gate_fusion.argtypes = [ctypes.c_int, ctypes.c_int]
     L.pp_set_layer_ops.argtypes = [ctypes.c_int]
+    L.pp_layer_stats.argtypes = [_vp, _u64p]
+    L.pp_set_layer_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.pp_get_layer_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     L.pp_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
     L.pp_set_merge_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
     L.pp_get_merge_tuning.argtypes = [ctypes.POINTER(ctypes.c_int)]
@@ -329,9 +332,10 @@ def pp_program_create(n, sub_start, gate_x, gate_z, theta, eps, max_weight, depo
 
 
 def pp_program_info(h):
-    out = (ctypes.c_uint64 * 3)()
+    out = (ctypes.c_uint64 * 4)()
     _check(lib().pp_program_info(h, out))
-    return dict(ops=int(out[0]), gate_launches=int(out[1]), gates=int(out[2]))
+    return dict(ops=int(out[0]), gate_launches=int(out[1]), gates=int(out[2]),
+                layer_ops=int(out[3]))
 
 
 def pp_program_destroy(h):
@@ -377,6 +381,27 @@ def pp_set_layer_ops(mode):
     """Layer ops for programs created afterwards: 0 off, 1 on, 2 on with
     every layer op falling back to its gate launches."""
     _check(lib().pp_set_layer_ops(int(mode)))
+
+
+def pp_set_layer_tuning(bucket_log2=0, block=0):
+    """Layer ops: log2 strings per bucket (4..10; 0 keeps) and threads per
+    bucket block (256 or 512; 0 keeps)."""
+    _check(lib().pp_set_layer_tuning(int(bucket_log2), int(block)))
+
+
+def pp_layer_stats(h):
+    """Layer ops completed, runs that overflowed a bucket, ops replaced by
+    their gate launches, and whether the handle runs gate launches only."""
+    out = np.zeros(4, dtype=np.uint64)
+    _check(lib().pp_layer_stats(h, out.ctypes.data_as(_u64p)))
+    return dict(layer_ops=int(out[0]), overflow_runs=int(out[1]), fallbacks=int(out[2]),
+                gates_only=bool(out[3]))
+
+
+def pp_get_layer_tuning():
+    out = (ctypes.c_int * 2)()
+    _check(lib().pp_get_layer_tuning(out))
+    return dict(bucket_log2=out[0], block=out[1])
 
 
 def pp_get_tuning():

@@ -44,6 +44,8 @@ struct Tuning {
   int gates_per_step = 4; // gate launches per batched step
   int part_shift = kPartShift;    // log2 records per bucket of the partitioned merge
   int part_agg_blocks = 0;        // aggregation blocks (0: one per item, up to 3P/2)
+  int layer_shift = kLayerShift;  // log2 strings per bucket of the layer op
+  int layer_block = 512;          // threads per bucket block of the layer op (256 or 512)
 };
 Tuning g_tune;
 int g_fuse = kMaxFuse;    // pp_set_gate_fusion: rotations per gate launch (<= 1: off)
@@ -108,6 +110,9 @@ struct pp_state {
   bool layer_off = false;              // layer ops failed too often: their fallbacks run
   int layer_fallbacks = 0;             // layer ops that fell back (this handle)
   size_t fb_lo = 0, fb_hi = 0;         // fallback ops [fb_lo, fb_hi) that launch_range runs
+  bool layer_tried[2 * kLayerMaxBoost + 1] = {};   // bucket boosts a failing layer op tried
+  size_t layer_fail_pc = ~size_t(0);   // the layer op they were tried for
+  int layer_retries = 0;               // runs of that op with other bucket counts
   const pp_program* batch_prog = nullptr;
   const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
@@ -324,6 +329,8 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
   // staging of the layer op (once a layer op has run on this handle)
   nb.lstx = nb.lstz = nullptr;
   nb.lstc = nullptr;
+  nb.lsta = nullptr;
+  nb.lsth = nullptr;
   nb.lcount = nullptr;
   nb.lslots = 0;
   nb.lmaxbits = 0;
@@ -333,6 +340,8 @@ int alloc_store(pp_state* s, uint32_t cap, InstBuf* b, std::vector<void*>* alloc
     ok = ok && (nb.lstx = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots));
     ok = ok && (nb.lstz = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots));
     ok = ok && (nb.lstc = (double*)take(sizeof(double) * nb.lslots));
+    ok = ok && (nb.lsta = (uint64_t*)take(sizeof(uint64_t) * nb.lslots));
+    ok = ok && (nb.lsth = (uint32_t*)take(sizeof(uint32_t) * nb.lslots));
     ok = ok && (nb.lcount = (uint32_t*)take(sizeof(uint32_t) << nb.lmaxbits));
   }
   const bool wide = !nb.narrow;
@@ -454,7 +463,8 @@ SoloFn solo_of(int kind, bool big, uint32_t nrot = 1, int lane_it = 0, int group
 
 SoloFn layer_of(int kind, int W) {
   if (kind == PP_K_LAYER_SCATTER) return W == 1 ? &k_layer_scatter<1> : &k_layer_scatter<2>;
-  return W == 1 ? &k_layer_apply<1> : &k_layer_apply<2>;
+  if (g_tune.layer_block == 256) return W == 1 ? &k_layer_apply<1, 256> : &k_layer_apply<2, 256>;
+  return W == 1 ? &k_layer_apply<1, 512> : &k_layer_apply<2, 512>;
 }
 
 // The layer op's staging, allocated when a handle first runs one (and
@@ -475,11 +485,15 @@ int ensure_layer(pp_state* s) {
   bool ok = (nb.lstx = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots)) != nullptr;
   ok = ok && (nb.lstz = (uint64_t*)take(sizeof(uint64_t) * W * nb.lslots));
   ok = ok && (nb.lstc = (double*)take(sizeof(double) * nb.lslots));
+  ok = ok && (nb.lsta = (uint64_t*)take(sizeof(uint64_t) * nb.lslots));
+  ok = ok && (nb.lsth = (uint32_t*)take(sizeof(uint32_t) * nb.lslots));
   ok = ok && (nb.lcount = (uint32_t*)take(sizeof(uint32_t) << nb.lmaxbits));
   if (!ok) {
     for (void* p : got) dev_free(s, p);
     nb.lstx = nb.lstz = nullptr;
     nb.lstc = nullptr;
+    nb.lsta = nullptr;
+    nb.lsth = nullptr;
     nb.lcount = nullptr;
     nb.lslots = nb.lmaxbits = 0;
     return fail(PP_ENOMEM, "allocation of the layer staging failed");
@@ -637,6 +651,7 @@ void kinds_of(const pp_state* s, const Op& op, std::vector<int>* out) {
 // whole, so the events do not sit between the launches they time.
 int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
   std::vector<int> kinds;
+  s->buf.lshift = (uint32_t)g_tune.layer_shift;   // layer ops launched from here on
   const bool big = s->m_hint >= kBigSet;   // last term count seen on the host
   // a set last seen well below the partitioned merge's threshold merges
   // unpartitioned (correct at any size): its two kernels are not launched
@@ -672,12 +687,12 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
                                       : launch_blocks(elems, items_of(kind, big));
       if (kind == PP_K_LAYER_APPLY) {       // about two blocks per bucket of the last size seen
         const uint32_t bits = layer_bits(std::max<uint32_t>(s->m_hint, 1), s->h_dyn->lboost,
-                                         s->buf.lmaxbits);
-        grid = (int)std::min<uint32_t>(2u << bits, 8192u);
+                                         s->buf.lmaxbits, s->buf.lshift);
+        grid = (int)std::min<uint32_t>(1u << bits, 8192u);   // one bucket per block
       }
       const int block = kind == PP_K_PART_SCAN ? kPCBlock
                         : kind == PP_K_PART_AGG ? kPABlock
-                        : kind == PP_K_LAYER_APPLY ? kLBlock
+                        : kind == PP_K_LAYER_APPLY ? g_tune.layer_block
                         : is_part_kind(kind)    ? kPHBlock
                                                 : kBlock;
       Solo S;
@@ -1079,6 +1094,23 @@ int pp_set_merge_tuning(int bucket_log2, int agg_blocks) {
   return PP_OK;
 }
 
+int pp_set_layer_tuning(int bucket_log2, int block) {
+  if (bucket_log2 != 0 && (bucket_log2 < 4 || bucket_log2 > 11))
+    return fail(PP_EINVAL, "bucket_log2 must be 0 (keep) or 4..11");
+  if (block != 0 && block != 256 && block != 512)
+    return fail(PP_EINVAL, "block must be 0 (keep), 256 or 512");
+  if (bucket_log2) g_tune.layer_shift = bucket_log2;
+  if (block) g_tune.layer_block = block;
+  return PP_OK;
+}
+
+int pp_get_layer_tuning(int out[2]) {
+  if (!out) return fail(PP_EINVAL, "NULL argument");
+  out[0] = g_tune.layer_shift;
+  out[1] = g_tune.layer_block;
+  return PP_OK;
+}
+
 int pp_get_merge_tuning(int out[2]) {
   if (!out) return fail(PP_EINVAL, "NULL argument");
   out[0] = g_tune.part_shift;
@@ -1339,6 +1371,17 @@ int pp_store_bytes(int n_qubits, int group, int dtype, size_t cap, size_t* out) 
   int rc = alloc_store(&st, (uint32_t)cap, &b, &none, &bytes);
   if (rc) return rc;
   *out = bytes;
+  return PP_OK;
+}
+
+int pp_layer_stats(pp_state* s, uint64_t out[4]) {
+  if (!s || !out) return fail(PP_EINVAL, "NULL argument");
+  int rc = read_dyn(s);
+  if (rc) return rc;
+  out[0] = s->h_dyn->lops;
+  out[1] = s->h_dyn->lfails;
+  out[2] = (uint64_t)s->layer_fallbacks;
+  out[3] = s->layer_off ? 1u : 0u;
   return PP_OK;
 }
 
@@ -1891,14 +1934,17 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
   return PP_OK;
 }
 
-int pp_program_info(const pp_program* p, uint64_t out[3]) {
+int pp_program_info(const pp_program* p, uint64_t out[4]) {
   if (!p || !out) return fail(PP_EINVAL, "NULL argument");
-  uint64_t gates = 0;              // apply ops the one-instance path runs
-  for (const auto& op : p->ops)
-    gates += op.type == OP_LAYER || ((op.type == OP_GATE || op.type == OP_GATES) && !op.fallback);
+  uint64_t gates = 0, layers = 0;  // apply ops the one-instance path runs
+  for (const auto& op : p->ops) {
+    gates += (op.type == OP_GATE || op.type == OP_GATES) && !op.fallback;
+    layers += op.type == OP_LAYER;
+  }
   out[0] = p->ops.size();
-  out[1] = gates;
+  out[1] = gates + layers;
   out[2] = p->n_gates;
+  out[3] = layers;
   return PP_OK;
 }
 
@@ -2008,10 +2054,12 @@ int ensure_graph(BatchCtx* b) {
 // leaves a batch at a step boundary) instead of starting the program.
 // A layer op at pc reported a bucket that did not fit (ST_LAYER; h_dyn is
 // fresh and the device idles behind it): grow a crowded store, else run it
-// again with twice the buckets, else run its GATE(S) copies instead.  After
-// kLayerGiveUp fallbacks the handle runs the copies in place of every layer
-// op.
-constexpr int kLayerGiveUp = 8;
+// again with fewer buckets (staging slots overflowed) or more (the LDS
+// did), at most kLayerRetries times, else run its GATE(S) copies instead.
+// After kLayerGiveUp fallbacks the handle runs the copies in place of every
+// layer op.
+constexpr int kLayerGiveUp = 3;
+constexpr int kLayerRetries = 2;   // runs again with other bucket counts before a fallback
 
 int layer_failed(pp_state* s, const Op* ops, size_t len) {
   InstDyn& h = *s->h_dyn;
@@ -2019,13 +2067,27 @@ int layer_failed(pp_state* s, const Op* ops, size_t len) {
   const uint32_t k = h.pc;
   int rc;
   if (k < len && ops[k].type == OP_LAYER) {
-    if (!ops[k].fail_test && (uint64_t)h.M * 3 > s->buf.cap) {
+    // a bucket's staging slots overflowed: fewer, larger buckets (a set of
+    // strings closed under the rotations may be large); the LDS overflowed:
+    // more, smaller buckets
+    if (s->layer_fail_pc != k) {              // another op: every boost may be tried again
+      for (bool& t : s->layer_tried) t = false;
+      s->layer_fail_pc = k;
+      s->layer_retries = 0;
+    }
+    const int32_t step = h.lwhy & 1u ? -1 : 1;
+    const int32_t next = h.lboost + step;
+    if (!ops[k].fail_test && (h.lwhy & 1u) && (uint64_t)h.M * 3 > s->buf.cap) {
       if ((rc = grow(s))) return rc;           // more staging slots per bucket
-    } else if (!ops[k].fail_test && h.lboost < (uint32_t)kLayerMaxBoost) {
-      h.lboost += 1;
-      HIP_TRY(hipMemcpyAsync(&s->d_dyn->lboost, &h.lboost, sizeof(uint32_t),
+    } else if (!ops[k].fail_test && next >= -kLayerMaxBoost && next <= kLayerMaxBoost &&
+               !s->layer_tried[next + kLayerMaxBoost] && s->layer_retries < kLayerRetries) {
+      ++s->layer_retries;
+      s->layer_tried[h.lboost + kLayerMaxBoost] = true;
+      h.lboost = next;
+      HIP_TRY(hipMemcpyAsync(&s->d_dyn->lboost, &h.lboost, sizeof(int32_t),
                              hipMemcpyHostToDevice, s->stream));
     } else {
+      for (bool& t : s->layer_tried) t = false;
       s->fb_lo = k + 1;
       s->fb_hi = k + 1 + ops[k].skip;
       h.pc = k + 1;

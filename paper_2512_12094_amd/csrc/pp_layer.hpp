@@ -14,32 +14,36 @@
 // each string in it, its partner under every rotation and every child the
 // rotations can make: a block rotates its bucket in LDS with no other block.
 //
-// Within a bucket, rotation g runs over the strings live before it (their
-// stamp equals g), each with its partner P_g Q found in the bucket's LDS
-// hash table: both live -> the pair rotation (the lower index writes both),
-// partner absent or dropped -> cos on Q and a child sin on P_g Q (a dropped
-// partner's slot is reused), then the truncation of what changed, exactly as
-// the one-rotation gate kernel does it, so the results are bitwise those of
-// r gate launches.  Children of rotation g get indices past those it reads.
+// The same holds for any union of such sets, so within a bucket each wave
+// takes the strings of whole sets (by the key's hash): a wave rotates its
+// strings with no other wave and no barrier, and runs only the rotations one
+// of its strings anticommutes with (a is shared by a set's members).
+//
+// A wave's rotation g runs over its strings live before it, each with its
+// partner P_g Q found in the wave's LDS hash table: both live -> the pair
+// rotation (the lower index writes both), partner absent or dropped -> cos
+// on Q and a child sin on P_g Q (a dropped partner's slot is reused), then
+// the truncation of what changed, exactly as the one-rotation gate kernel
+// does it, so the results are bitwise those of r gate launches.  Children
+// of rotation g get indices past those it reads.
 #pragma once
 #include "pp_kernels.hpp"
 
 namespace pp {
 
-constexpr int kLBlock = 256;
-constexpr int kLWaves = kLBlock / 64;
+constexpr uint32_t kAlive = 0xFFu;   // died field of a live string (see live_before)
 
 template <int WW> struct LayerCap;
 template <> struct LayerCap<1> { static constexpr int n = 2048; };   // strings per bucket in LDS
 template <> struct LayerCap<2> { static constexpr int n = 1024; };
 
-// Bucket bits for a layer op over M entries: about 2^kLayerShift strings per
-// bucket, more after failures (boost), at most lmaxbits.
-__device__ __host__ __forceinline__ uint32_t layer_bits(uint32_t M, uint32_t boost,
-                                                        uint32_t maxbits) {
+// Bucket bits for a layer op over M entries: about 2^shift strings per
+// bucket, more after failures (boost), at most maxbits.
+__device__ __host__ __forceinline__ uint32_t layer_bits(uint32_t M, int32_t boost,
+                                                        uint32_t maxbits, uint32_t shift) {
   uint32_t lg = 0;
   while (lg < 32 && (1ull << lg) < (uint64_t)M) ++lg;
-  int bits = (int)lg - kLayerShift + (int)boost;
+  int bits = (int)lg - (int)shift + boost;   // boost: from earlier failures
   if (bits < 0) bits = 0;
   if (bits > (int)maxbits) bits = (int)maxbits;
   return (uint32_t)bits;
@@ -49,11 +53,12 @@ __device__ __forceinline__ uint64_t rot_word(const double* t, int k) {
   return (uint64_t)__double_as_longlong(t[k]);
 }
 
-// The bucket key's hash: anticommutation pattern and the bits no
-// anticommuting rotation touches.
+// The bucket key's hash (anticommutation pattern and the bits no
+// anticommuting rotation touches); *pat = the pattern.
 template <int WW>
 __device__ __forceinline__ uint64_t layer_key(const uint64_t* x, const uint64_t* z, uint32_t r,
-                                              const uint64_t (*px)[WW], const uint64_t (*pz)[WW]) {
+                                              const uint64_t (*px)[WW], const uint64_t (*pz)[WW],
+                                              uint64_t* pat) {
   uint64_t a = 0, ux[WW], uz[WW];
 #pragma unroll
   for (int w = 0; w < WW; ++w) ux[w] = uz[w] = 0;
@@ -76,13 +81,21 @@ __device__ __forceinline__ uint64_t layer_key(const uint64_t* x, const uint64_t*
     h = mix64(h ^ (x[w] & ~ux[w]));
     h = mix64(h ^ (z[w] & ~uz[w]) ^ 0x9e3779b97f4a7c15ull);
   }
+  *pat = a;
   return h;
 }
 
-// 1. Every live string of the current half to its bucket's staging slots.
+constexpr int kLTile = 4;                  // strings per thread per scatter round
+constexpr int kLAggMax = 2048;             // buckets counted in LDS before the global add
+
+// 1. Every live string of the current half to its bucket's staging slots,
+// with its pattern and key hash.  A round of kBlock * kLTile strings counts
+// its strings per bucket in LDS and reserves each bucket's slots with one
+// global add (buckets up to kLAggMax; beyond, one global add per string).
 template <int WW>
 __global__ __launch_bounds__(kBlock) void k_layer_scatter(Solo S) {
   __shared__ uint64_t s_px[kLayerMaxRot][WW], s_pz[kLayerMaxRot][WW];
+  __shared__ uint32_t s_cnt[kLAggMax];
   const InstBuf& b = S.b;
   InstDyn& d = *S.d;
   if (d.pc != S.k) return;                 // an earlier op did not complete
@@ -95,35 +108,65 @@ __global__ __launch_bounds__(kBlock) void k_layer_scatter(Solo S) {
       s_pz[g][w] = rot_word(op.table, g * kLayerRec + kMaxW + w);
     }
   }
-  __syncthreads();
-  const uint32_t M = d.M;
-  const uint32_t bits = layer_bits(M, d.lboost, b.lmaxbits);
-  const uint32_t slots = b.lslots >> bits, L = b.lslots;
+  const uint32_t M = op.fail_test ? 0u : d.M;
+  const uint32_t bits = layer_bits(d.M, d.lboost, b.lmaxbits, b.lshift);
+  const uint32_t P = 1u << bits, slots = b.lslots >> bits, L = b.lslots;
+  const bool agg = P <= (uint32_t)kLAggMax;
   const View v = view_of(b, d);
   bool over = op.fail_test != 0 && blockIdx.x == 0 && threadIdx.x == 0;
-  const uint32_t Mrun = op.fail_test ? 0u : M;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < Mrun; i += gridDim.x * kBlock) {
-    if (!v.al[i]) continue;
-    uint64_t x[WW], z[WW];
-#pragma unroll
-    for (int w = 0; w < WW; ++w) {
-      x[w] = v.X[(size_t)w * v.cap + i];
-      z[w] = v.Z[(size_t)w * v.cap + i];
+  const uint32_t round = kBlock * kLTile;
+  const uint32_t rounds = (M + round - 1) / round;
+  for (uint32_t t = blockIdx.x; t < rounds; t += gridDim.x) {
+    if (agg) {
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < P; k += kBlock) s_cnt[k] = 0;
     }
-    const double c = v.getc(i);
-    const uint64_t h = layer_key<WW>(x, z, r, s_px, s_pz);
-    const uint32_t bk = bits ? (uint32_t)(h >> (64 - bits)) : 0u;
-    const uint32_t rank = atomicAdd(&b.lcount[bk], 1u);
-    if (rank >= slots) { over = true; continue; }
-    const size_t pos = (size_t)bk * slots + rank;
+    __syncthreads();                       // rotations loaded, counts zero
+    uint64_t x[kLTile][WW], z[kLTile][WW], a[kLTile];
+    double c[kLTile];
+    uint32_t bk[kLTile], rank[kLTile], h32[kLTile];
+    bool has[kLTile];
 #pragma unroll
-    for (int w = 0; w < WW; ++w) {
-      b.lstx[(size_t)w * L + pos] = x[w];
-      b.lstz[(size_t)w * L + pos] = z[w];
+    for (int k = 0; k < kLTile; ++k) {
+      const uint32_t i = t * round + k * kBlock + threadIdx.x;
+      has[k] = i < M && v.al[i];
+      if (!has[k]) continue;
+#pragma unroll
+      for (int w = 0; w < WW; ++w) {
+        x[k][w] = v.X[(size_t)w * v.cap + i];
+        z[k][w] = v.Z[(size_t)w * v.cap + i];
+      }
+      c[k] = v.getc(i);
+      const uint64_t h = layer_key<WW>(x[k], z[k], r, s_px, s_pz, &a[k]);
+      h32[k] = (uint32_t)h;
+      bk[k] = bits ? (uint32_t)(h >> (64 - bits)) : 0u;
+      rank[k] = agg ? atomicAdd(&s_cnt[bk[k]], 1u) : atomicAdd(&b.lcount[bk[k]], 1u);
     }
-    b.lstc[pos] = c;
+    if (agg) {
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < P; k += kBlock) {
+        const uint32_t n = s_cnt[k];
+        s_cnt[k] = n ? atomicAdd(&b.lcount[k], n) : 0u;   // this round's first slot
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kLTile; ++k) {
+      if (!has[k]) continue;
+      const uint32_t rk = agg ? s_cnt[bk[k]] + rank[k] : rank[k];
+      if (rk >= slots) { over = true; continue; }
+      const size_t pos = (size_t)bk[k] * slots + rk;
+#pragma unroll
+      for (int w = 0; w < WW; ++w) {
+        b.lstx[(size_t)w * L + pos] = x[k][w];
+        b.lstz[(size_t)w * L + pos] = z[k][w];
+      }
+      b.lstc[pos] = c[k];
+      b.lsta[pos] = a[k];
+      b.lsth[pos] = h32[k];
+    }
   }
-  if (over) atomicOr(&d.lfail, 1u);
+  if (over) atomicOr(&d.lfail, 1u);        // a bucket's staging slots overflowed
 }
 
 template <int WW>
@@ -134,261 +177,135 @@ __device__ __forceinline__ uint32_t lds_hash(const uint64_t* x, const uint64_t* 
   return (uint32_t)((h ^ (h >> 31)) >> 32);
 }
 
-// Liveness stamps: a string kept through rotation g gets g + 1, a string
-// revived by rotation g (its slot reused for a child) gets kRevived + g + 1.
-// Rotation g reads the strings live before it: stamp g or kRevived + g, or
-// g + 1 when its pair's leader already kept it (a revival by rotation g,
-// kRevived + g + 1, is not live before it).
-constexpr uint8_t kRevived = 128;
-__device__ __forceinline__ bool live_before(uint8_t st, uint32_t g) {
-  return st == g || st == g + 1 || st == kRevived + g;
-}
-__device__ __forceinline__ bool live_after(uint8_t st, uint32_t g) {
-  return st == g + 1 || st == kRevived + g + 1;
+
+// Exclusive scan of one value per thread over a block of NW waves; *total
+// = block sum.  s_tmp needs NW + 1 entries.  Contains __syncthreads.
+template <int NW>
+__device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tmp[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int w = 0; w < NW; ++w) { const uint32_t t = s_tmp[w]; s_tmp[w] = acc; acc += t; }
+    s_tmp[NW] = acc;
+  }
+  __syncthreads();
+  const uint32_t r = x - v + s_tmp[wid];
+  *total = s_tmp[NW];
+  __syncthreads();
+  return r;
 }
 
-// 2. One block per bucket (grid-stride over buckets): the r rotations in
-// LDS, then the survivors to the other half.  The last block folds the
-// sums and advances the program (or reports the failure).
-template <int WW>
-__global__ __launch_bounds__(kLBlock) void k_layer_apply(Solo S) {
-  constexpr int CAP = LayerCap<WW>::n, HS = 2 * CAP;
-  constexpr int NS = 7;                    // sums, see below
-  __shared__ uint64_t s_x[WW][CAP], s_z[WW][CAP];
-  __shared__ double s_c[CAP];
-  __shared__ uint8_t s_st[CAP];            // liveness stamp
-  __shared__ uint16_t s_hash[HS];          // index + 1, 0 = empty
-  __shared__ uint64_t s_px[kLayerMaxRot][WW], s_pz[kLayerMaxRot][WW];
-  __shared__ double s_cs[kLayerMaxRot], s_sn[kLayerMaxRot];
-  __shared__ uint32_t s_inc[3], s_n0, s_fail, s_flag, s_tmp[kLWaves + 1], s_base;
-  __shared__ uint64_t s_red[kLWaves][NS];
-  const InstBuf& b = S.b;
-  InstDyn& d = *S.d;
-  if (d.pc != S.k) return;                 // uniform: pc changes only in the last block
-  const Op& op = b.prog[S.k];
-  const uint32_t r = op.nrot;
-  const double eps = op.eps;
-  const int wmax = op.wmax;
-  const bool full = op.full_check != 0, gtab = op.gtab != 0;
-  const bool has_next = op.next_gate != kNone32;
-  uint64_t nxm[WW], nzm[WW];
+__device__ __forceinline__ uint16_t lds_load16(const uint16_t* p) {
+  return *reinterpret_cast<const volatile uint16_t*>(p);
+}
+
+// local index of the string (x, z) in a wave's LDS table (its strings at
+// base + local index), or -1
+template <int WW, int CAP>
+__device__ __forceinline__ int lds_find(const uint16_t* tab, int HS, const uint64_t (*sx)[CAP],
+                                        const uint64_t (*sz)[CAP], uint32_t base,
+                                        const uint64_t* x, const uint64_t* z) {
+  uint32_t sl = lds_hash<WW>(x, z) & (HS - 1);
+  for (int probe = 0; probe < HS; ++probe) {
+    const uint32_t e = lds_load16(&tab[sl]);
+    if (e == 0) return -1;
+    const int j = (int)e - 1;
+    bool eq = true;
 #pragma unroll
-  for (int w = 0; w < WW; ++w) { nxm[w] = op.nx[w]; nzm[w] = op.nz[w]; }
-  for (uint32_t g = threadIdx.x; g < r; g += kLBlock) {
+    for (int w = 0; w < WW; ++w) eq = eq && sx[w][base + j] == x[w] && sz[w][base + j] == z[w];
+    if (eq) return j;
+    sl = (sl + 1) & (HS - 1);
+  }
+  return -1;
+}
+
+// publishes index j (its string already written) under (x, z)
+template <int WW>
+__device__ __forceinline__ void lds_insert(uint16_t* tab, int HS, const uint64_t* x,
+                                           const uint64_t* z, int j) {
+  uint32_t sl = lds_hash<WW>(x, z) & (HS - 1);
+  for (int probe = 0; probe < HS; ++probe) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(&tab[sl]);
+    uint32_t* wp = reinterpret_cast<uint32_t*>(a & ~uintptr_t(3));
+    const uint32_t shift = (a & 2) ? 16u : 0u;
+    uint32_t old = *reinterpret_cast<volatile uint32_t*>(wp);
+    for (;;) {
+      if ((old >> shift) & 0xFFFFu) break;                        // slot taken
+      const uint32_t got = atomicCAS(wp, old, old | ((uint32_t)(j + 1) << shift));
+      if (got == old) return;
+      old = got;
+    }
+    sl = (sl + 1) & (HS - 1);
+  }
+}
+
+template <int WW>
+__device__ __forceinline__ bool layer_heavy(const uint64_t* x, const uint64_t* z, int wmax) {
+  if (wmax < 0) return false;
+  int n = 0;
+#pragma unroll
+  for (int w = 0; w < WW; ++w) n += __popcll(x[w] | z[w]);
+  return n > wmax;
+}
+
+// The bucket's survivors (every LDS slot whose string lives; unused slots
+// read as dropped) to the other half of the store (one atomic per block and
+// bucket), with gate-table entries when the op asks for them.
+template <int WW, int NB, int CAP>
+__device__ __forceinline__ void emit_survivors(const InstBuf& b, InstDyn& d, const Op& op,
+                                               const uint64_t (*sx)[CAP], const uint64_t (*sz)[CAP],
+                                               const double* sc, const uint16_t* life,
+                                               uint32_t* s_tmp,
+                                               uint32_t* s_base, uint32_t* out, uint32_t* next) {
+  constexpr int NW = NB / 64;
+  auto alive = [&](uint32_t j) { return (life[j] & 0xFFu) == kAlive; };   // unused slots: died 0
+  uint32_t mine = 0;
+  for (uint32_t j = threadIdx.x; j < (uint32_t)CAP; j += NB) mine += alive(j) ? 1u : 0u;
+  uint32_t total;
+  uint32_t off = block_scan_n<NW>(mine, s_tmp, &total);
+  if (threadIdx.x == 0) *s_base = total ? atomicAdd(&d.nuniq, total) : 0u;
+  __syncthreads();
+  const uint32_t ob = *s_base, cap = b.cap, ho = d.half ^ 1u;
+  const bool has_next = op.next_gate != kNone32, gtab = op.gtab != 0;
+  *out += mine;
+  for (uint32_t j = threadIdx.x; j < (uint32_t)CAP; j += NB) {
+    if (!alive(j)) continue;
+    const uint32_t pos = ob + off++;
+    uint64_t x[kMaxW] = {}, z[kMaxW] = {};
+#pragma unroll
+    for (int w = 0; w < WW; ++w) { x[w] = sx[w][j]; z[w] = sz[w][j]; }
+    uint64_t nx[kMaxW] = {}, nz[kMaxW] = {};
+#pragma unroll
+    for (int w = 0; w < WW; ++w) { nx[w] = op.nx[w]; nz[w] = op.nz[w]; }
+    if (has_next && anticommutes(x, z, nx, nz, WW)) ++*next;
+    if (pos >= cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
 #pragma unroll
     for (int w = 0; w < WW; ++w) {
-      s_px[g][w] = rot_word(op.table, g * kLayerRec + w);
-      s_pz[g][w] = rot_word(op.table, g * kLayerRec + kMaxW + w);
+      b.x[ho][(size_t)w * cap + pos] = x[w];
+      b.z[ho][(size_t)w * cap + pos] = z[w];
     }
-    s_cs[g] = op.table[g * kLayerRec + 2 * kMaxW];
-    s_sn[g] = op.table[g * kLayerRec + 2 * kMaxW + 1];
+    if (b.f32)
+      static_cast<float*>(b.c[ho])[pos] = (float)sc[j];
+    else
+      static_cast<double*>(b.c[ho])[pos] = sc[j];
+    b.alive[ho][0][pos] = 1;
+    if (gtab) gt_insert(b.gtab, b.hg_bits, d.gen + 1, pos, hash_key(x, z, WW, 0));
   }
-  const uint32_t M = d.M;
-  const uint32_t bits = layer_bits(M, d.lboost, b.lmaxbits);
-  const uint32_t P = 1u << bits, slots = b.lslots >> bits, L = b.lslots;
-  const bool failed = ld_agent(&d.lfail) != 0;   // the scatter launch has ended
-  const uint32_t ho = d.half ^ 1u;
-  const uint32_t gen1 = d.gen + 1;
-  const bool f32 = b.f32 != 0;
-  const uint32_t cap = b.cap;
-  // sums: [0] live before each rotation, [1] anticommuting with it,
-  // [2] survivors, [3] survivors anticommuting with the next gate,
-  // [4] children, [5] strings held at the end, [6] strings entering
-  uint64_t sum[NS] = {0, 0, 0, 0, 0, 0, 0};
-  bool bad = false;
-  auto heavy = [&](const uint64_t* x, const uint64_t* z) {
-    if (wmax < 0) return false;
-    int w8 = 0;
-#pragma unroll
-    for (int w = 0; w < WW; ++w) w8 += __popcll(x[w] | z[w]);
-    return w8 > wmax;
-  };
-  // index of the string (x, z) in the bucket, or -1
-  auto find = [&](const uint64_t* x, const uint64_t* z) -> int {
-    uint32_t sl = lds_hash<WW>(x, z) & (HS - 1);
-    for (int probe = 0; probe < HS; ++probe) {
-      const uint32_t e = *reinterpret_cast<volatile uint16_t*>(&s_hash[sl]);
-      if (e == 0) return -1;
-      const int j = (int)e - 1;
-      bool eq = true;
-#pragma unroll
-      for (int w = 0; w < WW; ++w) eq = eq && s_x[w][j] == x[w] && s_z[w][j] == z[w];
-      if (eq) return j;
-      sl = (sl + 1) & (HS - 1);
-    }
-    return -1;
-  };
-  // publishes index j (its string already written) under (x, z)
-  auto insert = [&](const uint64_t* x, const uint64_t* z, int j) {
-    uint32_t sl = lds_hash<WW>(x, z) & (HS - 1);
-    for (int probe = 0; probe < HS; ++probe) {
-      const uintptr_t a = reinterpret_cast<uintptr_t>(&s_hash[sl]);
-      uint32_t* wp = reinterpret_cast<uint32_t*>(a & ~uintptr_t(3));
-      const uint32_t shift = (a & 2) ? 16u : 0u;
-      uint32_t old = *reinterpret_cast<volatile uint32_t*>(wp);
-      for (;;) {
-        if ((old >> shift) & 0xFFFFu) break;                      // slot taken
-        const uint32_t got = atomicCAS(wp, old, old | ((uint32_t)(j + 1) << shift));
-        if (got == old) return;
-        old = got;
-      }
-      sl = (sl + 1) & (HS - 1);
-    }
-  };
+}
 
-  for (uint32_t bk = blockIdx.x; bk < P; bk += gridDim.x) {
-    __syncthreads();                       // the previous bucket's LDS is free
-    if (threadIdx.x == 0) {
-      const uint32_t cnt = b.lcount[bk];
-      b.lcount[bk] = 0;                    // zero for the next layer op
-      s_n0 = cnt < slots ? cnt : slots;
-      s_fail = s_n0 > (uint32_t)CAP ? 1u : 0u;
-      s_inc[0] = s_inc[1] = s_inc[2] = 0;
-    }
-    for (int t = threadIdx.x; t < HS / 2; t += kLBlock) reinterpret_cast<uint32_t*>(s_hash)[t] = 0;
-    __syncthreads();
-    if (failed || s_fail) { bad = bad || s_fail; continue; }   // uniform
-    const uint32_t n0 = s_n0;
-    const size_t base = (size_t)bk * slots;
-    sum[6] += threadIdx.x == 0 ? n0 : 0u;
-    for (uint32_t j = threadIdx.x; j < n0; j += kLBlock) {
-      uint64_t x[WW], z[WW];
-#pragma unroll
-      for (int w = 0; w < WW; ++w) {
-        x[w] = b.lstx[(size_t)w * L + base + j];
-        z[w] = b.lstz[(size_t)w * L + base + j];
-        s_x[w][j] = x[w];
-        s_z[w][j] = z[w];
-      }
-      s_c[j] = b.lstc[base + j];
-      s_st[j] = 0;
-      __threadfence_block();
-      insert(x, z, (int)j);
-    }
-    __syncthreads();
-    uint32_t ng = n0;                      // strings before rotation g
-    for (uint32_t g = 0; g < r; ++g) {
-      if (threadIdx.x == 0) s_inc[(g + 1) % 3] = 0;
-      uint64_t px[WW], pz[WW];
-#pragma unroll
-      for (int w = 0; w < WW; ++w) { px[w] = s_px[g][w]; pz[w] = s_pz[g][w]; }
-      const double cs = s_cs[g], sn = s_sn[g];
-      const bool chk = g == 0 && full;
-      const uint8_t kept = (uint8_t)(g + 1), back = (uint8_t)(kRevived + g + 1);
-      for (uint32_t j = threadIdx.x; j < ng; j += kLBlock) {
-        if (!live_before(s_st[j], g)) continue;
-        ++sum[0];
-        uint64_t qx[WW], qz[WW];
-#pragma unroll
-        for (int w = 0; w < WW; ++w) { qx[w] = s_x[w][j]; qz[w] = s_z[w][j]; }
-        if (!anticommutes(qx, qz, px, pz, WW)) {      // unchanged
-          const double cq = s_c[j];
-          if (!chk || (fabs(cq) >= eps && !heavy(qx, qz))) s_st[j] = kept;
-          continue;
-        }
-        ++sum[1];
-        uint64_t rx[WW], rz[WW];
-#pragma unroll
-        for (int w = 0; w < WW; ++w) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
-        const int p = find(rx, rz);
-        const bool plive = p >= 0 && (uint32_t)p < ng && live_before(s_st[p], g);
-        if (plive && (uint32_t)p < j) continue;       // the partner's thread leads
-        const int sig = product_sign(px, pz, qx, qz, rx, rz, WW);   // i P Q = sig R
-        const double cq = s_c[j];
-        if (plive) {                       // Q and R = PQ live: a rotation of the pair
-          double nq, nr;
-          rotate_pair(f32, cs, sn, sig, cq, s_c[p], &nq, &nr);
-          s_c[j] = nq;
-          s_c[p] = nr;
-          if (fabs(nq) >= eps && !(chk && heavy(qx, qz))) s_st[j] = kept;
-          if (fabs(nr) >= eps && !(chk && heavy(rx, rz))) s_st[p] = kept;
-        } else {
-          double nq, child;
-          rotate_single(f32, cs, sn, sig, cq, &nq, &child);
-          s_c[j] = nq;
-          if (fabs(nq) >= eps && !(chk && heavy(qx, qz))) s_st[j] = kept;
-          if (fabs(child) >= eps && !heavy(rx, rz)) {
-            ++sum[4];
-            if (p >= 0) {                  // a dropped string comes back in its slot
-              s_c[p] = child;
-              s_st[p] = back;
-            } else {
-              const uint32_t k = ng + atomicAdd(&s_inc[g % 3], 1u);
-              if (k >= (uint32_t)CAP) {
-                s_fail = 1;
-              } else {
-#pragma unroll
-                for (int w = 0; w < WW; ++w) { s_x[w][k] = rx[w]; s_z[w][k] = rz[w]; }
-                s_c[k] = child;
-                s_st[k] = back;
-                __threadfence_block();
-                insert(rx, rz, (int)k);
-              }
-            }
-          }
-        }
-      }
-      __syncthreads();
-      const uint32_t add = s_inc[g % 3];
-      ng = ng + add < (uint32_t)CAP ? ng + add : (uint32_t)CAP;
-    }
-    sum[5] += threadIdx.x == 0 ? ng : 0u;
-    if (s_fail) { bad = true; continue; }  // uniform: read after the last barrier
-    // survivors to the other half: one atomic per block and bucket
-    uint32_t mine = 0;
-    for (uint32_t j = threadIdx.x; j < ng; j += kLBlock) mine += live_after(s_st[j], r - 1) ? 1u : 0u;
-    uint32_t total;
-    uint32_t off = block_scan(mine, s_tmp, &total);
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(&d.nuniq, total) : 0u;
-    __syncthreads();
-    const uint32_t ob = s_base;
-    sum[2] += mine;
-    for (uint32_t j = threadIdx.x; j < ng; j += kLBlock) {
-      if (!live_after(s_st[j], r - 1)) continue;
-      const uint32_t pos = ob + off++;
-      uint64_t x[kMaxW] = {}, z[kMaxW] = {};
-#pragma unroll
-      for (int w = 0; w < WW; ++w) { x[w] = s_x[w][j]; z[w] = s_z[w][j]; }
-      if (has_next && anticommutes(x, z, nxm, nzm, WW)) ++sum[3];
-      if (pos >= cap) { atomicOr(&d.status, ST_OVERFLOW); continue; }
-#pragma unroll
-      for (int w = 0; w < WW; ++w) {
-        b.x[ho][(size_t)w * cap + pos] = x[w];
-        b.z[ho][(size_t)w * cap + pos] = z[w];
-      }
-      if (f32)
-        static_cast<float*>(b.c[ho])[pos] = (float)s_c[j];
-      else
-        static_cast<double*>(b.c[ho])[pos] = s_c[j];
-      b.alive[ho][0][pos] = 1;
-      if (gtab) gt_insert(b.gtab, b.hg_bits, gen1, pos, hash_key(x, z, WW, 0));
-    }
-  }
-  // block sums -> this block's shard line, entries 1..NS
-  {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      uint64_t t = sum[k];
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-      if (lane == 0) s_red[wid][k] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x < NS) {
-      uint64_t t = 0;
-      for (int q = 0; q < kLWaves; ++q) t += s_red[q][threadIdx.x];
-      if (t)
-        atomicAdd((unsigned long long*)&b.accs[(blockIdx.x % kAccShards) * kLineU64 + 1 + threadIdx.x],
-                  (unsigned long long)t);
-    }
-    if (threadIdx.x == 0 && bad) atomicOr(&d.lfail, 1u);
-  }
-  if (!last_block(S.sync, &s_flag, gridDim.x, true)) return;
-  if (threadIdx.x != 0) return;
-  uint64_t t[NS];
-  for (int k = 0; k < NS; ++k) t[k] = 0;
+// Last block, one thread: folds the sums; on success the op's counts, the
+// other half becomes current and pc passes the op's fallback copies.
+__device__ __forceinline__ void layer_finish(const InstBuf& b, InstDyn& d, const Op& op, int ns) {
+  uint64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int sh = 0; sh < kAccShards; ++sh)
-    for (int k = 0; k < NS; ++k)
+    for (int k = 0; k < ns; ++k)
       t[k] += atomicExch((unsigned long long*)&b.accs[sh * kLineU64 + 1 + k], 0ull);
   const uint32_t out = ld_agent(&d.nuniq);
   d.nuniq = 0;
@@ -398,12 +315,16 @@ __global__ __launch_bounds__(kLBlock) void k_layer_apply(Solo S) {
     d.failed_pc = d.pc;
     return;
   }
-  if (ld_agent(&d.lfail)) {                 // a bucket did not fit: the host decides
+  const uint32_t why = ld_agent(&d.lfail);
+  if (why) {                                // a bucket did not fit: the host decides
     d.lfail = 0;
+    d.lwhy = why;                           // 1 staging slots, 2 LDS
+    d.lfails += 1;
     d.status |= ST_LAYER;
     d.failed_pc = d.pc;
     return;
   }
+  d.lops += 1;
   d.propagated += t[0];
   d.merged += t[0] + t[1];
   d.anti_total += t[1];
@@ -416,11 +337,241 @@ __global__ __launch_bounds__(kLBlock) void k_layer_apply(Solo S) {
   d.count = (uint32_t)t[3];
   const uint64_t held = t[5] > out ? t[5] : out;
   if (held > d.peak) d.peak = held < 0xFFFFFFFFull ? (uint32_t)held : 0xFFFFFFFFu;
-  d.half = ho;
+  d.half ^= 1u;
   d.parity = 0;
-  if (gtab) d.gen = gen1;
+  if (op.gtab) d.gen += 1;
   d.count_for = op.next_gate;
   d.pc += 1 + op.skip;
+}
+
+// Liveness of a bucket's string: born (the rotation before which it first
+// exists: 0, or g + 1 for a child of rotation g) and died (the rotation
+// after which it was dropped, kAlive while it lives), packed in 16 bits so
+// that one store changes both.  A string is live before rotation g iff
+// born <= g <= died.  Rotation g writes `died = g` for strings it drops and
+// (g + 1, kAlive) for a dropped string it makes again; a string's own thread
+// never reads these mid-rotation values as "live before" wrongly: died = g
+// still reads live before g, and born = g + 1 reads not live.
+__device__ __forceinline__ bool live_before(uint32_t life, uint32_t g) {
+  return (life >> 8) <= g && (life & 0xFFu) >= g;
+}
+__device__ __forceinline__ uint16_t life_of(uint32_t born, uint32_t died) {
+  return (uint16_t)((born << 8) | died);
+}
+
+// 2. One block per bucket (grid-stride over buckets): the bucket's strings
+// into LDS (one hash table), then the rotations some of them anticommute
+// with (and the first one if the op re-checks every string there), each
+// over all the bucket's strings with a block barrier after it; then the
+// survivors go to the other half.  The last block folds the sums and
+// advances the program (or reports the failure).  Live counts before each
+// rotation follow from the strings entering and the births and drops of
+// the rotations before it.
+template <int WW, int NB>
+__global__ __launch_bounds__(NB) void k_layer_apply(Solo S) {
+  constexpr int kLWaves = NB / 64;
+  constexpr int CAP = LayerCap<WW>::n, HS = 2 * CAP;
+  constexpr int NS = 7;                    // sums, see below
+  __shared__ uint64_t s_x[WW][CAP], s_z[WW][CAP];
+  __shared__ double s_c[CAP];
+  __shared__ uint16_t s_life[CAP];
+  __shared__ uint16_t s_hash[HS];          // index + 1, 0 = empty
+  __shared__ uint64_t s_px[kLayerMaxRot][WW], s_pz[kLayerMaxRot][WW];
+  __shared__ double s_cs[kLayerMaxRot], s_sn[kLayerMaxRot];
+  __shared__ unsigned long long s_pat;     // rotations some string anticommutes with
+  __shared__ uint32_t s_inc[3], s_n0, s_fail, s_flag, s_tmp[kLWaves + 1], s_base;
+  __shared__ uint64_t s_red[kLWaves][NS];
+  const InstBuf& b = S.b;
+  InstDyn& d = *S.d;
+  if (d.pc != S.k) return;                 // uniform: pc changes only in the last block
+  const Op& op = b.prog[S.k];
+  const uint32_t r = op.nrot;
+  for (uint32_t g = threadIdx.x; g < r; g += NB) {
+#pragma unroll
+    for (int w = 0; w < WW; ++w) {
+      s_px[g][w] = rot_word(op.table, g * kLayerRec + w);
+      s_pz[g][w] = rot_word(op.table, g * kLayerRec + kMaxW + w);
+    }
+    s_cs[g] = op.table[g * kLayerRec + 2 * kMaxW];
+    s_sn[g] = op.table[g * kLayerRec + 2 * kMaxW + 1];
+  }
+  const uint32_t M = d.M;
+  const uint32_t bits = layer_bits(M, d.lboost, b.lmaxbits, b.lshift);
+  const uint32_t P = 1u << bits, slots = b.lslots >> bits;
+  const bool failed = ld_agent(&d.lfail) != 0;   // the scatter launch has ended
+  const double eps = op.eps;
+  const int wmax = op.wmax;
+  const bool full = op.full_check != 0;
+  const bool f32 = b.f32 != 0;
+  // per-thread sums: live before each rotation (as r * entering + weighted
+  // births - drops), anticommuting, survivors, survivors anticommuting with
+  // the next gate, children, strings held at the end, strings entering
+  int64_t s_lw = 0;
+  uint32_t s_an = 0, s_out = 0, s_nx = 0, s_ch = 0, s_held = 0, s_in = 0;
+  bool bad = false;
+
+  for (uint32_t bk = blockIdx.x; bk < P; bk += gridDim.x) {
+    __syncthreads();                       // the previous bucket's LDS is free
+    if (threadIdx.x == 0) {
+      const uint32_t cnt = b.lcount[bk];
+      b.lcount[bk] = 0;                    // zero for the next layer op
+      s_n0 = cnt < slots ? cnt : slots;
+      s_fail = s_n0 > (uint32_t)CAP ? 1u : 0u;
+      s_inc[0] = s_inc[1] = s_inc[2] = 0;
+      s_pat = 0;
+    }
+    for (int t = threadIdx.x; t < HS / 2; t += NB) reinterpret_cast<uint32_t*>(s_hash)[t] = 0;
+    for (int t = threadIdx.x; t < CAP; t += NB) s_life[t] = life_of(0xFF, 0);   // unused: never live
+    __syncthreads();
+    if (failed || s_fail) { bad = bad || s_fail; continue; }   // uniform
+    const uint32_t n0 = s_n0;
+    {
+      const size_t base = (size_t)bk * slots, L = b.lslots;
+      if (threadIdx.x == 0) s_in += n0;
+      s_lw += threadIdx.x == 0 ? (int64_t)r * n0 : 0;
+      uint64_t pat = 0;
+      for (uint32_t j = threadIdx.x; j < n0; j += NB) {
+        uint64_t x[WW], z[WW];
+#pragma unroll
+        for (int q = 0; q < WW; ++q) {
+          x[q] = b.lstx[(size_t)q * L + base + j];
+          z[q] = b.lstz[(size_t)q * L + base + j];
+          s_x[q][j] = x[q];
+          s_z[q][j] = z[q];
+        }
+        s_c[j] = b.lstc[base + j];
+        pat |= b.lsta[base + j];
+        s_life[j] = life_of(0, kAlive);
+        __threadfence_block();
+        lds_insert<WW>(s_hash, HS, x, z, (int)j);
+      }
+      for (int o = 32; o > 0; o >>= 1) pat |= __shfl_xor(pat, o, 64);
+      if ((threadIdx.x & 63) == 0 && pat) atomicOr(&s_pat, (unsigned long long)pat);
+    }
+    __syncthreads();
+    uint64_t todo = s_pat | (full ? 1ull : 0ull);
+    uint32_t ng = n0, q = 0;               // strings before the rotation; rotations run
+    while (todo) {
+      const uint32_t g = (uint32_t)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      if (threadIdx.x == 0) s_inc[(q + 1) % 3] = 0;
+      const bool chk = g == 0 && full;
+      const int wt = (int)(r - 1 - g);     // rotations after g (live-count weight)
+      int born_here = 0, died_here = 0;
+      uint64_t px[WW], pz[WW];             // the rotation, in registers
+#pragma unroll
+      for (int w = 0; w < WW; ++w) { px[w] = s_px[g][w]; pz[w] = s_pz[g][w]; }
+      const double cs = s_cs[g], sn = s_sn[g];
+      for (uint32_t j = threadIdx.x; j < ng; j += NB) {
+        // key, stamp and coefficient in one round trip (a coefficient read
+        // here is used only by a string that leads its pair or has none,
+        // and no other thread writes those)
+        uint64_t qx[WW], qz[WW];
+#pragma unroll
+        for (int w = 0; w < WW; ++w) { qx[w] = s_x[w][j]; qz[w] = s_z[w][j]; }
+        const uint32_t life = s_life[j];
+        const double cq = s_c[j];
+        uint32_t par = 0;
+#pragma unroll
+        for (int w = 0; w < WW; ++w) par += __popcll((qx[w] & pz[w]) ^ (qz[w] & px[w]));
+        const bool anti = par & 1u;
+        if (!anti && !chk) continue;       // untouched (and live or not, unchanged)
+        if (!live_before(life, g)) continue;
+        if (!anti) {                       // the sub-layer's first rotation checks all
+          if (!(fabs(cq) >= eps && !layer_heavy<WW>(qx, qz, wmax))) {
+            s_life[j] = life_of(life >> 8, g);
+            ++died_here;
+          }
+          continue;
+        }
+        ++s_an;
+        uint64_t rx[WW], rz[WW];
+#pragma unroll
+        for (int w = 0; w < WW; ++w) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
+        const int pk = lds_find<WW>(s_hash, HS, s_x, s_z, 0, rx, rz);
+        const uint32_t p = (uint32_t)pk;
+        uint32_t plife = 0;
+        double cp = 0.0;
+        if (pk >= 0) { plife = s_life[p]; cp = s_c[p]; }
+        const bool plive = pk >= 0 && p < ng && live_before(plife, g);
+        if (plive && p < j) continue;      // the partner's thread leads
+        const int sig = product_sign(px, pz, qx, qz, rx, rz, WW);   // i P Q = sig R
+        if (plive) {                       // Q and R = PQ live: a rotation of the pair
+          double nq, nr;
+          rotate_pair(f32, cs, sn, sig, cq, cp, &nq, &nr);
+          s_c[j] = nq;
+          s_c[p] = nr;
+          if (!(fabs(nq) >= eps && !(chk && layer_heavy<WW>(qx, qz, wmax)))) {
+            s_life[j] = life_of(life >> 8, g);
+            ++died_here;
+          }
+          if (!(fabs(nr) >= eps && !(chk && layer_heavy<WW>(rx, rz, wmax)))) {
+            s_life[p] = life_of(plife >> 8, g);
+            ++died_here;
+          }
+        } else {
+          double nq, child;
+          rotate_single(f32, cs, sn, sig, cq, &nq, &child);
+          s_c[j] = nq;
+          if (!(fabs(nq) >= eps && !(chk && layer_heavy<WW>(qx, qz, wmax)))) {
+            s_life[j] = life_of(life >> 8, g);
+            ++died_here;
+          }
+          if (fabs(child) >= eps && !layer_heavy<WW>(rx, rz, wmax)) {
+            ++s_ch;
+            if (pk >= 0) {                 // a dropped string comes back in its slot
+              s_c[p] = child;
+              s_life[p] = life_of(g + 1, kAlive);
+              ++born_here;
+            } else {
+              const uint32_t k = ng + atomicAdd(&s_inc[q % 3], 1u);
+              if (k >= (uint32_t)CAP) {
+                s_fail = 1;
+              } else {
+#pragma unroll
+                for (int w = 0; w < WW; ++w) { s_x[w][k] = rx[w]; s_z[w][k] = rz[w]; }
+                s_c[k] = child;
+                s_life[k] = life_of(g + 1, kAlive);
+                ++born_here;
+                __threadfence_block();
+                lds_insert<WW>(s_hash, HS, rx, rz, (int)k);
+              }
+            }
+          }
+        }
+      }
+      s_lw += (int64_t)wt * (born_here - died_here);
+      __syncthreads();
+      const uint32_t add = s_inc[q % 3];
+      ng = ng + add < (uint32_t)CAP ? ng + add : (uint32_t)CAP;
+      ++q;
+    }
+    if (threadIdx.x == 0) s_held += ng;
+    if (s_fail) { bad = true; continue; }  // uniform: read after the last barrier
+    emit_survivors<WW, NB>(b, d, op, s_x, s_z, s_c, s_life, s_tmp, &s_base, &s_out, &s_nx);
+  }
+  // block sums -> this block's shard line, entries 1..NS
+  {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t v[NS] = {(uint64_t)s_lw, s_an, s_out, s_nx, s_ch, s_held, s_in};
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      uint64_t t = v[k];
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      if (lane == 0) s_red[wid][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+      uint64_t t = 0;
+      for (int w = 0; w < kLWaves; ++w) t += s_red[w][threadIdx.x];
+      if (t)
+        atomicAdd((unsigned long long*)&b.accs[(blockIdx.x % kAccShards) * kLineU64 + 1 + threadIdx.x],
+                  (unsigned long long)t);
+    }
+    if (threadIdx.x == 0 && bad) atomicOr(&d.lfail, 2u);   // a bucket overflowed the LDS
+  }
+  if (!last_block(S.sync, &s_flag, gridDim.x, true)) return;
+  if (threadIdx.x == 0) layer_finish(b, d, op, NS);
 }
 
 }  // namespace pp

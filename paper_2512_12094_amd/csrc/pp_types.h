@@ -119,15 +119,18 @@ constexpr int kPartProbe = 64;       // probes before the LDS table refuses a ke
 //   2. apply: one block per bucket runs the r rotations with the exact
 //      merge and truncation after each, then writes the survivors to the
 //      other half of the store.
-// A bucket that does not fit its staging slots or the LDS fails the op; the
-// host then retries it with twice the buckets, then falls back to the
-// op's GATE(S) copies.
+// Within a bucket each wave takes whole groups (by the key's hash; strings
+// that commute with every rotation anywhere), so a wave rotates its strings
+// with no barrier between rotations and skips the rotations none of them
+// anticommutes with.  A bucket that does not fit its staging slots or a
+// wave's share of the LDS fails the op; the host then retries it with more
+// buckets, then falls back to the op's GATE(S) copies.
 constexpr int kLayerMaxRot = 64;
 constexpr int kLayerMinRot = 4;
-constexpr int kLayerShift = 7;        // strings per bucket aimed at: 2^7
+constexpr int kLayerShift = 8;        // strings per bucket aimed at: 2^8 (default)
 constexpr int kLayerMaxBits = 20;
 constexpr int kLayerMinSlots = 64;    // staging slots per bucket, at least
-constexpr int kLayerMaxBoost = 1;     // extra bucket bits after a failure
+constexpr int kLayerMaxBoost = 3;     // bucket bits added or taken after failures
 constexpr int kLayerAcc = 8;          // per-shard layer sums (accs line entries 1..8)
 
 constexpr int kFxFrac = 104;   // fixed-point fraction bits of merge sums
@@ -194,9 +197,12 @@ struct InstBuf {
   uint64_t* lstx;        // [W][lslots] staged x words
   uint64_t* lstz;        // [W][lslots] staged z words
   double* lstc;          // [lslots] staged coefficients (exact in FP64)
+  uint64_t* lsta;        // [lslots] staged anticommutation patterns (bit g: P_g)
+  uint32_t* lsth;        // [lslots] staged low 32 bits of the bucket key's hash
   uint32_t* lcount;      // [2^lmaxbits] strings per bucket (zero between ops)
   uint32_t lslots;       // staging slots (a power of two)
   uint32_t lmaxbits;     // largest bucket bits (lslots >> lmaxbits >= kLayerMinSlots)
+  uint32_t lshift;       // log2 of the strings per bucket aimed at (tuning)
   uint32_t nolayer;      // LAYER ops are skipped (their fallback ops run)
   const Op* prog;
   uint32_t prog_len;
@@ -253,7 +259,10 @@ struct InstDyn {
   uint32_t pover;        // buckets summed in several selector passes
   uint32_t pglob;        // keys that went through the global merge table
   uint32_t peak;         // most entries (live and not yet compacted) the store held
-  uint32_t lboost;       // layer ops: extra bucket bits after a failed op
+  int32_t lboost;        // layer ops: bucket bits added (or taken) after failures
+  uint32_t lwhy;         // layer op: why the last run failed (1 staging slots, 2 LDS)
+  uint32_t lops;         // layer ops completed (pp_layer_stats)
+  uint32_t lfails;       // layer ops that reported a bucket overflow
   uint32_t lfail;        // layer op: a bucket overflowed its slots or the LDS
   uint32_t lneed;        // layer op: survivors of an op whose output did not fit
 };

@@ -83,9 +83,10 @@ def run(gpu, prog, mode, dtype="f64"):
     prop, merged = ps.counters()
     terms = ps.as_dict()
     info = L.pp_program_info(dp.h)
+    stats = L.pp_layer_stats(ps.h)
     ps.close()
     dp.close()
-    return dict(e=e, terms=terms, prop=prop, merged=merged, prof=prof, info=info)
+    return dict(e=e, terms=terms, prop=prop, merged=merged, prof=prof, info=info, stats=stats)
 
 
 def same(a, b, what):
@@ -104,8 +105,12 @@ def test_layer_ops_equal_gate_launches(gpu, name):
     same(on, off, f"{name}: layer ops vs gate launches")
     same(forced, off, f"{name}: forced fallback vs gate launches")
     assert on["prof"]["layer_apply"][0] > 0, on["prof"]
+    assert on["stats"]["layer_ops"] > 0, on["stats"]
     assert off["prof"]["layer_apply"][0] == 0
     assert forced["prof"]["gate"][0] > 0
+    assert forced["stats"]["layer_ops"] == 0 and forced["stats"]["fallbacks"] > 0, forced["stats"]
+    if name in ("c2_z32",):
+        assert on["stats"]["fallbacks"] == 0, on["stats"]   # every sub-layer as one layer op
     if name in ORACLE:
         ref = O.run_program(prog)
         eps = prog.sublayers[0].eps

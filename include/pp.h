@@ -251,7 +251,9 @@ int pp_layer_stats(pp_state* s, uint64_t out[4]);
 /*
  * Device bytes of a term store of `cap` entries for a handle of n_qubits,
  * group and dtype (both halves, tables and the merge staging, as the
- * library would allocate them now; no allocation happens).  A handle's
+ * library would allocate them now; no allocation happens).  A handle that
+ * has run a layer op (one-instance programs, see pp_set_layer_ops) also
+ * carries its staging: 16W + 20 bytes per entry more.  A handle's
  * store grows to hold its largest set with headroom (4x below 2^24
  * entries, 2x below 2^27, 1.5x above), and the old store is freed only
  * after the new one is filled.  PP_EINVAL for a bad group or size.

@@ -1364,7 +1364,6 @@ int pp_store_bytes(int n_qubits, int group, int dtype, size_t cap, size_t* out) 
   st.buf.group = group;
   st.buf.narrow = (group == PP_GROUP_PERMUTATION || n_qubits <= 32) ? 1u : 0u;
   st.buf.f32 = dtype == PP_F32_COMPENSATED ? 1u : 0u;
-  st.layer_used = g_layer != 0;          // programs may run layer ops
   InstBuf b;
   std::vector<void*> none;
   size_t bytes = 0;

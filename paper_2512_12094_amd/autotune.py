@@ -1,4 +1,6 @@
-"""Autotuner for the library's launch parameters (pp_set_tuning).
+"""Autotuner for the library's launch parameters (pp_set_tuning), the
+layer op's bucket size and block size (pp_set_layer_tuning) and the
+partitioned merge's bucket size and aggregation grid (pp_set_merge_tuning).
 
 A workload class (e.g. "single:Zn:n32" for one-instance programs of Z_n
 rings near 32 qubits, "batch:Zn" for batched rings) maps to the knob values
@@ -21,15 +23,44 @@ from . import _lib as L
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
 
-KNOBS = {
+LAUNCH_KNOBS = {
     "gate_items": [1, 2, 4],
     "stream_items": [1, 2, 4, 8],
     "max_blocks": [256, 512, 1024, 2048],
     "graph_steps": [8, 16, 32, 64],
     "gates_per_step": [1, 2, 4, 8, 16],
 }
-SINGLE_KNOBS = ("gate_items", "stream_items", "max_blocks")
-BATCH_KNOBS = tuple(KNOBS)
+LAYER_KNOBS = {"layer_shift": [6, 7, 8, 9], "layer_block": [256, 512]}
+MERGE_KNOBS = {"part_shift": [12, 13, 14, 15], "part_agg_blocks": [0, 512, 1024, 2048]}
+KNOBS = {**LAUNCH_KNOBS, **LAYER_KNOBS, **MERGE_KNOBS}
+SINGLE_KNOBS = ("gate_items", "stream_items", "max_blocks", "layer_shift", "layer_block")
+BATCH_KNOBS = tuple(LAUNCH_KNOBS)
+MERGE_PASS_KNOBS = tuple(MERGE_KNOBS)
+
+
+def get_knobs() -> dict:
+    """Every knob's current value."""
+    out = dict(L.pp_get_tuning())
+    lt = L.pp_get_layer_tuning()
+    out.update(layer_shift=lt["bucket_log2"], layer_block=lt["block"])
+    mt = L.pp_get_merge_tuning()
+    out.update(part_shift=mt[0] if isinstance(mt, (list, tuple)) else mt["bucket_log2"],
+               part_agg_blocks=mt[1] if isinstance(mt, (list, tuple)) else mt["agg_blocks"])
+    return out
+
+
+def set_knobs(setting: dict):
+    """Sets the knobs named in `setting` (the others keep their values)."""
+    launch = {k: int(v) for k, v in setting.items() if k in LAUNCH_KNOBS}
+    if launch:
+        cur = L.pp_get_tuning()
+        L.pp_set_tuning(**{k: int(launch.get(k, cur[k])) for k in LAUNCH_KNOBS})
+    if "layer_shift" in setting or "layer_block" in setting:
+        L.pp_set_layer_tuning(int(setting.get("layer_shift", 0)), int(setting.get("layer_block", 0)))
+    if "part_shift" in setting or "part_agg_blocks" in setting:
+        cur = get_knobs()
+        L.pp_set_merge_tuning(int(setting.get("part_shift", cur["part_shift"])),
+                              int(setting.get("part_agg_blocks", cur["part_agg_blocks"])))
 
 
 def cache_path() -> str:
@@ -75,7 +106,7 @@ def apply(key: str, path: str | None = None) -> dict | None:
     entry = load_cache(path).get(device_name(), {}).get(key)
     if entry is None:
         return None
-    L.pp_set_tuning(**{k: int(entry["knobs"][k]) for k in KNOBS if k in entry["knobs"]})
+    set_knobs({k: v for k, v in entry["knobs"].items() if k in KNOBS})
     return entry["knobs"]
 
 
@@ -94,10 +125,10 @@ def tune(key: str, run, knobs=BATCH_KNOBS, reps: int = 3, rounds: int = 2,
     if sync is None:
         import torch
         sync = torch.cuda.synchronize
-    best = L.pp_get_tuning()
+    best = {k: v for k, v in get_knobs().items() if k in knobs}
 
     def measure(setting):
-        L.pp_set_tuning(**setting)
+        set_knobs(setting)
         run()                                   # warm (graph capture, allocation)
         return statistics.median(time_once(run, sync) for _ in range(reps))
 
@@ -117,7 +148,7 @@ def tune(key: str, run, knobs=BATCH_KNOBS, reps: int = 3, rounds: int = 2,
                     log(f"[autotune] {key}: {k}={v} -> {t * 1e3:.2f} ms")
         if not improved:
             break
-    L.pp_set_tuning(**best)
+    set_knobs(best)
     cache = load_cache(path)
     cache.setdefault(device_name(), {})[key] = dict(
         knobs=best, seconds=best_t, trials=len(trials),
@@ -164,6 +195,15 @@ def _tune_workloads(path: str | None, log=print) -> dict:
                 s.close()
 
         out["batch:Zn"] = tune(class_key("batch", "Zn"), batch, BATCH_KNOBS, path=path, log=log)
+
+        x, z, c = W.merge_stress_records(24, 32, seed=7)
+
+        def merge_pass():
+            h = L.pp_create(32, "Zn", x.reshape(-1, 1), z.reshape(-1, 1), c, stream, alloc)
+            L.pp_destroy(h)
+
+        out["merge:Zn:n32"] = tune(class_key("merge", "Zn", 32), merge_pass, MERGE_PASS_KNOBS,
+                                   path=path, log=log)
     return out
 
 

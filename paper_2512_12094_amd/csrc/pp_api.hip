@@ -131,6 +131,9 @@ struct pp_state {
   // two events, and the interval is shared by the run's launches (0 = off)
   int prof_every = 0;
   uint32_t m_hint = 0;     // term count last read back (picks tile sizes)
+  double m_growth = 2.0;   // records a merge took over the set size before it (last seen)
+  uint64_t m_prev_in = 0;  // merge_in and set size at the last read-back
+  uint32_t m_prev = 0;
   int lx = 0;              // torus width (PP_GROUP_TORUS)
   std::vector<uint8_t> gperm;   // PP_GROUP_EXPLICIT: element list (host copy)
   uint8_t* d_gperm = nullptr;   // and its device copy
@@ -654,8 +657,11 @@ int launch_range(pp_state* s, const Op* ops, size_t from, size_t to) {
   s->buf.lshift = (uint32_t)g_tune.layer_shift;   // layer ops launched from here on
   const bool big = s->m_hint >= kBigSet;   // last term count seen on the host
   // a set last seen well below the partitioned merge's threshold merges
-  // unpartitioned (correct at any size): its two kernels are not launched
-  const bool small = (uint64_t)s->m_hint * 4 < kPartMin;
+  // unpartitioned (correct at any size): the partitioned kernels are not
+  // launched.  The records a merge takes are estimated from the last set
+  // size and the growth of the last sub-layer seen (at least 2x).
+  const double grow_f = std::max(2.0, std::min(1.5 * s->m_growth, 1e9));
+  const bool small = (double)s->m_hint * grow_f < (double)kPartMin;
   int run_kind = -1;
   uint32_t run_len = 0;
   hipEvent_t run_ev = nullptr;
@@ -2169,6 +2175,10 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
     inflight.erase(inflight.begin());
     HIP_TRY(hipEventSynchronize(s->solo_ev[c & 1]));
     const InstDyn dy = s->solo_slots[c & 1];
+    if (dy.merge_in > s->m_prev_in && s->m_prev)
+      s->m_growth = (double)(dy.merge_in - s->m_prev_in) / (double)s->m_prev;
+    s->m_prev_in = dy.merge_in;
+    s->m_prev = dy.M;
     s->m_hint = dy.M;
     if (dy.status & ST_RANGE)
       return fail(PP_EINVAL, "a coefficient is not finite or exceeds 2^54 in magnitude");

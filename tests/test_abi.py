@@ -77,3 +77,20 @@ def test_explicit_group_list_is_validated_on_the_host():
         with pytest.raises(L.PPError) as e:
             L.pp_create_group(3, perms, **one)
         assert e.value.code == -1, why
+
+
+def test_autotune_knobs_round_trip():
+    """The autotuner's knob families reach their setters and read back
+    (host-side calls only)."""
+    from paper_2512_12094_amd import autotune as A
+    before = A.get_knobs()
+    try:
+        A.set_knobs(dict(layer_shift=6, layer_block=256, part_shift=13, part_agg_blocks=512,
+                         gate_items=2))
+        now = A.get_knobs()
+        assert now["layer_shift"] == 6 and now["layer_block"] == 256
+        assert now["part_shift"] == 13 and now["part_agg_blocks"] == 512
+        assert now["gate_items"] == 2 and now["max_blocks"] == before["max_blocks"]
+    finally:
+        A.set_knobs(before)
+    assert A.get_knobs() == before

@@ -70,6 +70,7 @@ uint32_t ceil_log2(uint64_t v) {
 
 struct pp_program {
   int n = 0;
+  bool has_layer = false;     // some op is a layer op
   std::vector<Op> ops;        // host copy (table pointers already device)
   Op* d_ops = nullptr;
   double* d_tab = nullptr;
@@ -1385,7 +1386,7 @@ int pp_layer_stats(pp_state* s, uint64_t out[4]) {
   if (rc) return rc;
   out[0] = s->h_dyn->lops;
   out[1] = s->h_dyn->lfails;
-  out[2] = (uint64_t)s->layer_fallbacks;
+  out[2] = (uint64_t)s->layer_fallbacks + s->h_dyn->lfb;
   out[3] = s->layer_off ? 1u : 0u;
   return PP_OK;
 }
@@ -1923,6 +1924,7 @@ int pp_program_create(pp_program** out, int n_qubits, size_t n_sub, const size_t
     }
   }
   set_next_gates(ops);
+  for (const auto& op : ops) p->has_layer = p->has_layer || op.type == OP_LAYER;
   if (hipMalloc((void**)&p->d_ops, sizeof(Op) * ops.size()) != hipSuccess ||
       hipMalloc((void**)&p->d_tab, sizeof(double) * std::max<size_t>(tab.size(), 1)) !=
           hipSuccess) {
@@ -1980,6 +1982,7 @@ struct BatchCtx {
   InstDyn** h_dynp = nullptr;
   hipGraphExec_t exec = nullptr;
   int exec_steps = 0, exec_blocks = 0, exec_sig = 0;
+  int layer_w = 0;   // bit w-1: some instance runs layer ops with w key words
 };
 
 std::mutex g_batch_mu;
@@ -2014,6 +2017,17 @@ int batch_ctx(hipStream_t stream, BatchCtx** out) {
 // gates_per_step gates, then merges, compactions and the streaming ops run
 // for the instances that reached them (two scans: truncation, then the
 // next layer's damping).
+// Dynamic LDS of the batched layer apply (above the 64 KB default).
+template <int WW>
+void allow_layer_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_layer_apply_multi<WW, 512>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(ApplySh<WW, 512>));
+  });
+}
+
 void launch_step(BatchCtx* b, int blocks) {
   Ctx C;
   C.bufs = b->d_bufp;
@@ -2021,6 +2035,19 @@ void launch_step(BatchCtx* b, int blocks) {
   C.ninst = b->d_ninst;
   C.sync = b->d_sync;
   const dim3 g(blocks), t(kBlock);
+  // layer ops first: an instance at one finishes it within the step
+  if (b->layer_w & 1) {
+    allow_layer_lds<1>();
+    hipLaunchKernelGGL(k_layer_scatter_multi<1>, g, t, 0, b->stream, C);
+    hipLaunchKernelGGL((k_layer_apply_multi<1, 512>), g, dim3(512), sizeof(ApplySh<1, 512>),
+                       b->stream, C);
+  }
+  if (b->layer_w & 2) {
+    allow_layer_lds<2>();
+    hipLaunchKernelGGL(k_layer_scatter_multi<2>, g, t, 0, b->stream, C);
+    hipLaunchKernelGGL((k_layer_apply_multi<2, 512>), g, dim3(512), sizeof(ApplySh<2, 512>),
+                       b->stream, C);
+  }
   for (int k = 0; k < std::max(1, g_tune.gates_per_step); ++k)
     hipLaunchKernelGGL(kernel_of(PP_K_GATE), g, t, 0, b->stream, C);
   for (int kind : {PP_K_MERGE_NARROW, PP_K_MERGE_WIDE1, PP_K_MERGE_WIDE2, PP_K_MERGE_COLLECT,
@@ -2030,7 +2057,8 @@ void launch_step(BatchCtx* b, int blocks) {
 
 int ensure_graph(BatchCtx* b) {
   const int steps = std::max(1, g_tune.graph_steps), blocks = g_tune.max_blocks;
-  const int sig = g_tune.gates_per_step * 1000003 + g_tune.gate_items * 101 + g_tune.stream_items;
+  const int sig = g_tune.gates_per_step * 1000003 + g_tune.gate_items * 101 + g_tune.stream_items +
+                  b->layer_w * 7919;
   if (b->exec && b->exec_steps == steps && b->exec_blocks == blocks && b->exec_sig == sig)
     return PP_OK;
   if (b->exec) {
@@ -2262,6 +2290,14 @@ int shrink_finished(pp_state* s) {
   return read_dyn(s);
 }
 
+// Whether a batched instance runs its program's layer ops (the program has
+// some, layer ops are not off for the handle, and its staging exists).
+bool batch_layer(pp_state* s, const pp_program* p) {
+  if (s->layer_off || !p->has_layer) return false;
+  s->buf.lshift = (uint32_t)g_tune.layer_shift;
+  return ensure_layer(s) == PP_OK;
+}
+
 // Instances whose store has held this many entries leave the batch at the
 // next step boundary and finish on the one-instance path (partitioned
 // merges, the whole GPU), while the rest of the batch waits.
@@ -2292,18 +2328,21 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
       s->buf.prog_len = (uint32_t)programs[i]->ops.size();
       s->batch_prog = programs[i];
       s->buf.nopart = 1;                   // the batched steps have no partitioned merge
-      s->buf.nolayer = 1;                  // nor layer ops (their GATE(S) copies run)
+      s->buf.nolayer = batch_layer(s, programs[i]) ? 0u : 1u;
       if ((rc = upload_buf(s))) return rc;
       hipLaunchKernelGGL(k_set_pc, dim3(1), dim3(1), 0, stream, s->d_dyn, 0u);
-    } else if (!s->buf.nopart || !s->buf.nolayer) {
+    } else if (!s->buf.nopart || s->buf.nolayer != (batch_layer(s, programs[i]) ? 0u : 1u)) {
       s->buf.nopart = 1;
-      s->buf.nolayer = 1;
+      s->buf.nolayer = batch_layer(s, programs[i]) ? 0u : 1u;
       if ((rc = upload_buf(s))) return rc;
     }
     b->h_bufp[i] = s->d_buf;
     b->h_dynp[i] = s->d_dyn;
   }
   *b->h_ninst = (int)n;
+  b->layer_w = 0;
+  for (size_t i = 0; i < n; ++i)
+    if (!states[i]->buf.nolayer) b->layer_w |= 1 << (states[i]->W - 1);
   HIP_TRY(hipMemcpyAsync(b->d_bufp, b->h_bufp, sizeof(void*) * n, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(b->d_dynp, b->h_dynp, sizeof(void*) * n, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(b->d_ninst, b->h_ninst, sizeof(int), hipMemcpyHostToDevice, stream));
@@ -2348,7 +2387,7 @@ int batch_common(pp_state* const* states, const pp_program* const* programs, siz
         s->buf.prog = prog->d_ops;
         s->buf.prog_len = (uint32_t)prog->ops.size();
         s->buf.nopart = 1;
-        s->buf.nolayer = 1;
+        s->buf.nolayer = batch_layer(s, prog) ? 0u : 1u;
         s->batch_prog = prog;
         if (g) {
           s->h_dyn->status |= ST_FAILED | ST_OVERFLOW;

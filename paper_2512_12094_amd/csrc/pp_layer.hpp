@@ -93,80 +93,152 @@ constexpr int kLAggMax = 2048;             // buckets counted in LDS before the 
 // its strings per bucket in LDS and reserves each bucket's slots with one
 // global add (buckets up to kLAggMax; beyond, one global add per string).
 template <int WW>
+struct ScatterSh {
+  uint64_t px[kLayerMaxRot][WW], pz[kLayerMaxRot][WW];
+  uint32_t cnt[kLAggMax];
+};
+
+// The op's rotation strings into LDS (the caller synchronises before use).
+template <int WW, int NT>
+__device__ __forceinline__ void load_rot_strings(const Op& op, uint64_t (*px)[WW],
+                                                 uint64_t (*pz)[WW]) {
+  for (uint32_t g = threadIdx.x; g < op.nrot; g += NT) {
+#pragma unroll
+    for (int w = 0; w < WW; ++w) {
+      px[g][w] = rot_word(op.table, g * kLayerRec + w);
+      pz[g][w] = rot_word(op.table, g * kLayerRec + kMaxW + w);
+    }
+  }
+}
+
+// Round t (kBlock * kLTile entries from t * kBlock * kLTile) of one
+// instance's scatter; M = the entries scattered (0 for a forced failure),
+// bits = the op's bucket bits.  Returns true if a bucket's staging slots
+// overflowed.  Every thread of the block calls it (barriers inside).
+template <int WW>
+__device__ __forceinline__ bool scatter_round(const InstBuf& b, const InstDyn& d, const Op& op,
+                                              uint32_t M, uint32_t bits, uint32_t t,
+                                              ScatterSh<WW>& sh) {
+  const uint32_t r = op.nrot;
+  const uint32_t P = 1u << bits, slots = b.lslots >> bits, L = b.lslots;
+  const bool agg = P <= (uint32_t)kLAggMax;
+  const View v = view_of(b, d);
+  const uint32_t round = kBlock * kLTile;
+  bool over = false;
+  if (agg) {
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < P; k += kBlock) sh.cnt[k] = 0;
+  }
+  __syncthreads();                         // rotations loaded, counts zero
+  uint64_t x[kLTile][WW], z[kLTile][WW], a[kLTile];
+  double c[kLTile];
+  uint32_t bk[kLTile], rank[kLTile], h32[kLTile];
+  bool has[kLTile];
+#pragma unroll
+  for (int k = 0; k < kLTile; ++k) {
+    const uint32_t i = t * round + k * kBlock + threadIdx.x;
+    has[k] = i < M && v.al[i];
+    if (!has[k]) continue;
+#pragma unroll
+    for (int w = 0; w < WW; ++w) {
+      x[k][w] = v.X[(size_t)w * v.cap + i];
+      z[k][w] = v.Z[(size_t)w * v.cap + i];
+    }
+    c[k] = v.getc(i);
+    const uint64_t h = layer_key<WW>(x[k], z[k], r, sh.px, sh.pz, &a[k]);
+    h32[k] = (uint32_t)h;
+    bk[k] = bits ? (uint32_t)(h >> (64 - bits)) : 0u;
+    rank[k] = agg ? atomicAdd(&sh.cnt[bk[k]], 1u) : atomicAdd(&b.lcount[bk[k]], 1u);
+  }
+  if (agg) {
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < P; k += kBlock) {
+      const uint32_t n = sh.cnt[k];
+      sh.cnt[k] = n ? atomicAdd(&b.lcount[k], n) : 0u;   // this round's first slot
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kLTile; ++k) {
+    if (!has[k]) continue;
+    const uint32_t rk = agg ? sh.cnt[bk[k]] + rank[k] : rank[k];
+    if (rk >= slots) { over = true; continue; }
+    const size_t pos = (size_t)bk[k] * slots + rk;
+#pragma unroll
+    for (int w = 0; w < WW; ++w) {
+      b.lstx[(size_t)w * L + pos] = x[k][w];
+      b.lstz[(size_t)w * L + pos] = z[k][w];
+    }
+    b.lstc[pos] = c[k];
+    b.lsta[pos] = a[k];
+    b.lsth[pos] = h32[k];
+  }
+  return over;
+}
+
+template <int WW>
 __global__ __launch_bounds__(kBlock) void k_layer_scatter(Solo S) {
-  __shared__ uint64_t s_px[kLayerMaxRot][WW], s_pz[kLayerMaxRot][WW];
-  __shared__ uint32_t s_cnt[kLAggMax];
+  __shared__ ScatterSh<WW> sh;
   const InstBuf& b = S.b;
   InstDyn& d = *S.d;
   if (d.pc != S.k) return;                 // an earlier op did not complete
   const Op& op = b.prog[S.k];
-  const uint32_t r = op.nrot;
-  for (uint32_t g = threadIdx.x; g < r; g += kBlock) {
-#pragma unroll
-    for (int w = 0; w < WW; ++w) {
-      s_px[g][w] = rot_word(op.table, g * kLayerRec + w);
-      s_pz[g][w] = rot_word(op.table, g * kLayerRec + kMaxW + w);
-    }
-  }
+  load_rot_strings<WW, kBlock>(op, sh.px, sh.pz);
   const uint32_t M = op.fail_test ? 0u : d.M;
   const uint32_t bits = layer_bits(d.M, d.lboost, b.lmaxbits, b.lshift);
-  const uint32_t P = 1u << bits, slots = b.lslots >> bits, L = b.lslots;
-  const bool agg = P <= (uint32_t)kLAggMax;
-  const View v = view_of(b, d);
   bool over = op.fail_test != 0 && blockIdx.x == 0 && threadIdx.x == 0;
-  const uint32_t round = kBlock * kLTile;
-  const uint32_t rounds = (M + round - 1) / round;
-  for (uint32_t t = blockIdx.x; t < rounds; t += gridDim.x) {
-    if (agg) {
-      __syncthreads();
-      for (uint32_t k = threadIdx.x; k < P; k += kBlock) s_cnt[k] = 0;
-    }
-    __syncthreads();                       // rotations loaded, counts zero
-    uint64_t x[kLTile][WW], z[kLTile][WW], a[kLTile];
-    double c[kLTile];
-    uint32_t bk[kLTile], rank[kLTile], h32[kLTile];
-    bool has[kLTile];
-#pragma unroll
-    for (int k = 0; k < kLTile; ++k) {
-      const uint32_t i = t * round + k * kBlock + threadIdx.x;
-      has[k] = i < M && v.al[i];
-      if (!has[k]) continue;
-#pragma unroll
-      for (int w = 0; w < WW; ++w) {
-        x[k][w] = v.X[(size_t)w * v.cap + i];
-        z[k][w] = v.Z[(size_t)w * v.cap + i];
-      }
-      c[k] = v.getc(i);
-      const uint64_t h = layer_key<WW>(x[k], z[k], r, s_px, s_pz, &a[k]);
-      h32[k] = (uint32_t)h;
-      bk[k] = bits ? (uint32_t)(h >> (64 - bits)) : 0u;
-      rank[k] = agg ? atomicAdd(&s_cnt[bk[k]], 1u) : atomicAdd(&b.lcount[bk[k]], 1u);
-    }
-    if (agg) {
-      __syncthreads();
-      for (uint32_t k = threadIdx.x; k < P; k += kBlock) {
-        const uint32_t n = s_cnt[k];
-        s_cnt[k] = n ? atomicAdd(&b.lcount[k], n) : 0u;   // this round's first slot
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < kLTile; ++k) {
-      if (!has[k]) continue;
-      const uint32_t rk = agg ? s_cnt[bk[k]] + rank[k] : rank[k];
-      if (rk >= slots) { over = true; continue; }
-      const size_t pos = (size_t)bk[k] * slots + rk;
-#pragma unroll
-      for (int w = 0; w < WW; ++w) {
-        b.lstx[(size_t)w * L + pos] = x[k][w];
-        b.lstz[(size_t)w * L + pos] = z[k][w];
-      }
-      b.lstc[pos] = c[k];
-      b.lsta[pos] = a[k];
-      b.lsth[pos] = h32[k];
-    }
-  }
+  const uint32_t rounds = (M + kBlock * kLTile - 1) / (kBlock * kLTile);
+  for (uint32_t t = blockIdx.x; t < rounds; t += gridDim.x)
+    over = scatter_round<WW>(b, d, op, M, bits, t, sh) || over;
   if (over) atomicOr(&d.lfail, 1u);        // a bucket's staging slots overflowed
+}
+
+// An instance of a batch takes the layer op when it stands at one with
+// staging, its key width matches the kernel's and nothing stopped it.
+template <int WW>
+__device__ __forceinline__ bool layer_served(const InstBuf& b, const InstDyn& d) {
+  const Op* op = cur_op(b, d);
+  return op && op->type == OP_LAYER && b.W == WW && b.lcount && !b.nolayer &&
+         !(d.status & ST_OVERFLOW);
+}
+
+// Batched form, step 1: every instance that stands at a layer op scatters;
+// rounds of all instances are dealt out to the blocks.  Block 0 records in
+// each instance whether this step serves it (d.lserved, read by step 2).
+template <int WW>
+__global__ __launch_bounds__(kBlock) void k_layer_scatter_multi(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  __shared__ uint32_t s_tmp[kWaves + 1];
+  __shared__ ScatterSh<WW> sh;
+  const int ninst = *C.ninst;
+  const uint32_t round = kBlock * kLTile;
+  const uint32_t total = plan_tiles(ninst, [&](int i) -> uint32_t {
+    const InstBuf& b = *C.bufs[i];
+    const InstDyn& d = *C.dyns[i];
+    if (!layer_served<WW>(b, d)) return 0u;
+    const uint32_t M = b.prog[d.pc].fail_test ? 0u : d.M;
+    return M ? (M + round - 1) / round : 1u;   // a forced failure takes one empty round
+  }, s_pref, s_tmp);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < ninst; i += kBlock)
+      if (C.bufs[i]->W == WW) C.dyns[i]->lserved = layer_served<WW>(*C.bufs[i], *C.dyns[i]) ? 1u : 0u;
+  int cur = -1;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    const Op& op = b.prog[d.pc];
+    if (i != cur) {
+      __syncthreads();                     // the last round's rotations are read
+      load_rot_strings<WW, kBlock>(op, sh.px, sh.pz);
+      cur = i;
+    }
+    const uint32_t M = op.fail_test ? 0u : d.M;
+    const uint32_t bits = layer_bits(d.M, d.lboost, b.lmaxbits, b.lshift);
+    const bool over = scatter_round<WW>(b, d, op, M, bits, t - s_pref[i], sh) ||
+                      (op.fail_test != 0 && t == s_pref[i] && threadIdx.x == 0);
+    if (over) atomicOr(&d.lfail, 1u);      // a bucket's staging slots overflowed
+  }
 }
 
 template <int WW>
@@ -302,7 +374,8 @@ __device__ __forceinline__ void emit_survivors(const InstBuf& b, InstDyn& d, con
 
 // Last block, one thread: folds the sums; on success the op's counts, the
 // other half becomes current and pc passes the op's fallback copies.
-__device__ __forceinline__ void layer_finish(const InstBuf& b, InstDyn& d, const Op& op, int ns) {
+__device__ __forceinline__ void layer_finish(const InstBuf& b, InstDyn& d, const Op& op, int ns,
+                                             bool batched) {
   uint64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int sh = 0; sh < kAccShards; ++sh)
     for (int k = 0; k < ns; ++k)
@@ -316,11 +389,16 @@ __device__ __forceinline__ void layer_finish(const InstBuf& b, InstDyn& d, const
     return;
   }
   const uint32_t why = ld_agent(&d.lfail);
-  if (why) {                                // a bucket did not fit: the host decides
+  if (why) {                                // a bucket did not fit
     d.lfail = 0;
     d.lwhy = why;                           // 1 staging slots, 2 LDS
     d.lfails += 1;
-    d.status |= ST_LAYER;
+    if (batched) {                          // the batched form runs the gate copies
+      d.lfb += 1;
+      d.pc += 1;
+      return;
+    }
+    d.status |= ST_LAYER;                   // the one-instance path: the host decides
     d.failed_pc = d.pc;
     return;
   }
@@ -359,219 +437,325 @@ __device__ __forceinline__ uint16_t life_of(uint32_t born, uint32_t died) {
   return (uint16_t)((born << 8) | died);
 }
 
-// 2. One block per bucket (grid-stride over buckets): the bucket's strings
-// into LDS (one hash table), then the rotations some of them anticommute
-// with (and the first one if the op re-checks every string there), each
-// over all the bucket's strings with a block barrier after it; then the
-// survivors go to the other half.  The last block folds the sums and
-// advances the program (or reports the failure).  Live counts before each
-// rotation follow from the strings entering and the births and drops of
-// the rotations before it.
+// 2. One block per bucket: the bucket's strings into LDS (one hash table),
+// then the rotations some of them anticommute with (and the first one if
+// the op re-checks every string there), each over all the bucket's strings
+// with a block barrier after it; then the survivors go to the other half.
+// Live counts before each rotation follow from the strings entering and the
+// births and drops of the rotations before it.
 template <int WW, int NB>
-__global__ __launch_bounds__(NB) void k_layer_apply(Solo S) {
-  constexpr int kLWaves = NB / 64;
-  constexpr int CAP = LayerCap<WW>::n, HS = 2 * CAP;
-  constexpr int NS = 7;                    // sums, see below
-  __shared__ uint64_t s_x[WW][CAP], s_z[WW][CAP];
-  __shared__ double s_c[CAP];
-  __shared__ uint16_t s_life[CAP];
-  __shared__ uint16_t s_hash[HS];          // index + 1, 0 = empty
-  __shared__ uint64_t s_px[kLayerMaxRot][WW], s_pz[kLayerMaxRot][WW];
-  __shared__ double s_cs[kLayerMaxRot], s_sn[kLayerMaxRot];
-  __shared__ unsigned long long s_pat;     // rotations some string anticommutes with
-  __shared__ uint32_t s_inc[3], s_n0, s_fail, s_flag, s_tmp[kLWaves + 1], s_base;
-  __shared__ uint64_t s_red[kLWaves][NS];
-  const InstBuf& b = S.b;
-  InstDyn& d = *S.d;
-  if (d.pc != S.k) return;                 // uniform: pc changes only in the last block
-  const Op& op = b.prog[S.k];
-  const uint32_t r = op.nrot;
-  for (uint32_t g = threadIdx.x; g < r; g += NB) {
-#pragma unroll
-    for (int w = 0; w < WW; ++w) {
-      s_px[g][w] = rot_word(op.table, g * kLayerRec + w);
-      s_pz[g][w] = rot_word(op.table, g * kLayerRec + kMaxW + w);
-    }
-    s_cs[g] = op.table[g * kLayerRec + 2 * kMaxW];
-    s_sn[g] = op.table[g * kLayerRec + 2 * kMaxW + 1];
+struct ApplySh {
+  static constexpr int CAP = LayerCap<WW>::n, HS = 2 * CAP, NW = NB / 64, NS = 7;
+  uint64_t x[WW][CAP], z[WW][CAP];
+  double c[CAP];
+  uint16_t life[CAP];
+  uint16_t hash[HS];                       // index + 1, 0 = empty
+  uint64_t px[kLayerMaxRot][WW], pz[kLayerMaxRot][WW];
+  double cs[kLayerMaxRot], sn[kLayerMaxRot];
+  unsigned long long pat;                  // rotations some string anticommutes with
+  uint32_t inc[3], n0, fail, flag, tmp[NW + 1], base;
+  uint64_t red[NW][NS];
+};
+
+// Per-thread sums of one instance: live before each rotation (as r *
+// entering + weighted births - drops), anticommuting, survivors, survivors
+// anticommuting with the next gate, children, strings held at the end,
+// strings entering; bad: a bucket did not fit the LDS.
+struct LayerSums {
+  int64_t lw = 0;
+  uint32_t an = 0, out = 0, nx = 0, ch = 0, held = 0, in = 0;
+  bool bad = false;
+};
+
+template <int WW, int NB>
+__device__ __forceinline__ void load_rotations(const Op& op, ApplySh<WW, NB>& sh) {
+  load_rot_strings<WW, NB>(op, sh.px, sh.pz);
+  for (uint32_t g = threadIdx.x; g < op.nrot; g += NB) {
+    sh.cs[g] = op.table[g * kLayerRec + 2 * kMaxW];
+    sh.sn[g] = op.table[g * kLayerRec + 2 * kMaxW + 1];
   }
-  const uint32_t M = d.M;
-  const uint32_t bits = layer_bits(M, d.lboost, b.lmaxbits, b.lshift);
-  const uint32_t P = 1u << bits, slots = b.lslots >> bits;
-  const bool failed = ld_agent(&d.lfail) != 0;   // the scatter launch has ended
+}
+
+// Bucket bk of one instance (bits: the op's bucket bits).  Every thread of
+// the block calls it; it starts with a barrier (the LDS of the previous
+// bucket, and the rotations, are then free and loaded).
+template <int WW, int NB>
+__device__ __forceinline__ void apply_bucket(const InstBuf& b, InstDyn& d, const Op& op,
+                                             uint32_t bits, uint32_t bk, ApplySh<WW, NB>& sh,
+                                             LayerSums& sum) {
+  constexpr int CAP = ApplySh<WW, NB>::CAP, HS = ApplySh<WW, NB>::HS;
+  const uint32_t r = op.nrot;
+  const uint32_t slots = b.lslots >> bits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t cnt = b.lcount[bk];
+    b.lcount[bk] = 0;                      // zero for the next layer op
+    sh.n0 = cnt < slots ? cnt : slots;
+    sh.fail = sh.n0 > (uint32_t)CAP ? 1u : 0u;
+    sh.inc[0] = sh.inc[1] = sh.inc[2] = 0;
+    sh.pat = 0;
+  }
+  for (int t = threadIdx.x; t < HS / 2; t += NB) reinterpret_cast<uint32_t*>(sh.hash)[t] = 0;
+  for (int t = threadIdx.x; t < CAP; t += NB) sh.life[t] = life_of(0xFF, 0);   // unused: never live
+  __syncthreads();
+  if (sh.fail) { sum.bad = true; return; }   // uniform
+  const uint32_t n0 = sh.n0;
+  {
+    const size_t base = (size_t)bk * slots, L = b.lslots;
+    if (threadIdx.x == 0) sum.in += n0;
+    sum.lw += threadIdx.x == 0 ? (int64_t)r * n0 : 0;
+    uint64_t pat = 0;
+    for (uint32_t j = threadIdx.x; j < n0; j += NB) {
+      uint64_t x[WW], z[WW];
+#pragma unroll
+      for (int q = 0; q < WW; ++q) {
+        x[q] = b.lstx[(size_t)q * L + base + j];
+        z[q] = b.lstz[(size_t)q * L + base + j];
+        sh.x[q][j] = x[q];
+        sh.z[q][j] = z[q];
+      }
+      sh.c[j] = b.lstc[base + j];
+      pat |= b.lsta[base + j];
+      sh.life[j] = life_of(0, kAlive);
+      __threadfence_block();
+      lds_insert<WW>(sh.hash, HS, x, z, (int)j);
+    }
+    for (int o = 32; o > 0; o >>= 1) pat |= __shfl_xor(pat, o, 64);
+    if ((threadIdx.x & 63) == 0 && pat) atomicOr(&sh.pat, (unsigned long long)pat);
+  }
+  __syncthreads();
   const double eps = op.eps;
   const int wmax = op.wmax;
   const bool full = op.full_check != 0;
   const bool f32 = b.f32 != 0;
-  // per-thread sums: live before each rotation (as r * entering + weighted
-  // births - drops), anticommuting, survivors, survivors anticommuting with
-  // the next gate, children, strings held at the end, strings entering
-  int64_t s_lw = 0;
-  uint32_t s_an = 0, s_out = 0, s_nx = 0, s_ch = 0, s_held = 0, s_in = 0;
-  bool bad = false;
-
-  for (uint32_t bk = blockIdx.x; bk < P; bk += gridDim.x) {
-    __syncthreads();                       // the previous bucket's LDS is free
-    if (threadIdx.x == 0) {
-      const uint32_t cnt = b.lcount[bk];
-      b.lcount[bk] = 0;                    // zero for the next layer op
-      s_n0 = cnt < slots ? cnt : slots;
-      s_fail = s_n0 > (uint32_t)CAP ? 1u : 0u;
-      s_inc[0] = s_inc[1] = s_inc[2] = 0;
-      s_pat = 0;
-    }
-    for (int t = threadIdx.x; t < HS / 2; t += NB) reinterpret_cast<uint32_t*>(s_hash)[t] = 0;
-    for (int t = threadIdx.x; t < CAP; t += NB) s_life[t] = life_of(0xFF, 0);   // unused: never live
-    __syncthreads();
-    if (failed || s_fail) { bad = bad || s_fail; continue; }   // uniform
-    const uint32_t n0 = s_n0;
-    {
-      const size_t base = (size_t)bk * slots, L = b.lslots;
-      if (threadIdx.x == 0) s_in += n0;
-      s_lw += threadIdx.x == 0 ? (int64_t)r * n0 : 0;
-      uint64_t pat = 0;
-      for (uint32_t j = threadIdx.x; j < n0; j += NB) {
-        uint64_t x[WW], z[WW];
+  uint64_t todo = sh.pat | (full ? 1ull : 0ull);
+  uint32_t ng = n0, q = 0;                 // strings before the rotation; rotations run
+  while (todo) {
+    const uint32_t g = (uint32_t)__builtin_ctzll(todo);
+    todo &= todo - 1;
+    if (threadIdx.x == 0) sh.inc[(q + 1) % 3] = 0;
+    const bool chk = g == 0 && full;
+    const int wt = (int)(r - 1 - g);       // rotations after g (live-count weight)
+    int born_here = 0, died_here = 0;
+    uint64_t px[WW], pz[WW];               // the rotation, in registers
 #pragma unroll
-        for (int q = 0; q < WW; ++q) {
-          x[q] = b.lstx[(size_t)q * L + base + j];
-          z[q] = b.lstz[(size_t)q * L + base + j];
-          s_x[q][j] = x[q];
-          s_z[q][j] = z[q];
+    for (int w = 0; w < WW; ++w) { px[w] = sh.px[g][w]; pz[w] = sh.pz[g][w]; }
+    const double cs = sh.cs[g], sn = sh.sn[g];
+    for (uint32_t j = threadIdx.x; j < ng; j += NB) {
+      // key, stamp and coefficient in one round trip (a coefficient read
+      // here is used only by a string that leads its pair or has none, and
+      // no other thread writes those)
+      uint64_t qx[WW], qz[WW];
+#pragma unroll
+      for (int w = 0; w < WW; ++w) { qx[w] = sh.x[w][j]; qz[w] = sh.z[w][j]; }
+      const uint32_t life = sh.life[j];
+      const double cq = sh.c[j];
+      uint32_t par = 0;
+#pragma unroll
+      for (int w = 0; w < WW; ++w) par += __popcll((qx[w] & pz[w]) ^ (qz[w] & px[w]));
+      const bool anti = par & 1u;
+      if (!anti && !chk) continue;         // untouched (and live or not, unchanged)
+      if (!live_before(life, g)) continue;
+      if (!anti) {                         // the sub-layer's first rotation checks all
+        if (!(fabs(cq) >= eps && !layer_heavy<WW>(qx, qz, wmax))) {
+          sh.life[j] = life_of(life >> 8, g);
+          ++died_here;
         }
-        s_c[j] = b.lstc[base + j];
-        pat |= b.lsta[base + j];
-        s_life[j] = life_of(0, kAlive);
-        __threadfence_block();
-        lds_insert<WW>(s_hash, HS, x, z, (int)j);
+        continue;
       }
-      for (int o = 32; o > 0; o >>= 1) pat |= __shfl_xor(pat, o, 64);
-      if ((threadIdx.x & 63) == 0 && pat) atomicOr(&s_pat, (unsigned long long)pat);
-    }
-    __syncthreads();
-    uint64_t todo = s_pat | (full ? 1ull : 0ull);
-    uint32_t ng = n0, q = 0;               // strings before the rotation; rotations run
-    while (todo) {
-      const uint32_t g = (uint32_t)__builtin_ctzll(todo);
-      todo &= todo - 1;
-      if (threadIdx.x == 0) s_inc[(q + 1) % 3] = 0;
-      const bool chk = g == 0 && full;
-      const int wt = (int)(r - 1 - g);     // rotations after g (live-count weight)
-      int born_here = 0, died_here = 0;
-      uint64_t px[WW], pz[WW];             // the rotation, in registers
+      ++sum.an;
+      uint64_t rx[WW], rz[WW];
 #pragma unroll
-      for (int w = 0; w < WW; ++w) { px[w] = s_px[g][w]; pz[w] = s_pz[g][w]; }
-      const double cs = s_cs[g], sn = s_sn[g];
-      for (uint32_t j = threadIdx.x; j < ng; j += NB) {
-        // key, stamp and coefficient in one round trip (a coefficient read
-        // here is used only by a string that leads its pair or has none,
-        // and no other thread writes those)
-        uint64_t qx[WW], qz[WW];
-#pragma unroll
-        for (int w = 0; w < WW; ++w) { qx[w] = s_x[w][j]; qz[w] = s_z[w][j]; }
-        const uint32_t life = s_life[j];
-        const double cq = s_c[j];
-        uint32_t par = 0;
-#pragma unroll
-        for (int w = 0; w < WW; ++w) par += __popcll((qx[w] & pz[w]) ^ (qz[w] & px[w]));
-        const bool anti = par & 1u;
-        if (!anti && !chk) continue;       // untouched (and live or not, unchanged)
-        if (!live_before(life, g)) continue;
-        if (!anti) {                       // the sub-layer's first rotation checks all
-          if (!(fabs(cq) >= eps && !layer_heavy<WW>(qx, qz, wmax))) {
-            s_life[j] = life_of(life >> 8, g);
-            ++died_here;
-          }
-          continue;
+      for (int w = 0; w < WW; ++w) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
+      const int pk = lds_find<WW>(sh.hash, HS, sh.x, sh.z, 0, rx, rz);
+      const uint32_t p = (uint32_t)pk;
+      uint32_t plife = 0;
+      double cp = 0.0;
+      if (pk >= 0) { plife = sh.life[p]; cp = sh.c[p]; }
+      const bool plive = pk >= 0 && p < ng && live_before(plife, g);
+      if (plive && p < j) continue;        // the partner's thread leads
+      const int sig = product_sign(px, pz, qx, qz, rx, rz, WW);   // i P Q = sig R
+      if (plive) {                         // Q and R = PQ live: a rotation of the pair
+        double nq, nr;
+        rotate_pair(f32, cs, sn, sig, cq, cp, &nq, &nr);
+        sh.c[j] = nq;
+        sh.c[p] = nr;
+        if (!(fabs(nq) >= eps && !(chk && layer_heavy<WW>(qx, qz, wmax)))) {
+          sh.life[j] = life_of(life >> 8, g);
+          ++died_here;
         }
-        ++s_an;
-        uint64_t rx[WW], rz[WW];
-#pragma unroll
-        for (int w = 0; w < WW; ++w) { rx[w] = qx[w] ^ px[w]; rz[w] = qz[w] ^ pz[w]; }
-        const int pk = lds_find<WW>(s_hash, HS, s_x, s_z, 0, rx, rz);
-        const uint32_t p = (uint32_t)pk;
-        uint32_t plife = 0;
-        double cp = 0.0;
-        if (pk >= 0) { plife = s_life[p]; cp = s_c[p]; }
-        const bool plive = pk >= 0 && p < ng && live_before(plife, g);
-        if (plive && p < j) continue;      // the partner's thread leads
-        const int sig = product_sign(px, pz, qx, qz, rx, rz, WW);   // i P Q = sig R
-        if (plive) {                       // Q and R = PQ live: a rotation of the pair
-          double nq, nr;
-          rotate_pair(f32, cs, sn, sig, cq, cp, &nq, &nr);
-          s_c[j] = nq;
-          s_c[p] = nr;
-          if (!(fabs(nq) >= eps && !(chk && layer_heavy<WW>(qx, qz, wmax)))) {
-            s_life[j] = life_of(life >> 8, g);
-            ++died_here;
-          }
-          if (!(fabs(nr) >= eps && !(chk && layer_heavy<WW>(rx, rz, wmax)))) {
-            s_life[p] = life_of(plife >> 8, g);
-            ++died_here;
-          }
-        } else {
-          double nq, child;
-          rotate_single(f32, cs, sn, sig, cq, &nq, &child);
-          s_c[j] = nq;
-          if (!(fabs(nq) >= eps && !(chk && layer_heavy<WW>(qx, qz, wmax)))) {
-            s_life[j] = life_of(life >> 8, g);
-            ++died_here;
-          }
-          if (fabs(child) >= eps && !layer_heavy<WW>(rx, rz, wmax)) {
-            ++s_ch;
-            if (pk >= 0) {                 // a dropped string comes back in its slot
-              s_c[p] = child;
-              s_life[p] = life_of(g + 1, kAlive);
-              ++born_here;
+        if (!(fabs(nr) >= eps && !(chk && layer_heavy<WW>(rx, rz, wmax)))) {
+          sh.life[p] = life_of(plife >> 8, g);
+          ++died_here;
+        }
+      } else {
+        double nq, child;
+        rotate_single(f32, cs, sn, sig, cq, &nq, &child);
+        sh.c[j] = nq;
+        if (!(fabs(nq) >= eps && !(chk && layer_heavy<WW>(qx, qz, wmax)))) {
+          sh.life[j] = life_of(life >> 8, g);
+          ++died_here;
+        }
+        if (fabs(child) >= eps && !layer_heavy<WW>(rx, rz, wmax)) {
+          ++sum.ch;
+          if (pk >= 0) {                   // a dropped string comes back in its slot
+            sh.c[p] = child;
+            sh.life[p] = life_of(g + 1, kAlive);
+            ++born_here;
+          } else {
+            const uint32_t k = ng + atomicAdd(&sh.inc[q % 3], 1u);
+            if (k >= (uint32_t)CAP) {
+              sh.fail = 1;
             } else {
-              const uint32_t k = ng + atomicAdd(&s_inc[q % 3], 1u);
-              if (k >= (uint32_t)CAP) {
-                s_fail = 1;
-              } else {
 #pragma unroll
-                for (int w = 0; w < WW; ++w) { s_x[w][k] = rx[w]; s_z[w][k] = rz[w]; }
-                s_c[k] = child;
-                s_life[k] = life_of(g + 1, kAlive);
-                ++born_here;
-                __threadfence_block();
-                lds_insert<WW>(s_hash, HS, rx, rz, (int)k);
-              }
+              for (int w = 0; w < WW; ++w) { sh.x[w][k] = rx[w]; sh.z[w][k] = rz[w]; }
+              sh.c[k] = child;
+              sh.life[k] = life_of(g + 1, kAlive);
+              ++born_here;
+              __threadfence_block();
+              lds_insert<WW>(sh.hash, HS, rx, rz, (int)k);
             }
           }
         }
       }
-      s_lw += (int64_t)wt * (born_here - died_here);
-      __syncthreads();
-      const uint32_t add = s_inc[q % 3];
-      ng = ng + add < (uint32_t)CAP ? ng + add : (uint32_t)CAP;
-      ++q;
     }
-    if (threadIdx.x == 0) s_held += ng;
-    if (s_fail) { bad = true; continue; }  // uniform: read after the last barrier
-    emit_survivors<WW, NB>(b, d, op, s_x, s_z, s_c, s_life, s_tmp, &s_base, &s_out, &s_nx);
-  }
-  // block sums -> this block's shard line, entries 1..NS
-  {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint64_t v[NS] = {(uint64_t)s_lw, s_an, s_out, s_nx, s_ch, s_held, s_in};
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      uint64_t t = v[k];
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-      if (lane == 0) s_red[wid][k] = t;
-    }
+    sum.lw += (int64_t)wt * (born_here - died_here);
     __syncthreads();
-    if (threadIdx.x < NS) {
-      uint64_t t = 0;
-      for (int w = 0; w < kLWaves; ++w) t += s_red[w][threadIdx.x];
-      if (t)
-        atomicAdd((unsigned long long*)&b.accs[(blockIdx.x % kAccShards) * kLineU64 + 1 + threadIdx.x],
-                  (unsigned long long)t);
-    }
-    if (threadIdx.x == 0 && bad) atomicOr(&d.lfail, 2u);   // a bucket overflowed the LDS
+    const uint32_t add = sh.inc[q % 3];
+    ng = ng + add < (uint32_t)CAP ? ng + add : (uint32_t)CAP;
+    ++q;
   }
-  if (!last_block(S.sync, &s_flag, gridDim.x, true)) return;
-  if (threadIdx.x == 0) layer_finish(b, d, op, NS);
+  if (threadIdx.x == 0) sum.held += ng;
+  if (sh.fail) { sum.bad = true; return; }  // uniform: read after the last barrier
+  emit_survivors<WW, NB>(b, d, op, sh.x, sh.z, sh.c, sh.life, sh.tmp, &sh.base, &sum.out, &sum.nx);
+}
+
+// The block's sums of one instance to its shard line (entries 1..NS) and
+// its LDS overflow flag; resets the sums.  Every thread calls it.
+template <int WW, int NB>
+__device__ __forceinline__ void flush_sums(const InstBuf& b, InstDyn& d, ApplySh<WW, NB>& sh,
+                                           LayerSums& sum) {
+  constexpr int NS = ApplySh<WW, NB>::NS, NW = ApplySh<WW, NB>::NW;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t v[NS] = {(uint64_t)sum.lw, sum.an, sum.out, sum.nx, sum.ch, sum.held, sum.in};
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    uint64_t t = v[k];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) sh.red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    uint64_t t = 0;
+    for (int w = 0; w < NW; ++w) t += sh.red[w][threadIdx.x];
+    if (t)
+      atomicAdd((unsigned long long*)&b.accs[(blockIdx.x % kAccShards) * kLineU64 + 1 + threadIdx.x],
+                (unsigned long long)t);
+  }
+  if (threadIdx.x == 0 && sum.bad) atomicOr(&d.lfail, 2u);   // a bucket overflowed the LDS
+  sum = LayerSums();
+}
+
+template <int WW, int NB>
+__global__ __launch_bounds__(NB) void k_layer_apply(Solo S) {
+  __shared__ ApplySh<WW, NB> sh;
+  const InstBuf& b = S.b;
+  InstDyn& d = *S.d;
+  if (d.pc != S.k) return;                 // uniform: pc changes only in the last block
+  const Op& op = b.prog[S.k];
+  load_rotations<WW, NB>(op, sh);
+  const uint32_t bits = layer_bits(d.M, d.lboost, b.lmaxbits, b.lshift);
+  // the scatter's failure (bit 0, set before this launch); bit 1 comes from
+  // blocks of this launch and must not steer a block's control flow
+  const bool failed = (ld_agent(&d.lfail) & 1u) != 0;
+  LayerSums sum;
+  for (uint32_t bk = blockIdx.x; bk < (1u << bits); bk += gridDim.x) {
+    if (failed) {                          // only zero the counts (uniform)
+      if (threadIdx.x == 0) b.lcount[bk] = 0;
+      continue;
+    }
+    apply_bucket<WW, NB>(b, d, op, bits, bk, sh, sum);
+  }
+  flush_sums<WW, NB>(b, d, sh, sum);
+  if (!last_block(S.sync, &sh.flag, gridDim.x, true)) return;
+  if (threadIdx.x == 0) layer_finish(b, d, op, ApplySh<WW, NB>::NS, false);
+}
+
+// Block scan for NB-thread blocks over instances (as plan_tiles).
+template <int NB, class F>
+__device__ __forceinline__ uint32_t plan_tiles_n(int ninst, F tiles, uint32_t* s_pref,
+                                                 uint32_t* s_tmp) {
+  constexpr int kPer = (kMaxInst + NB - 1) / NB;
+  uint32_t loc[kPer];
+  uint32_t sum = 0;
+  const int base = threadIdx.x * kPer;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = base + k;
+    loc[k] = (i < ninst) ? tiles(i) : 0u;
+    sum += loc[k];
+  }
+  uint32_t total;
+  uint32_t off = block_scan_n<NB / 64>(sum, s_tmp, &total);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = base + k;
+    if (i < ninst) s_pref[i] = off;
+    off += loc[k];
+  }
+  __syncthreads();
+  return total;
+}
+
+// Batched form, step 2: the buckets of every instance whose layer op step 1
+// took, dealt out to the blocks; the last block finishes those instances
+// (a bucket that did not fit sends the instance to the op's gate copies).
+template <int WW, int NB>
+__global__ __launch_bounds__(NB) void k_layer_apply_multi(Ctx C) {
+  __shared__ uint32_t s_pref[kMaxInst];
+  extern __shared__ __align__(16) uint64_t s_layer_dyn[];   // sizeof(ApplySh<WW, NB>) bytes
+  ApplySh<WW, NB>& sh = *reinterpret_cast<ApplySh<WW, NB>*>(s_layer_dyn);
+  const int ninst = *C.ninst;
+  auto served = [&](int i) {
+    return C.bufs[i]->W == WW && ld_agent(&C.dyns[i]->lserved) != 0;
+  };
+  const uint32_t total = plan_tiles_n<NB>(ninst, [&](int i) -> uint32_t {
+    if (!served(i)) return 0u;
+    const InstBuf& b = *C.bufs[i];
+    const InstDyn& d = *C.dyns[i];
+    return 1u << layer_bits(d.M, d.lboost, b.lmaxbits, b.lshift);
+  }, s_pref, sh.tmp);
+  LayerSums sum;
+  int cur = -1;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_inst(s_pref, ninst, t);
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    const Op& op = b.prog[d.pc];
+    if (i != cur) {
+      if (cur >= 0) flush_sums<WW, NB>(*C.bufs[cur], *C.dyns[cur], sh, sum);
+      __syncthreads();                     // the last bucket's rotations are read
+      load_rotations<WW, NB>(op, sh);
+      cur = i;
+    }
+    const uint32_t bits = layer_bits(d.M, d.lboost, b.lmaxbits, b.lshift);
+    const uint32_t bk = t - s_pref[i];
+    if (ld_agent(&d.lfail) & 1u) {         // the scatter failed: only zero the counts
+      if (threadIdx.x == 0) b.lcount[bk] = 0;
+      continue;
+    }
+    apply_bucket<WW, NB>(b, d, op, bits, bk, sh, sum);
+  }
+  if (cur >= 0) flush_sums<WW, NB>(*C.bufs[cur], *C.dyns[cur], sh, sum);
+  if (!last_block(C.sync, &sh.flag, gridDim.x, true)) return;
+  for (int i = threadIdx.x; i < ninst; i += NB) {
+    if (!served(i)) continue;
+    const InstBuf& b = *C.bufs[i];
+    InstDyn& d = *C.dyns[i];
+    d.lserved = 0;
+    layer_finish(b, d, b.prog[d.pc], ApplySh<WW, NB>::NS, true);
+  }
 }
 
 }  // namespace pp

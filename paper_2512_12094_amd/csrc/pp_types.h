@@ -263,6 +263,8 @@ struct InstDyn {
   uint32_t lwhy;         // layer op: why the last run failed (1 staging slots, 2 LDS)
   uint32_t lops;         // layer ops completed (pp_layer_stats)
   uint32_t lfails;       // layer ops that reported a bucket overflow
+  uint32_t lfb;          // layer ops the batched form replaced by their gate copies
+  uint32_t lserved;      // batched form: this step's scatter took the instance's layer op
   uint32_t lfail;        // layer op: a bucket overflowed its slots or the LDS
   uint32_t lneed;        // layer op: survivors of an op whose output did not fit
 };

@@ -143,18 +143,33 @@ def test_layer_ops_with_store_growth(gpu):
     assert on["prof"]["grow"][0] > 0
 
 
-def test_batched_form_runs_the_gate_copies(gpu):
-    """Programs with layer ops in the batched form (several instances): the
-    instances run the gate copies and equal their one-instance runs."""
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batched_form_runs_layer_ops(gpu, mode):
+    """Programs with layer ops in the batched form (several instances,
+    uneven n): the batched steps run the layer ops (mode 1) or, when every
+    layer op reports a failure (mode 2), send the instances to the gate
+    copies on the device; either way every instance equals its
+    one-instance run bitwise."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
-    progs = [CASES[k]() for k in ("c1_z8", "dn_12", "noise_z16")]
-    print("[case] batched programs with layer ops", flush=True)
-    e, sets, dprogs, _ = driver.batch_propagate(progs, gpu["handle"], gpu["alloc"])
+    progs = [CASES[k]() for k in ("c1_z8", "dn_12", "noise_z16", "c2_z32", "two_words_n80")]
+    print(f"[case] batched programs with layer ops, mode {mode}", flush=True)
+    L.pp_set_layer_ops(mode)
+    try:
+        dprogs = [driver.DeviceProgram(p) for p in progs]
+    finally:
+        L.pp_set_layer_ops(1)
+    sets = [driver.PauliSet.from_program(p, None, gpu["handle"], gpu["alloc"]) for p in progs]
+    e = L.pp_batch_run([s.h for s in sets], [d.h for d in dprogs], gpu["handle"])
     for p, s, d, ei in zip(progs, sets, dprogs, e):
         solo = run(gpu, p, 1)
         assert s.as_dict() == solo["terms"], p.name
         assert float(ei) == solo["e"], p.name
         assert s.counters() == (solo["prop"], solo["merged"]), p.name
+        st = L.pp_layer_stats(s.h)
+        if mode == 1:
+            assert st["layer_ops"] > 0, (p.name, st)
+        else:
+            assert st["layer_ops"] == 0 and st["fallbacks"] > 0, (p.name, st)
         s.close()
         d.close()

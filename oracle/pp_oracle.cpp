@@ -428,18 +428,24 @@ double orc_expectation(void* h, double bx, double by, double bz) {
 
 size_t orc_size(void* h) { return static_cast<Oracle*>(h)->terms.size(); }
 
-// Rows of W = ceil(n/64) words each.
+// Rows of W = ceil(n/64) words each, in ascending order of the strings'
+// integers (Appendix E.2: the same base-4 integer that picks the
+// representative), so the set comes out key-sorted.
 void orc_export(void* h, uint64_t* x, uint64_t* z, double* c) {
   auto* o = static_cast<Oracle*>(h);
   const int W = (o->n + 63) / 64;
-  size_t r = 0;
-  for (const auto& [s, v] : o->terms) {
+  std::vector<const std::pair<const Pauli, double>*> rows;
+  rows.reserve(o->terms.size());
+  for (const auto& t : o->terms) rows.push_back(&t);
+  const int n = o->n;
+  std::sort(rows.begin(), rows.end(),
+            [n](const auto* a, const auto* b) { return int_less(a->first, b->first, n); });
+  for (size_t r = 0; r < rows.size(); ++r) {
     for (int w = 0; w < W; ++w) {
-      x[r * W + w] = s.x[w];
-      z[r * W + w] = s.z[w];
+      x[r * W + w] = rows[r]->first.x[w];
+      z[r * W + w] = rows[r]->first.z[w];
     }
-    c[r] = v;
-    ++r;
+    c[r] = rows[r]->second;
   }
 }
 

@@ -43,6 +43,11 @@ def int_value(x, z, n):
     return sum(DIGIT[ch] * 4 ** q for q, ch in enumerate(s))
 
 
+def join(words):
+    """Row of uint64 words (word w holds qubits 64w..64w+63) -> one integer."""
+    return sum(int(v) << (64 * w) for w, v in enumerate(words))
+
+
 def rotate_letters(s, j):
     """T^j: qubit q takes the letter of qubit q+j (T.(IXI) = XII)."""
     n = len(s)
@@ -216,6 +221,21 @@ def test_int_order_matches_integer_encoding():
             a, b = random_string(rng, n), random_string(rng, n)
             A, B = W.from_letters(a), W.from_letters(b)
             assert O.int_less(n, A, B) == (int_value(*A, n) < int_value(*B, n))
+
+
+@pytest.mark.parametrize("n,group", [(8, "Zn"), (40, "none"), (70, "none"), (12, "Sn")])
+def test_export_is_key_sorted(n, group):
+    """The exported set is one record per representative, in ascending order
+    of the App. E.2 integer (computed here from the letters)."""
+    rng = random.Random(n)
+    o = O.Oracle(n, group)
+    for _ in range(300):
+        o.add(*W.from_letters(random_string(rng, n)), rng.uniform(-1, 1))
+    o.merge()
+    x, z, c = o.export()
+    keys = [int_value(join(x[i]), join(z[i]), n) for i in range(len(c))]
+    assert len(keys) > 100
+    assert all(a < b for a, b in zip(keys, keys[1:]))
 
 
 # ----------------------------------------------------------------------------

@@ -265,8 +265,17 @@ int pp_num_terms(pp_state* s, size_t* out);
 
 /*
  * Copies the live terms to caller-owned host arrays (x, z: cap rows of W
- * words; coef: cap doubles) in unspecified order; *n_out = number written.
- * PP_EINVAL if cap is smaller than the number of live terms.
+ * words, row r at [r*W, r*W + W); coef: cap doubles, FP32 coefficients
+ * widened) sorted by key: ascending in the integer of Appendix E.2 (qubit q
+ * the base-4 digit of weight 4^q, I, X, Y, Z = 0, 1, 2, 3), the integer
+ * whose minimum picks a representative in Algorithms 2 and 3.  After a
+ * symmetry merge that is one record per representative in key order.  The
+ * sort runs on the device (radix passes over the store, 8 bits of the
+ * integer each) in workspace taken from the handle's allocator and freed
+ * before the call returns; synchronises the handle's stream.  *n_out =
+ * number written.  PP_EINVAL if cap is smaller than the number of live
+ * terms or an array is NULL; PP_ENOMEM if the workspace cannot be had;
+ * PP_EDEVICE if the liveness flags disagree with the term count.
  */
 int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef,
                     size_t cap, size_t* n_out);

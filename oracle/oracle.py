@@ -228,10 +228,12 @@ class OracleResult:
     peak: int            # largest set size seen after any gate
     wall: float
     sublayers_done: int
+    rows: tuple | None = None    # export(): (x, z, c) in ascending integer order
 
 
 def run_program(prog, group: str | None = None, max_sublayers: int | None = None,
-                keep_terms: bool = True, time_budget: float | None = None) -> OracleResult:
+                keep_terms: bool = True, time_budget: float | None = None,
+                keep_rows: bool = False) -> OracleResult:
     """Algorithm 1 on the oracle.  ``max_sublayers``/``time_budget`` stop
     early (a bounded prefix, for timing samples)."""
     group = prog.group if group is None else group
@@ -262,4 +264,4 @@ def run_program(prog, group: str | None = None, max_sublayers: int | None = None
     prop, merged = o.counters()
     wall = time.perf_counter() - t0
     return OracleResult(e, o.as_dict() if keep_terms else {}, prop, merged, sizes,
-                        peak, wall, done)
+                        peak, wall, done, o.export() if keep_rows else None)

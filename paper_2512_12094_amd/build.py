@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpp.so")
 SOURCES = [os.path.join(CSRC, "pp_api.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("pp_kernels.hpp", "pp_merge.hpp", "pp_layer.hpp", "pp_types.h", "pp_fixed.h")] + \
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("pp_kernels.hpp", "pp_merge.hpp", "pp_layer.hpp", "pp_sort.hpp", "pp_types.h", "pp_fixed.h")] + \
     [os.path.join(ROOT, "include", "pp.h")]
 
 

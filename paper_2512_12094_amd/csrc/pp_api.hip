@@ -23,6 +23,7 @@
 #include "pp_kernels.hpp"
 #include "pp_merge.hpp"
 #include "pp_layer.hpp"
+#include "pp_sort.hpp"
 #include "pp_types.h"
 
 using namespace pp;
@@ -1803,42 +1804,87 @@ int pp_export_terms(pp_state* s, uint64_t* x, uint64_t* z, double* coef, size_t 
   if (cap < d.live) return fail(PP_EINVAL, "export capacity " + std::to_string(cap) + " < " +
                                                std::to_string(d.live) + " live terms");
   if (d.live && (!x || !z || !coef)) return fail(PP_EINVAL, "export arrays are NULL");
-  const int W = s->W;
-  const uint32_t M = d.M, C = s->buf.cap;
-  std::vector<uint64_t> xs((size_t)W * M), zs((size_t)W * M);
-  std::vector<double> cs(M);
-  std::vector<float> cf(s->buf.f32 ? M : 0);
-  std::vector<uint8_t> al(M);
-  for (int w = 0; w < W && M; ++w) {
-    HIP_TRY(hipMemcpyAsync(xs.data() + (size_t)w * M, s->buf.x[d.half] + (size_t)w * C,
-                           sizeof(uint64_t) * M, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(zs.data() + (size_t)w * M, s->buf.z[d.half] + (size_t)w * C,
-                           sizeof(uint64_t) * M, hipMemcpyDeviceToHost, s->stream));
-  }
-  if (M) {
-    if (s->buf.f32)
-      HIP_TRY(hipMemcpyAsync(cf.data(), s->buf.c[d.half], sizeof(float) * M,
-                             hipMemcpyDeviceToHost, s->stream));
-    else
-      HIP_TRY(hipMemcpyAsync(cs.data(), s->buf.c[d.half], sizeof(double) * M,
-                             hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(al.data(), s->buf.alive[d.half][d.parity], M, hipMemcpyDeviceToHost,
-                           s->stream));
-  }
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  for (size_t i = 0; i < cf.size(); ++i) cs[i] = (double)cf[i];
-  size_t r = 0;
-  for (uint32_t i = 0; i < M; ++i) {
-    if (!al[i]) continue;
-    if (r >= cap) return fail(PP_EDEVICE, "live count mismatch");
-    for (int w = 0; w < W; ++w) {
-      x[r * W + w] = xs[(size_t)w * M + i];
-      z[r * W + w] = zs[(size_t)w * M + i];
+  *n_out = 0;
+  const int W = s->W, n = s->n;
+  const uint32_t M = d.M, C = s->buf.cap, N = (uint32_t)d.live;
+  if (N == 0) return PP_OK;
+  // Workspace: two orders, the histogram of the first pass (the largest),
+  // the scan's block totals and grand total, and the rows.
+  const uint32_t tiles0 = (M + kSortTile - 1) / kSortTile;
+  const size_t nhist = (size_t)kSortBlock * tiles0;
+  const uint32_t nscan = (uint32_t)((nhist + kScanTile - 1) / kScanTile);
+  const size_t rows = (size_t)N * W * sizeof(uint64_t);
+  struct Ws {
+    pp_state* s;
+    std::vector<void*> p;
+    ~Ws() { for (void* q : p) dev_free(s, q); }
+    void* get(size_t bytes) {
+      void* q = dev_alloc(s, bytes);
+      if (q) p.push_back(q);
+      return q;
     }
-    coef[r] = cs[i];
-    ++r;
+  } ws{s, {}};
+  auto* ord0 = static_cast<uint32_t*>(ws.get(sizeof(uint32_t) * N));
+  auto* ord1 = static_cast<uint32_t*>(ws.get(sizeof(uint32_t) * N));
+  auto* hist = static_cast<uint32_t*>(ws.get(sizeof(uint32_t) * nhist));
+  auto* part = static_cast<uint32_t*>(ws.get(sizeof(uint32_t) * (nscan + 1)));
+  auto* ox = static_cast<uint64_t*>(ws.get(rows));
+  auto* oz = static_cast<uint64_t*>(ws.get(rows));
+  auto* oc = static_cast<double*>(ws.get(sizeof(double) * N));
+  if (!ord0 || !ord1 || !hist || !part || !ox || !oz || !oc)
+    return fail(PP_ENOMEM, "export workspace");
+  SortPass p{};
+  p.x = s->buf.x[d.half];
+  p.z = s->buf.z[d.half];
+  p.alive = s->buf.alive[d.half][d.parity];
+  p.cap = C;
+  uint32_t* out = ord0;
+  bool first = true;
+  uint32_t total = 0;
+  for (int j = 0; 32 * j < n; ++j) {
+    const int bits = 2 * std::min(32, n - 32 * j);
+    for (int sh = 0; sh < bits; sh += 8) {
+      p.first = first;
+      p.n_in = first ? M : N;
+      p.tiles = (p.n_in + kSortTile - 1) / kSortTile;
+      p.word = j;
+      p.shift = sh;
+      p.src = first ? nullptr : out;
+      p.dst = first ? ord0 : (out == ord0 ? ord1 : ord0);
+      p.dst_cap = N;
+      p.hist = hist;
+      const uint32_t nh = kSortBlock * p.tiles;
+      const uint32_t nb = (nh + kScanTile - 1) / kScanTile;
+      hipLaunchKernelGGL(k_sort_hist, dim3(p.tiles), dim3(kSortBlock), 0, s->stream, p);
+      hipLaunchKernelGGL(k_sort_scan_reduce, dim3(nb), dim3(kSortBlock), 0, s->stream, hist, nh,
+                         part);
+      hipLaunchKernelGGL(k_sort_scan_top, dim3(1), dim3(kSortBlock), 0, s->stream, part, nb,
+                         part + nscan);
+      hipLaunchKernelGGL(k_sort_scan_down, dim3(nb), dim3(kSortBlock), 0, s->stream, hist, nh,
+                         part);
+      hipLaunchKernelGGL(k_sort_scatter, dim3(p.tiles), dim3(kSortBlock), 0, s->stream, p);
+      HIP_TRY(hipGetLastError());
+      if (first) {
+        HIP_TRY(hipMemcpyAsync(&total, part + nscan, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (total != N)
+          return fail(PP_EDEVICE, "live count mismatch: " + std::to_string(total) +
+                                      " flagged, " + std::to_string(N) + " counted");
+      }
+      out = p.dst;
+      first = false;
+    }
   }
-  *n_out = r;
+  hipLaunchKernelGGL(k_sort_emit, dim3((N + kSortBlock - 1) / kSortBlock), dim3(kSortBlock), 0,
+                     s->stream, out, N, p.x, p.z, s->buf.c[d.half], (int)s->buf.f32, C, W, ox,
+                     oz, oc);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(x, ox, rows, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(z, oz, rows, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(coef, oc, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  *n_out = N;
   return PP_OK;
 }
 

@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the gate-at-scale leg")
     ap.add_argument("--no-ising", action="store_true", help="skip the Ising layers leg")
+    ap.add_argument("--no-ising-family", action="store_true",
+                    help="skip the Ising n = 3..20 family leg")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-cap-terms", type=int, default=1 << 26,
                     help="store limit (entries) of a batched instance at full depth")
@@ -260,6 +262,51 @@ def ising_layers_leg(stream, alloc, n=12, layers=(2, 4, 6, 8, 10), dt=0.25):
     neck = sum(4 ** math.gcd(j, n) for j in range(1, n + 1)) // n
     return dict(workload=f"tilted-field Ising ring n={n}, dt={dt}, untruncated",
                 necklaces=neck, rows=rows)
+
+
+def ising_family_leg(stream, alloc, ns=range(3, 21), max_layers=10, cap=1 << 21,
+                     budget_s=3.0, dt=0.25):
+    """Fig. 2 / Supp. Fig. 1 across n: the tilted-field Ising ring of Sec. IV
+    (O = Z at the middle site, untruncated, merged after every Trotter layer)
+    for n = 3..20, set size and time per propagation against the number of
+    layers, next to plain PP on the same circuit.  A series stops once its set
+    passes `cap` terms or a propagation takes longer than `budget_s`."""
+    from paper_2512_12094_amd import _lib as L
+    from paper_2512_12094_amd import driver
+    from paper_2512_12094_amd import workloads as W
+    import torch
+    rows = []
+    for n in ns:
+        row = dict(n=n, necklaces=sum(4 ** math.gcd(j, n) for j in range(1, n + 1)) // n)
+        for mode in ("symmetry", "plain"):
+            series = []
+            for nl in range(1, max_layers + 1):
+                prog = W.tilted_ising_ring(n, nl, dt, merge="layer")
+                dp = driver.device_program(prog)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ps = driver.PauliSet.from_program(prog, "none" if mode == "plain" else None,
+                                                  stream, alloc)
+                L.pp_batch_run([ps.h], [dp.h], stream)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                terms = L.pp_num_terms(ps.h)
+                ps.close()
+                dp.close()
+                series.append((nl, int(terms), round(wall * 1e3, 3)))
+                if terms > cap or wall > budget_s:
+                    break
+            row[mode] = dict(layers=[a for a, _, _ in series], terms=[b for _, b, _ in series],
+                             ms=[c for _, _, c in series])
+        sat = [t for t in row["symmetry"]["terms"]]
+        row["saturated"] = bool(sat) and max(sat) == row["necklaces"] - 1
+        assert max(sat) <= row["necklaces"] - 1, (n, max(sat))
+        rows.append(row)
+        print(f"[ising family] n={n} sym {row['symmetry']['terms'][-1]} terms at "
+              f"{row['symmetry']['layers'][-1]} layers", file=sys.stderr, flush=True)
+    return dict(workload=f"tilted-field Ising ring n={ns[0]}..{ns[-1]}, dt={dt}, untruncated, "
+                         f"merged per Trotter layer, up to {max_layers} layers or {cap} terms",
+                rows=rows)
 
 
 def batched_leg(stream, alloc, count, cap_terms):
@@ -773,6 +820,9 @@ def main():
         ising = None
         if not args.no_ising:
             ising = ising_layers_leg(stream, alloc)
+        ising_family = None
+        if not args.no_ising_family:
+            ising_family = ising_family_leg(stream, alloc)
             print(f"[bench] Ising layers leg done", file=sys.stderr, flush=True)
         scale = None
         if not args.no_scale:
@@ -817,6 +867,7 @@ def main():
         "dihedral_pp": dihedral,
         "gate_at_scale": scale,
         "ising_layers": ising,
+        "ising_family": ising_family,
         "roofline": roof,
         "roofline_merge": roof_merge,
         "kernels": kernels,

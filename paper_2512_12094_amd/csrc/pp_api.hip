@@ -78,6 +78,14 @@ struct pp_program {
   size_t n_gates = 0;
 };
 
+// solo_program: sub-layers per chunk (the host reads the device state once
+// per chunk), chunks launched ahead of the oldest unchecked one, and the
+// pinned state slots / events they cycle through (>= the chunks in flight).
+constexpr int kChunkSubs = 1;
+constexpr size_t kSoloInflight = 2;
+constexpr int kSoloSlots = 4;
+static_assert(kSoloSlots >= (int)kSoloInflight, "a chunk in flight would reuse a live slot");
+
 struct pp_state {
   int n = 0, W = 1, group = 0;
   hipStream_t stream = nullptr;
@@ -119,7 +127,7 @@ struct pp_state {
   const std::vector<Op>* run_ops_list = nullptr;   // ops of a pp_apply_* call in flight
   int fail_code = PP_OK;               // why a batched instance stopped
   InstDyn* solo_slots = nullptr;       // pinned status slots of solo_program
-  hipEvent_t solo_ev[2] = {nullptr, nullptr};
+  hipEvent_t solo_ev[kSoloSlots] = {};
   // pinned staging ring for program uploads of calls that do not sync
   struct Stage {
     char* h = nullptr;
@@ -2212,7 +2220,6 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
   resume_window(s, ops, len, resume ? s->h_dyn->pc : 0);
   // chunk ends: after every kChunkSubs-th sub-layer (its MERGE and the TRUNC
   // that follows it), or the last op; the host reads the state once per chunk
-  constexpr int kChunkSubs = 1;
   std::vector<size_t> ends;
   int subs = 0;
   for (size_t k = 0; k < len; ++k) {
@@ -2222,7 +2229,8 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
       ends.push_back(k + 1);
   }
   if (!s->solo_slots) {
-    HIP_TRY(hipHostMalloc((void**)&s->solo_slots, sizeof(InstDyn) * 2, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&s->solo_slots, sizeof(InstDyn) * kSoloSlots,
+                          hipHostMallocDefault));
     for (auto& e : s->solo_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   size_t next_chunk = 0, launched_to = resume ? s->h_dyn->pc : 0;
@@ -2233,10 +2241,10 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
   }
   std::vector<size_t> inflight;            // chunk indices, oldest first
   for (int guard = 0; guard < 1 << 30; ++guard) {
-    while (inflight.size() < 2 && next_chunk < ends.size()) {
+    while (inflight.size() < kSoloInflight && next_chunk < ends.size()) {
       const size_t end = ends[next_chunk];
       if ((rc = launch_range(s, ops, launched_to, end))) return rc;
-      const int slot = (int)(next_chunk & 1);
+      const int slot = (int)(next_chunk % kSoloSlots);
       HIP_TRY(hipMemcpyAsync(&s->solo_slots[slot], s->d_dyn, sizeof(InstDyn),
                              hipMemcpyDeviceToHost, st));
       HIP_TRY(hipEventRecord(s->solo_ev[slot], st));
@@ -2247,8 +2255,8 @@ int solo_program(pp_state* s, const pp_program* p, double* expectation, bool res
     if (inflight.empty()) break;
     const size_t c = inflight.front();
     inflight.erase(inflight.begin());
-    HIP_TRY(hipEventSynchronize(s->solo_ev[c & 1]));
-    const InstDyn dy = s->solo_slots[c & 1];
+    HIP_TRY(hipEventSynchronize(s->solo_ev[c % kSoloSlots]));
+    const InstDyn dy = s->solo_slots[c % kSoloSlots];
     if (dy.merge_in > s->m_prev_in && s->m_prev)
       s->m_growth = (double)(dy.merge_in - s->m_prev_in) / (double)s->m_prev;
     s->m_prev_in = dy.merge_in;

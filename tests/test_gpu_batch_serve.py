@@ -51,6 +51,30 @@ def test_batch_config4_instances(gpu):
     L.pp_set_tuning(gates_per_step=4)
 
 
+def test_batch_config4_instances_full_depth(gpu):
+    """Twelve instances of the batched ring workload at their full depth
+    (n = 16 to 64, 15 to 66 sub-layers, eps 2e-6 to 9e-5: the ones the
+    oracle finishes in seconds), in one batch with layer ops: sets,
+    coefficients, expectations and work counters against the oracle, and
+    expectations bitwise equal to the solo runs."""
+    from paper_2512_12094_amd import driver
+    pick = (11, 19, 20, 22, 25, 27, 29, 32, 34, 44, 47, 54)
+    allp = W.config4()
+    progs = [allp[i] for i in pick]
+    print("[case] full-depth batch", [(p.n, len(p.sublayers)) for p in progs], flush=True)
+    e, sets, dprogs, wall = driver.batch_propagate(progs, gpu["handle"], gpu["alloc"])
+    for p, ei, s in zip(progs, e, sets):
+        ref = O.run_program(p)
+        compare_terms(s.as_dict(), ref.terms, p.meta["eps"], what=p.name)
+        compare_expectation(ei, ref.expectation, ref.terms, what=p.name)
+        assert s.counters() == (ref.propagated, ref.merged), p.name
+        solo = driver.propagate_program(p, stream=gpu["handle"], allocator=gpu["alloc"])
+        assert ei == solo.expectation, (p.name, ei, solo.expectation)
+        s.close()
+    for d in dprogs:
+        d.close()
+
+
 def test_serve_alone_equals_in_the_mix(gpu):
     """Continuous batching: jobs arriving while others run; each result is
     the job's solo result (bitwise) and matches the oracle."""
@@ -82,6 +106,36 @@ def test_serve_alone_equals_in_the_mix(gpu):
         compare_expectation(r.expectation, ref.expectation, ref.terms, what=r.name)
         assert r.units == ref.propagated + ref.merged, r.name
         assert r.finished >= r.arrival
+
+
+def test_serve_config5_jobs_at_their_sizes(gpu):
+    """Jobs of the served workload itself: five of its ring jobs at full
+    depth (n = 16, 24) and its all-to-all S_n jobs at n = 32, 64 and 128
+    over their first two sub-layers (their full depth passes the store limit
+    the served leg uses), arriving together.  Each result equals the job's
+    solo run bitwise and the oracle's by the FP64 rules, with equal work."""
+    from paper_2512_12094_amd import driver, serve
+    want_rings = {"c5_101_z16", "c5_109_z16", "c5_124_z16", "c5_151_z16", "c5_160_z24"}
+    picked, sn_seen = [], set()
+    for j in W.config5(count=200):
+        p = j.program
+        if p.name in want_rings:
+            picked.append(W.Job(j.arrival * 1e-3, p))
+        elif p.group == W.GROUP_SN and p.n in (32, 64, 128) and p.n not in sn_seen:
+            sn_seen.add(p.n)
+            picked.append(W.Job(j.arrival * 1e-3, prefix(p, 2)))
+    assert len(picked) == 8, [j.program.name for j in picked]
+    print("[case] serve config5 jobs", [(j.program.name, len(j.program.sublayers))
+                                        for j in picked], flush=True)
+    eng = serve.GpuEngine(gpu["handle"], gpu["alloc"], steps_per_iter=16)
+    srv = serve.Server(eng, hbm_budget=20e9, max_active=8)
+    res = srv.run(picked)
+    for j, r in zip(picked, res):
+        solo = driver.propagate_program(j.program, stream=gpu["handle"], allocator=gpu["alloc"])
+        assert r.expectation == solo.expectation, (r.name, r.expectation, solo.expectation)
+        ref = O.run_program(j.program)
+        compare_expectation(r.expectation, ref.expectation, ref.terms, what=r.name)
+        assert r.units == ref.propagated + ref.merged, r.name
 
 
 def test_batch_instance_failure_is_isolated(gpu):

@@ -7,7 +7,7 @@ tests/parity.py; strings within the truncation band of eps, which either side
 may keep, are dropped from both sequences first), and the order is checked
 against the integer computed here from the letters.  Sizes span several
 4096-row sort tiles with a ragged last tile; one to four 64-bit words of the
-integer (n = 8 to 100); the groups Z_n, D_n, S_n, the torus and none; both
+integer (n = 8 to 128); the groups Z_n, D_n, S_n, the torus and none; both
 launch paths; FP32 coefficients; an empty set."""
 import numpy as np
 import pytest
@@ -81,6 +81,7 @@ CASES = {
     "torus_3x3": lambda: W.power_law_xxz_torus(3, 3, 1, 0.1, eps=1e-6),
     "w2_n80": lambda: brickwork(80, 2, 0.2, 1e-4),
     "w2_n100": lambda: brickwork(100, 1, 0.25, 1e-5),
+    "w2_n128": lambda: brickwork(128, 1, 0.3, 1e-5),
 }
 
 

@@ -85,7 +85,9 @@ __device__ __forceinline__ uint64_t layer_key(const uint64_t* x, const uint64_t*
   return h;
 }
 
-constexpr int kLTile = 4;                  // strings per thread per scatter round
+// strings per thread per scatter round: one gives the most rounds (blocks)
+// and the shortest chain per block (measured faster than 2, 4 or 8)
+constexpr int kLTile = 1;
 constexpr int kLAggMax = 2048;             // buckets counted in LDS before the global add
 
 // 1. Every live string of the current half to its bucket's staging slots,

@@ -264,13 +264,14 @@ def ising_layers_leg(stream, alloc, n=12, layers=(2, 4, 6, 8, 10), dt=0.25):
                 necklaces=neck, rows=rows)
 
 
-def ising_family_leg(stream, alloc, ns=range(3, 21), max_layers=10, cap=1 << 21,
-                     budget_s=3.0, dt=0.25):
+def ising_family_leg(stream, alloc, ns=range(3, 21), max_layers=10, cap=1 << 26,
+                     budget_s=8.0, dt=0.25, max_entries=1 << 29):
     """Fig. 2 / Supp. Fig. 1 across n: the tilted-field Ising ring of Sec. IV
     (O = Z at the middle site, untruncated, merged after every Trotter layer)
     for n = 3..20, set size and time per propagation against the number of
     layers, next to plain PP on the same circuit.  A series stops once its set
-    passes `cap` terms or a propagation takes longer than `budget_s`."""
+    passes `cap` terms, a propagation takes longer than `budget_s`, or its
+    store would need more than `max_entries` entries (the error is kept)."""
     from paper_2512_12094_amd import _lib as L
     from paper_2512_12094_amd import driver
     from paper_2512_12094_amd import workloads as W
@@ -287,26 +288,36 @@ def ising_family_leg(stream, alloc, ns=range(3, 21), max_layers=10, cap=1 << 21,
                 t0 = time.perf_counter()
                 ps = driver.PauliSet.from_program(prog, "none" if mode == "plain" else None,
                                                   stream, alloc)
-                L.pp_batch_run([ps.h], [dp.h], stream)
+                L.pp_set_max_terms(ps.h, max_entries)
+                stop = None
+                try:
+                    L.pp_batch_run([ps.h], [dp.h], stream)
+                except L.PPError as e:
+                    stop = f"{nl} layers: {e}"
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t0
                 terms = L.pp_num_terms(ps.h)
                 ps.close()
                 dp.close()
+                if stop:
+                    break
                 series.append((nl, int(terms), round(wall * 1e3, 3)))
                 if terms > cap or wall > budget_s:
                     break
             row[mode] = dict(layers=[a for a, _, _ in series], terms=[b for _, b, _ in series],
                              ms=[c for _, _, c in series])
+            if stop:
+                row[mode]["stopped"] = stop
         sat = [t for t in row["symmetry"]["terms"]]
         row["saturated"] = bool(sat) and max(sat) == row["necklaces"] - 1
         assert max(sat) <= row["necklaces"] - 1, (n, max(sat))
         rows.append(row)
         print(f"[ising family] n={n} sym {row['symmetry']['terms'][-1]} terms at "
               f"{row['symmetry']['layers'][-1]} layers", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()                  # the largest stores are not kept for later legs
     return dict(workload=f"tilted-field Ising ring n={ns[0]}..{ns[-1]}, dt={dt}, untruncated, "
-                         f"merged per Trotter layer, up to {max_layers} layers or {cap} terms",
-                rows=rows)
+                         f"merged per Trotter layer, up to {max_layers} layers, {cap} terms or "
+                         f"a store of {max_entries} entries", rows=rows)
 
 
 def batched_leg(stream, alloc, count, cap_terms):

@@ -696,9 +696,9 @@ def host_info():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the term set "
-              "would shard by representative hash with an all-to-all per layer, which this "
-              "build does not implement.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "term set by representative hash, with an all-to-all per layer, is not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2512_12094_amd import _lib as L

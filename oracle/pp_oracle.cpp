@@ -4,7 +4,7 @@
 //
 // TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously-correct
 // host implementation that the tests, the smoke check and the benchmark's
-// CPU-baseline leg use to judge the HIP library.  The product path never
+// CPU-baseline leg use to check the HIP library.  The product path never
 // links, loads or calls it, and it shares no code with the HIP sources.
 //
 // Everything is FP64 with exact integer Pauli algebra, kept in std::map

@@ -12,7 +12,8 @@ is counted by pp_merge_stats:
   rows are five strings), summed through the global merge table;
 * buckets with more distinct representatives than one table holds (every
   string once), summed in selector passes;
-* the one key equal to the merge table's empty marker (Y on all 32 qubits).
+* the one key equal to the merge table's empty marker (Y on all 32 qubits);
+* a group given by its element list (D_32's 64 permutations).
 Algorithm 1 step 1; Algorithms 2 and 3."""
 import numpy as np
 import pytest
@@ -107,6 +108,40 @@ def test_partitioned_merge_dihedral_and_plain(gpu):
         want = O.merge_records(32, group, x, z, c)
         check_bitwise(terms, want, wc, len(c))
         assert st["partitioned_merges"] == 1, st
+
+
+def test_partitioned_merge_explicit_group(gpu):
+    """The same path for a group given by its element list (D_32, its 64
+    permutations): 2^18 + 4097 distinct Z_32 rows (so every row is its own
+    addend on both sides) against the oracle's orbit sums for that list,
+    bitwise, and equal to the named dihedral handle's result."""
+    from paper_2512_12094_amd import _lib as L
+    x, z, c = W.merge_stress_records(20, 4, seed=23)
+    keys = np.stack([x, z], axis=1)
+    _, first = np.unique(keys, axis=0, return_index=True)
+    first = np.sort(first)[:(1 << 18) + 4097]
+    x, z, c = x[first], z[first], c[first]
+    perms = W.elements_dihedral(32)
+    print(f"[case] partitioned merge {len(c)} rows, explicit group of {len(perms)}", flush=True)
+    L.pp_profile(None, 1)
+    h = L.pp_create_group(32, perms, x.reshape(-1, 1), z.reshape(-1, 1), c, gpu["handle"],
+                          gpu["alloc"])
+    L.pp_profile(None, 0)
+    prof = L.pp_profile_read(h)
+    wc = L.pp_work_counters(h)
+    st = L.pp_merge_stats(h)
+    gx, gz, gc = L.pp_export_terms(h, 1)
+    L.pp_destroy(h)
+    terms = {(int(a), int(b)): float(v) for a, b, v in zip(gx[:, 0], gz[:, 0], gc)}
+    assert prof["part_hist"][0] == 1 and st["partitioned_merges"] == 1, (prof, st)
+    o = O.Oracle(32, "G", perms=perms)
+    for a, b, v in zip(x, z, c):
+        o.add(int(a), int(b), float(v))
+    o.merge()
+    want = o.as_dict()
+    check_bitwise(terms, want, wc, len(c))
+    named, _, _, _ = merge_on_gpu(gpu, x, z, c, group="Dn")
+    assert named == terms
 
 
 def test_partitioned_merge_ragged_sizes(gpu):
